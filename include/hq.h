@@ -1,0 +1,171 @@
+/*
+ * hq.h -- C ABI of libhq, DQMC sweeps of the 2D Holstein model on one
+ * MI355X (gfx950) GPU.
+ *
+ * The method is the determinant quantum Monte Carlo of Li, Dee, Khatami and
+ * Johnston, "Accelerating lattice quantum Monte Carlo simulations using
+ * artificial neural networks: an application to the Holstein model":
+ *   - Hamiltonian and units: section "Model";
+ *   - Trotter slices, weight W = exp(-S_ph dtau) det M_up det M_dn,
+ *     M = I + B_L ... B_1, B_l = exp(-dtau H_eph) exp(-dtau H_0), local and
+ *     block moves accepted with W'/W: section "Determinant quantum Monte Carlo";
+ *   - the network local move and the cumulative update p_c: sections
+ *     "Local Updates" and "Global Updates" (the p_c equation).
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - site i = ix + nx*iy, periodic hopping -t to four neighbours (with
+ *     multiplicity), -mu on the diagonal; slices l = 0..L-1, L = beta/dtau,
+ *     periodic in imaginary time;
+ *   - coupling g*x_i*(n_i - 1): B_l = diag(exp(-dtau g x[l,:])) exp(-dtau K)
+ *     and the bosonic action S_b = dtau*S_ph - dtau*g*sum(x);
+ *   - both spins are equal, W = exp(-S_b) det(M)^2; only log|det M| is kept;
+ *   - sweep: slices ascending; per slice the wrap G <- B_l G B_l^-1, then
+ *     sites ascending, one local move each; G and log|det M| recomputed
+ *     (FP64, QR-stabilised) after every n_stab slices; then, if enabled, one
+ *     block move per site in ascending order;
+ *   - every random number comes from Philox4x64-10 with key (seed, 0) and
+ *     counter (chain, sweep, slot, kind), so results do not depend on the
+ *     execution order on the GPU.
+ *
+ * Memory: the caller owns one device buffer (the workspace, size from
+ * hq_workspace_bytes) and the HIP stream; both must outlive the context.
+ * The library allocates no device memory of its own.  Host buffers passed
+ * to hq_read_* / hq_set_* are caller-owned and only used during the call.
+ *
+ * Errors: every call returns an hq_status.  Invalid arguments give
+ * HQ_EINVAL and change nothing.  A failed HIP call gives HQ_EDEVICE and makes
+ * the context unusable (later calls return HQ_ESTATE).  hq_last_error gives a
+ * message owned by the context, valid until the next call on it.
+ *
+ * Threading: one context per host thread; all device work is ordered on the
+ * context's stream.
+ */
+#ifndef HQ_H
+#define HQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hq_ctx hq_ctx;
+
+typedef enum {
+  HQ_OK = 0,
+  HQ_EINVAL = -1,   /* bad argument; nothing changed */
+  HQ_ENOMEM = -2,   /* workspace too small */
+  HQ_EDEVICE = -3,  /* a HIP call failed */
+  HQ_ESTATE = -4,   /* context unusable after an earlier device error */
+  HQ_ENUMERIC = -5  /* non-finite G or log det in some chain (see hq_stats.flags) */
+} hq_status;
+
+enum { HQ_PREC_FP64 = 0, HQ_PREC_MIXED = 1 };
+enum { HQ_PROPOSAL_DQMC = 0, HQ_PROPOSAL_NETWORK = 1 };
+/* decision kinds; equal to word 3 of the Philox counter of the draw */
+enum { HQ_KIND_LOCAL = 0, HQ_KIND_GLOBAL = 1, HQ_KIND_NN = 3, HQ_KIND_CUMULATIVE = 4 };
+
+/* One group of chains sharing a lattice and model parameters.  Chains are
+ * numbered consecutively over the groups in the order given. */
+typedef struct {
+  int32_t nx;            /* lattice is nx*nx, periodic; N = nx*nx <= 256 */
+  int32_t n_chains;      /* >= 1 */
+  double t, mu;          /* hopping and chemical potential (section "Model") */
+  double mass, omega;    /* ion mass M and phonon frequency Omega */
+  double g;              /* e-ph coupling, used when g_hi <= g_lo */
+  double g_lo, g_hi;     /* if g_hi > g_lo: per-chain g ~ U(g_lo, g_hi) */
+  double beta, dtau;     /* L = beta/dtau must be an integer >= 2 */
+  int32_t n_stab;        /* FP64 recompute every n_stab slices; must divide L */
+  int32_t proposal;      /* HQ_PROPOSAL_DQMC or HQ_PROPOSAL_NETWORK */
+  double local_width;    /* local move d ~ U(-w, w) */
+  double global_width;   /* 0: no block moves; else one per site per sweep, d ~ U(-w, w) */
+} hq_group;
+
+typedef struct {
+  int32_t precision;     /* HQ_PREC_FP64 or HQ_PREC_MIXED (FP32 wraps and updates) */
+  int32_t delay;         /* delayed-update depth k (8, 16 or 32); 0 = autotuned */
+  int32_t activation;    /* network hidden activation: 0 ReLU, 1 softplus */
+  int32_t record;        /* 1: keep every decision of the last sweep (hq_read_decisions) */
+} hq_options;
+
+typedef struct {
+  double logdet;             /* tracked log|det M| */
+  double g;                  /* this chain's coupling */
+  int64_t local_proposals, local_accepts;
+  int64_t global_proposals, global_accepts;
+  int64_t nn_proposals, nn_accepts;
+  int64_t cumulative_proposals, cumulative_accepts;
+  double max_drift_green;    /* max |G_tracked - G_recomputed| at stabilisation points */
+  double max_drift_logdet;   /* max |logdet_tracked - logdet_recomputed| */
+  double last_drift_green;   /* the same, last stabilisation point only */
+  double density, double_occupancy, s_cdw, x_mean, x2_mean;  /* from the current G, x */
+  int64_t replay_overrides;  /* decisions taken from the replay log inside the tie band */
+  int64_t replay_mismatches; /* replay disagreements outside the tie band */
+  int32_t n, L, flags;       /* flags: bit 0 non-finite G / log det seen */
+} hq_stats;
+
+/* Bytes of device workspace needed for these groups and options; 0 if invalid. */
+size_t hq_workspace_bytes(const hq_group* groups, int32_t n_groups, const hq_options* opt);
+
+/* Create a context on the current HIP device, carve the workspace, draw the
+ * initial fields x[l,i] ~ N(0,1) (Box-Muller on Philox kind 2) and per-chain
+ * couplings (kind 5), and compute G and log|det M| from scratch.  stream is a
+ * hipStream_t (not the null stream: sweeps are captured into a HIP graph). */
+hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* opt,
+                    uint64_t seed, void* workspace, size_t workspace_bytes,
+                    void* stream, hq_ctx** out);
+
+/* Replace one chain's fields (host array x[l*N + i], L*N doubles) and recompute
+ * G and log|det M| of its group from scratch.  Counters are kept. */
+hq_status hq_set_fields(hq_ctx* ctx, int32_t chain, const double* x_host, int64_t n);
+
+/* Load the 45-64-64-1 network (7169 FP32 values: W1[64][45], b1[64],
+ * W2[64][64], b2[64], W3[64], b3) used by HQ_PROPOSAL_NETWORK groups. */
+hq_status hq_set_network(hq_ctx* ctx, const float* weights, int64_t n);
+
+/* Run n_sweeps full sweeps of every chain (asynchronous on the stream). */
+hq_status hq_sweep(hq_ctx* ctx, int32_t n_sweeps);
+
+/* Recompute G and log|det M| of every chain from its fields (FP64). */
+hq_status hq_recompute(hq_ctx* ctx);
+
+/* Copy one chain's state to host memory (synchronises the stream).
+ * green: N*N row-major FP64, G_ij = <c_i c_j^dagger> at the imaginary-time
+ * boundary.  fields: L*N FP64, x[l*N + i]. */
+hq_status hq_read_green(hq_ctx* ctx, int32_t chain, double* out, int64_t n);
+hq_status hq_read_fields(hq_ctx* ctx, int32_t chain, double* out, int64_t n);
+hq_status hq_read_stats(hq_ctx* ctx, int32_t chain, hq_stats* out);
+
+/* Decisions of the last sweep for one chain and kind, in slot order (local
+ * and network: l*N + i; block: i; cumulative: 0).  accept[k] is 0/1;
+ * margin[k] = ln u - ln R (FP32).  Needs options.record = 1. */
+hq_status hq_read_decisions(hq_ctx* ctx, int32_t chain, int32_t kind,
+                            uint8_t* accept, float* margin, int64_t n);
+
+/* Tie-band replay for the next sweep only: where |ln u - ln R| <= band the
+ * chain takes bits[slot] instead of its own decision; elsewhere a
+ * disagreement is counted in hq_stats.replay_mismatches.  n = 0 clears. */
+hq_status hq_set_replay(hq_ctx* ctx, int32_t chain, int32_t kind,
+                        const uint8_t* bits, int64_t n, double band);
+
+/* Number of chains, and one chain's N and L. */
+int32_t hq_num_chains(const hq_ctx* ctx);
+hq_status hq_chain_shape(const hq_ctx* ctx, int32_t chain, int32_t* n, int32_t* L);
+
+/* Average device time per launch of the named kernel over the last hq_sweep
+ * calls, measured with HIP events on the context's stream when profiling is
+ * on.  names: "wrap", "local", "stab", "global", "network". */
+hq_status hq_set_profiling(hq_ctx* ctx, int32_t on);
+hq_status hq_phase_time(hq_ctx* ctx, const char* phase, double* ms_total, int64_t* launches);
+
+/* Wait for all work on the context's stream. */
+hq_status hq_synchronize(hq_ctx* ctx);
+
+const char* hq_last_error(const hq_ctx* ctx);
+void hq_destroy(hq_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HQ_H */

@@ -1,0 +1,146 @@
+// Batched dense products on MFMA for the wraps, block products and UDT
+// combines of the DQMC sweep.  C = alpha * diag(rs) op(A) op(B) diag(cs)
+// + beta * C, row-major, one workgroup per (tile, batch entry).
+//
+// FP64 uses v_mfma_f64_16x16x4f64, FP32 uses v_mfma_f32_16x16x4f32 with
+// FP32 accumulation.  A workgroup tile of BM x BN is split over WM x WN
+// waves, each computing FM x FN fragments of 16 x 16; K advances in stages
+// of BK = 16 staged through LDS.  Edges are zero-padded on load and masked
+// on store, so any M, N, K works.
+#include "hq_device.h"
+#include "hq_internal.h"
+
+namespace hq {
+
+__device__ inline double scale_value(const Scale& s, int z, int inner_count, int i) {
+  if (!s.v) return 1.0;
+  const int outer = z / inner_count, inner = z - outer * inner_count;
+  double v = s.v[(long)outer * s.so + (long)inner * s.si + s.off + i];
+  if (s.coef) v = exp(s.cmul * s.coef[outer] * v);
+  if (s.invert) v = 1.0 / v;
+  return v;
+}
+
+template <typename T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
+  constexpr int NT = WM * WN * 64;
+  constexpr int BK = 16;
+  constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
+  constexpr int PAD = 2;
+  static_assert(FM >= 1 && FN >= 1, "tile too small");
+  __shared__ T As[BK][BM + PAD];
+  __shared__ T Bs[BK][BN + PAD];
+  __shared__ double rsv[BM];
+  __shared__ double csv[BN];
+
+  const int z = blockIdx.z;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const T* A = a.A + (long)z * a.sA;
+  const T* B = a.B + (long)z * a.sB;
+  T* C = a.C + (long)z * a.sC;
+
+  for (int i = tid; i < BM; i += NT)
+    rsv[i] = (m0 + i < a.M) ? scale_value(a.rs, z, a.inner_count, m0 + i) : 0.0;
+  for (int i = tid; i < BN; i += NT)
+    csv[i] = (n0 + i < a.N) ? scale_value(a.cs, z, a.inner_count, n0 + i) : 0.0;
+
+  typedef typename Frag<T>::type F;
+  F acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = F{0, 0, 0, 0};
+
+  for (int k0 = 0; k0 < a.K; k0 += BK) {
+    // stage A: As[k][m] = op(A)(m0+m, k0+k)
+    for (int e = tid; e < BM * BK; e += NT) {
+      int m, k;
+      if (a.tA) { m = e % BM; k = e / BM; } else { k = e % BK; m = e / BK; }
+      const int gm = m0 + m, gk = k0 + k;
+      T v = 0;
+      if (gm < a.M && gk < a.K) v = a.tA ? A[(long)gk * a.lda + gm] : A[(long)gm * a.lda + gk];
+      As[k][m] = v;
+    }
+    // stage B: Bs[k][n] = op(B)(k0+k, n0+n)
+    for (int e = tid; e < BN * BK; e += NT) {
+      int n, k;
+      if (a.tB) { k = e % BK; n = e / BK; } else { n = e % BN; k = e / BN; }
+      const int gn = n0 + n, gk = k0 + k;
+      T v = 0;
+      if (gn < a.N && gk < a.K) v = a.tB ? B[(long)gn * a.ldb + gk] : B[(long)gk * a.ldb + gn];
+      Bs[k][n] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      T af[FM], bf[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) af[i] = As[kk + (lane >> 4)][wm * FM * 16 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bf[j] = Bs[kk + (lane >> 4)][wn * FN * 16 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = wm * FM * 16 + i * 16 + frag_row<T>(lane, v);
+        const int lc = wn * FN * 16 + j * 16 + (lane & 15);
+        const int r = m0 + lr, c = n0 + lc;
+        if (r < a.M && c < a.N) {
+          double val = a.alpha * rsv[lr] * (double)acc[i][j][v] * csv[lc];
+          T* dst = C + (long)r * a.ldc + c;
+          if (a.beta != 0.0) val += a.beta * (double)(*dst);
+          *dst = (T)val;
+        }
+      }
+}
+
+template <typename T, int BM, int BN, int WM, int WN>
+static hipError_t launch_tile(const GemmArgs<T>& a, hipStream_t s) {
+  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, a.batch);
+  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_any(const GemmArgs<T>& a, int tile, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
+  switch (tile) {
+    case TILE_32x32: return launch_tile<T, 32, 32, 1, 1>(a, s);
+    case TILE_48x48: return launch_tile<T, 48, 48, 3, 1>(a, s);
+    case TILE_16x64: return launch_tile<T, 16, 64, 1, 4>(a, s);
+    default: return launch_tile<T, 64, 64, 2, 2>(a, s);
+  }
+}
+
+hipError_t launch_gemm(const GemmArgs<double>& a, int tile, hipStream_t s) { return launch_any(a, tile, s); }
+hipError_t launch_gemm(const GemmArgs<float>& a, int tile, hipStream_t s) { return launch_any(a, tile, s); }
+
+// P[z] = diag(rs(z)) * A, A shared by the batch
+__global__ void scale_rows_kernel(double* P, long sP, const double* A, int n, Scale rs, int inner_count) {
+  const int z = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int r = e / n;
+  P[(long)z * sP + e] = scale_value(rs, z, inner_count, r) * A[e];
+}
+
+hipError_t launch_scale_rows(double* P, long sP, const double* A, int n, Scale rs, int batch,
+                             int inner_count, hipStream_t s) {
+  dim3 grid((n * n + 255) / 256, batch);
+  hipLaunchKernelGGL(scale_rows_kernel, grid, dim3(256), 0, s, P, sP, A, n, rs, inner_count);
+  return hipGetLastError();
+}
+
+}  // namespace hq

@@ -1,0 +1,981 @@
+// Host layer of libhq: validation, workspace layout, model set-up, the sweep
+// schedule (captured once into a HIP graph and replayed), and the C ABI of
+// include/hq.h.
+//
+// Sweep schedule of one group (paper, section "Determinant quantum Monte
+// Carlo"; stabilisation as in the DQMC literature the paper cites):
+//   right stack R_b = C_{nb-1} ... C_{b+1} (as UDT of its transpose) from the
+//     cached block products C_b = B_{(b+1)ns-1} ... B_{b ns}, which are valid
+//     because no field has changed since they were formed;
+//   for each block b: for its n_stab slices: wrap, local moves; then form C_b
+//     with the new fields, fold it into the left UDT L_b = C_b L_{b-1}, and
+//     merge G = (I + L_b R_b)^-1 and log|det M| (FP64);
+//   then the block moves (if enabled), each with a from-scratch determinant;
+//   network groups instead run the colour classes of network proposals, a
+//     from-scratch determinant of the proposal, and the cumulative accept.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hq.h"
+#include "hq_device.h"
+#include "hq_internal.h"
+
+using namespace hq;
+
+namespace {
+
+const int N_KIND_SLOTS = 5;   // indexed by HQ_KIND_* (0, 1, 3, 4 used)
+
+struct Group {
+  hq_group p{};
+  int nx = 0, n = 0, L = 0, ns = 0, nb = 0, C = 0, chain0 = 0;
+  int nt = 256, kd = 16, tile = TILE_64x64, tile32 = TILE_64x64;
+  bool global = false, network = false;
+  // fields, couplings, model matrices
+  double *x = nullptr, *xp = nullptr, *g = nullptr;
+  double *expk = nullptr, *expkinv = nullptr, *ident = nullptr, *ones = nullptr;
+  float *expk32 = nullptr, *expkinv32 = nullptr;
+  // Green's functions
+  void* G = nullptr;             // [C][n][n], precision of the context
+  void* Wt = nullptr;            // wrap temporary, same precision
+  double* Gnew = nullptr;        // [C][n][n]
+  // block products and UDT stacks
+  double *blk = nullptr, *blkp = nullptr, *blks = nullptr;     // [C][nb][n][n]
+  double *RU = nullptr, *RD = nullptr, *RT = nullptr;          // [C][nb][n][n], [C][nb][n]
+  double *LU = nullptr, *LD = nullptr, *LT[2] = {nullptr, nullptr};
+  double *Z = nullptr, *Rt = nullptr, *M = nullptr, *Minv = nullptr, *Xm = nullptr;
+  double *dLbinv = nullptr, *dLs = nullptr, *dRbinv = nullptr, *dRs = nullptr, *sumlog = nullptr;
+  double *logdet = nullptr, *logdet_new = nullptr, *shift = nullptr;
+  int64_t* counters = nullptr;
+  double *drift = nullptr, *obs = nullptr, *lastpc = nullptr;
+  int* flags = nullptr;
+  int64_t* replay_counts = nullptr;
+  float* log_margin[N_KIND_SLOTS] = {};
+  uint8_t* log_accept[N_KIND_SLOTS] = {};
+  uint8_t* replay[N_KIND_SLOTS] = {};
+  double band[N_KIND_SLOTS] = {};
+  double* sum_y = nullptr;
+  uint8_t* nn_acc = nullptr;
+  long kind_slots(int kind) const {
+    if (kind == HQ_KIND_LOCAL || kind == HQ_KIND_NN) return (long)L * n;
+    if (kind == HQ_KIND_GLOBAL) return n;
+    return 1;
+  }
+};
+
+// bump allocator over the caller's workspace (a null base only measures)
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct hq_ctx {
+  std::vector<Group> groups;
+  hq_options opt{};
+  uint64_t seed = 0;
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int64_t* sweep_counter = nullptr;
+  float* net = nullptr;
+  bool net_loaded = false;
+  int n_chains = 0;
+  bool broken = false;
+  std::string err;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool profiling = false;
+  // per-phase event timing (profiling mode runs the schedule eagerly)
+  struct Phase { const char* name; double ms; int64_t launches; };
+  std::vector<Phase> phases;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<int> pending_phase;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+hq_status fail(hq_ctx* c, hq_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) {
+    c->err = buf;
+    if (st == HQ_EDEVICE) c->broken = true;
+  }
+  return st;
+}
+
+#define HQ_TRY(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(ctx, HQ_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+bool valid_group(const hq_group& p, const hq_options& o, std::string& why) {
+  char b[256];
+  if (p.nx < 1 || p.nx * p.nx > 256) { why = "nx must give 1 <= N <= 256"; return false; }
+  if (p.n_chains < 1) { why = "n_chains must be >= 1"; return false; }
+  if (!(p.dtau > 0) || !(p.beta > 0) || !std::isfinite(p.beta / p.dtau)) { why = "beta, dtau must be > 0"; return false; }
+  const long L = lround(p.beta / p.dtau);
+  if (L < 2 || std::fabs(L * p.dtau - p.beta) > 1e-9) { why = "beta/dtau must be an integer >= 2"; return false; }
+  if (p.n_stab < 1 || L % p.n_stab) { why = "n_stab must divide L"; return false; }
+  if (!(p.mass > 0) || !std::isfinite(p.t) || !std::isfinite(p.mu) || !std::isfinite(p.g) ||
+      !std::isfinite(p.omega) || !(p.local_width >= 0) || !(p.global_width >= 0)) {
+    why = "model parameters must be finite (mass > 0, widths >= 0)";
+    return false;
+  }
+  if (p.proposal != HQ_PROPOSAL_DQMC && p.proposal != HQ_PROPOSAL_NETWORK) { why = "bad proposal"; return false; }
+  if (p.proposal == HQ_PROPOSAL_NETWORK && (p.nx % 2 || L % 4)) {
+    why = "network proposals need even nx and L divisible by 4";
+    return false;
+  }
+  const int n = p.nx * p.nx;
+  if (!qr_supported(n) || !gj_supported(n)) {
+    snprintf(b, sizeof b, "N = %d exceeds the register-resident factorization (N <= 192)", n);
+    why = b;
+    return false;
+  }
+  if (p.proposal == HQ_PROPOSAL_DQMC) {
+    const int nt = n <= 64 ? 64 : 256;
+    const int kd = o.delay ? o.delay : 16;
+    if (!local_supported(n, o.precision, nt, kd)) {
+      snprintf(b, sizeof b, "N = %d (precision %d, delay %d) does not fit the LDS-resident local kernel", n,
+               o.precision, kd);
+      why = b;
+      return false;
+    }
+  }
+  return true;
+}
+
+// carve every buffer of every group; returns total bytes
+size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options& o) {
+  Carver cv(base);
+  const size_t ts = o.precision ? sizeof(float) : sizeof(double);
+  for (Group& g : gs) {
+    const long n = g.n, nn = n * n, C = g.C, L = g.L, nb = g.nb;
+    g.x = cv.take<double>(C * L * n);
+    g.xp = cv.take<double>(C * L * n);
+    g.g = cv.take<double>(C);
+    g.expk = cv.take<double>(nn);
+    g.expkinv = cv.take<double>(nn);
+    g.ident = cv.take<double>(nn);
+    g.ones = cv.take<double>(C * n);
+    g.expk32 = cv.take<float>(nn);
+    g.expkinv32 = cv.take<float>(nn);
+    g.G = cv.take<char>(C * nn * ts);
+    g.Wt = cv.take<char>(C * nn * ts);
+    g.Gnew = cv.take<double>(C * nn);
+    g.blk = cv.take<double>(C * nb * nn);
+    g.blkp = cv.take<double>(C * nb * nn);
+    g.blks = cv.take<double>(C * nb * nn);
+    g.RU = cv.take<double>(C * nb * nn);
+    g.RD = cv.take<double>(C * nb * n);
+    g.RT = cv.take<double>(C * nb * nn);
+    g.LU = cv.take<double>(C * nn);
+    g.LD = cv.take<double>(C * n);
+    g.LT[0] = cv.take<double>(C * nn);
+    g.LT[1] = cv.take<double>(C * nn);
+    g.Z = cv.take<double>(C * nn);
+    g.Rt = cv.take<double>(C * nn);
+    g.M = cv.take<double>(C * nn);
+    g.Minv = cv.take<double>(C * nn);
+    g.Xm = cv.take<double>(C * nn);
+    g.dLbinv = cv.take<double>(C * n);
+    g.dLs = cv.take<double>(C * n);
+    g.dRbinv = cv.take<double>(C * n);
+    g.dRs = cv.take<double>(C * n);
+    g.sumlog = cv.take<double>(C);
+    g.logdet = cv.take<double>(C);
+    g.logdet_new = cv.take<double>(C);
+    g.shift = cv.take<double>(C);
+    g.counters = cv.take<int64_t>(C * N_COUNTERS);
+    g.drift = cv.take<double>(C * 5);
+    g.obs = cv.take<double>(C * 5);
+    g.lastpc = cv.take<double>(C * 2);
+    g.flags = cv.take<int>(C);
+    g.replay_counts = cv.take<int64_t>(C * 2);
+    for (int k : {HQ_KIND_LOCAL, HQ_KIND_GLOBAL, HQ_KIND_NN, HQ_KIND_CUMULATIVE}) {
+      const long slots = C * g.kind_slots(k);
+      g.replay[k] = cv.take<uint8_t>(slots);
+      if (o.record) {
+        g.log_margin[k] = cv.take<float>(slots);
+        g.log_accept[k] = cv.take<uint8_t>(slots);
+      }
+    }
+    if (g.network) {
+      g.sum_y = cv.take<double>(C * L * n);
+      g.nn_acc = cv.take<uint8_t>(C * L * n);
+    }
+  }
+  if (ctx) {
+    ctx->sweep_counter = cv.take<int64_t>(1);
+    ctx->net = cv.take<float>(7169 + 7);
+  } else {
+    cv.take<int64_t>(1);
+    cv.take<float>(7169 + 7);
+  }
+  return cv.off + 256;
+}
+
+bool build_groups(const hq_group* gp, int ng, const hq_options& o, std::vector<Group>& out, std::string& why) {
+  out.clear();
+  int chain0 = 0;
+  for (int k = 0; k < ng; ++k) {
+    if (!valid_group(gp[k], o, why)) return false;
+    Group g;
+    g.p = gp[k];
+    g.nx = gp[k].nx;
+    g.n = g.nx * g.nx;
+    g.L = (int)lround(gp[k].beta / gp[k].dtau);
+    g.ns = gp[k].n_stab;
+    g.nb = g.L / g.ns;
+    g.C = gp[k].n_chains;
+    g.chain0 = chain0;
+    g.global = gp[k].global_width > 0.0 && gp[k].proposal == HQ_PROPOSAL_DQMC;
+    g.network = gp[k].proposal == HQ_PROPOSAL_NETWORK;
+    g.nt = g.n <= 64 ? 64 : 256;
+    g.kd = o.delay ? o.delay : 16;
+    g.tile = g.n <= 32 ? TILE_32x32 : TILE_64x64;
+    g.tile32 = g.tile;
+    chain0 += g.C;
+    out.push_back(g);
+  }
+  return true;
+}
+
+// exp(sign * dtau * K) from the plane-wave decomposition of the periodic
+// hopping matrix: (1/N) sum_k cos(k . (r_i - r_j)) exp(-sign' dtau eps_k),
+// eps_k = -2t (cos kx + cos ky) - mu.
+void exp_hopping(const hq_group& p, double sign, std::vector<double>& out) {
+  const int nx = p.nx, n = nx * nx;
+  std::vector<double> f((size_t)n, 0.0);
+  const double tw = 2.0 * M_PI / nx;
+  for (int dy = 0; dy < nx; ++dy)
+    for (int dx = 0; dx < nx; ++dx) {
+      double s = 0.0;
+      for (int my = 0; my < nx; ++my)
+        for (int mx = 0; mx < nx; ++mx) {
+          const double kx = tw * mx, ky = tw * my;
+          const double eps = -2.0 * p.t * (std::cos(kx) + std::cos(ky)) - p.mu;
+          s += std::cos(kx * dx + ky * dy) * std::exp(sign * p.dtau * eps);
+        }
+      f[dx + nx * dy] = s / n;
+    }
+  out.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const int dx = ((i % nx) - (j % nx) + nx) % nx, dy = ((i / nx) - (j / nx) + nx) % nx;
+      out[(size_t)i * n + j] = f[dx + nx * dy];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// schedule building blocks (all FP64 unless noted)
+// ---------------------------------------------------------------------------
+struct Sched {
+  hq_ctx* ctx;
+  hipStream_t s;
+  int phase = -1;   // profiling phase of the launches being issued
+};
+
+hq_status begin_phase(Sched& S, int ph) {
+  hq_ctx* ctx = S.ctx;
+  if (!ctx->profiling) return HQ_OK;
+  hipEvent_t a, b;
+  if (ctx->event_pool.size() >= 2) {
+    a = ctx->event_pool.back(); ctx->event_pool.pop_back();
+    b = ctx->event_pool.back(); ctx->event_pool.pop_back();
+  } else {
+    HQ_TRY(hipEventCreate(&a));
+    HQ_TRY(hipEventCreate(&b));
+  }
+  HQ_TRY(hipEventRecord(a, S.s));
+  ctx->pending.push_back({a, b});
+  ctx->pending_phase.push_back(ph);
+  S.phase = ph;
+  return HQ_OK;
+}
+hq_status end_phase(Sched& S) {
+  hq_ctx* ctx = S.ctx;
+  if (!ctx->profiling || S.phase < 0) return HQ_OK;
+  HQ_TRY(hipEventRecord(ctx->pending.back().second, S.s));
+  S.phase = -1;
+  return HQ_OK;
+}
+enum { PH_WRAP = 0, PH_LOCAL, PH_STAB, PH_GLOBAL, PH_NETWORK, N_PHASES };
+const char* kPhaseNames[N_PHASES] = {"wrap", "local", "stab", "global", "network"};
+
+#define SCHED_TRY(expr)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(S.ctx, HQ_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+#define ST_TRY(expr)                  \
+  do {                                \
+    hq_status st_ = (expr);           \
+    if (st_ != HQ_OK) return st_;     \
+  } while (0)
+
+GemmArgs<double> sq(const Group& g, int batch) {
+  GemmArgs<double> a;
+  a.M = a.N = a.K = g.n;
+  a.lda = a.ldb = a.ldc = g.n;
+  a.batch = batch;
+  return a;
+}
+
+// block products C_{c,b} = B_{b ns + ns - 1} ... B_{b ns} of the fields xs for
+// blocks b0 .. b0+nblk-1 of every chain.  dst stride per chain: nb*n*n when
+// nblk == 1 (into the cached array), else dst is [C][nblk][n][n] contiguous.
+hq_status block_products(Sched& S, Group& g, const double* xs, double* dst, long dst_chain_stride, double* scratch,
+                         int b0, int nblk) {
+  const long nn = (long)g.n * g.n;
+  const int batch = g.C * nblk;
+  // with nblk == 1 the batch index is the chain; dst advances by dst_chain_stride
+  const long sdst = (nblk == 1) ? dst_chain_stride : nn;
+  double* bufs[2] = {dst, scratch};
+  long strides[2] = {sdst, nn};
+  int cur = ((g.ns - 1) % 2 == 0) ? 0 : 1;
+  Scale rs;
+  rs.v = xs;
+  rs.so = (long)g.L * g.n;
+  rs.si = (long)g.ns * g.n;
+  rs.coef = g.g;
+  rs.cmul = -g.p.dtau;
+  rs.off = (long)b0 * g.ns * g.n;
+  SCHED_TRY(launch_scale_rows(bufs[cur], strides[cur], g.expk, g.n, rs, batch, nblk, S.s));
+  for (int t = 1; t < g.ns; ++t) {
+    GemmArgs<double> a = sq(g, batch);
+    a.A = g.expk; a.sA = 0;
+    a.B = bufs[cur]; a.sB = strides[cur];
+    a.C = bufs[1 - cur]; a.sC = strides[1 - cur];
+    a.rs = rs;
+    a.rs.off = (long)(b0 * g.ns + t) * g.n;
+    a.inner_count = nblk;
+    SCHED_TRY(launch_gemm(a, g.tile, S.s));
+    cur = 1 - cur;
+  }
+  return HQ_OK;
+}
+
+// (Uout, Dout, Tout) = QR-UDT of op(A) * Uin * diag(Din) combined with Tin.
+// A, Uin, Tin advance by the given per-chain strides.
+hq_status combine(Sched& S, Group& g, const double* A, long sA, int tA, const double* Uin, long sU, const double* Din,
+                  long sD, const double* Tin, long sT, double* Uout, long sUo, double* Dout, long sDo, double* Tout,
+                  long sTo) {
+  const long nn = (long)g.n * g.n;
+  GemmArgs<double> a = sq(g, g.C);
+  a.A = A; a.sA = sA; a.tA = tA;
+  a.B = Uin; a.sB = sU;
+  a.C = g.Z; a.sC = nn;
+  a.cs.v = Din; a.cs.so = sD;
+  SCHED_TRY(launch_gemm(a, g.tile, S.s));
+  // Q and D go straight into the UDT arrays, which are contiguous per chain
+  if (sUo != nn || sDo != g.n) return fail(S.ctx, HQ_EINVAL, "internal: strided QR output");
+  SCHED_TRY(launch_qr(g.Z, Uout, Dout, g.Rt, g.n, g.C, S.s));
+  GemmArgs<double> b = sq(g, g.C);
+  b.A = g.Rt; b.sA = nn;
+  b.B = Tin; b.sB = sT;
+  b.C = Tout; b.sC = sTo;
+  SCHED_TRY(launch_gemm(b, g.tile, S.s));
+  return HQ_OK;
+}
+
+// G = (I + L R)^-1 and log|det|, L = U_L D_L T_L, R = T_R^T D_R U_R^T
+// (identity R when UR == nullptr).  Results in g.Gnew, g.logdet_new.
+hq_status merge(Sched& S, Group& g, const double* UL, const double* DL, const double* TL, const double* UR, long sUR,
+                const double* DR, long sDR, const double* TR, long sTR) {
+  const long nn = (long)g.n * g.n;
+  const int n = g.n;
+  SCHED_TRY(launch_dsplit(DL, g.dLbinv, g.dLs, g.sumlog, 0, n, g.C, S.s));
+  const double *rb = g.ones, *rs_ = g.ones;
+  if (UR) {
+    // D_R may be strided (right stack); dsplit wants [C][n] contiguous
+    if (sDR != n) return fail(S.ctx, HQ_EINVAL, "internal: strided D_R");
+    SCHED_TRY(launch_dsplit(DR, g.dRbinv, g.dRs, g.sumlog, 1, n, g.C, S.s));
+    rb = g.dRbinv;
+    rs_ = g.dRs;
+  } else {
+    UR = g.ident; sUR = 0;
+    TR = g.ident; sTR = 0;
+  }
+  GemmArgs<double> a = sq(g, g.C);                 // M = Db_L^-1 (U_L^T U_R) Db_R^-1
+  a.A = UL; a.sA = nn; a.tA = 1;
+  a.B = UR; a.sB = sUR;
+  a.C = g.M; a.sC = nn;
+  a.rs.v = g.dLbinv; a.rs.so = n;
+  a.cs.v = rb; a.cs.so = n;
+  SCHED_TRY(launch_gemm(a, g.tile, S.s));
+  GemmArgs<double> b = sq(g, g.C);                 // M += Ds_L (T_L T_R^T) Ds_R
+  b.A = TL; b.sA = nn;
+  b.B = TR; b.sB = sTR; b.tB = 1;
+  b.C = g.M; b.sC = nn;
+  b.beta = 1.0;
+  b.rs.v = g.dLs; b.rs.so = n;
+  b.cs.v = rs_; b.cs.so = n;
+  SCHED_TRY(launch_gemm(b, g.tile, S.s));
+  // Minv = Db_R^-1 M^-1 Db_L^-1, logdet_new = sumlog + log|det M|
+  SCHED_TRY(launch_gj(g.M, g.Minv, rb, g.dLbinv, g.sumlog, g.logdet_new, n, g.C, S.s));
+  GemmArgs<double> c = sq(g, g.C);                 // X = Minv U_L^T
+  c.A = g.Minv; c.sA = nn;
+  c.B = UL; c.sB = nn; c.tB = 1;
+  c.C = g.Xm; c.sC = nn;
+  SCHED_TRY(launch_gemm(c, g.tile, S.s));
+  GemmArgs<double> d = sq(g, g.C);                 // G = U_R X
+  d.A = UR; d.sA = sUR;
+  d.B = g.Xm; d.sB = nn;
+  d.C = g.Gnew; d.sC = nn;
+  SCHED_TRY(launch_gemm(d, g.tile, S.s));
+  return HQ_OK;
+}
+
+// G and log|det M| of the fields xs from scratch: all block products, the
+// left UDT chain over every block, and the merge with an identity right part.
+// Leaves the block products in `blocks`.
+hq_status from_scratch(Sched& S, Group& g, const double* xs, double* blocks) {
+  const long nn = (long)g.n * g.n;
+  ST_TRY(block_products(S, g, xs, blocks, 0, g.blks, 0, g.nb));
+  SCHED_TRY(launch_identity(g.LU, g.LD, g.LT[0], g.n, g.C, S.s));
+  int t = 0;
+  for (int b = 0; b < g.nb; ++b) {
+    ST_TRY(combine(S, g, blocks + b * nn, (long)g.nb * nn, 0, g.LU, nn, g.LD, g.n, g.LT[t], nn, g.LU, nn, g.LD, g.n,
+                   g.LT[1 - t], nn));
+    t = 1 - t;
+  }
+  return merge(S, g, g.LU, g.LD, g.LT[t], nullptr, 0, nullptr, 0, nullptr, 0);
+}
+
+hq_status wrap(Sched& S, Group& g, int slice) {
+  const long nn = (long)g.n * g.n;
+  Scale rs, cs;
+  rs.v = g.x; rs.so = (long)g.L * g.n; rs.off = (long)slice * g.n; rs.coef = g.g; rs.cmul = -g.p.dtau;
+  cs = rs; cs.cmul = g.p.dtau;
+  if (S.ctx->opt.precision == HQ_PREC_MIXED) {
+    GemmArgs<float> a;
+    a.M = a.N = a.K = g.n; a.lda = a.ldb = a.ldc = g.n; a.batch = g.C;
+    a.A = g.expk32; a.sA = 0;
+    a.B = (const float*)g.G; a.sB = nn;
+    a.C = (float*)g.Wt; a.sC = nn;
+    SCHED_TRY(launch_gemm(a, g.tile32, S.s));
+    GemmArgs<float> b = a;
+    b.A = (const float*)g.Wt; b.sA = nn;
+    b.B = g.expkinv32; b.sB = 0;
+    b.C = (float*)g.G; b.sC = nn;
+    b.rs = rs; b.cs = cs;
+    SCHED_TRY(launch_gemm(b, g.tile32, S.s));
+  } else {
+    GemmArgs<double> a = sq(g, g.C);
+    a.A = g.expk; a.sA = 0;
+    a.B = (const double*)g.G; a.sB = nn;
+    a.C = (double*)g.Wt; a.sC = nn;
+    SCHED_TRY(launch_gemm(a, g.tile, S.s));
+    GemmArgs<double> b = a;
+    b.A = (const double*)g.Wt; b.sA = nn;
+    b.B = g.expkinv; b.sB = 0;
+    b.C = (double*)g.G; b.sC = nn;
+    b.rs = rs; b.cs = cs;
+    SCHED_TRY(launch_gemm(b, g.tile, S.s));
+  }
+  return HQ_OK;
+}
+
+hq_status local(Sched& S, Group& g, int slice) {
+  LocalArgs a;
+  a.n = g.n; a.L = g.L; a.slice = slice;
+  a.G = g.G; a.x = g.x; a.g = g.g;
+  a.dtau = g.p.dtau; a.mass = g.p.mass; a.omega = g.p.omega; a.width = g.p.local_width;
+  a.seed = S.ctx->seed; a.chain0 = g.chain0; a.sweep = S.ctx->sweep_counter;
+  a.logdet = g.logdet; a.counters = g.counters;
+  a.log_margin = g.log_margin[HQ_KIND_LOCAL]; a.log_accept = g.log_accept[HQ_KIND_LOCAL];
+  a.replay = g.replay[HQ_KIND_LOCAL]; a.band = g.band[HQ_KIND_LOCAL]; a.replay_counts = g.replay_counts;
+  SCHED_TRY(launch_local(a, S.ctx->opt.precision, g.nt, g.kd, g.C, S.s));
+  return HQ_OK;
+}
+
+hq_status stab_point(Sched& S, Group& g, int b, int& t) {
+  const long nn = (long)g.n * g.n;
+  ST_TRY(block_products(S, g, g.x, g.blk + b * nn, (long)g.nb * nn, g.Z, b, 1));
+  ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 0, g.LU, nn, g.LD, g.n, g.LT[t], nn, g.LU, nn, g.LD, g.n,
+                 g.LT[1 - t], nn));
+  t = 1 - t;
+  // right stack entry b lives at RU[b] etc. in [nb][C] order (contiguous per b)
+  ST_TRY(merge(S, g, g.LU, g.LD, g.LT[t], g.RU + (long)b * g.C * nn, nn, g.RD + (long)b * g.C * g.n, g.n,
+               g.RT + (long)b * g.C * nn, nn));
+  SCHED_TRY(launch_stab_finish(g.G, S.ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.n, g.C, 1, S.s));
+  return HQ_OK;
+}
+
+hq_status right_stack(Sched& S, Group& g) {
+  const long nn = (long)g.n * g.n;
+  const long eU = (long)g.C * nn, eD = (long)g.C * g.n;   // one stack entry, all chains
+  SCHED_TRY(launch_identity(g.RU + (g.nb - 1) * eU, g.RD + (g.nb - 1) * eD, g.RT + (g.nb - 1) * eU, g.n, g.C, S.s));
+  for (int b = g.nb - 2; b >= 0; --b) {
+    // R_b^T = C_{b+1}^T R_{b+1}^T
+    ST_TRY(combine(S, g, g.blk + (b + 1) * nn, (long)g.nb * nn, 1, g.RU + (b + 1) * eU, nn, g.RD + (b + 1) * eD, g.n,
+                   g.RT + (b + 1) * eU, nn, g.RU + b * eU, nn, g.RD + b * eD, g.n, g.RT + b * eU, nn));
+  }
+  return HQ_OK;
+}
+
+hq_status global_moves(Sched& S, Group& g) {
+  for (int i = 0; i < g.n; ++i) {
+    GlobalArgs a;
+    a.n = g.n; a.L = g.L; a.nb = g.nb; a.site = i;
+    a.x = g.x; a.xp = g.xp; a.g = g.g;
+    a.dtau = g.p.dtau; a.mass = g.p.mass; a.omega = g.p.omega; a.width = g.p.global_width;
+    a.seed = S.ctx->seed; a.chain0 = g.chain0; a.sweep = S.ctx->sweep_counter;
+    a.shift = g.shift; a.logdet = g.logdet; a.logdet_new = g.logdet_new;
+    a.G = g.G; a.precision = S.ctx->opt.precision; a.Gnew = g.Gnew;
+    a.blk = g.blk; a.blkp = g.blkp; a.counters = g.counters;
+    a.log_margin = g.log_margin[HQ_KIND_GLOBAL]; a.log_accept = g.log_accept[HQ_KIND_GLOBAL];
+    a.replay = g.replay[HQ_KIND_GLOBAL]; a.band = g.band[HQ_KIND_GLOBAL]; a.replay_counts = g.replay_counts;
+    SCHED_TRY(launch_global_propose(a, g.C, S.s));
+    ST_TRY(from_scratch(S, g, g.xp, g.blkp));
+    SCHED_TRY(launch_global_accept(a, g.C, S.s));
+  }
+  return HQ_OK;
+}
+
+hq_status network_sweep(Sched& S, Group& g) {
+  hq_ctx* ctx = S.ctx;
+  const long ln = (long)g.L * g.n;
+  SCHED_TRY(launch_copy_f64(g.xp, g.x, (long)g.C * ln, S.s));
+  for (int colour = 0; colour < 16; ++colour) {
+    NetArgs a;
+    a.nx = g.nx; a.n = g.n; a.L = g.L; a.colour = colour;
+    a.xp = g.xp; a.g = g.g;
+    a.dtau = g.p.dtau; a.mass = g.p.mass; a.omega = g.p.omega; a.width = g.p.local_width;
+    a.seed = ctx->seed; a.chain0 = g.chain0; a.sweep = ctx->sweep_counter;
+    a.w = ctx->net; a.activation = ctx->opt.activation; a.chains = g.C;
+    a.sum_y = g.sum_y; a.accepted = g.nn_acc; a.counters = g.counters;
+    a.log_margin = g.log_margin[HQ_KIND_NN]; a.log_accept = g.log_accept[HQ_KIND_NN];
+    a.replay = g.replay[HQ_KIND_NN]; a.band = g.band[HQ_KIND_NN]; a.replay_counts = g.replay_counts;
+    SCHED_TRY(launch_network_colour(a, g.C, S.s));
+  }
+  ST_TRY(from_scratch(S, g, g.xp, g.blkp));
+  CumulativeArgs c;
+  c.n = g.n; c.L = g.L; c.nb = g.nb;
+  c.x = g.x; c.xp = g.xp; c.logdet = g.logdet; c.logdet_new = g.logdet_new;
+  c.G = g.G; c.precision = ctx->opt.precision; c.Gnew = g.Gnew;
+  c.blk = g.blk; c.blkp = g.blkp; c.sum_y = g.sum_y; c.accepted = g.nn_acc;
+  c.seed = ctx->seed; c.chain0 = g.chain0; c.sweep = ctx->sweep_counter; c.counters = g.counters;
+  c.log_margin = g.log_margin[HQ_KIND_CUMULATIVE]; c.log_accept = g.log_accept[HQ_KIND_CUMULATIVE];
+  c.replay = g.replay[HQ_KIND_CUMULATIVE]; c.band = g.band[HQ_KIND_CUMULATIVE]; c.replay_counts = g.replay_counts;
+  c.last_log_pc = g.lastpc;
+  SCHED_TRY(launch_cumulative(c, g.C, S.s));
+  return HQ_OK;
+}
+
+hq_status sweep_group(Sched& S, Group& g) {
+  if (g.network) {
+    ST_TRY(begin_phase(S, PH_NETWORK));
+    ST_TRY(network_sweep(S, g));
+    return end_phase(S);
+  }
+  ST_TRY(begin_phase(S, PH_STAB));
+  ST_TRY(right_stack(S, g));
+  SCHED_TRY(launch_identity(g.LU, g.LD, g.LT[0], g.n, g.C, S.s));
+  ST_TRY(end_phase(S));
+  int t = 0;
+  for (int b = 0; b < g.nb; ++b) {
+    for (int k = 0; k < g.ns; ++k) {
+      const int slice = b * g.ns + k;
+      ST_TRY(begin_phase(S, PH_WRAP));
+      ST_TRY(wrap(S, g, slice));
+      ST_TRY(end_phase(S));
+      ST_TRY(begin_phase(S, PH_LOCAL));
+      ST_TRY(local(S, g, slice));
+      ST_TRY(end_phase(S));
+    }
+    ST_TRY(begin_phase(S, PH_STAB));
+    ST_TRY(stab_point(S, g, b, t));
+    ST_TRY(end_phase(S));
+  }
+  if (g.global) {
+    ST_TRY(begin_phase(S, PH_GLOBAL));
+    ST_TRY(global_moves(S, g));
+    ST_TRY(end_phase(S));
+  }
+  return HQ_OK;
+}
+
+hq_status enqueue_sweep(hq_ctx* ctx) {
+  Sched S{ctx, ctx->stream};
+  for (Group& g : ctx->groups) ST_TRY(sweep_group(S, g));
+  for (Group& g : ctx->groups)
+    for (int k : {HQ_KIND_LOCAL, HQ_KIND_GLOBAL, HQ_KIND_NN, HQ_KIND_CUMULATIVE})
+      SCHED_TRY(launch_fill_u8(g.replay[k], 255, (long)g.C * g.kind_slots(k), S.s));
+  SCHED_TRY(launch_add_i64(ctx->sweep_counter, 1, S.s));
+  return HQ_OK;
+}
+
+hq_status recompute_all(hq_ctx* ctx) {
+  Sched S{ctx, ctx->stream};
+  for (Group& g : ctx->groups) {
+    ST_TRY(from_scratch(S, g, g.x, g.blk));
+    SCHED_TRY(launch_stab_finish(g.G, ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.n, g.C, 0,
+                                 S.s));
+  }
+  return HQ_OK;
+}
+
+hq_status check_ctx(hq_ctx* ctx) {
+  if (!ctx) return HQ_EINVAL;
+  if (ctx->broken) return HQ_ESTATE;
+  return HQ_OK;
+}
+
+hq_status sync(hq_ctx* ctx) {
+  HQ_TRY(hipStreamSynchronize(ctx->stream));
+  return HQ_OK;
+}
+
+hq_status collect_profile(hq_ctx* ctx) {
+  if (ctx->pending.empty()) return HQ_OK;
+  ST_TRY(sync(ctx));
+  for (size_t k = 0; k < ctx->pending.size(); ++k) {
+    float ms = 0.f;
+    HQ_TRY(hipEventElapsedTime(&ms, ctx->pending[k].first, ctx->pending[k].second));
+    ctx->phases[ctx->pending_phase[k]].ms += ms;
+    ctx->phases[ctx->pending_phase[k]].launches += 1;
+    ctx->event_pool.push_back(ctx->pending[k].first);
+    ctx->event_pool.push_back(ctx->pending[k].second);
+  }
+  ctx->pending.clear();
+  ctx->pending_phase.clear();
+  return HQ_OK;
+}
+
+Group* find_chain(hq_ctx* ctx, int chain, int& local) {
+  for (Group& g : ctx->groups)
+    if (chain >= g.chain0 && chain < g.chain0 + g.C) {
+      local = chain - g.chain0;
+      return &g;
+    }
+  return nullptr;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+size_t hq_workspace_bytes(const hq_group* groups, int32_t n_groups, const hq_options* opt) {
+  if (!groups || n_groups < 1 || !opt) return 0;
+  if (opt->precision != HQ_PREC_FP64 && opt->precision != HQ_PREC_MIXED) return 0;
+  std::vector<Group> gs;
+  std::string why;
+  if (!build_groups(groups, n_groups, *opt, gs, why)) return 0;
+  return layout(nullptr, gs, nullptr, *opt);
+}
+
+hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* opt, uint64_t seed, void* workspace,
+                    size_t workspace_bytes, void* stream, hq_ctx** out) {
+  if (!out) return HQ_EINVAL;
+  *out = nullptr;
+  if (!groups || n_groups < 1 || !opt || !workspace || !stream) return HQ_EINVAL;
+  if (opt->precision != HQ_PREC_FP64 && opt->precision != HQ_PREC_MIXED) return HQ_EINVAL;
+  if (opt->delay != 0 && opt->delay != 8 && opt->delay != 16 && opt->delay != 32) return HQ_EINVAL;
+  if (opt->activation != 0 && opt->activation != 1) return HQ_EINVAL;
+  hq_ctx* ctx = new hq_ctx();
+  ctx->opt = *opt;
+  ctx->seed = seed;
+  ctx->stream = (hipStream_t)stream;
+  std::string why;
+  if (!build_groups(groups, n_groups, *opt, ctx->groups, why)) {
+    delete ctx;
+    return HQ_EINVAL;
+  }
+  const size_t need = layout(nullptr, ctx->groups, nullptr, *opt);
+  if (workspace_bytes < need) {
+    delete ctx;
+    return HQ_ENOMEM;
+  }
+  ctx->ws = workspace;
+  ctx->ws_bytes = workspace_bytes;
+  // align the base to 256 bytes
+  char* base = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+  layout(ctx, ctx->groups, base, *opt);
+  for (int k = 0; k < N_PHASES; ++k) ctx->phases.push_back({kPhaseNames[k], 0.0, 0});
+  for (const Group& g : ctx->groups) ctx->n_chains += g.C;
+  *out = ctx;
+
+  HQ_TRY(prepare_local());
+  HQ_TRY(prepare_factor());
+  hipStream_t s = ctx->stream;
+  // host-side model set-up and initial state
+  for (Group& g : ctx->groups) {
+    const int n = g.n, L = g.L, C = g.C;
+    std::vector<double> ek, eki, id((size_t)n * n, 0.0), ones((size_t)C * n, 1.0);
+    exp_hopping(g.p, -1.0, ek);
+    exp_hopping(g.p, +1.0, eki);
+    for (int i = 0; i < n; ++i) id[(size_t)i * n + i] = 1.0;
+    std::vector<float> ek32(ek.begin(), ek.end()), eki32(eki.begin(), eki.end());
+    std::vector<double> x((size_t)C * L * n), gc((size_t)C);
+    for (int c = 0; c < C; ++c) {
+      const uint64_t chain = (uint64_t)(g.chain0 + c);
+      if (g.p.g_hi > g.p.g_lo) {
+        const Philox4 r = philox4x64_10(chain, 0, 0, KIND_COUPLING, seed, 0);
+        gc[c] = g.p.g_lo + (g.p.g_hi - g.p.g_lo) * u53(r.w[0]);
+      } else {
+        gc[c] = g.p.g;
+      }
+      for (int l = 0; l < L; ++l)
+        for (int i = 0; i < n; ++i) {
+          const Philox4 r = philox4x64_10(chain, 0, (uint64_t)(l * n + i), KIND_INIT, seed, 0);
+          const double u0 = u53(r.w[0]), u1 = u53(r.w[1]);
+          x[((size_t)c * L + l) * n + i] = std::sqrt(-2.0 * std::log(1.0 - u0)) * std::cos(2.0 * M_PI * u1);
+        }
+    }
+    HQ_TRY(hipMemcpyAsync(g.expk, ek.data(), ek.size() * 8, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipMemcpyAsync(g.expkinv, eki.data(), eki.size() * 8, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipMemcpyAsync(g.expk32, ek32.data(), ek32.size() * 4, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipMemcpyAsync(g.expkinv32, eki32.data(), eki32.size() * 4, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipMemcpyAsync(g.ident, id.data(), id.size() * 8, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipMemcpyAsync(g.ones, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipMemcpyAsync(g.x, x.data(), x.size() * 8, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipMemcpyAsync(g.g, gc.data(), gc.size() * 8, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipStreamSynchronize(s));   // host vectors die at the end of this iteration
+    HQ_TRY(launch_fill_i64(g.counters, 0, (long)C * N_COUNTERS, s));
+    HQ_TRY(launch_fill_i64(g.replay_counts, 0, (long)C * 2, s));
+    HQ_TRY(launch_fill_f64(g.drift, 0.0, (long)C * 5, s));
+    HQ_TRY(launch_fill_f64(g.lastpc, 0.0, (long)C * 2, s));
+    HQ_TRY(launch_fill_i64((int64_t*)g.flags, 0, ((long)C * sizeof(int) + 7) / 8, s));
+    for (int k : {HQ_KIND_LOCAL, HQ_KIND_GLOBAL, HQ_KIND_NN, HQ_KIND_CUMULATIVE})
+      HQ_TRY(launch_fill_u8(g.replay[k], 255, (long)C * g.kind_slots(k), s));
+  }
+  HQ_TRY(launch_fill_i64(ctx->sweep_counter, 0, 1, s));
+  hq_status st = recompute_all(ctx);
+  if (st != HQ_OK) return st;
+  return sync(ctx);
+}
+
+hq_status hq_set_fields(hq_ctx* ctx, int32_t chain, const double* x_host, int64_t n) {
+  ST_TRY(check_ctx(ctx));
+  int lc = 0;
+  Group* g = find_chain(ctx, chain, lc);
+  if (!g || !x_host || n != (int64_t)g->L * g->n) return fail(ctx, HQ_EINVAL, "bad chain or field count");
+  for (int64_t k = 0; k < n; ++k)
+    if (!std::isfinite(x_host[k])) return fail(ctx, HQ_EINVAL, "non-finite field");
+  HQ_TRY(hipMemcpyAsync(g->x + (long)lc * n, x_host, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  Sched S{ctx, ctx->stream};
+  ST_TRY(from_scratch(S, *g, g->x, g->blk));
+  SCHED_TRY(launch_stab_finish(g->G, ctx->opt.precision, g->Gnew, g->logdet, g->logdet_new, g->drift, g->n, g->C, 0,
+                               ctx->stream));
+  return sync(ctx);
+}
+
+hq_status hq_set_network(hq_ctx* ctx, const float* w, int64_t n) {
+  ST_TRY(check_ctx(ctx));
+  if (!w || n != 7169) return fail(ctx, HQ_EINVAL, "network needs 7169 weights");
+  for (int64_t k = 0; k < n; ++k)
+    if (!std::isfinite(w[k])) return fail(ctx, HQ_EINVAL, "non-finite weight");
+  HQ_TRY(hipMemcpyAsync(ctx->net, w, n * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+  ctx->net_loaded = true;
+  return sync(ctx);
+}
+
+hq_status hq_sweep(hq_ctx* ctx, int32_t n_sweeps) {
+  ST_TRY(check_ctx(ctx));
+  if (n_sweeps < 0) return fail(ctx, HQ_EINVAL, "n_sweeps < 0");
+  for (const Group& g : ctx->groups)
+    if (g.network && !ctx->net_loaded) return fail(ctx, HQ_EINVAL, "network proposals need hq_set_network first");
+  if (ctx->profiling) {
+    for (int k = 0; k < n_sweeps; ++k) ST_TRY(enqueue_sweep(ctx));
+    return collect_profile(ctx);
+  }
+  if (!ctx->exec) {
+    HQ_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    hq_status st = enqueue_sweep(ctx);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+    if (st != HQ_OK) return st;
+    if (e != hipSuccess) return fail(ctx, HQ_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    ctx->graph = graph;
+    HQ_TRY(hipGraphInstantiate(&ctx->exec, graph, nullptr, nullptr, 0));
+  }
+  for (int k = 0; k < n_sweeps; ++k) HQ_TRY(hipGraphLaunch(ctx->exec, ctx->stream));
+  return HQ_OK;
+}
+
+hq_status hq_recompute(hq_ctx* ctx) {
+  ST_TRY(check_ctx(ctx));
+  ST_TRY(recompute_all(ctx));
+  return sync(ctx);
+}
+
+hq_status hq_read_green(hq_ctx* ctx, int32_t chain, double* out, int64_t n) {
+  ST_TRY(check_ctx(ctx));
+  int lc = 0;
+  Group* g = find_chain(ctx, chain, lc);
+  if (!g || !out || n != (int64_t)g->n * g->n) return fail(ctx, HQ_EINVAL, "bad chain or size");
+  ST_TRY(sync(ctx));
+  if (ctx->opt.precision == HQ_PREC_MIXED) {
+    std::vector<float> tmp((size_t)n);
+    HQ_TRY(hipMemcpy(tmp.data(), (float*)g->G + (long)lc * n, n * sizeof(float), hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < n; ++k) out[k] = tmp[k];
+  } else {
+    HQ_TRY(hipMemcpy(out, (double*)g->G + (long)lc * n, n * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return HQ_OK;
+}
+
+hq_status hq_read_fields(hq_ctx* ctx, int32_t chain, double* out, int64_t n) {
+  ST_TRY(check_ctx(ctx));
+  int lc = 0;
+  Group* g = find_chain(ctx, chain, lc);
+  if (!g || !out || n != (int64_t)g->L * g->n) return fail(ctx, HQ_EINVAL, "bad chain or size");
+  ST_TRY(sync(ctx));
+  HQ_TRY(hipMemcpy(out, g->x + (long)lc * n, n * sizeof(double), hipMemcpyDeviceToHost));
+  return HQ_OK;
+}
+
+hq_status hq_read_stats(hq_ctx* ctx, int32_t chain, hq_stats* out) {
+  ST_TRY(check_ctx(ctx));
+  int lc = 0;
+  Group* g = find_chain(ctx, chain, lc);
+  if (!g || !out) return fail(ctx, HQ_EINVAL, "bad chain");
+  ObsArgs a;
+  a.n = g->n; a.L = g->L; a.nx = g->nx;
+  a.G = g->G; a.precision = ctx->opt.precision; a.x = g->x;
+  a.out = g->obs; a.flags = g->flags; a.logdet = g->logdet;
+  HQ_TRY(launch_observables(a, g->C, ctx->stream));
+  ST_TRY(sync(ctx));
+  double ld = 0, gg = 0, dr[5], ob[5];
+  int64_t cnt[N_COUNTERS], rc[2];
+  int fl = 0;
+  HQ_TRY(hipMemcpy(&ld, g->logdet + lc, 8, hipMemcpyDeviceToHost));
+  HQ_TRY(hipMemcpy(&gg, g->g + lc, 8, hipMemcpyDeviceToHost));
+  HQ_TRY(hipMemcpy(dr, g->drift + lc * 5, sizeof dr, hipMemcpyDeviceToHost));
+  HQ_TRY(hipMemcpy(ob, g->obs + lc * 5, sizeof ob, hipMemcpyDeviceToHost));
+  HQ_TRY(hipMemcpy(cnt, g->counters + (long)lc * N_COUNTERS, sizeof cnt, hipMemcpyDeviceToHost));
+  HQ_TRY(hipMemcpy(rc, g->replay_counts + 2 * lc, sizeof rc, hipMemcpyDeviceToHost));
+  HQ_TRY(hipMemcpy(&fl, g->flags + lc, sizeof fl, hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof *out);
+  out->logdet = ld;
+  out->g = gg;
+  out->local_proposals = cnt[CNT_LOCAL_P]; out->local_accepts = cnt[CNT_LOCAL_A];
+  out->global_proposals = cnt[CNT_GLOBAL_P]; out->global_accepts = cnt[CNT_GLOBAL_A];
+  out->nn_proposals = cnt[CNT_NN_P]; out->nn_accepts = cnt[CNT_NN_A];
+  out->cumulative_proposals = cnt[CNT_CUM_P]; out->cumulative_accepts = cnt[CNT_CUM_A];
+  out->max_drift_green = dr[0]; out->max_drift_logdet = dr[1]; out->last_drift_green = dr[2];
+  out->density = ob[0]; out->double_occupancy = ob[1]; out->s_cdw = ob[2]; out->x_mean = ob[3]; out->x2_mean = ob[4];
+  out->replay_overrides = rc[0]; out->replay_mismatches = rc[1];
+  out->n = g->n; out->L = g->L;
+  out->flags = fl | (dr[4] != 0.0 ? 1 : 0);
+  if (out->flags & 1) return fail(ctx, HQ_ENUMERIC, "non-finite G or log det in chain %d", chain);
+  return HQ_OK;
+}
+
+hq_status hq_read_decisions(hq_ctx* ctx, int32_t chain, int32_t kind, uint8_t* accept, float* margin, int64_t n) {
+  ST_TRY(check_ctx(ctx));
+  int lc = 0;
+  Group* g = find_chain(ctx, chain, lc);
+  if (!g || (kind != HQ_KIND_LOCAL && kind != HQ_KIND_GLOBAL && kind != HQ_KIND_NN && kind != HQ_KIND_CUMULATIVE))
+    return fail(ctx, HQ_EINVAL, "bad chain or kind");
+  if (!ctx->opt.record) return fail(ctx, HQ_EINVAL, "decisions are only kept with options.record = 1");
+  const long slots = g->kind_slots(kind);
+  if (n != slots || !accept || !margin) return fail(ctx, HQ_EINVAL, "expected %ld slots", slots);
+  ST_TRY(sync(ctx));
+  HQ_TRY(hipMemcpy(accept, g->log_accept[kind] + lc * slots, slots, hipMemcpyDeviceToHost));
+  HQ_TRY(hipMemcpy(margin, g->log_margin[kind] + lc * slots, slots * sizeof(float), hipMemcpyDeviceToHost));
+  return HQ_OK;
+}
+
+hq_status hq_set_replay(hq_ctx* ctx, int32_t chain, int32_t kind, const uint8_t* bits, int64_t n, double band) {
+  ST_TRY(check_ctx(ctx));
+  int lc = 0;
+  Group* g = find_chain(ctx, chain, lc);
+  if (!g || (kind != HQ_KIND_LOCAL && kind != HQ_KIND_GLOBAL && kind != HQ_KIND_NN && kind != HQ_KIND_CUMULATIVE))
+    return fail(ctx, HQ_EINVAL, "bad chain or kind");
+  const long slots = g->kind_slots(kind);
+  if (!(band >= 0) || (n != 0 && (n != slots || !bits))) return fail(ctx, HQ_EINVAL, "expected %ld bits", slots);
+  if (g->band[kind] != band && ctx->exec) {
+    // the band is a kernel argument: rebuild the graph
+    hipGraphExecDestroy(ctx->exec);
+    hipGraphDestroy(ctx->graph);
+    ctx->exec = nullptr;
+    ctx->graph = nullptr;
+  }
+  g->band[kind] = band;
+  if (n == 0) {
+    HQ_TRY(launch_fill_u8(g->replay[kind] + lc * slots, 255, slots, ctx->stream));
+  } else {
+    std::vector<uint8_t> b(bits, bits + n);
+    for (auto& v : b) v = v ? 1 : 0;
+    HQ_TRY(hipMemcpyAsync(g->replay[kind] + lc * slots, b.data(), n, hipMemcpyHostToDevice, ctx->stream));
+    HQ_TRY(hipStreamSynchronize(ctx->stream));
+  }
+  return HQ_OK;
+}
+
+int32_t hq_num_chains(const hq_ctx* ctx) { return ctx ? ctx->n_chains : 0; }
+
+hq_status hq_chain_shape(const hq_ctx* ctx, int32_t chain, int32_t* n, int32_t* L) {
+  if (!ctx || !n || !L) return HQ_EINVAL;
+  for (const Group& g : ctx->groups)
+    if (chain >= g.chain0 && chain < g.chain0 + g.C) {
+      *n = g.n;
+      *L = g.L;
+      return HQ_OK;
+    }
+  return HQ_EINVAL;
+}
+
+hq_status hq_set_profiling(hq_ctx* ctx, int32_t on) {
+  ST_TRY(check_ctx(ctx));
+  ctx->profiling = on != 0;
+  for (auto& p : ctx->phases) { p.ms = 0.0; p.launches = 0; }
+  return HQ_OK;
+}
+
+hq_status hq_phase_time(hq_ctx* ctx, const char* phase, double* ms_total, int64_t* launches) {
+  ST_TRY(check_ctx(ctx));
+  if (!phase || !ms_total || !launches) return HQ_EINVAL;
+  for (auto& p : ctx->phases)
+    if (!std::strcmp(p.name, phase)) {
+      *ms_total = p.ms;
+      *launches = p.launches;
+      return HQ_OK;
+    }
+  return fail(ctx, HQ_EINVAL, "unknown phase %s", phase);
+}
+
+hq_status hq_synchronize(hq_ctx* ctx) {
+  ST_TRY(check_ctx(ctx));
+  return sync(ctx);
+}
+
+const char* hq_last_error(const hq_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void hq_destroy(hq_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  for (auto& pe : ctx->pending) { (void)hipEventDestroy(pe.first); (void)hipEventDestroy(pe.second); }
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+// Internal interfaces between the host layer (hq_api.hip) and the kernel
+// translation units of libhq.  Every launcher enqueues on the given stream
+// and returns the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hq {
+
+// Diagonal scaling used by the GEMM epilogue and the block products:
+//   value(z, i) = v[outer*so + inner*si + off + i]            (plain)
+//   value(z, i) = exp(cmul * coef[outer] * v[...])             (coef != null)
+// with outer = z / inner_count, inner = z % inner_count for batch entry z.
+// A null v means value 1.  invert = 1 takes the reciprocal.
+struct Scale {
+  const double* v = nullptr;
+  long off = 0, so = 0, si = 0;
+  const double* coef = nullptr;
+  double cmul = 0.0;
+  int invert = 0;
+};
+
+// C[z] = alpha * diag(rs) * op(A[z]) * op(B[z]) * diag(cs) + beta * C[z]
+// for z in [0, batch); matrices row-major.  op = transpose when trans != 0.
+// Matrix pointers advance by the stride per batch entry (stride 0 = shared).
+template <typename T>
+struct GemmArgs {
+  int M = 0, N = 0, K = 0;
+  const T* A = nullptr; long lda = 0, sA = 0; int tA = 0;
+  const T* B = nullptr; long ldb = 0, sB = 0; int tB = 0;
+  T* C = nullptr; long ldc = 0, sC = 0;
+  double alpha = 1.0, beta = 0.0;
+  Scale rs, cs;
+  int batch = 1, inner_count = 1;
+};
+
+// GEMM tile configurations (see gemm.hip); the autotuner picks one per shape.
+enum GemmTile { TILE_64x64 = 0, TILE_32x32 = 1, TILE_48x48 = 2, TILE_16x64 = 3, N_GEMM_TILES = 4 };
+
+hipError_t launch_gemm(const GemmArgs<double>& a, int tile, hipStream_t s);
+hipError_t launch_gemm(const GemmArgs<float>& a, int tile, hipStream_t s);
+
+// P[z] = diag(rs(z)) * A  (A shared), used for the first slice of a block product
+hipError_t launch_scale_rows(double* P, long sP, const double* A, int n, Scale rs, int batch,
+                             int inner_count, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// local moves of one slice: one workgroup per chain (local.hip)
+// ---------------------------------------------------------------------------
+struct LocalArgs {
+  int n = 0, L = 0, slice = 0;
+  void* G = nullptr;            // [C][n][n], double or float
+  double* x = nullptr;          // [C][L][n]
+  const double* g = nullptr;    // [C]
+  double dtau = 0, mass = 0, omega = 0, width = 0;
+  uint64_t seed = 0;
+  int chain0 = 0;               // global index of chain 0 of this group
+  const int64_t* sweep = nullptr;   // device sweep counter
+  double* logdet = nullptr;     // [C]
+  int64_t* counters = nullptr;  // [C][8]: proposals, accepts per kind
+  float* log_margin = nullptr;  // [C][L*n] or null
+  uint8_t* log_accept = nullptr;
+  const uint8_t* replay = nullptr;  // [C][L*n] (255 = none) or null
+  double band = 0;
+  int64_t* replay_counts = nullptr; // [C][2]
+};
+hipError_t launch_local(const LocalArgs& a, int precision, int nt, int kd, int chains, hipStream_t s);
+size_t local_lds_bytes(int n, int precision, int nt, int kd);
+bool local_supported(int n, int precision, int nt, int kd);
+hipError_t prepare_local();
+
+// ---------------------------------------------------------------------------
+// dense FP64 factorizations: one workgroup per matrix (factor.hip)
+// ---------------------------------------------------------------------------
+// Householder QR of Z[z] (n x n) with columns pre-sorted by decreasing norm:
+// Z P = Q R.  Outputs Q (explicit), D = |diag R|, Rt = D^-1 R P^T.
+hipError_t launch_qr(const double* Z, double* Q, double* D, double* Rt, int n, int batch, hipStream_t s);
+bool qr_supported(int n);
+
+// Gauss-Jordan inversion with partial pivoting: X = diag(rs) M^-1 diag(cs)
+// (rs, cs: [batch][n]) and logdet[z] = base[z] + log|det M|.
+hipError_t launch_gj(const double* M, double* X, const double* rs, const double* cs,
+                     const double* base, double* logdet, int n, int batch, hipStream_t s);
+bool gj_supported(int n);
+hipError_t prepare_factor();
+
+// ---------------------------------------------------------------------------
+// small kernels (misc.hip)
+// ---------------------------------------------------------------------------
+hipError_t launch_identity(double* U, double* D, double* T, int n, int batch, hipStream_t s);
+// dbinv = 1/max(D,1), ds = min(D,1), sumlog[z] (+)= sum log max(D,1)
+hipError_t launch_dsplit(const double* D, double* dbinv, double* ds, double* sumlog, int accumulate,
+                         int n, int batch, hipStream_t s);
+// drift of the tracked state against the recomputed one, then replace it
+hipError_t launch_stab_finish(void* G, int precision, const double* Gnew, double* logdet,
+                              const double* logdet_new, double* drift, int n, int batch,
+                              int record_drift, hipStream_t s);
+hipError_t launch_copy_f64_to_f32(float* dst, const double* src, long count, hipStream_t s);
+hipError_t launch_copy_f32_to_f64(double* dst, const float* src, long count, hipStream_t s);
+hipError_t launch_fill_i64(int64_t* p, int64_t v, long count, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, long count, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, long count, hipStream_t s);
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
+
+struct GlobalArgs {
+  int n = 0, L = 0, nb = 0, site = 0;
+  double* x = nullptr;          // [C][L][n]
+  double* xp = nullptr;         // [C][L][n] proposal fields
+  const double* g = nullptr;
+  double dtau = 0, mass = 0, omega = 0, width = 0;
+  uint64_t seed = 0;
+  int chain0 = 0;
+  const int64_t* sweep = nullptr;
+  double* shift = nullptr;      // [C] proposed shift
+  double* logdet = nullptr;
+  const double* logdet_new = nullptr;
+  void* G = nullptr; int precision = 0;
+  const double* Gnew = nullptr;
+  double* blk = nullptr; const double* blkp = nullptr;   // [C][nb][n][n]
+  int64_t* counters = nullptr;
+  float* log_margin = nullptr; uint8_t* log_accept = nullptr;
+  const uint8_t* replay = nullptr; double band = 0; int64_t* replay_counts = nullptr;
+};
+hipError_t launch_global_propose(const GlobalArgs& a, int chains, hipStream_t s);
+hipError_t launch_global_accept(const GlobalArgs& a, int chains, hipStream_t s);
+
+struct ObsArgs {
+  int n = 0, L = 0, nx = 0;
+  const void* G = nullptr; int precision = 0;
+  const double* x = nullptr;
+  double* out = nullptr;        // [C][5]: density, double occ, S_cdw, <x>, <x^2>
+  int* flags = nullptr;         // [C]
+  const double* logdet = nullptr;
+};
+hipError_t launch_observables(const ObsArgs& a, int chains, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// network proposals (network.hip)
+// ---------------------------------------------------------------------------
+struct NetArgs {
+  int nx = 0, n = 0, L = 0, colour = 0;
+  double* xp = nullptr;         // [C][L][n] proposal fields (updated in place)
+  const double* g = nullptr;
+  double dtau = 0, mass = 0, omega = 0, width = 0;
+  uint64_t seed = 0;
+  int chain0 = 0;
+  const int64_t* sweep = nullptr;
+  const float* w = nullptr;     // 7169 weights
+  int activation = 0;
+  int chains = 0;
+  double* sum_y = nullptr;      // [C][L*n]: network output of each accepted proposal, else 0
+  uint8_t* accepted = nullptr;  // [C][L*n]
+  int64_t* counters = nullptr;
+  float* log_margin = nullptr; uint8_t* log_accept = nullptr;
+  const uint8_t* replay = nullptr; double band = 0; int64_t* replay_counts = nullptr;
+};
+hipError_t launch_network_colour(const NetArgs& a, int chains, hipStream_t s);
+struct CumulativeArgs {
+  int n = 0, L = 0, nb = 0;
+  double* x = nullptr; const double* xp = nullptr;
+  double* logdet = nullptr; const double* logdet_new = nullptr;
+  void* G = nullptr; int precision = 0; const double* Gnew = nullptr;
+  double* blk = nullptr; const double* blkp = nullptr;
+  const double* sum_y = nullptr; const uint8_t* accepted = nullptr;
+  uint64_t seed = 0; int chain0 = 0; const int64_t* sweep = nullptr;
+  int64_t* counters = nullptr;
+  float* log_margin = nullptr; uint8_t* log_accept = nullptr;
+  const uint8_t* replay = nullptr; double band = 0; int64_t* replay_counts = nullptr;
+  double* last_log_pc = nullptr;
+};
+hipError_t launch_cumulative(const CumulativeArgs& a, int chains, hipStream_t s);
+hipError_t launch_copy_f64(double* dst, const double* src, long count, hipStream_t s);
+
+// counters layout per chain
+enum { CNT_LOCAL_P = 0, CNT_LOCAL_A, CNT_GLOBAL_P, CNT_GLOBAL_A, CNT_NN_P, CNT_NN_A, CNT_CUM_P,
+       CNT_CUM_A, N_COUNTERS };
+
+}  // namespace hq

@@ -1,0 +1,240 @@
+"""ctypes binding of libhq (include/hq.h).  Argument marshalling only: every
+step of the sweep runs in the library's HIP kernels.  PyTorch supplies the
+device workspace and the stream.
+
+    ctx = Context(groups, precision=0, seed=1)
+    ctx.sweep(5)
+    G = ctx.green(0); x = ctx.fields(0); st = ctx.stats(0)
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhq.so")
+
+HQ_OK, HQ_EINVAL, HQ_ENOMEM, HQ_EDEVICE, HQ_ESTATE, HQ_ENUMERIC = 0, -1, -2, -3, -4, -5
+KIND_LOCAL, KIND_GLOBAL, KIND_NN, KIND_CUMULATIVE = 0, 1, 3, 4
+PREC_FP64, PREC_MIXED = 0, 1
+
+
+class HQError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("libhq status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Group(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("n_chains", ctypes.c_int32),
+        ("t", ctypes.c_double), ("mu", ctypes.c_double),
+        ("mass", ctypes.c_double), ("omega", ctypes.c_double),
+        ("g", ctypes.c_double), ("g_lo", ctypes.c_double), ("g_hi", ctypes.c_double),
+        ("beta", ctypes.c_double), ("dtau", ctypes.c_double),
+        ("n_stab", ctypes.c_int32), ("proposal", ctypes.c_int32),
+        ("local_width", ctypes.c_double), ("global_width", ctypes.c_double),
+    ]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("delay", ctypes.c_int32),
+                ("activation", ctypes.c_int32), ("record", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("logdet", ctypes.c_double), ("g", ctypes.c_double),
+        ("local_proposals", ctypes.c_int64), ("local_accepts", ctypes.c_int64),
+        ("global_proposals", ctypes.c_int64), ("global_accepts", ctypes.c_int64),
+        ("nn_proposals", ctypes.c_int64), ("nn_accepts", ctypes.c_int64),
+        ("cumulative_proposals", ctypes.c_int64), ("cumulative_accepts", ctypes.c_int64),
+        ("max_drift_green", ctypes.c_double), ("max_drift_logdet", ctypes.c_double),
+        ("last_drift_green", ctypes.c_double),
+        ("density", ctypes.c_double), ("double_occupancy", ctypes.c_double),
+        ("s_cdw", ctypes.c_double), ("x_mean", ctypes.c_double), ("x2_mean", ctypes.c_double),
+        ("replay_overrides", ctypes.c_int64), ("replay_mismatches", ctypes.c_int64),
+        ("n", ctypes.c_int32), ("L", ctypes.c_int32), ("flags", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = [
+    "hq_workspace_bytes", "hq_create", "hq_set_fields", "hq_set_network", "hq_sweep",
+    "hq_recompute", "hq_read_green", "hq_read_fields", "hq_read_stats", "hq_read_decisions",
+    "hq_set_replay", "hq_num_chains", "hq_chain_shape", "hq_set_profiling", "hq_phase_time",
+    "hq_synchronize", "hq_last_error", "hq_destroy",
+]
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libhq.so and declare its signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libhq.so is not built; run `python -m paper_1905_07440_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    GP = ctypes.POINTER(Group)
+    OP = ctypes.POINTER(Options)
+    lib.hq_workspace_bytes.argtypes = [GP, I32, OP]
+    lib.hq_workspace_bytes.restype = ctypes.c_size_t
+    lib.hq_create.argtypes = [GP, I32, OP, ctypes.c_uint64, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+    lib.hq_set_fields.argtypes = [P, I32, P, I64]
+    lib.hq_set_network.argtypes = [P, P, I64]
+    lib.hq_sweep.argtypes = [P, I32]
+    lib.hq_recompute.argtypes = [P]
+    lib.hq_read_green.argtypes = [P, I32, P, I64]
+    lib.hq_read_fields.argtypes = [P, I32, P, I64]
+    lib.hq_read_stats.argtypes = [P, I32, ctypes.POINTER(Stats)]
+    lib.hq_read_decisions.argtypes = [P, I32, I32, P, P, I64]
+    lib.hq_set_replay.argtypes = [P, I32, I32, P, I64, D]
+    lib.hq_num_chains.argtypes = [P]
+    lib.hq_num_chains.restype = I32
+    lib.hq_chain_shape.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.hq_set_profiling.argtypes = [P, I32]
+    lib.hq_phase_time.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)]
+    lib.hq_synchronize.argtypes = [P]
+    lib.hq_last_error.argtypes = [P]
+    lib.hq_last_error.restype = ctypes.c_char_p
+    lib.hq_destroy.argtypes = [P]
+    lib.hq_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("hq_workspace_bytes", "hq_num_chains", "hq_last_error", "hq_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def make_group(nx, n_chains, t=1.0, mu=0.0, mass=1.0, omega=1.0, g=1.0, g_range=None, beta=4.0,
+               dtau=0.1, n_stab=10, proposal=0, local_width=0.5, global_width=0.0):
+    lo, hi = (g_range if g_range is not None else (0.0, 0.0))
+    return Group(nx, n_chains, t, mu, mass, omega, g, lo, hi, beta, dtau, n_stab, proposal,
+                 local_width, global_width)
+
+
+def groups_from_workload(w):
+    return [make_group(gr.nx, gr.n_chains, gr.t, gr.mu, gr.mass, gr.omega, gr.g, gr.g_range, gr.beta,
+                       gr.dtau, gr.n_stab, gr.proposal, gr.local_width, gr.global_width)
+            for gr in w.groups]
+
+
+class Context:
+    """A set of Markov chains on the current GPU (torch supplies memory and stream)."""
+
+    def __init__(self, groups, precision=PREC_FP64, seed=1, delay=0, activation=0, record=False,
+                 device="cuda"):
+        import torch
+        lib = load()
+        self._lib = lib
+        self._groups = (Group * len(groups))(*groups)
+        self._opt = Options(precision, delay, activation, 1 if record else 0)
+        nbytes = lib.hq_workspace_bytes(self._groups, len(groups), ctypes.byref(self._opt))
+        if nbytes == 0:
+            raise HQError(HQ_EINVAL, "invalid groups/options (see include/hq.h limits)")
+        self.workspace_bytes = int(nbytes)
+        self._ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+        self._stream = torch.cuda.Stream(device=device)
+        self._ctx = ctypes.c_void_p()
+        st = lib.hq_create(self._groups, len(groups), ctypes.byref(self._opt), ctypes.c_uint64(seed),
+                           ctypes.c_void_p(self._ws.data_ptr()), ctypes.c_size_t(self._ws.numel()),
+                           ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(self._ctx))
+        if st != HQ_OK:
+            msg = lib.hq_last_error(self._ctx).decode() if self._ctx else "create failed"
+            if self._ctx:
+                lib.hq_destroy(self._ctx)
+                self._ctx = ctypes.c_void_p()
+            raise HQError(st, msg)
+        self.n_chains = lib.hq_num_chains(self._ctx)
+        self.precision = precision
+
+    def _check(self, st):
+        if st != HQ_OK:
+            raise HQError(st, self._lib.hq_last_error(self._ctx).decode())
+
+    def shape(self, chain):
+        n, L = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.hq_chain_shape(self._ctx, chain, ctypes.byref(n), ctypes.byref(L)))
+        return n.value, L.value
+
+    def sweep(self, n=1):
+        self._check(self._lib.hq_sweep(self._ctx, n))
+
+    def recompute(self):
+        self._check(self._lib.hq_recompute(self._ctx))
+
+    def synchronize(self):
+        self._check(self._lib.hq_synchronize(self._ctx))
+
+    def green(self, chain):
+        n, _ = self.shape(chain)
+        out = np.empty((n, n))
+        self._check(self._lib.hq_read_green(self._ctx, chain, out.ctypes.data, out.size))
+        return out
+
+    def fields(self, chain):
+        n, L = self.shape(chain)
+        out = np.empty((L, n))
+        self._check(self._lib.hq_read_fields(self._ctx, chain, out.ctypes.data, out.size))
+        return out
+
+    def set_fields(self, chain, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        self._check(self._lib.hq_set_fields(self._ctx, chain, x.ctypes.data, x.size))
+
+    def set_network(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(self._lib.hq_set_network(self._ctx, w.ctypes.data, w.size))
+
+    def stats(self, chain):
+        s = Stats()
+        st = self._lib.hq_read_stats(self._ctx, chain, ctypes.byref(s))
+        if st not in (HQ_OK, HQ_ENUMERIC):
+            self._check(st)
+        return s.as_dict()
+
+    def decisions(self, chain, kind):
+        n, L = self.shape(chain)
+        slots = {KIND_LOCAL: n * L, KIND_NN: n * L, KIND_GLOBAL: n, KIND_CUMULATIVE: 1}[kind]
+        acc = np.empty(slots, dtype=np.uint8)
+        margin = np.empty(slots, dtype=np.float32)
+        self._check(self._lib.hq_read_decisions(self._ctx, chain, kind, acc.ctypes.data,
+                                                margin.ctypes.data, slots))
+        return acc, margin
+
+    def set_replay(self, chain, kind, bits, band):
+        if bits is None:
+            self._check(self._lib.hq_set_replay(self._ctx, chain, kind, None, 0, band))
+            return
+        b = np.ascontiguousarray(bits, dtype=np.uint8)
+        self._check(self._lib.hq_set_replay(self._ctx, chain, kind, b.ctypes.data, b.size, band))
+
+    def set_profiling(self, on):
+        self._check(self._lib.hq_set_profiling(self._ctx, 1 if on else 0))
+
+    def phase_time(self, phase):
+        ms, k = ctypes.c_double(), ctypes.c_int64()
+        self._check(self._lib.hq_phase_time(self._ctx, phase.encode(), ctypes.byref(ms), ctypes.byref(k)))
+        return ms.value, k.value
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx:
+            self._lib.hq_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
