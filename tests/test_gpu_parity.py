@@ -1,0 +1,335 @@
+"""Parity of the HIP path (through the C ABI) with the oracle, element by
+element on the same seeded inputs.
+
+Bars (the design notes derive them):
+  * fields: bit-identical (both sides add the same exactly drawn displacement
+    whenever they take the same decision);
+  * decisions: identical (FP64); in mixed precision and for the FP32 network,
+    identical outside a tie band |ln u - ln R| <= band where the GPU replays
+    the oracle's decision, with zero disagreements outside the band;
+  * G: max|dG| <= 1e-10 max|G| (FP64), <= 1e-5 max|G| (mixed: G is stored in FP32);
+  * log|det M|: |d| <= 1e-10 max(1, |logdet|).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dqmc, nnmc, philox
+from oracle.model import Params
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL_MIXED = 1e-5
+BAND_MIXED = 1e-4
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1905_07440_amd import hq as mod
+    mod.load()
+    return mod
+
+
+def params_of(gr, g=None):
+    return Params(nx=gr["nx"], t=gr.get("t", 1.0), mu=gr.get("mu", 0.0), mass=gr.get("mass", 1.0),
+                  omega=gr.get("omega", 1.0), g=gr.get("g", 1.0) if g is None else g,
+                  beta=gr["beta"], dtau=gr.get("dtau", 0.1), n_stab=gr["n_stab"],
+                  local_width=gr.get("local_width", 0.5), global_width=gr.get("global_width", 0.0))
+
+
+def make_ctx(hq, groups, precision=0, seed=1, delay=0, record=True):
+    hg = [hq.make_group(gr["nx"], gr["chains"], t=gr.get("t", 1.0), mu=gr.get("mu", 0.0),
+                        mass=gr.get("mass", 1.0), omega=gr.get("omega", 1.0), g=gr.get("g", 1.0),
+                        g_range=gr.get("g_range"), beta=gr["beta"], dtau=gr.get("dtau", 0.1),
+                        n_stab=gr["n_stab"], proposal=gr.get("proposal", 0),
+                        local_width=gr.get("local_width", 0.5), global_width=gr.get("global_width", 0.0))
+          for gr in groups]
+    return hq.Context(hg, precision=precision, seed=seed, delay=delay, record=record)
+
+
+def rel_g(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def assert_state(ctx, c, ch, tol_g, tag):
+    x = ctx.fields(c)
+    G = ctx.green(c)
+    st = ctx.stats(c)
+    assert np.array_equal(x, ch.x), "%s: fields differ (max %g)" % (tag, np.max(np.abs(x - ch.x)))
+    rg = rel_g(G, ch.G)
+    assert rg <= tol_g, "%s: G rel diff %g" % (tag, rg)
+    dl = abs(st["logdet"] - ch.logdet)
+    assert dl <= TOL64 * max(1.0, abs(ch.logdet)), "%s: logdet diff %g" % (tag, dl)
+    assert st["local_accepts"] == ch.local_accepts, tag
+    assert st["global_accepts"] == ch.global_accepts, tag
+    return st
+
+
+def oracle_local_bits(ch, sweep):
+    n_slots = ch.p.L * ch.p.n
+    bits = np.zeros(n_slots, dtype=np.uint8)
+    for d in ch.decisions:
+        if d.kind == philox.KIND_LOCAL and d.sweep == sweep:
+            bits[d.slot] = 1 if d.accept else 0
+    return bits
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nx,beta,ns,prec", [(2, 1.0, 5, 0), (4, 4.0, 10, 0), (8, 8.0, 8, 0),
+                                             (10, 2.0, 10, 0), (12, 2.0, 10, 1), (6, 0.2, 1, 0)])
+def test_initial_state(hq, nx, beta, ns, prec):
+    say("initial state nx=%d beta=%g ns=%d prec=%d" % (nx, beta, ns, prec))
+    gr = dict(nx=nx, chains=2, g=1.1, beta=beta, n_stab=ns)
+    ctx = make_ctx(hq, [gr], precision=prec, seed=7)
+    for c in range(2):
+        ch = dqmc.Chain(params_of(gr), 7, c)
+        assert np.array_equal(ctx.fields(c), ch.x)
+        assert rel_g(ctx.green(c), ch.G) <= (TOL_MIXED if prec else TOL64)
+        assert abs(ctx.stats(c)["logdet"] - ch.logdet) <= TOL64 * max(1, abs(ch.logdet))
+    ctx.close()
+
+
+def test_holstein_4x4_all_sweeps(hq):
+    """The whole 4x4 single-chain workload: 20 FP64 sweeps, every decision compared."""
+    w = workloads.holstein_4x4_single()
+    g = w.groups[0]
+    say("4x4 single chain, %d sweeps" % w.sweeps)
+    gr = dict(nx=g.nx, chains=1, g=g.g, beta=g.beta, n_stab=g.n_stab)
+    ctx = make_ctx(hq, [gr], seed=w.seed)
+    ch = dqmc.Chain(params_of(gr), w.seed, 0)
+    for s in range(w.sweeps):
+        ctx.sweep(1)
+        ch.sweep()
+        acc, margin = ctx.decisions(0, hq.KIND_LOCAL)
+        assert np.array_equal(acc, oracle_local_bits(ch, s)), "sweep %d" % s
+    st = assert_state(ctx, 0, ch, TOL64, "4x4")
+    assert st["max_drift_green"] < 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("delay", [8, 16, 32])
+def test_delay_depths_agree_with_oracle(hq, delay):
+    say("8x8 delay=%d" % delay)
+    gr = dict(nx=8, chains=2, g=1.2, beta=2.0, n_stab=4)
+    ctx = make_ctx(hq, [gr], seed=11, delay=delay)
+    ctx.sweep(2)
+    for c in range(2):
+        ch = dqmc.Chain(params_of(gr), 11, c)
+        ch.sweep(); ch.sweep()
+        assert_state(ctx, c, ch, TOL64, "delay %d chain %d" % (delay, c))
+    ctx.close()
+
+
+def test_block_moves_8x8(hq):
+    """8x8 chains with one block move per site per sweep (the batched FP64 workload's moves)."""
+    say("8x8 block moves")
+    gr = dict(nx=8, chains=3, g=1.2, beta=1.6, n_stab=8, global_width=1.0)
+    ctx = make_ctx(hq, [gr], seed=2)
+    ctx.sweep(2)
+    for c in range(3):
+        ch = dqmc.Chain(params_of(gr), 2, c)
+        ch.sweep(); ch.sweep()
+        st = assert_state(ctx, c, ch, TOL64, "block chain %d" % c)
+        acc, _ = ctx.decisions(c, hq.KIND_GLOBAL)
+        obits = [d.accept for d in ch.decisions if d.kind == philox.KIND_GLOBAL and d.sweep == 1]
+        assert list(acc.astype(bool)) == obits
+        assert st["global_proposals"] == 2 * 64
+    ctx.close()
+
+
+def test_batched_8x8_full_size_sampled(hq):
+    """64 chains of 8x8, L = 80, n_stab = 8 with block moves (full size); chains 0 and 63 vs the oracle."""
+    w = workloads.holstein_8x8_batched_global()
+    g = w.groups[0]
+    say("8x8 x64 full size, one sweep")
+    gr = dict(nx=g.nx, chains=g.n_chains, g=g.g, beta=g.beta, n_stab=g.n_stab, global_width=g.global_width)
+    ctx = make_ctx(hq, [gr], seed=w.seed)
+    ctx.sweep(1)
+    for c in (0, 63):
+        ch = dqmc.Chain(params_of(gr), w.seed, c)
+        ch.sweep()
+        assert_state(ctx, c, ch, TOL64, "8x8 chain %d" % c)
+    ctx.close()
+
+
+def _mixed_replay_case(hq, gr, chains_to_check, seed, sweeps=1):
+    ctx = make_ctx(hq, [gr], precision=1, seed=seed, delay=32)
+    oracles = {c: dqmc.Chain(params_of(gr), seed, c) for c in chains_to_check}
+    for s in range(sweeps):
+        for c, ch in oracles.items():
+            ch.sweep()
+            ctx.set_replay(c, hq.KIND_LOCAL, oracle_local_bits(ch, s), BAND_MIXED)
+        ctx.sweep(1)
+    for c, ch in oracles.items():
+        st = ctx.stats(c)
+        assert st["replay_mismatches"] == 0, "chain %d: decision outside the tie band differs" % c
+        assert np.array_equal(ctx.fields(c), ch.x)
+        assert rel_g(ctx.green(c), ch.G) <= TOL_MIXED
+        assert abs(st["logdet"] - ch.logdet) <= TOL64 * max(1.0, abs(ch.logdet))
+        assert st["local_accepts"] == ch.local_accepts
+        say("  chain %d: overrides in band %d, max drift %.2e" % (c, st["replay_overrides"],
+                                                                 st["max_drift_green"]))
+    ctx.close()
+
+
+def test_mixed_12x12_small(hq):
+    say("12x12 mixed, beta=2")
+    _mixed_replay_case(hq, dict(nx=12, chains=2, g=1.5, beta=2.0, n_stab=10), (0, 1), seed=3, sweeps=2)
+
+
+def test_mixed_12x12_full_size_sampled(hq):
+    """128 chains of 12x12, L = 120 (the mixed workload at full size); chains 0 and 127 vs the oracle."""
+    w = workloads.holstein_12x12_mixed()
+    g = w.groups[0]
+    say("12x12 x128 mixed full size")
+    _mixed_replay_case(hq, dict(nx=g.nx, chains=g.n_chains, g=g.g, beta=g.beta, n_stab=g.n_stab),
+                       (0, 127), seed=w.seed)
+
+
+def test_uneven_groups_per_chain_coupling(hq):
+    """Two lattice sizes in one context, g per chain from U(0.8, 1.6)."""
+    say("uneven groups 4x4 + 6x6")
+    groups = [dict(nx=4, chains=2, beta=2.0, n_stab=10, g_range=(0.8, 1.6)),
+              dict(nx=6, chains=2, beta=2.0, n_stab=10, g_range=(0.8, 1.6))]
+    ctx = make_ctx(hq, groups, seed=4)
+    ctx.sweep(1)
+    chain = 0
+    for gr in groups:
+        for _ in range(gr["chains"]):
+            from oracle.model import chain_coupling
+            gc = chain_coupling(4, chain, 0.8, 1.6)
+            ch = dqmc.Chain(params_of(gr, g=gc), 4, chain)
+            ch.sweep()
+            st = assert_state(ctx, chain, ch, TOL64, "uneven chain %d" % chain)
+            assert st["g"] == gc
+            chain += 1
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", ["atomic", "free", "nx2", "two_slices"])
+def test_edge_cases(hq, case):
+    say("edge case %s" % case)
+    gr = {"atomic": dict(nx=3, chains=1, t=0.0, beta=1.0, n_stab=5, g=1.3),
+          "free": dict(nx=4, chains=1, g=0.0, beta=2.0, n_stab=5),
+          "nx2": dict(nx=2, chains=1, beta=2.0, n_stab=4, g=1.0, mu=0.3),
+          "two_slices": dict(nx=4, chains=1, beta=0.2, n_stab=1, g=1.0)}[case]
+    ctx = make_ctx(hq, [gr], seed=5)
+    ctx.sweep(2)
+    ch = dqmc.Chain(params_of(gr), 5, 0)
+    ch.sweep(); ch.sweep()
+    assert_state(ctx, 0, ch, TOL64, case)
+    ctx.close()
+
+
+def test_observables_match_oracle(hq):
+    say("observables")
+    gr = dict(nx=4, chains=1, g=1.0, beta=2.0, n_stab=5)
+    ctx = make_ctx(hq, [gr], seed=9)
+    ctx.sweep(1)
+    ch = dqmc.Chain(params_of(gr), 9, 0)
+    ch.sweep()
+    st = ctx.stats(0)
+    ob = ch.observables()
+    for k_gpu, k_or in [("density", "density"), ("double_occupancy", "double_occupancy"),
+                        ("s_cdw", "s_cdw"), ("x_mean", "x_mean"), ("x2_mean", "x2_mean")]:
+        assert abs(st[k_gpu] - ob[k_or]) <= 1e-10 * max(1.0, abs(ob[k_or])), k_gpu
+    ctx.close()
+
+
+def test_set_fields_and_recompute(hq):
+    say("set_fields")
+    gr = dict(nx=6, chains=2, g=1.2, beta=2.0, n_stab=10)
+    p = params_of(gr)
+    x = workloads.random_fields(123, p.L, p.n, scale=0.7)
+    ctx = make_ctx(hq, [gr], seed=1)
+    ctx.set_fields(1, x)
+    ch = dqmc.Chain(p, 1, 1, x=x)
+    assert np.array_equal(ctx.fields(1), x)
+    assert rel_g(ctx.green(1), ch.G) <= TOL64
+    ctx.sweep(1)
+    ch.sweep()
+    assert_state(ctx, 1, ch, TOL64, "after set_fields")
+    G_before = ctx.green(1)
+    ctx.recompute()
+    assert rel_g(ctx.green(1), G_before) <= TOL64
+    ctx.close()
+
+
+def test_bitwise_deterministic(hq):
+    say("determinism")
+    gr = dict(nx=8, chains=2, g=1.2, beta=2.0, n_stab=4, global_width=0.5)
+    out = []
+    for _ in range(2):
+        ctx = make_ctx(hq, [gr], seed=21)
+        ctx.sweep(2)
+        out.append((ctx.fields(1), ctx.green(1), ctx.stats(1)["logdet"]))
+        ctx.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
+
+
+def test_invalid_arguments(hq):
+    say("invalid arguments")
+    gr = dict(nx=4, chains=1, beta=2.0, n_stab=5)
+    ctx = make_ctx(hq, [gr])
+    with pytest.raises(hq.HQError):
+        ctx.set_fields(0, np.zeros(7))
+    bad = np.zeros((20, 16))
+    bad[3, 3] = np.nan
+    with pytest.raises(hq.HQError):
+        ctx.set_fields(0, bad)
+    with pytest.raises(hq.HQError):
+        ctx.green(5)
+    with pytest.raises(hq.HQError):
+        ctx.set_network(np.zeros(10, dtype=np.float32))
+    ctx.sweep(1)                       # the context is still usable
+    assert ctx.stats(0)["local_proposals"] == 16 * 20
+    ctx.close()
+    with pytest.raises(hq.HQError):
+        make_ctx(hq, [dict(nx=4, chains=1, beta=2.0, n_stab=5, proposal=1)]).sweep(1)   # no network loaded
+
+
+def test_network_proposals_and_cumulative_update(hq):
+    """Network-proposed sweeps on 4x4 (L = 8): inner decisions replayed inside the
+    tie band (FP32 network vs the oracle's FP64 forward), cumulative accepts compared."""
+    say("network proposals 4x4")
+    gr = dict(nx=4, chains=2, g=1.2, beta=0.8, n_stab=4, proposal=1)
+    w = workloads.random_network(17, scale=0.1)
+    ctx = make_ctx(hq, [gr], seed=6)
+    ctx.set_network(w)
+    nets = [nnmc.NNChain(dqmc.Chain(params_of(gr), 6, c), w) for c in range(2)]
+    p = params_of(gr)
+    for s in range(3):
+        for c, nn in enumerate(nets):
+            nn.sweep()
+            bits = np.zeros(p.L * p.n, dtype=np.uint8)
+            cum = np.zeros(1, dtype=np.uint8)
+            for kind, sw, slot, acc, _ in nn.decisions:
+                if sw == s and kind == philox.KIND_NN:
+                    bits[slot] = acc
+                if sw == s and kind == philox.KIND_CUMULATIVE:
+                    cum[0] = acc
+            ctx.set_replay(c, hq.KIND_NN, bits, BAND_MIXED)
+            ctx.set_replay(c, hq.KIND_CUMULATIVE, cum, BAND_MIXED)
+        ctx.sweep(1)
+        for c, nn in enumerate(nets):
+            st = ctx.stats(c)
+            assert st["replay_mismatches"] == 0
+            assert np.array_equal(ctx.fields(c), nn.c.x), "sweep %d chain %d" % (s, c)
+            assert abs(st["logdet"] - nn.c.logdet) <= TOL64 * max(1.0, abs(nn.c.logdet))
+            assert st["cumulative_accepts"] == nn.cumulative_accepts
+            assert st["nn_accepts"] == nn.inner_accepts
+    ctx.close()
