@@ -2,333 +2,469 @@
 //
 // The paper defines G through M = I + B_L ... B_1 and refers to the standard
 // DQMC literature for computing it without overflow: the running product is
-// kept as U D T with a pivoted QR after every block of n_stab slices.  Two
-// kernels serve that scheme, one workgroup per matrix, the matrix held in
-// registers (thread = (column, row part); rows r = part + TPC*k):
+// kept as U D T, re-factored with a pivoted QR after every block of n_stab
+// slices, and G comes from one more solve at the end.  Two kernels serve that
+// scheme, one workgroup (4 waves) per matrix, the matrix in global memory
+// (it stays in L2), blocked by panels of NB = 16 columns:
 //
-//  qr_kernel  Householder QR of Z with columns pre-sorted by decreasing norm
-//             (pre-pivoting: the column order is fixed before the
-//             factorization, which keeps the graded scales of Z = (C U) D in
-//             order without per-step pivot searches).  Outputs Q, D = |diag R|
-//             and Rt = D^-1 R P^T, so Z = Q D Rt.
-//  gj_kernel  in-place Gauss-Jordan inversion with partial (row) pivoting,
-//             M^-1 scaled as diag(rs) M^-1 diag(cs), and log|det M|.
+//  qr_blocked   Householder QR with the columns pre-sorted by decreasing norm
+//               (pre-pivoting keeps the graded scales of Z = (C U) D in order
+//               without per-step pivot searches).  Each panel is factored by
+//               one wave in registers (reductions by shuffles, no barriers);
+//               the block reflector I - V T V^T (compact WY, T from the Gram
+//               matrix V^T V) is applied to the trailing columns with MFMA by
+//               all waves.  Q is accumulated backwards the same way.  Outputs
+//               Q, D = |diag R| and Rt = D^-1 R P^T (over Z), so
+//               Z = Q diag(D) Rt.
+//  inv_blocked  in-place Gauss-Jordan inversion with partial (row) pivoting,
+//               blocked the same way: one wave eliminates a panel (pivot
+//               search over all unused rows), then every other column gets
+//               the rank-NB update
+//                   A[r][C] = [r not a pivot row of the panel] A[r][C] + F[r][:] A_old[P][C]
+//               (F: the eliminated panel, P: its pivot rows).  Output
+//               diag(rs) M^-1 diag(cs) (over M) and log|det M|.
 #include "hq_device.h"
 #include "hq_internal.h"
 
 namespace hq {
 
-// value of the (column-group-shared) element at row `row`
-template <int TPC, int RPT>
-__device__ inline double pick_row(const double (&a)[RPT], int q, int row) {
-  double v = 0.0;
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) v = (q + TPC * k == row) ? a[k] : v;
-  return group_sum<TPC>(v);
+constexpr int NB = 16;           // panel width
+constexpr int MAXN = 256;        // largest N (lattices up to 16 x 16)
+constexpr int VLD = MAXN + 16;   // panel row length in LDS (zero tail)
+// kernels are instantiated for N <= MX with MX in {64, 160, 256}: panel rows
+// per lane and 16-row tiles per strip are sized for MX
+template <int MX> struct Cap { enum { rpl = (MX + 63) / 64, tiles = (MX + 15) / 16 }; };
+
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// data-parallel-primitive moves of a double (both 32-bit halves); lanes whose
+// source is outside the enabled rows read 0
+template <int CTRL, int ROWMASK = 0xF>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+// sum over the 64 lanes, returned uniform: within rows of 16 by quad
+// permutations and mirrors, then across rows by the row broadcasts
+__device__ inline double wave_total(double v) {
+  v += dpp_move<0xB1>(v);          // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);          // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);         // row_half_mirror
+  v += dpp_move<0x140>(v);         // row_mirror
+  v += dpp_move<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+  return lane_value(v, 63);
 }
 
 // ---------------------------------------------------------------------------
-// QR with pre-pivoting
+// A <- A - V op(T) (V^T A) on rows [p0, n) and columns [c_begin, n),
+// op(T) = T^T (transT) or T.  V: Vs[k][r] (r relative to p0, zero outside the
+// panel's rows), T: Ts.  Each wave takes 16-column strips and holds a strip in
+// registers as 16-row MFMA tiles: in the f64 16x16x4 layout the B operands of
+// four consecutive 4-row chunks are exactly the C/D tile of those 16 rows.
 // ---------------------------------------------------------------------------
-template <int TPC, int RPT, int MAXT>
-__global__ __launch_bounds__(MAXT) void qr_kernel(const double* __restrict__ Zg, double* __restrict__ Qg,
-                                                  double* __restrict__ Dg, double* __restrict__ Rtg, int n) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* norms = (double*)smem;          // n
-  double* tau = norms + n;                // n
-  double* beta = tau + n;                 // n
-  int* perm = (int*)(beta + n);           // n
-  double* vst = (double*)(perm + ((n + 1) & ~1));   // packed: v_j[r], r >= j, at off(j) + r - j
-  const int z = blockIdx.x;
+template <int MX>
+__device__ void apply_reflector(double* A, int n, int p0, int m, const double (*Vs)[VLD],
+                                const double (*Ts)[NB + 1], int transT, int c_begin, double (*Sc)[NB + 1]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nstrip = (n - c_begin + 15) / 16;
+  const int ntile = (m + 15) / 16;
+  for (int s = wave; s < nstrip; s += 4) {
+    const int col = c_begin + 16 * s + li;
+    d4 tile[Cap<MX>::tiles];
+#pragma unroll
+    for (int t = 0; t < Cap<MX>::tiles; ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = p0 + 16 * t + frag_row<double>(lane, v);
+        tile[t][v] = (t < ntile && row < n && col < n) ? A[(long)row * n + col] : 0.0;
+      }
+    }
+    d4 w1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < Cap<MX>::tiles; ++t)
+      if (t < ntile) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w1 = mfma16(Vs[li][16 * t + 4 * q + lk], tile[t][q], w1);
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Sc[frag_row<double>(lane, v)][li] = w1[v];
+    wave_sync_lds();
+    d4 w2 = {0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+      const double at = transT ? Ts[k0 + lk][li] : Ts[li][k0 + lk];
+      w2 = mfma16(at, Sc[k0 + lk][li], w2);
+    }
+    wave_sync_lds();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Sc[frag_row<double>(lane, v)][li] = w2[v];
+    wave_sync_lds();
+    double wb[NB / 4];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) wb[q] = Sc[4 * q + lk][li];
+#pragma unroll
+    for (int t = 0; t < Cap<MX>::tiles; ++t)
+      if (t < ntile) {
+#pragma unroll
+        for (int q = 0; q < NB / 4; ++q) tile[t] = mfma16(-Vs[4 * q + lk][16 * t + li], wb[q], tile[t]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = p0 + 16 * t + frag_row<double>(lane, v);
+          if (row < n && col < n) A[(long)row * n + col] = tile[t][v];
+        }
+      }
+    wave_sync_lds();
+  }
+}
+
+// T (upper triangular; H_0 ... H_{nb-1} = I - V T V^T) from the Gram matrix:
+// T[j][j] = tau_j,  T[i][j] = -tau_j sum_{k=i}^{j-1} T[i][k] (V^T V)[k][j].
+__device__ void form_t(const double (*Vs)[VLD], int m, int nbw, const double* tau, double (*Gm)[NB + 1],
+                       double (*Ts)[NB + 1]) {
   const int tid = threadIdx.x;
-  const int c = tid / TPC, q = tid % TPC;
-  const bool live = c < n;
-  const double* Z = Zg + (long)z * n * n;
-
-  double a[RPT];
-  // column norms of Z for the pre-pivoting order
-  double ss = 0.0;
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int r = q + TPC * k;
-    a[k] = (live && r < n) ? Z[(long)r * n + c] : 0.0;
-    ss += a[k] * a[k];
-  }
-  ss = group_sum<TPC>(ss);
-  if (!(ss == ss)) ss = -1.0;   // a NaN column sorts last; ranks stay a permutation
-  if (live && q == 0) norms[c] = ss;
+  const int a = tid >> 4, b = tid & 15;
+  double s = 0.0;
+  if (a < nbw && b < nbw && b > a)
+    for (int r = b; r < m; ++r) s += Vs[a][r] * Vs[b][r];
+  Gm[a][b] = s;
   __syncthreads();
-  if (live && q == 0) {
-    int rank = 0;
-    for (int k = 0; k < n; ++k) {
-      const double o = norms[k];
-      rank += (o > ss || (o == ss && k < c)) ? 1 : 0;
-    }
-    perm[rank] = c;
-  }
-  __syncthreads();
-  const int pc = live ? min(max(perm[c], 0), n - 1) : 0;
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int r = q + TPC * k;
-    a[k] = (live && r < n) ? Z[(long)r * n + pc] : 0.0;
-  }
-
-  for (int j = 0; j < n; ++j) {
-    const long off = (long)j * n - (long)j * (j - 1) / 2;   // start of v_j in the packed store
-    if (live && c == j) {
-      double sig = 0.0, alpha = 0.0;
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int r = q + TPC * k;
-        if (r > j && r < n) sig += a[k] * a[k];
-        if (r == j) alpha = a[k];
+  if (tid < NB) {
+    const int i = tid;
+    for (int j = 0; j < NB; ++j) {
+      double v = 0.0;
+      if (j < nbw) {
+        if (i < j) {
+          for (int k = i; k < j; ++k) v += Ts[i][k] * Gm[k][j];
+          v *= -tau[j];
+        } else if (i == j) {
+          v = tau[j];
+        }
       }
-      sig = group_sum<TPC>(sig);
-      alpha = group_sum<TPC>(alpha);
-      double t = 0.0, b = alpha, scl = 0.0;
-      if (sig > 0.0) {
-        const double nrm = sqrt(alpha * alpha + sig);
-        b = (alpha >= 0.0) ? -nrm : nrm;
-        t = (b - alpha) / b;
-        scl = 1.0 / (alpha - b);
-      }
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int r = q + TPC * k;
-        if (r == j) { vst[off] = 1.0; a[k] = b; }
-        else if (r > j && r < n) { vst[off + r - j] = a[k] * scl; }
-      }
-      if (q == 0) { tau[j] = t; beta[j] = b; }
-    }
-    __syncthreads();
-    if (live && c > j) {
-      const double t = tau[j];
-      double w = 0.0;
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int r = q + TPC * k;
-        if (r >= j && r < n) w += vst[off + r - j] * a[k];
-      }
-      w = group_sum<TPC>(w) * t;
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int r = q + TPC * k;
-        if (r >= j && r < n) a[k] -= vst[off + r - j] * w;
-      }
+      Ts[i][j] = v;
     }
   }
   __syncthreads();
+}
 
-  // D = |diag R|, Rt = D^-1 R P^T (column c of R goes to column perm[c])
-  double* Rt = Rtg + (long)z * n * n;
-  if (live) {
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-      const int r = q + TPC * k;
-      if (r < n) Rt[(long)r * n + pc] = (r <= c) ? a[k] / fabs(beta[r]) : 0.0;
-    }
-    if (q == 0) Dg[(long)z * n + c] = fabs(beta[c]);
-  }
-
-  // Q = H_0 H_1 ... H_{n-1}, accumulated backwards from the identity
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int r = q + TPC * k;
-    a[k] = (live && r == c) ? 1.0 : 0.0;
-  }
-  for (int j = n - 1; j >= 0; --j) {
-    if (live && c >= j) {
-      const long off = (long)j * n - (long)j * (j - 1) / 2;
-      const double t = tau[j];
-      double w = 0.0;
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int r = q + TPC * k;
-        if (r >= j && r < n) w += vst[off + r - j] * a[k];
-      }
-      w = group_sum<TPC>(w) * t;
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int r = q + TPC * k;
-        if (r >= j && r < n) a[k] -= vst[off + r - j] * w;
-      }
-    }
-  }
+template <int MX>
+__global__ __launch_bounds__(256) void qr_blocked_kernel(double* __restrict__ Zg, double* __restrict__ Wg,
+                                                         double* __restrict__ Qg, double* __restrict__ Dg,
+                                                         double* __restrict__ Tg, int n) {
+  __shared__ double Vs[NB][VLD];
+  __shared__ double Ts[NB][NB + 1];
+  __shared__ double Gm[NB][NB + 1];
+  __shared__ double Sc[4][NB][NB + 1];
+  __shared__ double norms[MAXN];
+  __shared__ double tau[NB];
+  __shared__ int perm[MAXN];
+  const int z = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* Z = Zg + (long)z * n * n;
+  double* W = Wg + (long)z * n * n;
   double* Q = Qg + (long)z * n * n;
-  if (live) {
+  double* Tst = Tg + (long)z * NB * (n + NB);
+  const int npan = (n + NB - 1) / NB;
+
+  // pre-pivoting: columns of Z in order of decreasing norm (NaN last)
+  if (tid < n) {
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int r0 = 0; r0 < n; r0 += 8) {
+      double v[8];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-      const int r = q + TPC * k;
-      if (r < n) Q[(long)r * n + c] = a[k];
+      for (int u = 0; u < 8; ++u) v[u] = (r0 + u < n) ? Z[(long)(r0 + u) * n + tid] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] += v[u] * v[u];
     }
+    const double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    norms[tid] = (t == t) ? t : -1.0;
   }
-}
-
-static size_t qr_lds(int n) {
-  return sizeof(double) * (3 * (size_t)n) + sizeof(int) * ((n + 1) & ~1) +
-         sizeof(double) * ((size_t)n * (n + 1) / 2);
-}
-
-struct FactorCfg { int tpc, rpt, threads; };
-
-static FactorCfg factor_cfg(int n) {
-  FactorCfg f{0, 0, 0};
-  if (n <= 16) f = {16, 1, 0};
-  else if (n <= 32) f = {16, 2, 0};
-  else if (n <= 64) f = {16, 4, 0};
-  else if (n <= 128) f = {8, 16, 0};
-  else if (n <= 144) f = {4, 36, 0};
-  else if (n <= 192) f = {4, 48, 0};
-  else return f;
-  f.threads = (f.tpc * n + 63) / 64 * 64;
-  return f;
-}
-
-bool qr_supported(int n) { return n >= 1 && factor_cfg(n).tpc > 0 && qr_lds(n) <= 160 * 1024; }
-
-// largest block each register layout is launched with: TPC * max n, rounded to waves
-template <int TPC, int RPT> struct MaxThreads { enum { value = (TPC * TPC * RPT + 63) / 64 * 64 }; };
-
-template <int TPC, int RPT>
-static hipError_t qr_launch_t(const double* Z, double* Q, double* D, double* Rt, int n, int batch,
-                              int threads, hipStream_t s) {
-  hipLaunchKernelGGL((qr_kernel<TPC, RPT, MaxThreads<TPC, RPT>::value>), dim3(batch), dim3(threads), qr_lds(n), s,
-                     Z, Q, D, Rt, n);
-  return hipGetLastError();
-}
-
-template <int TPC, int RPT>
-static hipError_t qr_allow_lds() {
-  return hipFuncSetAttribute((const void*)qr_kernel<TPC, RPT, MaxThreads<TPC, RPT>::value>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             160 * 1024);
-}
-
-hipError_t prepare_factor() {
-  hipError_t e = hipSuccess;
-  const hipError_t all[] = {qr_allow_lds<16, 1>(), qr_allow_lds<16, 2>(), qr_allow_lds<16, 4>(),
-                            qr_allow_lds<8, 16>(), qr_allow_lds<4, 36>(), qr_allow_lds<4, 48>()};
-  for (hipError_t x : all)
-    if (x != hipSuccess) e = x;
-  return e;
-}
-
-hipError_t launch_qr(const double* Z, double* Q, double* D, double* Rt, int n, int batch, hipStream_t s) {
-  if (!qr_supported(n)) return hipErrorInvalidValue;
-  const FactorCfg f = factor_cfg(n);
-  switch (f.rpt) {
-    case 1: return qr_launch_t<16, 1>(Z, Q, D, Rt, n, batch, f.threads, s);
-    case 2: return qr_launch_t<16, 2>(Z, Q, D, Rt, n, batch, f.threads, s);
-    case 4: return qr_launch_t<16, 4>(Z, Q, D, Rt, n, batch, f.threads, s);
-    case 16: return qr_launch_t<8, 16>(Z, Q, D, Rt, n, batch, f.threads, s);
-    case 36: return qr_launch_t<4, 36>(Z, Q, D, Rt, n, batch, f.threads, s);
-    default: return qr_launch_t<4, 48>(Z, Q, D, Rt, n, batch, f.threads, s);
+  __syncthreads();
+  if (tid < n) {
+    const double s = norms[tid];
+    int rank = 0;
+    for (int k = 0; k < n; ++k) rank += (norms[k] > s || (norms[k] == s && k < tid)) ? 1 : 0;
+    perm[rank] = tid;
   }
-}
-
-// ---------------------------------------------------------------------------
-// Gauss-Jordan inversion in place, partial pivoting
-//
-// Step j picks the unused row p with the largest |W[p][j]|, scales row p by
-// 1/piv and eliminates column j from every other row; column j's storage then
-// holds the column p of the accumulated inverse.  At the end
-// M^-1[j][perm[k]] = W[perm[j]][k], perm[j] being the pivot row of step j.
-// ---------------------------------------------------------------------------
-template <int TPC, int RPT, int MAXT>
-__global__ __launch_bounds__(MAXT) void gj_kernel(const double* __restrict__ Mg, double* __restrict__ Xg,
-                                                  const double* __restrict__ rsg, const double* __restrict__ csg,
-                                                  const double* __restrict__ base, double* __restrict__ logdet,
-                                                  int n) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* fbuf = (double*)smem;           // 2 x n: column j of W before step j
-  double* red = fbuf + 2 * n;             // 2 x 2: pivot value, pivot index
-  double* logp = red + 4;                 // n
-  int* perm = (int*)(logp + n);           // n
-  int* pinv = perm + n;                   // n
-  int* used = pinv + n;                   // n
-  const int z = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int c = tid / TPC, q = tid % TPC;
-  const bool live = c < n;
-  const double* M = Mg + (long)z * n * n;
-
-  double a[RPT];
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int r = q + TPC * k;
-    a[k] = (live && r < n) ? M[(long)r * n + c] : 0.0;
-  }
-  for (int e = tid; e < n; e += blockDim.x) used[e] = 0;
+  __syncthreads();
+  batched_copy<256, 16, double>(n * n, [&](int e) { const int r = e / n; return Z[(long)r * n + perm[e - r * n]]; },
+                                [&](int e, double v) { W[e] = v; });
   __syncthreads();
 
-  for (int j = 0; j < n; ++j) {
-    double* f = fbuf + (j & 1) * n;
-    double* rd = red + (j & 1) * 2;
-    if (live && c == j) {
-      double best = -1.0;
-      int bi = n, fu = n;            // fu: first unused row, the fallback for a NaN column
+  for (int pi = 0; pi < npan; ++pi) {
+    const int p0 = pi * NB, nbw = min(NB, n - p0), m = n - p0;
+    if (wave == 0) {
+      double a[NB][Cap<MX>::rpl];
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int r = q + TPC * k;
-        if (r < n) {
-          f[r] = a[k];
-          const double v = fabs(a[k]);
-          if (!used[r]) {
-            fu = min(fu, r);
-            if (v > best || (v == best && r < bi)) { best = v; bi = r; }
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int t = 0; t < Cap<MX>::rpl; ++t) {
+          const int r = lane + 64 * t;
+          a[j][t] = (j < nbw && r < m) ? W[(long)(p0 + r) * n + p0 + j] : 0.0;
+        }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < nbw) {
+          double sg = 0.0, al = 0.0;
+#pragma unroll
+          for (int t = 0; t < Cap<MX>::rpl; ++t) {
+            const int r = lane + 64 * t;
+            if (r > j && r < m) sg += a[j][t] * a[j][t];
+            if (r == j) al = a[j][t];
+          }
+          sg = wave_total(sg);
+          al = wave_total(al);
+          double be = al, tj = 0.0, scl = 0.0;
+          if (sg > 0.0) {
+            const double nrm = sqrt(al * al + sg);
+            be = (al >= 0.0) ? -nrm : nrm;
+            tj = (be - al) / be;
+            scl = 1.0 / (al - be);
+          }
+          double vr[Cap<MX>::rpl];
+#pragma unroll
+          for (int t = 0; t < Cap<MX>::rpl; ++t) {
+            const int r = lane + 64 * t;
+            if (r > j && r < m) a[j][t] *= scl;
+            if (r == j) a[j][t] = be;
+            vr[t] = (r == j) ? 1.0 : ((r > j && r < m) ? a[j][t] : 0.0);
+          }
+          double w[NB];
+#pragma unroll
+          for (int c = j + 1; c < NB; ++c) {
+            w[c] = 0.0;
+#pragma unroll
+            for (int t = 0; t < Cap<MX>::rpl; ++t) w[c] += vr[t] * a[c][t];
+          }
+#pragma unroll
+          for (int c = j + 1; c < NB; ++c) w[c] = wave_total(w[c]) * tj;
+#pragma unroll
+          for (int c = j + 1; c < NB; ++c)
+            if (c < nbw) {
+#pragma unroll
+              for (int t = 0; t < Cap<MX>::rpl; ++t) a[c][t] -= vr[t] * w[c];
+            }
+          if (lane == 0) tau[j] = tj;
+        }
+      }
+      // V to LDS (unit diagonal, zero above and below the panel rows); R and V back to W
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int t = 0; t < Cap<MX>::rpl; ++t) {
+          const int r = lane + 64 * t;
+          Vs[j][r] = (j < nbw && r < m) ? ((r == j) ? 1.0 : ((r > j) ? a[j][t] : 0.0)) : 0.0;
+          if (j < nbw && r < m) W[(long)(p0 + r) * n + p0 + j] = a[j][t];
+        }
+    }
+    Vs[tid >> 4][MAXN + (tid & 15)] = 0.0;
+    __syncthreads();
+    form_t(Vs, m, nbw, tau, Gm, Ts);
+    Tst[(long)pi * NB * NB + tid] = Ts[tid >> 4][tid & 15];
+    apply_reflector<MX>(W, n, p0, m, Vs, Ts, 1, p0 + nbw, Sc[wave]);
+    __syncthreads();
+  }
+
+  // D = |diag R|, Rt = D^-1 R P^T written over Z
+  for (int r = tid; r < n; r += 256) norms[r] = fabs(W[(long)r * n + r]);
+  __syncthreads();
+  for (int r = tid; r < n; r += 256) Dg[(long)z * n + r] = norms[r];
+  batched_copy<256, 16, double>(n * n, [&](int e) { return W[e]; },
+                                [&](int e, double v) {
+                                  const int r = e / n, c = e - r * n;
+                                  Z[(long)r * n + perm[c]] = (r <= c) ? v / norms[r] : 0.0;
+                                });
+  // Q = H_0 H_1 ... accumulated backwards from the identity
+  for (int e = tid; e < n * n; e += 256) {
+    const int r = e / n, c = e - r * n;
+    Q[e] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int pi = npan - 1; pi >= 0; --pi) {
+    const int p0 = pi * NB, nbw = min(NB, n - p0), m = n - p0;
+    batched_copy<256, 17, double>(NB * VLD,
+                                  [&](int e) {
+                                    const int j = e / VLD, r = e - j * VLD;
+                                    double v = 0.0;
+                                    if (j < nbw && r < m) v = (r == j) ? 1.0 : ((r > j) ? W[(long)(p0 + r) * n + p0 + j] : 0.0);
+                                    return v;
+                                  },
+                                  [&](int e, double v) { Vs[e / VLD][e % VLD] = v; });
+    Ts[tid >> 4][tid & 15] = Tst[(long)pi * NB * NB + tid];
+    __syncthreads();
+    apply_reflector<MX>(Q, n, p0, m, Vs, Ts, 0, p0, Sc[wave]);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// blocked Gauss-Jordan inversion in place
+// ---------------------------------------------------------------------------
+template <int MX>
+__global__ __launch_bounds__(256) void inv_blocked_kernel(double* __restrict__ Mg, double* __restrict__ Wg,
+                                                          const double* __restrict__ rsg,
+                                                          const double* __restrict__ csg,
+                                                          const double* __restrict__ base,
+                                                          double* __restrict__ logdet, int n) {
+  __shared__ double Fs[NB][VLD];          // eliminated panel, column-major, zero tail
+  __shared__ double Sc[4][NB][NB + 1];
+  __shared__ int perm[MAXN];              // perm[j]: pivot row of column j
+  __shared__ int pinv[MAXN];
+  __shared__ int panel_of[MAXN];          // panel in which a row became a pivot row
+  __shared__ double logp[MAXN];
+  const int z = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  double* M = Mg + (long)z * n * n;
+  double* W = Wg + (long)z * n * n;
+  batched_copy<256, 16, double>(n * n, [&](int e) { return M[e]; }, [&](int e, double v) { W[e] = v; });
+  panel_of[tid] = -1;
+  __syncthreads();
+  const int npan = (n + NB - 1) / NB;
+  bool used[Cap<MX>::rpl];                         // wave 0: rows of this lane already pivoted
+#pragma unroll
+  for (int t = 0; t < Cap<MX>::rpl; ++t) used[t] = false;
+
+  for (int pi = 0; pi < npan; ++pi) {
+    const int p0 = pi * NB, nbw = min(NB, n - p0);
+    if (wave == 0) {
+      double a[NB][Cap<MX>::rpl];
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int t = 0; t < Cap<MX>::rpl; ++t) {
+          const int r = lane + 64 * t;
+          a[j][t] = (j < nbw && r < n) ? W[(long)r * n + p0 + j] : 0.0;
+        }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < nbw) {
+          // pivot: largest |a| among unused rows, first index on ties; first unused row if none compares
+          double best = -1.0;
+          int bi = MAXN, fu = MAXN;
+#pragma unroll
+          for (int t = 0; t < Cap<MX>::rpl; ++t) {
+            const int r = lane + 64 * t;
+            if (r < n && !used[t]) {
+              fu = min(fu, r);
+              const double v = fabs(a[j][t]);
+              if (v > best || (v == best && r < bi)) { best = v; bi = r; }
+            }
+          }
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            fu = min(fu, __shfl_xor(fu, o, 64));
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+          }
+          if (bi >= n) bi = (fu < n) ? fu : 0;
+          const int p = __builtin_amdgcn_readfirstlane(bi), pl = p & 63, pt = p >> 6;
+          double prow[NB];
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
+            double mine = 0.0;
+#pragma unroll
+            for (int t = 0; t < Cap<MX>::rpl; ++t) mine = (t == pt) ? a[c][t] : mine;
+            prow[c] = lane_value(mine, pl);
+          }
+          const double ip = 1.0 / prow[j];
+#pragma unroll
+          for (int t = 0; t < Cap<MX>::rpl; ++t) {
+            const int r = lane + 64 * t;
+            const bool isp = (r == p);
+            const double aj = a[j][t];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+              if (c != j) {
+                const double wp = prow[c] * ip;
+                a[c][t] = isp ? wp : a[c][t] - aj * wp;
+              }
+            }
+            a[j][t] = isp ? ip : -aj * ip;
+            if (isp) used[t] = true;
+          }
+          if (lane == 0) {
+            perm[p0 + j] = p;
+            pinv[p] = p0 + j;
+            panel_of[p] = pi;
+            logp[p0 + j] = log(fabs(prow[j]));
           }
         }
       }
 #pragma unroll
-      for (int o = TPC / 2; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        fu = min(fu, __shfl_xor(fu, o, 64));
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int t = 0; t < Cap<MX>::rpl; ++t) {
+          const int r = lane + 64 * t;
+          Fs[j][r] = (j < nbw && r < n) ? a[j][t] : 0.0;
+          if (j < nbw && r < n) W[(long)r * n + p0 + j] = a[j][t];
+        }
+    }
+    Fs[tid >> 4][MAXN + (tid & 15)] = 0.0;
+    __syncthreads();
+    // rank-NB update of every column outside the panel, all rows
+    const int nstrip = (n + 15) / 16;
+    for (int s = wave; s < nstrip; s += 4) {
+      const int c0 = 16 * s;
+      const int col = c0 + li;
+      const bool incol = col < n && !(col >= p0 && col < p0 + nbw);
+      for (int e = lane; e < NB * 16; e += 64) {   // old pivot rows of this strip
+        const int k = e >> 4, cc = e & 15;
+        const int cg = c0 + cc;
+        double v = 0.0;
+        if (k < nbw && cg < n && !(cg >= p0 && cg < p0 + nbw)) v = W[(long)perm[p0 + k] * n + cg];
+        Sc[wave][k][cc] = v;
       }
-      if (bi >= n) bi = (fu < n) ? fu : 0;
-      if (q == 0) { rd[1] = (double)bi; perm[j] = bi; pinv[bi] = j; used[bi] = 1; }
+      wave_sync_lds();
+      const int ntile = (n + 15) / 16;
+      d4 tile[Cap<MX>::tiles];
+#pragma unroll
+      for (int t = 0; t < Cap<MX>::tiles; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + frag_row<double>(lane, v);
+          tile[t][v] = (t < ntile && row < n && incol && panel_of[row] != pi) ? W[(long)row * n + col] : 0.0;
+        }
+      double tb[NB / 4];
+#pragma unroll
+      for (int q = 0; q < NB / 4; ++q) tb[q] = Sc[wave][4 * q + lk][li];
+#pragma unroll
+      for (int t = 0; t < Cap<MX>::tiles; ++t)
+        if (t < ntile) {
+#pragma unroll
+          for (int q = 0; q < NB / 4; ++q) tile[t] = mfma16(Fs[4 * q + lk][16 * t + li], tb[q], tile[t]);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * t + frag_row<double>(lane, v);
+            if (row < n && incol) W[(long)row * n + col] = tile[t][v];
+          }
+        }
+      wave_sync_lds();
     }
     __syncthreads();
-    const int p = (int)rd[1];
-    const double piv = f[p];
-    const double pinv_v = 1.0 / piv;
-    if (live) {
-      if (c == j) {
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-          const int r = q + TPC * k;
-          a[k] = (r == p) ? pinv_v : -a[k] * pinv_v;
-        }
-      } else {
-        const double wp = pick_row<TPC, RPT>(a, q, p) * pinv_v;
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-          const int r = q + TPC * k;
-          a[k] = (r == p) ? wp : a[k] - f[r < n ? r : 0] * wp;
-        }
-      }
-    }
-    if (tid == 0) logp[j] = log(fabs(piv));
   }
-  __syncthreads();
 
-  // scatter: X[j][perm[k]] = rs[j] * W[perm[j]][k] * cs[perm[k]]
-  if (live) {
-    const int pk = perm[c];
-    const double* rs = rsg + (long)z * n;
-    const double* cs = csg + (long)z * n;
-    double* X = Xg + (long)z * n * n;
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-      const int r = q + TPC * k;
-      if (r < n) {
-        const int jr = pinv[r];
-        X[(long)jr * n + pk] = rs[jr] * a[k] * cs[pk];
-      }
-    }
-  }
+  // M^-1[j][perm[k]] = W[perm[j]][k]; written scaled over M
+  const double* rs = rsg + (long)z * n;
+  const double* cs = csg + (long)z * n;
+  batched_copy<256, 16, double>(n * n, [&](int e) { return W[e]; },
+                                [&](int e, double v) {
+                                  const int r = e / n, k = e - r * n;
+                                  const int j = pinv[r], pk = perm[k];
+                                  M[(long)j * n + pk] = rs[j] * v * cs[pk];
+                                });
   if (tid == 0) {
     double s = 0.0;
     for (int j = 0; j < n; ++j) s += logp[j];
@@ -336,31 +472,31 @@ __global__ __launch_bounds__(MAXT) void gj_kernel(const double* __restrict__ Mg,
   }
 }
 
-static size_t gj_lds(int n) { return sizeof(double) * (3 * (size_t)n + 4) + sizeof(int) * 4 * (size_t)n; }
+bool qr_supported(int n) { return n >= 1 && n <= MAXN; }
+bool gj_supported(int n) { return n >= 1 && n <= MAXN; }
+size_t qr_t_doubles(int n) { return (size_t)NB * (n + NB); }
 
-bool gj_supported(int n) { return n >= 1 && factor_cfg(n).tpc > 0; }
-
-template <int TPC, int RPT>
-static hipError_t gj_launch_t(const double* M, double* X, const double* rs, const double* cs,
-                              const double* base, double* logdet, int n, int batch, int threads,
-                              hipStream_t s) {
-  hipLaunchKernelGGL((gj_kernel<TPC, RPT, MaxThreads<TPC, RPT>::value>), dim3(batch), dim3(threads), gj_lds(n), s,
-                     M, X, rs, cs, base, logdet, n);
+hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int n, int batch, hipStream_t s) {
+  if (!qr_supported(n)) return hipErrorInvalidValue;
+  if (n <= 64)
+    hipLaunchKernelGGL(qr_blocked_kernel<64>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
+  else if (n <= 160)
+    hipLaunchKernelGGL(qr_blocked_kernel<160>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
+  else
+    hipLaunchKernelGGL(qr_blocked_kernel<256>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
   return hipGetLastError();
 }
 
-hipError_t launch_gj(const double* M, double* X, const double* rs, const double* cs, const double* base,
-                     double* logdet, int n, int batch, hipStream_t s) {
+hipError_t launch_gj(double* M, double* W, const double* rs, const double* cs, const double* base, double* logdet,
+                     int n, int batch, hipStream_t s) {
   if (!gj_supported(n)) return hipErrorInvalidValue;
-  const FactorCfg f = factor_cfg(n);
-  switch (f.rpt) {
-    case 1: return gj_launch_t<16, 1>(M, X, rs, cs, base, logdet, n, batch, f.threads, s);
-    case 2: return gj_launch_t<16, 2>(M, X, rs, cs, base, logdet, n, batch, f.threads, s);
-    case 4: return gj_launch_t<16, 4>(M, X, rs, cs, base, logdet, n, batch, f.threads, s);
-    case 16: return gj_launch_t<8, 16>(M, X, rs, cs, base, logdet, n, batch, f.threads, s);
-    case 36: return gj_launch_t<4, 36>(M, X, rs, cs, base, logdet, n, batch, f.threads, s);
-    default: return gj_launch_t<4, 48>(M, X, rs, cs, base, logdet, n, batch, f.threads, s);
-  }
+  if (n <= 64)
+    hipLaunchKernelGGL(inv_blocked_kernel<64>, dim3(batch), dim3(256), 0, s, M, W, rs, cs, base, logdet, n);
+  else if (n <= 160)
+    hipLaunchKernelGGL(inv_blocked_kernel<160>, dim3(batch), dim3(256), 0, s, M, W, rs, cs, base, logdet, n);
+  else
+    hipLaunchKernelGGL(inv_blocked_kernel<256>, dim3(batch), dim3(256), 0, s, M, W, rs, cs, base, logdet, n);
+  return hipGetLastError();
 }
 
 }  // namespace hq

@@ -47,7 +47,7 @@ struct Group {
   double *blk = nullptr, *blkp = nullptr, *blks = nullptr;     // [C][nb][n][n]
   double *RU = nullptr, *RD = nullptr, *RT = nullptr;          // [C][nb][n][n], [C][nb][n]
   double *LU = nullptr, *LD = nullptr, *LT[2] = {nullptr, nullptr};
-  double *Z = nullptr, *Rt = nullptr, *M = nullptr, *Minv = nullptr, *Xm = nullptr;
+  double *Z = nullptr, *Rt = nullptr, *M = nullptr, *Minv = nullptr, *Xm = nullptr, *Tq = nullptr;
   double *dLbinv = nullptr, *dLs = nullptr, *dRbinv = nullptr, *dRs = nullptr, *sumlog = nullptr;
   double *logdet = nullptr, *logdet_new = nullptr, *shift = nullptr;
   int64_t* counters = nullptr;
@@ -148,7 +148,7 @@ bool valid_group(const hq_group& p, const hq_options& o, std::string& why) {
   }
   const int n = p.nx * p.nx;
   if (!qr_supported(n) || !gj_supported(n)) {
-    snprintf(b, sizeof b, "N = %d exceeds the register-resident factorization (N <= 192)", n);
+    snprintf(b, sizeof b, "N = %d exceeds the factorization kernels (N <= 256)", n);
     why = b;
     return false;
   }
@@ -198,6 +198,7 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
     g.M = cv.take<double>(C * nn);
     g.Minv = cv.take<double>(C * nn);
     g.Xm = cv.take<double>(C * nn);
+    g.Tq = cv.take<double>(C * (long)qr_t_doubles(g.n));
     g.dLbinv = cv.take<double>(C * n);
     g.dLs = cv.take<double>(C * n);
     g.dRbinv = cv.take<double>(C * n);
@@ -388,11 +389,12 @@ hq_status combine(Sched& S, Group& g, const double* A, long sA, int tA, const do
   a.C = g.Z; a.sC = nn;
   a.cs.v = Din; a.cs.so = sD;
   SCHED_TRY(launch_gemm(a, g.tile, S.s));
-  // Q and D go straight into the UDT arrays, which are contiguous per chain
+  // Q and D go straight into the UDT arrays, which are contiguous per chain;
+  // Rt comes back over Z
   if (sUo != nn || sDo != g.n) return fail(S.ctx, HQ_EINVAL, "internal: strided QR output");
-  SCHED_TRY(launch_qr(g.Z, Uout, Dout, g.Rt, g.n, g.C, S.s));
+  SCHED_TRY(launch_qr(g.Z, g.Rt, Uout, Dout, g.Tq, g.n, g.C, S.s));
   GemmArgs<double> b = sq(g, g.C);
-  b.A = g.Rt; b.sA = nn;
+  b.A = g.Z; b.sA = nn;
   b.B = Tin; b.sB = sT;
   b.C = Tout; b.sC = sTo;
   SCHED_TRY(launch_gemm(b, g.tile, S.s));
@@ -434,8 +436,8 @@ hq_status merge(Sched& S, Group& g, const double* UL, const double* DL, const do
   SCHED_TRY(launch_gemm(b, g.tile, S.s));
   // Minv = Db_R^-1 M^-1 Db_L^-1, logdet_new = sumlog + log|det M|
   SCHED_TRY(launch_gj(g.M, g.Minv, rb, g.dLbinv, g.sumlog, g.logdet_new, n, g.C, S.s));
-  GemmArgs<double> c = sq(g, g.C);                 // X = Minv U_L^T
-  c.A = g.Minv; c.sA = nn;
+  GemmArgs<double> c = sq(g, g.C);                 // X = Minv U_L^T (Minv over M)
+  c.A = g.M; c.sA = nn;
   c.B = UL; c.sB = nn; c.tB = 1;
   c.C = g.Xm; c.sC = nn;
   SCHED_TRY(launch_gemm(c, g.tile, S.s));
@@ -721,7 +723,6 @@ hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* 
   *out = ctx;
 
   HQ_TRY(prepare_local());
-  HQ_TRY(prepare_factor());
   hipStream_t s = ctx->stream;
   // host-side model set-up and initial state
   for (Group& g : ctx->groups) {

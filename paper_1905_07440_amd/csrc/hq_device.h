@@ -123,4 +123,24 @@ __device__ inline double block_max(double v, double* scratch) {
   return s;
 }
 
+// dst(e, src(e)) for e in [0, count) over NT threads, with UNR loads of each
+// thread in flight before the first store (a copy loop that waited for every
+// load on its own would be bound by memory latency, not bandwidth)
+template <int NT, int UNR, typename T, typename Src, typename Dst>
+__device__ inline void batched_copy(int count, Src src, Dst dst) {
+  for (int base = 0; base < count; base += NT * UNR) {
+    T v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int e = base + u * NT + (int)threadIdx.x;
+      v[u] = (e < count) ? src(e) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int e = base + u * NT + (int)threadIdx.x;
+      if (e < count) dst(e, v[u]);
+    }
+  }
+}
+
 }  // namespace hq

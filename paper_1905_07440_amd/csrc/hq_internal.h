@@ -72,17 +72,18 @@ hipError_t prepare_local();
 // ---------------------------------------------------------------------------
 // dense FP64 factorizations: one workgroup per matrix (factor.hip)
 // ---------------------------------------------------------------------------
-// Householder QR of Z[z] (n x n) with columns pre-sorted by decreasing norm:
-// Z P = Q R.  Outputs Q (explicit), D = |diag R|, Rt = D^-1 R P^T.
-hipError_t launch_qr(const double* Z, double* Q, double* D, double* Rt, int n, int batch, hipStream_t s);
+// Householder QR of Z[z] (n x n, n <= 256) with columns pre-sorted by
+// decreasing norm, Z P = Q R.  Outputs Q (explicit), D = |diag R| and, over Z,
+// Rt = D^-1 R P^T.  W: n x n work per matrix; T: qr_t_doubles(n) per matrix.
+hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int n, int batch, hipStream_t s);
 bool qr_supported(int n);
+size_t qr_t_doubles(int n);
 
-// Gauss-Jordan inversion with partial pivoting: X = diag(rs) M^-1 diag(cs)
-// (rs, cs: [batch][n]) and logdet[z] = base[z] + log|det M|.
-hipError_t launch_gj(const double* M, double* X, const double* rs, const double* cs,
-                     const double* base, double* logdet, int n, int batch, hipStream_t s);
+// Gauss-Jordan inversion with partial pivoting: over M, diag(rs) M^-1 diag(cs)
+// (rs, cs: [batch][n]); logdet[z] = base[z] + log|det M|.  W: n x n work.
+hipError_t launch_gj(double* M, double* W, const double* rs, const double* cs, const double* base,
+                     double* logdet, int n, int batch, hipStream_t s);
 bool gj_supported(int n);
-hipError_t prepare_factor();
 
 // ---------------------------------------------------------------------------
 // small kernels (misc.hip)

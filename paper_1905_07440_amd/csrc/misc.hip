@@ -59,12 +59,12 @@ __global__ void stab_finish_kernel(T* G, const double* Gnew, double* logdet, con
   T* g = G + (long)z * n * n;
   const double* gn = Gnew + (long)z * n * n;
   double mx = 0.0, bad = 0.0;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const double v = gn[e];
-    if (!isfinite(v)) bad = 1.0;
-    if (record) mx = fmax(mx, fabs((double)g[e] - v));
-    g[e] = (T)v;
-  }
+  batched_copy<256, 16, double>(n * n, [&](int e) { return gn[e]; },
+                                [&](int e, double v) {
+                                  if (!isfinite(v)) bad = 1.0;
+                                  if (record) mx = fmax(mx, fabs((double)g[e] - v));
+                                  g[e] = (T)v;
+                                });
   mx = block_max<256>(mx, red);
   bad = block_max<256>(bad, red);
   if (threadIdx.x == 0) {
@@ -177,10 +177,8 @@ __global__ void global_propose_kernel(GlobalArgs a) {
   const double d = a.width * (2.0 * u53(rn.w[0]) - 1.0);
   const double* x = a.x + (long)c * L * n;
   double* xp = a.xp + (long)c * L * n;
-  for (int e = threadIdx.x; e < L * n; e += blockDim.x) {
-    const int i = e % n;
-    xp[e] = x[e] + ((i == a.site) ? d : 0.0);
-  }
+  batched_copy<256, 16, double>(L * n, [&](int e) { return x[e]; },
+                                [&](int e, double v) { xp[e] = v + ((e % n == a.site) ? d : 0.0); });
   if (threadIdx.x == 0) a.shift[c] = d;
 }
 
@@ -191,7 +189,7 @@ hipError_t launch_global_propose(const GlobalArgs& a, int chains, hipStream_t s)
 
 template <typename T>
 __device__ void copy_green(T* dst, const double* src, long count) {
-  for (long e = threadIdx.x; e < count; e += blockDim.x) dst[e] = (T)src[e];
+  batched_copy<256, 16, double>((int)count, [&](int e) { return src[e]; }, [&](int e, double v) { dst[e] = (T)v; });
 }
 
 __global__ void global_accept_kernel(GlobalArgs a) {
@@ -247,7 +245,9 @@ __global__ void global_accept_kernel(GlobalArgs a) {
   else
     copy_green<double>((double*)a.G + c * nn, a.Gnew + c * nn, nn);
   const long nbk = (long)a.nb * nn;
-  for (long e = threadIdx.x; e < nbk; e += blockDim.x) a.blk[c * nbk + e] = a.blkp[c * nbk + e];
+  const double* src = a.blkp + c * nbk;
+  double* dst = a.blk + c * nbk;
+  batched_copy<256, 16, double>((int)nbk, [&](int e) { return src[e]; }, [&](int e, double v) { dst[e] = v; });
 }
 
 hipError_t launch_global_accept(const GlobalArgs& a, int chains, hipStream_t s) {

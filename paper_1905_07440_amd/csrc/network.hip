@@ -161,14 +161,22 @@ __global__ void cumulative_kernel(CumulativeArgs a) {
   }
   __syncthreads();
   if (!acc_s) return;
-  for (long e = threadIdx.x; e < ln; e += blockDim.x) a.x[c * ln + e] = a.xp[c * ln + e];
+  double* x = a.x + c * ln;
+  const double* xp = a.xp + c * ln;
+  batched_copy<256, 16, double>((int)ln, [&](int e) { return xp[e]; }, [&](int e, double v) { x[e] = v; });
   const long nn = (long)n * n;
-  if (a.precision)
-    for (long e = threadIdx.x; e < nn; e += blockDim.x) ((float*)a.G)[c * nn + e] = (float)a.Gnew[c * nn + e];
-  else
-    for (long e = threadIdx.x; e < nn; e += blockDim.x) ((double*)a.G)[c * nn + e] = a.Gnew[c * nn + e];
+  const double* gn = a.Gnew + c * nn;
+  if (a.precision) {
+    float* G = (float*)a.G + c * nn;
+    batched_copy<256, 16, double>((int)nn, [&](int e) { return gn[e]; }, [&](int e, double v) { G[e] = (float)v; });
+  } else {
+    double* G = (double*)a.G + c * nn;
+    batched_copy<256, 16, double>((int)nn, [&](int e) { return gn[e]; }, [&](int e, double v) { G[e] = v; });
+  }
   const long nbk = (long)a.nb * nn;
-  for (long e = threadIdx.x; e < nbk; e += blockDim.x) a.blk[c * nbk + e] = a.blkp[c * nbk + e];
+  const double* bp = a.blkp + c * nbk;
+  double* bk = a.blk + c * nbk;
+  batched_copy<256, 16, double>((int)nbk, [&](int e) { return bp[e]; }, [&](int e, double v) { bk[e] = v; });
 }
 
 hipError_t launch_cumulative(const CumulativeArgs& a, int chains, hipStream_t s) {
