@@ -166,7 +166,7 @@ def main():
         "dtype": "f32+f64" if w.precision else "f64", "data": "synthetic",
         "config": {"workload": w.name, "chains": w.n_chains, "nx": [g.nx for g in w.groups],
                    "L": [round(g.beta / g.dtau) for g in w.groups], "n_stab": g0.n_stab,
-                   "precision": "mixed" if w.precision else "fp64", "delay": w.delay,
+                   "precision": "mixed" if w.precision else "fp64", "delay": w.delay or 16,
                    "parallelism": "independent chains, one GPU"},
         "accuracy": {"max_abs_G_minus_fp64": max_dg, "max_logdet_err": max_dl,
                      "log_weight_err": 2 * max_dl, "gate_1e-5": max_dg <= 1e-5},

@@ -156,7 +156,7 @@ bool valid_group(const hq_group& p, const hq_options& o, std::string& why) {
     const int nt = n <= 64 ? 64 : 256;
     const int kd = o.delay ? o.delay : 16;
     if (!local_supported(n, o.precision, nt, kd)) {
-      snprintf(b, sizeof b, "N = %d (precision %d, delay %d) does not fit the LDS-resident local kernel", n,
+      snprintf(b, sizeof b, "N = %d (precision %d, delay %d) does not fit the local kernel's LDS", n,
                o.precision, kd);
       why = b;
       return false;

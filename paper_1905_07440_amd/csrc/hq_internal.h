@@ -45,7 +45,8 @@ hipError_t launch_scale_rows(double* P, long sP, const double* A, int n, Scale r
                              int inner_count, hipStream_t s);
 
 // ---------------------------------------------------------------------------
-// local moves of one slice: one workgroup per chain (local.hip)
+// local moves of one slice: one workgroup per chain, sites in blocks of kd
+// (local.hip)
 // ---------------------------------------------------------------------------
 struct LocalArgs {
   int n = 0, L = 0, slice = 0;
@@ -67,6 +68,8 @@ struct LocalArgs {
 hipError_t launch_local(const LocalArgs& a, int precision, int nt, int kd, int chains, hipStream_t s);
 size_t local_lds_bytes(int n, int precision, int nt, int kd);
 bool local_supported(int n, int precision, int nt, int kd);
+// whether the slice keeps G in LDS (else it is streamed from global memory)
+bool local_g_in_lds(int n, int precision, int kd);
 hipError_t prepare_local();
 
 // ---------------------------------------------------------------------------

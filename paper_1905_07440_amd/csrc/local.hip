@@ -9,38 +9,49 @@
 //     new G                 G' = G - (delta / r) G[:,i] (e_i - G[i,:])
 // and W'/W = r^2 exp(-dS_b).
 //
-// Delayed form: G_cur = G0 - A Bv^T with A, Bv of width k.  An accepted move
-// at site i appends A[:,m] = (delta/r) G_cur[:,i] and Bv[:,m] = e_i - G_cur[i,:]
-// (both from G0 and the first m columns); after k accepts, or at the end of
-// the slice, G0 <- G0 - A Bv^T as one rank-k MFMA product.
+// Delayed form: after p accepted moves at sites i_1..i_p,
+//     G_cur = G0 - A Bv^T,  A[:,m] = c_m G_{m-1}[:,i_m],  Bv[:,m] = e_{i_m} - G_{m-1}[i_m,:]^T
+// with c_m = delta_m / r_m.  Row by row this is a short recurrence:
+//     A[j,m]  = c_m (G0[j,i_m] - sum_{m'<m} A[j,m'] Bv[i_m,m'])
+//     Bv[j,m] = [j = i_m] - G0[i_m,j] + sum_{m'<m} A[i_m,m'] Bv[j,m']
+// and G0 <- G0 - A Bv^T is one rank-p MFMA product.
 //
-// Design: one workgroup per chain, G0 resident in LDS for the whole slice.
-// The sites are visited by a single "walker" wave, so the sequential chain
-// has no barriers at all: lane q owns rows q, q+64, q+128, ... -- their
-// random numbers and bosonic action changes (prepared up front, since they do
-// not depend on G), their running diagonal G_cur[j][j], and their rows of A
-// and Bv in registers.  The decision for site i reads the owner lane's values
-// with readlane and is taken by the whole wave; on accept, row i of A and Bv
-// is broadcast the same way and every lane extends its rows.  The other three
-// waves sleep at a barrier and join only for the rank-k flushes, which read A
-// and Bv from LDS mirrors the walker keeps up to date.
+// Design (submatrix blocks): the sites are taken K at a time.  For a block S
+// of K consecutive sites the decisions need only G_cur[S,S], so one "walker"
+// wave holds that K x K block in registers (K*K/64 entries per lane), takes
+// the K decisions in order with no barrier, and applies each accepted rank-1
+// update to the block alone (one shuffle and one FMA per entry).  The walker
+// also records A[S,m] and Bv[S,m], the only entries the row recurrences above
+// need from other rows.  Then all four waves run the recurrences for every
+// row of A and Bv (the rows are independent) and apply the rank-p flush, and
+// the next block starts from the flushed G.  The result is the sequential
+// rank-1 chain up to rounding order.
+//
+// Two forms of the same slice:
+//   local_regs_kernel    G lives in the MFMA accumulators of the four waves
+//                        for the whole slice (the register file is larger than
+//                        LDS); only the K columns and K rows of the current
+//                        block pass through LDS.  The flush is pure MFMA work.
+//   local_stream_kernel  G stays in global memory and the flush streams it in
+//                        batches of tiles: any N <= 256, any K.
 #include "hq_device.h"
 #include "hq_internal.h"
 
 namespace hq {
 
-__host__ __device__ inline int lds_ld(int n) { return (n % 2 == 0) ? n + 1 : n; }
 __host__ __device__ inline int pad16(int n) { return (n + 15) / 16 * 16; }
-// G0 occupies n * ld elements, rounded up so that the mirrors after it are 16-byte aligned
-__host__ __device__ inline int g0_elems(int n) { return (n * lds_ld(n) + 3) / 4 * 4; }
-template <typename T, int KD> struct Mirror { enum { ld = KD + 16 / (int)sizeof(T) }; };
+__host__ __device__ inline int pad64(int n) { return (n + 63) / 64 * 64; }
+__host__ __device__ inline size_t align16(size_t b) { return (b + 15) / 16 * 16; }
 
-__host__ __device__ inline int site_table_len(int n) { return n <= 64 ? 64 : (n <= 192 ? 192 : 256); }
+// per-site constants of the slice: delta, exp(-dS_b), u and the displacement
+struct SiteConst { double delta, bos, u, d; };
 
-template <typename T, int KD>
-__host__ __device__ inline size_t local_lds_size(int n) {
-  return 64 + 32 * (size_t)site_table_len(n) + sizeof(T) * (size_t)(g0_elems(n) + 2 * pad16(n) * Mirror<T, KD>::ld);
-}
+// the accepted moves of the current block
+struct BlockHdr {
+  int p[2];
+  int site[32];
+  double c[32];
+};
 
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ inline float bcast(float v, int lane) {
@@ -51,332 +62,762 @@ __device__ inline double bcast(double v, int lane) {
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
   return __hiloint2double(hi, lo);
 }
-
-// G0 <- G0 - A Bv^T over the first m columns (all four waves; tiles split by wave)
-template <typename T, int KD>
-__device__ inline void flush_tiles(T* G0, int ld, const T* Am, const T* Bm, int n, int np, int m) {
-  constexpr int KL = Mirror<T, KD>::ld;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  typedef typename Frag<T>::type F;
-  const int nt = np / 16;
-  const int mm = (m + 3) & ~3;
-  for (int t = wave; t < nt * nt; t += 4) {
-    const int ti = t / nt, tj = t - ti * nt;
-    const int cc = tj * 16 + (lane & 15);
-    F acc;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = ti * 16 + frag_row<T>(lane, v);
-      acc[v] = (r < n && cc < n) ? G0[r * ld + cc] : T(0);
-    }
-    for (int k0 = 0; k0 < mm; k0 += 4) {
-      const T av = -Am[(ti * 16 + (lane & 15)) * KL + k0 + (lane >> 4)];
-      const T bv = Bm[(tj * 16 + (lane & 15)) * KL + k0 + (lane >> 4)];
-      acc = mfma16(av, bv, acc);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = ti * 16 + frag_row<T>(lane, v);
-      if (r < n && cc < n) G0[r * ld + cc] = acc[v];
-    }
-  }
+// the value v of lane src, src chosen per lane
+__device__ inline float from_lane(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+__device__ inline double from_lane(double v, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+  return __hiloint2double(hi, lo);
 }
 
-// per-site constants of the slice, prepared by the owner lane: delta,
-// exp(-dS_b), u, replay bit (255 = none)
-struct SiteConst { double delta, bos, u, rp; };
+struct WalkState {
+  double logr;
+  int nacc;
+  int counts[2];   // replay overrides inside the band, disagreements outside it
+};
 
-template <typename T, int RPL>
-__device__ inline T pick(const T (&v)[RPL], int t) {
-  T r = v[0];
-#pragma unroll
-  for (int q = 1; q < RPL; ++q) r = (t == q) ? v[q] : r;
-  return r;
-}
-
-template <typename T> struct Vec;
-template <> struct Vec<float> { typedef float4 type; enum { w = 4 }; };
-template <> struct Vec<double> { typedef double2 type; enum { w = 2 }; };
-
-// sum_{q<m} a[q] * b[q] for a, b in LDS (16-byte aligned rows)
-template <typename T>
-__device__ __forceinline__ T dot_lds(const T* a, const T* b, int m) {
-  typedef typename Vec<T>::type V;
-  constexpr int W = Vec<T>::w;
-  T s0 = T(0), s1 = T(0);
-  for (int q = 0; q < m; q += W) {
-    const V va = *(const V*)(a + q);
-    const V vb = *(const V*)(b + q);
-    if constexpr (W == 4) {
-      s0 += va.x * vb.x;
-      s1 += va.y * vb.y;
-      s0 += va.z * vb.z;
-      s1 += va.w * vb.w;
-    } else {
-      s0 += va.x * vb.x;
-      s1 += va.y * vb.y;
-    }
-  }
-  return s0 + s1;
-}
-
-template <typename T, int KD, int RPL>
-__global__ __launch_bounds__(256) void local_slice_kernel(LocalArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int KL = Mirror<T, KD>::ld;
-  constexpr int MAXN = 64 * RPL;
+// Site constants of the slice for sites j = tid, tid + 256, ... (they do not
+// depend on G); replay bits into rp[], accept flags cleared.
+__device__ inline void site_constants(const LocalArgs& a, int c, SiteConst* sc, uint8_t* rp, uint8_t* flags,
+                                      double* Rv) {
   const int n = a.n, L = a.L, s = a.slice;
-  const int np = pad16(n), ld = lds_ld(n);
-  const int c = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-  int* cmd = (int*)smem;                   // flush command: m > 0 flush, -1 done
-  SiteConst* sc = (SiteConst*)(smem + 64);
-  T* G0 = (T*)(smem + 64 + sizeof(SiteConst) * MAXN);
-  T* Am = G0 + g0_elems(n);                // [np][KL] row-major A and Bv (entries >= m are zero)
-  T* Bm = Am + np * KL;
-
-  const T* Gg = (const T*)a.G + (long)c * n * n;
-  batched_copy<256, 16, T>(n * n, [&](int e) { return Gg[e]; },
-                           [&](int e, T v) { const int r = e / n; G0[r * ld + (e - r * n)] = v; });
-  for (int e = tid; e < 2 * np * KL; e += 256) Am[e] = T(0);
-
-  double* x = a.x + (long)c * L * n;
-  double d[RPL], xold[RPL];
-  if (wave == 0) {
+  const double* x = a.x + (long)c * L * n;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
     const int64_t sweep = *a.sweep;
-    const double g = a.g[c];
-#pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int j = lane + 64 * t;
-      d[t] = 0.0;
-      xold[t] = 0.0;
-      if (j < n) {
-        const double xa = x[s * n + j];
-        const double xprev = x[((s - 1 + L) % L) * n + j];
-        const double xnext = x[((s + 1) % L) * n + j];
-        const Philox4 rn = philox4x64_10((uint64_t)(a.chain0 + c), (uint64_t)sweep, (uint64_t)(s * n + j),
-                                         KIND_LOCAL, a.seed, 0);
-        d[t] = a.width * (2.0 * u53(rn.w[0]) - 1.0);
-        const double kin = (a.mass / a.dtau) * (d[t] * (2.0 * xa - xprev - xnext) + d[t] * d[t]);
-        const double pot = a.dtau * 0.5 * a.mass * a.omega * a.omega * (2.0 * xa * d[t] + d[t] * d[t]);
-        SiteConst k;
-        k.delta = expm1(-a.dtau * g * d[t]);
-        k.bos = exp(-(kin + pot - a.dtau * g * d[t]));
-        k.u = u53(rn.w[1]);
-        k.rp = a.replay ? (double)a.replay[(long)c * L * n + s * n + j] : 255.0;
-        sc[j] = k;
-        xold[t] = xa;
-      }
-    }
+    const double gc = a.g[c];
+    const double xa = x[s * n + j];
+    const double xprev = x[((s - 1 + L) % L) * n + j];
+    const double xnext = x[((s + 1) % L) * n + j];
+    const Philox4 rn = philox4x64_10((uint64_t)(a.chain0 + c), (uint64_t)sweep, (uint64_t)(s * n + j), KIND_LOCAL,
+                                     a.seed, 0);
+    const double d = a.width * (2.0 * u53(rn.w[0]) - 1.0);
+    const double kin = (a.mass / a.dtau) * (d * (2.0 * xa - xprev - xnext) + d * d);
+    const double pot = a.dtau * 0.5 * a.mass * a.omega * a.omega * (2.0 * xa * d + d * d);
+    SiteConst k;
+    k.delta = expm1(-a.dtau * gc * d);
+    k.bos = exp(-(kin + pot - a.dtau * gc * d));
+    k.u = u53(rn.w[1]);
+    k.d = d;
+    sc[j] = k;
+    rp[j] = a.replay ? a.replay[(long)c * L * n + s * n + j] : (uint8_t)255;
+    flags[j] = 0;
+    Rv[j] = 1.0;
   }
-  __syncthreads();
+}
 
-  double logr = 0.0;
-  int nacc = 0, novr = 0, nmis = 0;
-  if (wave != 0) {
-    // helpers: wake for each flush the walker requests
-    while (true) {
-      __syncthreads();
-      const int m = cmd[0];
-      if (m < 0) break;
-      flush_tiles<T, KD>(G0, ld, Am, Bm, n, np, m);
-      __syncthreads();
-    }
-  } else {
-    // ---- walker ----
-    T diag[RPL];
-    float my_margin[RPL];
-    int my_acc = 0;                        // bit t: site lane + 64 t accepted
+// The walker (one wave): the decisions of the block of cnt <= K sites
+// starting at `base`, on G_cur[S,S] = gget(r, c) held in registers.
+// Records the accepted sites and c_m in hdr, A[S,m] in As[m][.] and Bv[S,m]
+// in Bs[m][.].
+template <typename T, int K, typename GetG>
+__device__ inline void walk_block(GetG gget, int base, int cnt, int blk, const SiteConst* sc, const uint8_t* rp,
+                                  BlockHdr* hdr, T* As, T* Bs, uint8_t* flags, double* Rv, bool test_hooks,
+                                  double band_lo, double band_hi, WalkState& st) {
+  constexpr int RPV = K * K / 64;          // block rows per lane
+  const int lane = threadIdx.x & 63;
+  const int col = lane % K, rb = lane / K;
+  T gs[RPV];
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int j = lane + 64 * t;
-      diag[t] = (j < n) ? G0[j * ld + j] : T(0);
-      my_margin[t] = 0.0f;
-    }
-    const bool logging = (a.log_margin != nullptr);
-    int m = 0;
-    SiteConst nxt = sc[0];
-    for (int i = 0; i < n; ++i) {
-      const SiteConst cur = nxt;
-      if (i + 1 < n) nxt = sc[i + 1];
-      const int t = i >> 6, o = i & 63;
-      // decision for site i, taken by the whole wave from the owner lane's diagonal
-      const double dg = (double)bcast(pick<T, RPL>(diag, t), o);
-      const double r = 1.0 + cur.delta * (1.0 - dg);
-      const double R = r * r * cur.bos;
-      int acc = (cur.u < R) ? 1 : 0;
-      const int rpi = (int)cur.rp;
-      if (rpi != 255 || logging) {
-        const double margin = log(cur.u) - log(R);
+  for (int v = 0; v < RPV; ++v) {
+    const int r = rb * RPV + v;
+    gs[v] = (r < cnt && col < cnt) ? gget(r, col) : T(0);
+  }
+  SiteConst my = {0.0, 0.0, 2.0, 0.0};
+  int my_rp = 255;
+  if (lane < cnt) {
+    my = sc[base + lane];
+    my_rp = rp[base + lane];
+  }
+  double lp = 1.0;                         // product of |r| over the accepted moves
+  int m = 0;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    if (q < cnt) {                         // a guard, not a break: the loop stays unrolled
+      const double dg = (double)bcast(gs[q % RPV], q + K * (q / RPV));
+      const double delta = bcast(my.delta, q);
+      const double r = 1.0 + delta * (1.0 - dg);
+      const double R = r * r * bcast(my.bos, q);
+      const double u = bcast(my.u, q);
+      int acc = (u < R) ? 1 : 0;
+      if (test_hooks) {
+        // replay inside the tie band |ln u - ln R| <= band, tested as
+        // R e^-band <= u <= R e^band; ln u - ln R is formed after the walk
+        const int rpi = __builtin_amdgcn_readlane(my_rp, q);
         if (rpi != 255) {
-          if (fabs(margin) <= a.band) {
-            if (acc != rpi) ++novr;
+          if (u >= R * band_lo && u <= R * band_hi) {
+            st.counts[0] += (acc != rpi) ? 1 : 0;
             acc = rpi;
-          } else if (acc != rpi) {
-            ++nmis;
+          } else {
+            st.counts[1] += (acc != rpi) ? 1 : 0;
           }
         }
-        if (logging) {
-#pragma unroll
-          for (int q = 0; q < RPL; ++q)
-            if (lane == o && t == q) my_margin[q] = (float)margin;
-        }
+        if (lane == 0) Rv[base + q] = R;
       }
-      if (!acc) continue;
-      // accepted: site i becomes column m of A and Bv
-      if (lane == o) my_acc |= 1 << t;
-      logr += log(fabs(r));
-      ++nacc;
-      const T coef = (T)(cur.delta / r);
-      const T* ai = Am + i * KL;           // row i (broadcast: every lane reads the same address)
-      const T* bi = Bm + i * KL;
+      acc = uniform(acc);                  // a scalar branch: every lane holds the same value
+      if (acc) {
+        // rank-1 update of the block; column m of A and Bv on the rows of S
+        const T coef = (T)(delta / r);
+        T colv[RPV];
 #pragma unroll
-      for (int t2 = 0; t2 < RPL; ++t2) {
-        const int j = lane + 64 * t2;
-        if (j < np) {
-          const T colv = ((j < n) ? G0[j * ld + i] : T(0)) - dot_lds<T>(Am + j * KL, bi, m);
-          const T rowv = ((j < n) ? G0[i * ld + j] : T(0)) - dot_lds<T>(ai, Bm + j * KL, m);
-          T na = coef * colv;
-          T nb = ((j == i) ? T(1) : T(0)) - rowv;
-          if (j >= n) { na = T(0); nb = T(0); }
-          diag[t2] -= na * nb;
-          // the dots of every lane read row i before any lane writes column m
-          __builtin_amdgcn_wave_barrier();
-          Am[j * KL + m] = na;
-          Bm[j * KL + m] = nb;
-        }
-      }
-      m = uniform(m + 1);
-      if (m == KD) {
-        // window full: G0 <- G0 - A Bv^T with every wave, then a fresh window
-        cmd[0] = KD;
-        __syncthreads();
-        flush_tiles<T, KD>(G0, ld, Am, Bm, n, np, KD);
-        __syncthreads();
+        for (int v = 0; v < RPV; ++v) colv[v] = from_lane(gs[v], q + K * rb);
+        const T rowv = from_lane(gs[q % RPV], col + K * (q / RPV));
+        const T nb = ((col == q) ? T(1) : T(0)) - rowv;
+        if (col == q) {
 #pragma unroll
-        for (int t2 = 0; t2 < RPL; ++t2) {
-          const int j = lane + 64 * t2;
-          if (j < np)
-            for (int q = 0; q < KD; ++q) { Am[j * KL + q] = T(0); Bm[j * KL + q] = T(0); }
-          diag[t2] = (j < n) ? G0[j * ld + j] : T(0);
+          for (int v = 0; v < RPV; ++v) As[m * K + rb * RPV + v] = coef * gs[v];
         }
-        m = 0;
-      }
-    }
-    if (m > 0) {
-      cmd[0] = m;
-      __syncthreads();
-      flush_tiles<T, KD>(G0, ld, Am, Bm, n, np, m);
-      __syncthreads();
-    }
-    cmd[0] = -1;
-    __syncthreads();
+        if (rb == q / RPV) Bs[m * K + col] = nb;
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int j = lane + 64 * t;
-      if (j < n) {
-        const bool acc = (my_acc >> t) & 1;
-        if (acc) x[s * n + j] = xold[t] + d[t];
-        if (logging) {
-          const long o = (long)c * L * n + s * n + j;
-          a.log_margin[o] = my_margin[t];
-          a.log_accept[o] = (uint8_t)acc;
+        for (int v = 0; v < RPV; ++v) gs[v] -= (coef * colv[v]) * nb;
+        if (lane == 0) {
+          hdr->site[m] = base + q;
+          hdr->c[m] = delta / r;
+          flags[base + q] = 1;
         }
+        lp *= fabs(r);
+        m = uniform(m + 1);
       }
     }
   }
+  st.logr += log(lp);
+  st.nacc += m;
+  if (lane == 0) hdr->p[blk & 1] = m;
+}
+
+// A and Bv at the accepted rows, for the recurrences:
+//   ASm[m][m'] = A[i_m, m'], BSm[m][m'] = Bv[i_m, m'] for m' < m < p, else 0
+template <typename T, int K>
+__device__ inline void gather_small(const BlockHdr* hdr, const T* As, const T* Bs, T* ASm, T* BSm, int base, int p) {
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+    const int mi = e / K, mj = e - mi * K;
+    T av = T(0), bv = T(0);
+    if (mi < p && mj < mi) {
+      const int li = hdr->site[mi] - base;
+      av = As[mj * K + li];
+      bv = Bs[mj * K + li];
+    }
+    ASm[e] = av;
+    BSm[e] = bv;
+  }
+}
+
+// One row of the recurrences over KE >= p steps (entries >= p come out 0).
+//   A row (isA):  v[m] = c_m (g[m] - sum_{m'<m} v[m'] BSm[m][m'])     g[m] = G0[j, i_m]
+//   Bv row:       v[m] = [j = i_m] - g[m] + sum_{m'<m} ASm[m][m'] v[m']  g[m] = G0[i_m, j]
+// The step constants (i_m, c_m) are read per step as wave-uniform values so
+// that they sit in scalar registers.
+__device__ inline int uniform_site(const BlockHdr* hdr, int mq, int p) { return uniform(hdr->site[min(mq, p - 1)]); }
+__device__ inline double uniform_c(const BlockHdr* hdr, int mq, int p) {
+  const double c = hdr->c[min(mq, p - 1)];
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(c));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(c));
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline float uniform_val(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ inline double uniform_val(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// isA and W are the same for every lane of the wave: the W entries then live
+// in scalar registers instead of one vector register each
+template <typename T, int K, int KE>
+__device__ inline void recur_row(const BlockHdr* hdr, int p, bool isA, bool live, int j, const T (&g)[KE],
+                                 const T* W, T (&v)[KE]) {
+  const T sg = isA ? T(-1) : T(1);
+#pragma unroll
+  for (int mq = 0; mq < KE; ++mq) {
+    const int im = uniform_site(hdr, mq, p);
+    T a0 = isA ? g[mq] : (((j == im) ? T(1) : T(0)) - g[mq]);
+    T a1 = T(0);
+#pragma unroll
+    for (int m2 = 0; m2 < mq; ++m2) {
+      const T w = uniform_val(W[mq * K + m2]);
+      if (m2 & 1) a1 += v[m2] * w;
+      else a0 += sg * (v[m2] * w);
+    }
+    const T mul = (mq < p) ? (isA ? (T)uniform_c(hdr, mq, p) : T(1)) : T(0);
+    v[mq] = live ? mul * (a0 + sg * a1) : T(0);
+  }
+}
+
+// ===========================================================================
+// register-resident form
+// ===========================================================================
+// Four waves, one per SIMD, so that each has the whole register file of its
+// SIMD.  They hold G in their MFMA accumulators for the whole slice, as a
+// 2 x 2 grid over the nt x nt tiles: wave (wr, wc) = (w & 1, w >> 1) holds
+// tiles (wr + 2a, wc + 2b), so every tile address of a wave is one base plus
+// a compile-time offset.  Wave 0 is also the walker: during the walk it holds
+// the block's column strip G[:, S] and row strip G[S, :] in registers, lane l
+// keeping rows (and columns) l, l + 64, ...  Each accepted move is one rank-1 update of both
+// strips, and the column and row it used are column m of A and Bv, written to
+// LDS panels as they arise.  Per block: walk, then the tile waves apply the
+// rank-p flush G -= A Bv^T and extract the next block's strips; two barriers.
+//
+// LDS (bytes): header | site constants | replay bits | flags | ratios R |
+// A, Bv panels [npw][KL] | Cs = G[:, S] [npw][K+1] | Rs = G[S, :] [K][npw+1],
+// npw = N rounded up to 64 (the walker's rows).
+template <typename T, int K>
+struct RegLds {
+  enum { KL = K + 16 / (int)sizeof(T) };
+  static __host__ __device__ size_t sc() { return align16(sizeof(BlockHdr)); }
+  static __host__ __device__ size_t rp(int n) { return sc() + sizeof(SiteConst) * (size_t)n; }
+  static __host__ __device__ size_t flags(int n) { return rp(n) + n; }
+  static __host__ __device__ size_t rv(int n) { return align16(flags(n) + n); }
+  static __host__ __device__ size_t ap(int n) { return align16(rv(n) + 8 * (size_t)n); }
+  static __host__ __device__ size_t bp(int n) { return ap(n) + sizeof(T) * (size_t)pad64(n) * KL; }
+  static __host__ __device__ size_t cs(int n) { return bp(n) + sizeof(T) * (size_t)pad64(n) * KL; }
+  static __host__ __device__ size_t rs(int n) { return cs(n) + sizeof(T) * (size_t)pad64(n) * (K + 1); }
+  static __host__ __device__ size_t total(int n) { return align16(rs(n) + sizeof(T) * (size_t)K * (pad64(n) + 1)); }
+};
+
+template <typename T, int NT>
+struct RegTiles {
+  enum { H = (NT + 1) / 2 };
+  typename Frag<T>::type t[H][H];
+};
+
+// an opaque copy of v: address arithmetic derived from it is not merged with
+// earlier arithmetic on v, so those addresses need not stay live in registers
+__device__ inline int opaque(int v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
+// 1/r to a few ulp: the hardware seed and two Newton steps
+__device__ inline double recip(double r) {
+  double y = __builtin_amdgcn_rcp(r);
+  y = fma(fma(-r, y, 1.0), y, y);
+  return fma(fma(-r, y, 1.0), y, y);
+}
+__device__ inline float recip(float r) { return __builtin_amdgcn_rcpf(r); }
+
+// The walker: the block of cnt <= K sites at `base`.  base is a multiple of
+// K and K divides 64, so the block's own rows are lanes l0 .. l0 + K - 1 of
+// row group T0.
+template <typename T, int K, int RT>
+__device__ inline void walk_strips(int npw, int base, int cnt, int blk, const T* Cs, const T* Rs, int cl, int rl, T* Ap,
+                                   T* Bp,
+                                   const SiteConst* sc, const uint8_t* rp, BlockHdr* hdr, uint8_t* flags, double* Rv,
+                                   bool test_hooks, double band_lo, double band_hi, WalkState& st) {
+  constexpr int KL = RegLds<T, K>::KL;
+  const int lane = threadIdx.x & 63;
+  const int T0 = base >> 6, l0 = base & 63;
+  T cs[RT][K], rs[RT][K];                  // cs[t][k] = G[lane + 64t][base + k], rs[t][k] = G[base + k][lane + 64t]
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      cs[t][k] = (64 * t < npw) ? Cs[(lane + 64 * t) * cl + k] : T(0);
+      rs[t][k] = (64 * t < npw) ? Rs[k * rl + lane + 64 * t] : T(0);
+    }
+  SiteConst my = {0.0, 0.0, 2.0, 0.0};
+  int my_rp = 255;
+  if (lane < cnt) {
+    my = sc[base + lane];
+    my_rp = rp[base + lane];
+  }
+  double lp = 1.0;                         // product of |r| over the accepted moves
+  int m = 0;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    if (q < cnt) {                         // a guard, not a break: the loop stays unrolled
+      // column q and row q of the strips in the block's row group
+      T cq = cs[0][q], rq = rs[0][q];
+#pragma unroll
+      for (int t = 1; t < RT; ++t) {
+        cq = (T0 == t) ? cs[t][q] : cq;
+        rq = (T0 == t) ? rs[t][q] : rq;
+      }
+      const double dg = (double)bcast(cq, l0 + q);
+      const double delta = bcast(my.delta, q);
+      const double r = 1.0 + delta * (1.0 - dg);
+      const double R = r * r * bcast(my.bos, q);
+      const double u = bcast(my.u, q);
+      int acc = (u < R) ? 1 : 0;
+      if (test_hooks) {
+        // replay inside the tie band |ln u - ln R| <= band, tested as
+        // R e^-band <= u <= R e^band; ln u - ln R is formed after the walk
+        const int rpi = __builtin_amdgcn_readlane(my_rp, q);
+        if (rpi != 255) {
+          if (u >= R * band_lo && u <= R * band_hi) {
+            st.counts[0] += (acc != rpi) ? 1 : 0;
+            acc = rpi;
+          } else {
+            st.counts[1] += (acc != rpi) ? 1 : 0;
+          }
+        }
+        if (lane == 0) Rv[base + q] = R;
+      }
+      acc = uniform(acc);                  // a scalar branch: every lane holds the same value
+      if (acc) {
+        const int i = base + q;
+        const T coef = (T)delta * recip((T)r);
+        // G[i, S] and G[S, i] as wave-uniform values
+        T nb[K], ci[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          nb[k] = ((k == q) ? T(1) : T(0)) - bcast(rq, l0 + k);
+          ci[k] = bcast(cq, l0 + k);
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int j = lane + 64 * t;
+          const T na = coef * cs[t][q];    // A[j, m] = c G[j, i]
+          const T nr = ((j == i) ? T(1) : T(0)) - rs[t][q];   // Bv[j, m] = [j = i] - G[i, j]
+          if (64 * t < npw) {
+            Ap[j * KL + m] = na;
+            Bp[j * KL + m] = nr;
+          }
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            cs[t][k] -= na * nb[k];
+            rs[t][k] -= (coef * ci[k]) * nr;
+          }
+        }
+        if (lane == 0) {
+          hdr->site[m] = i;
+          flags[i] = 1;
+        }
+        lp *= fabs(r);
+        m = uniform(m + 1);
+      }
+    }
+  }
+  // zero A, Bv columns m .. round4(m) - 1: the flush reads whole groups of four
+  for (int mz = m; mz < ((m + 3) & ~3); ++mz)
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+      if (64 * t < npw) {
+        Ap[(lane + 64 * t) * KL + mz] = T(0);
+        Bp[(lane + 64 * t) * KL + mz] = T(0);
+      }
+  st.logr += log(lp);
+  st.nacc += m;
+  if (lane == 0) hdr->p[blk & 1] = m;
+}
+
+template <typename T, int K, int NT>
+__global__ __launch_bounds__(256) void local_regs_kernel(LocalArgs a) {
+  static_assert(K == 16 || K == 32, "blocks of whole tiles");
+  extern __shared__ __align__(16) unsigned char smem[];
+  typedef RegLds<T, K> Lay;
+  constexpr int KL = Lay::KL;
+  constexpr int H = RegTiles<T, NT>::H;
+  constexpr int RT = (16 * NT + 63) / 64;  // walker rows per lane
+  const int n = a.n, L = a.L, s = a.slice;
+  const int np = pad16(n), nt = np / 16;
+  const int cl = K + 1, rl = pad64(np) + 1;
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = uniform(tid >> 6);      // scalar: tile tests below become scalar branches
+  const bool walker = wave == 0;
+  const int wr = wave & 1, wc = wave >> 1;
+
+  BlockHdr* hdr = (BlockHdr*)smem;
+  SiteConst* sc = (SiteConst*)(smem + Lay::sc());
+  uint8_t* rp = smem + Lay::rp(n);
+  uint8_t* flags = smem + Lay::flags(n);
+  double* Rv = (double*)(smem + Lay::rv(n));
+  T* Ap = (T*)(smem + Lay::ap(n));         // [npw][KL]: A
+  T* Bp = (T*)(smem + Lay::bp(n));         // [npw][KL]: Bv
+  T* Cs = (T*)(smem + Lay::cs(n));         // [npw][K+1]
+  T* Rs = (T*)(smem + Lay::rs(n));         // [K][npw+1]
+
+  // G into the accumulators
+  RegTiles<T, NT> G;
+  {
+    const int nn = opaque(n);
+    const T* Gg = (const T*)a.G + (long)c * nn * nn;
+#pragma unroll
+    for (int ta = 0; ta < H; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < H; ++tb) {
+        const int ti = wr + 2 * ta, tj = wc + 2 * tb;
+        const int cc = tj * 16 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = ti * 16 + frag_row<T>(lane, v);
+          G.t[ta][tb][v] = (r < nn && cc < nn) ? Gg[r * nn + cc] : T(0);
+        }
+      }
+  }
+  site_constants(a, c, sc, rp, flags, Rv);
+  // strip rows and columns past N stay zero
+  for (int e = tid; e < pad64(np) * cl; e += blockDim.x) Cs[e] = T(0);
+  for (int e = tid; e < K * rl; e += blockDim.x) Rs[e] = T(0);
   __syncthreads();
 
-  T* Gw = (T*)a.G + (long)c * n * n;
-  batched_copy<256, 16, T>(n * n, [&](int e) { const int r = e / n; return G0[r * ld + (e - r * n)]; },
-                           [&](int e, T v) { Gw[e] = v; });
-  if (tid == 0) {
-    a.logdet[c] += logr;
+  // columns and rows [base, base + K) of G into Cs and Rs.  K is a multiple
+  // of 16 and base of K, so a tile lies wholly inside the block or outside it.
+  auto extract = [&](int base) {
+#pragma unroll
+    for (int ta = 0; ta < H; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < H; ++tb) {
+        const int ti = wr + 2 * ta, tj = wc + 2 * tb;
+        if (ti < nt && tj < nt) {
+          const int cc = tj * 16 + (lane & 15);
+          if (tj * 16 >= base && tj * 16 < base + K) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Cs[(ti * 16 + frag_row<T>(lane, v)) * cl + (cc - base)] = G.t[ta][tb][v];
+          }
+          if (ti * 16 >= base && ti * 16 < base + K) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Rs[(ti * 16 + frag_row<T>(lane, v) - base) * rl + cc] = G.t[ta][tb][v];
+          }
+        }
+      }
+  };
+  extract(0);
+  __syncthreads();
+
+  const bool test_hooks = a.log_margin != nullptr || a.replay != nullptr;
+  const double band_lo = exp(-a.band), band_hi = exp(a.band);
+  WalkState st = {0.0, 0, {0, 0}};
+  for (int base = 0, blk = 0; base < n; base += K, ++blk) {
+    if (walker)
+      walk_strips<T, K, RT>(pad64(np), base, min(K, n - base), blk, Cs, Rs, cl, rl, Ap, Bp, sc, rp, hdr, flags, Rv,
+                            test_hooks, band_lo, band_hi, st);
+    __syncthreads();
+    {
+      const int p = hdr->p[blk & 1];
+      // G -= A Bv^T on the accumulators
+      const int mm = (p + 3) & ~3;
+      for (int k0 = 0; k0 < mm; k0 += 4) {
+        const int kk = k0 + (lane >> 4);
+        T av[H], bv[H];
+        const int rmax = pad64(np) - 1;    // rows clamped into the panels; tiles past nt are skipped below
+#pragma unroll
+        for (int ta = 0; ta < H; ++ta) av[ta] = -Ap[min((wr + 2 * ta) * 16 + (lane & 15), rmax) * KL + kk];
+#pragma unroll
+        for (int tb = 0; tb < H; ++tb) bv[tb] = Bp[min((wc + 2 * tb) * 16 + (lane & 15), rmax) * KL + kk];
+#pragma unroll
+        for (int ta = 0; ta < H; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < H; ++tb)
+            if (wr + 2 * ta < nt && wc + 2 * tb < nt) G.t[ta][tb] = mfma16(av[ta], bv[tb], G.t[ta][tb]);
+      }
+      if (base + K < n) extract(base + K);
+    }
+    __syncthreads();
+  }
+
+  // fields, logs, counters; G back to global memory
+  double* x = a.x + (long)c * L * n;
+  for (int j = tid; j < n; j += blockDim.x) {
+    const bool acc = flags[j] != 0;
+    if (acc) x[s * n + j] = x[s * n + j] + sc[j].d;
+    if (a.log_margin) {
+      const long o = (long)c * L * n + s * n + j;
+      a.log_margin[o] = (float)(log(sc[j].u) - log(Rv[j]));
+      a.log_accept[o] = (uint8_t)acc;
+    }
+  }
+  {
+    const int nn = opaque(n);
+    T* Gg = (T*)a.G + (long)c * nn * nn;
+#pragma unroll
+    for (int ta = 0; ta < H; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < H; ++tb) {
+        const int ti = wr + 2 * ta, tj = wc + 2 * tb;
+        const int cc = tj * 16 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = ti * 16 + frag_row<T>(lane, v);
+          if (r < nn && cc < nn) Gg[r * nn + cc] = G.t[ta][tb][v];
+        }
+      }
+  }
+  if (walker && lane == 0) {
+    a.logdet[c] += st.logr;
     int64_t* cnt = a.counters + (long)c * N_COUNTERS;
     cnt[CNT_LOCAL_P] += n;
-    cnt[CNT_LOCAL_A] += nacc;
+    cnt[CNT_LOCAL_A] += st.nacc;
     if (a.replay_counts) {
-      a.replay_counts[2 * c] += novr;
-      a.replay_counts[2 * c + 1] += nmis;
+      a.replay_counts[2 * c] += st.counts[0];
+      a.replay_counts[2 * c + 1] += st.counts[1];
     }
   }
 }
 
-template <int KD>
-static size_t lds_for(int n, int precision) {
-  return precision ? local_lds_size<float, KD>(n) : local_lds_size<double, KD>(n);
+// ===========================================================================
+// streamed form: G in global memory
+// ===========================================================================
+// row stride (elements) of the A and Bv panels: 16-byte aligned rows
+template <typename T, int K> struct Panel { enum { ld = K + 16 / (int)sizeof(T) }; };
+
+template <typename T, int K>
+struct StreamLds {
+  static __host__ __device__ size_t sc() { return align16(sizeof(BlockHdr)); }
+  static __host__ __device__ size_t rp(int n) { return sc() + sizeof(SiteConst) * (size_t)n; }
+  static __host__ __device__ size_t flags(int n) { return rp(n) + n; }
+  static __host__ __device__ size_t rv(int n) { return align16(flags(n) + n); }
+  static __host__ __device__ size_t small(int n) { return align16(rv(n) + 8 * (size_t)n); }
+  static __host__ __device__ size_t am(int n) { return small(n) + 4 * sizeof(T) * K * K; }
+  static __host__ __device__ size_t bm(int n) { return am(n) + sizeof(T) * (size_t)pad16(n) * Panel<T, K>::ld; }
+  static __host__ __device__ size_t total(int n) {
+    return align16(bm(n) + sizeof(T) * (size_t)pad16(n) * Panel<T, K>::ld);
+  }
+};
+
+// G <- G - A Bv^T over the first p columns, G global (row stride n); each
+// wave takes TB tiles at a time so that their loads are in flight together
+template <typename T, int K, int TB>
+__device__ inline void flush_global(T* G, const T* Am, const T* Bm, int n, int np, int p) {
+  constexpr int KL = Panel<T, K>::ld;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  typedef typename Frag<T>::type F;
+  const int nt = np / 16, tiles = nt * nt;
+  const int mm = (p + 3) & ~3;
+  for (int t0 = wave * TB; t0 < tiles; t0 += 4 * TB) {
+    F acc[TB];
+    int ti[TB], tj[TB];
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      const int t = min(t0 + u, tiles - 1);
+      ti[u] = t / nt;
+      tj[u] = t - ti[u] * nt;
+      const int cc = tj[u] * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = ti[u] * 16 + frag_row<T>(lane, v);
+        acc[u][v] = (r < n && cc < n) ? G[r * n + cc] : T(0);
+      }
+    }
+    for (int k0 = 0; k0 < mm; k0 += 4) {
+#pragma unroll
+      for (int u = 0; u < TB; ++u) {
+        const T av = -Am[(ti[u] * 16 + (lane & 15)) * KL + k0 + (lane >> 4)];
+        const T bv = Bm[(tj[u] * 16 + (lane & 15)) * KL + k0 + (lane >> 4)];
+        acc[u] = mfma16(av, bv, acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      if (t0 + u >= tiles) break;
+      const int cc = tj[u] * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = ti[u] * 16 + frag_row<T>(lane, v);
+        if (r < n && cc < n) G[r * n + cc] = acc[u][v];
+      }
+    }
+  }
+}
+
+template <typename T, int K, int KE>
+__device__ inline void recur_all_stream(const BlockHdr* hdr, const T* G, T* Am, T* Bm, const T* ASm, const T* BSm,
+                                        int n, int np, int p) {
+  constexpr int KL = Panel<T, K>::ld;
+  const int npa = (np + 63) & ~63;         // A tasks fill whole waves, so isA is wave-uniform
+  for (int t = threadIdx.x; t < 2 * npa; t += blockDim.x) {
+    const bool isA = t < npa;
+    const int j = isA ? t : t - npa;
+    if (j >= np) continue;
+    const bool live = j < n;
+    const int jj = live ? j : 0;
+    T g[KE];
+#pragma unroll
+    for (int mq = 0; mq < KE; ++mq) {
+      const int im = uniform_site(hdr, mq, p);
+      g[mq] = isA ? G[jj * n + im] : G[im * n + jj];
+    }
+    T v[KE];
+    recur_row<T, K, KE>(hdr, p, isA, live, j, g, isA ? BSm : ASm, v);
+    T* dst = (isA ? Am : Bm) + j * KL;
+#pragma unroll
+    for (int mq = 0; mq < KE; ++mq) dst[mq] = v[mq];
+  }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void local_stream_kernel(LocalArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  typedef StreamLds<T, K> Lay;
+  const int n = a.n, L = a.L, s = a.slice;
+  const int np = pad16(n);
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x, wave = uniform(tid >> 6);
+
+  BlockHdr* hdr = (BlockHdr*)smem;
+  SiteConst* sc = (SiteConst*)(smem + Lay::sc());
+  uint8_t* rp = smem + Lay::rp(n);
+  uint8_t* flags = smem + Lay::flags(n);
+  double* Rv = (double*)(smem + Lay::rv(n));
+  T* As = (T*)(smem + Lay::small(n));
+  T* Bs = As + K * K;
+  T* ASm = Bs + K * K;
+  T* BSm = ASm + K * K;
+  T* Am = (T*)(smem + Lay::am(n));         // [np][KL] rows of A and Bv (entries >= p zero)
+  T* Bm = (T*)(smem + Lay::bm(n));
+  T* G = (T*)a.G + (long)c * n * n;
+
+  site_constants(a, c, sc, rp, flags, Rv);
+  for (int e = tid; e < 2 * np * Panel<T, K>::ld; e += 256) Am[e] = T(0);
+  __syncthreads();
+
+  const bool test_hooks = a.log_margin != nullptr || a.replay != nullptr;
+  const double band_lo = exp(-a.band), band_hi = exp(a.band);
+  WalkState st = {0.0, 0, {0, 0}};
+  for (int base = 0, blk = 0; base < n; base += K, ++blk) {
+    const int cnt = min(K, n - base);
+    if (wave == 0)
+      walk_block<T, K>([&](int r, int cc) { return G[(base + r) * n + base + cc]; }, base, cnt, blk, sc, rp, hdr, As,
+                       Bs, flags, Rv, test_hooks, band_lo, band_hi, st);
+    __syncthreads();
+    const int p = hdr->p[blk & 1];
+    if (p == 0) continue;                  // the same for every thread: nothing to flush
+    gather_small<T, K>(hdr, As, Bs, ASm, BSm, base, p);
+    __syncthreads();
+    if (p <= 8) recur_all_stream<T, K, 8>(hdr, G, Am, Bm, ASm, BSm, n, np, p);
+    else if (p <= 16) recur_all_stream<T, K, (K >= 16 ? 16 : 8)>(hdr, G, Am, Bm, ASm, BSm, n, np, p);
+    else recur_all_stream<T, K, (K >= 32 ? 32 : 8)>(hdr, G, Am, Bm, ASm, BSm, n, np, p);
+    __syncthreads();
+    flush_global<T, K, 8>(G, Am, Bm, n, np, p);
+    __syncthreads();
+  }
+
+  double* x = a.x + (long)c * L * n;
+  for (int j = tid; j < n; j += 256) {
+    const bool acc = flags[j] != 0;
+    if (acc) x[s * n + j] = x[s * n + j] + sc[j].d;
+    if (a.log_margin) {
+      const long o = (long)c * L * n + s * n + j;
+      a.log_margin[o] = (float)(log(sc[j].u) - log(Rv[j]));
+      a.log_accept[o] = (uint8_t)acc;
+    }
+  }
+  if (tid == 0) {
+    a.logdet[c] += st.logr;
+    int64_t* cnt = a.counters + (long)c * N_COUNTERS;
+    cnt[CNT_LOCAL_P] += n;
+    cnt[CNT_LOCAL_A] += st.nacc;
+    if (a.replay_counts) {
+      a.replay_counts[2 * c] += st.counts[0];
+      a.replay_counts[2 * c + 1] += st.counts[1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static const size_t kMaxLds = 160 * 1024;
+
+// tile-grid classes of the register form: N <= 16 * NT.  Beyond N = 144 the
+// tiles plus the working registers exceed the register file, and the
+// streamed form takes over.
+static int reg_class(int n, int precision) {
+  (void)precision;
+  const int nt = pad16(n) / 16;
+  if (nt <= 4) return 4;
+  if (nt <= 7) return 7;
+  if (nt <= 9) return 9;
+  return 0;
+}
+
+template <typename T, int K>
+static size_t lds_t(int n, bool regs) {
+  return regs ? RegLds<T, K>::total(n) : StreamLds<T, K>::total(n);
+}
+
+static bool use_regs(int n, int precision, int kd) {
+  if (kd != 16 && kd != 32) return false;
+  if (!reg_class(n, precision)) return false;
+  const size_t b = precision ? (kd == 16 ? lds_t<float, 16>(n, true) : lds_t<float, 32>(n, true))
+                             : (kd == 16 ? lds_t<double, 16>(n, true) : lds_t<double, 32>(n, true));
+  return b <= kMaxLds;
 }
 
 size_t local_lds_bytes(int n, int precision, int nt, int kd) {
   (void)nt;
-  if (kd == 8) return lds_for<8>(n, precision);
-  if (kd == 16) return lds_for<16>(n, precision);
-  return lds_for<32>(n, precision);
+  const bool r = use_regs(n, precision, kd);
+  if (precision) return kd == 8 ? lds_t<float, 8>(n, r) : kd == 16 ? lds_t<float, 16>(n, r) : lds_t<float, 32>(n, r);
+  return kd == 8 ? lds_t<double, 8>(n, r) : kd == 16 ? lds_t<double, 16>(n, r) : lds_t<double, 32>(n, r);
 }
 
 bool local_supported(int n, int precision, int nt, int kd) {
-  (void)nt;
   if (n < 1 || n > 256 || (kd != 8 && kd != 16 && kd != 32)) return false;
-  if (!precision && kd == 32 && n > 64) return false;   // FP64, 3-4 rows per lane: at most 16 columns in registers
-  return local_lds_bytes(n, precision, 256, kd) <= 160 * 1024;
+  return local_lds_bytes(n, precision, nt, kd) <= kMaxLds;
 }
 
-template <typename T, int KD, int RPL>
-static hipError_t launch_local_t(const LocalArgs& a, int chains, hipStream_t s) {
-  const size_t lds = local_lds_size<T, KD>(a.n);
-  hipLaunchKernelGGL((local_slice_kernel<T, KD, RPL>), dim3(chains), dim3(256), lds, s, a);
+bool local_g_in_lds(int n, int precision, int kd) { return use_regs(n, precision, kd); }
+
+template <typename T, int K, int NT>
+static hipError_t launch_regs(const LocalArgs& a, int chains, hipStream_t s) {
+  const size_t lds = RegLds<T, K>::total(a.n);
+  hipLaunchKernelGGL((local_regs_kernel<T, K, NT>), dim3(chains), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
-template <typename T, int KD>
-static hipError_t launch_local_k(const LocalArgs& a, int chains, hipStream_t s) {
-  if (a.n <= 64) return launch_local_t<T, KD, 1>(a, chains, s);
-  if constexpr (sizeof(T) == 8 && KD == 32) {
-    return hipErrorInvalidValue;
-  } else {
-    if (a.n <= 192) return launch_local_t<T, KD, 3>(a, chains, s);
-    return launch_local_t<T, KD, 4>(a, chains, s);
+template <typename T, int K>
+static hipError_t launch_k(const LocalArgs& a, int precision, int chains, hipStream_t s) {
+  if constexpr (K == 16 || K == 32) {
+    if (use_regs(a.n, precision, K)) {
+      switch (reg_class(a.n, precision)) {
+        case 4: return launch_regs<T, K, 4>(a, chains, s);
+        case 7: return launch_regs<T, K, 7>(a, chains, s);
+        case 9: return launch_regs<T, K, 9>(a, chains, s);
+        default: break;
+      }
+      return hipErrorInvalidValue;
+    }
   }
+  const size_t lds = StreamLds<T, K>::total(a.n);
+  hipLaunchKernelGGL((local_stream_kernel<T, K>), dim3(chains), dim3(256), lds, s, a);
+  return hipGetLastError();
 }
 
-template <typename T, int KD>
-static hipError_t allow_lds_k() {
+template <typename F>
+static hipError_t allow(F* f) {
+  return hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+}
+
+template <typename T>
+static hipError_t allow_all_t() {
   hipError_t e = hipSuccess, x;
-  x = hipFuncSetAttribute((const void*)local_slice_kernel<T, KD, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          160 * 1024);
+#define HQ_ALLOW(...)                  \
+  x = allow(__VA_ARGS__);              \
   if (x != hipSuccess) e = x;
-  if constexpr (!(sizeof(T) == 8 && KD == 32)) {
-    x = hipFuncSetAttribute((const void*)local_slice_kernel<T, KD, 3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-    if (x != hipSuccess) e = x;
-    x = hipFuncSetAttribute((const void*)local_slice_kernel<T, KD, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-    if (x != hipSuccess) e = x;
-  }
+  HQ_ALLOW(local_stream_kernel<T, 8>);
+  HQ_ALLOW(local_stream_kernel<T, 16>);
+  HQ_ALLOW(local_stream_kernel<T, 32>);
+  HQ_ALLOW(local_regs_kernel<T, 16, 4>);
+  HQ_ALLOW(local_regs_kernel<T, 16, 7>);
+  HQ_ALLOW(local_regs_kernel<T, 16, 9>);
+  HQ_ALLOW(local_regs_kernel<T, 32, 4>);
+  HQ_ALLOW(local_regs_kernel<T, 32, 7>);
+  HQ_ALLOW(local_regs_kernel<T, 32, 9>);
+#undef HQ_ALLOW
   return e;
 }
 
 // raise the dynamic-LDS limit of every instantiation once, before any capture
 hipError_t prepare_local() {
-  hipError_t e = hipSuccess;
-  const hipError_t all[] = {allow_lds_k<double, 8>(), allow_lds_k<double, 16>(), allow_lds_k<double, 32>(),
-                            allow_lds_k<float, 8>(), allow_lds_k<float, 16>(), allow_lds_k<float, 32>()};
-  for (hipError_t x : all)
-    if (x != hipSuccess) e = x;
-  return e;
+  const hipError_t e1 = allow_all_t<double>();
+  const hipError_t e2 = allow_all_t<float>();
+  return e1 != hipSuccess ? e1 : e2;
 }
 
 hipError_t launch_local(const LocalArgs& a, int precision, int nt, int kd, int chains, hipStream_t s) {
   if (!local_supported(a.n, precision, nt, kd)) return hipErrorInvalidValue;
   if (precision) {
-    if (kd == 8) return launch_local_k<float, 8>(a, chains, s);
-    if (kd == 16) return launch_local_k<float, 16>(a, chains, s);
-    return launch_local_k<float, 32>(a, chains, s);
+    if (kd == 8) return launch_k<float, 8>(a, precision, chains, s);
+    if (kd == 16) return launch_k<float, 16>(a, precision, chains, s);
+    return launch_k<float, 32>(a, precision, chains, s);
   }
-  if (kd == 8) return launch_local_k<double, 8>(a, chains, s);
-  if (kd == 16) return launch_local_k<double, 16>(a, chains, s);
-  return launch_local_k<double, 32>(a, chains, s);
+  if (kd == 8) return launch_k<double, 8>(a, precision, chains, s);
+  if (kd == 16) return launch_k<double, 16>(a, precision, chains, s);
+  return launch_k<double, 32>(a, precision, chains, s);
 }
 
 }  // namespace hq

@@ -63,7 +63,7 @@ def holstein_8x8_batched_global():
 def holstein_12x12_mixed(precision=1):
     return Workload("holstein-12x12-L120-%s-128chains" % ("mixed" if precision else "fp64"), 3,
                     [Lattice(nx=12, n_chains=128, g=1.5, beta=12.0, n_stab=10)],
-                    precision=precision, delay=32)
+                    precision=precision)
 
 
 def holstein_uneven_batch():
