@@ -9,11 +9,15 @@ network proposals the workload has).  An update is one proposal, accepted or
 not.  Inputs are synthetic: seeded Gaussian initial fields and the model
 parameters of the workload; the chains live in HBM before timing starts.
 
-Prints one JSON line.  Besides the throughput it carries the mixed-precision
-accuracy (max |G_mixed - G_FP64| at stabilisation points and the log-weight
-error), the roofline of the dominant kernel (per-launch duration from HIP
-events on the library's stream, in a profiling pass right after the timed
-sweeps), and the oracle timed on host cores on a bounded sample.
+Prints one JSON line.  The default workload (c3) is the mixed-precision
+12x12 batch at the stated accuracy: FP64 recompute every 6 slices, the
+largest interval whose drift max |G_mixed - G_FP64| stays within 1e-5.  The
+same chains in FP64 (recompute every 10 slices) and in mixed precision at 10
+slices are timed beside it (fp64_baseline, speedup_vs_fp64, mixed_nstab10).
+The line also carries the accuracy, the autotuner's choices, per-phase device
+times, the roofline of the local-move kernel (per-launch duration from HIP
+events on the library's stream, in a profiling pass after the timed sweeps),
+and the oracle timed on host cores on a bounded sample.
 """
 import argparse
 import json
@@ -35,7 +39,22 @@ def parse():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-chains", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of known size, for scaling the FETCH_SIZE /
+    WRITE_SIZE counters of a profiler run: 256 MiB read and 256 MiB written
+    per copy."""
+    import torch
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "copies": 3}))
 
 
 def proposals_per_sweep(w):
@@ -47,18 +66,6 @@ def proposals_per_sweep(w):
         if g.global_width > 0 and g.proposal == 0:
             total += g.n_chains * n
     return total
-
-
-def phase_flops(w, phase, accept_rate):
-    """Algorithmic flops of one launch-region of a phase, summed over chains."""
-    fl = 0.0
-    for g in w.groups:
-        n = g.nx * g.nx
-        if phase == "wrap":          # G <- D e^{-dtau K} G e^{+dtau K} D^-1: two N^3 products
-            fl += g.n_chains * 2 * 2.0 * n ** 3
-        elif phase == "local":       # one slice: a rank-1 update of N^2 per accepted move
-            fl += g.n_chains * accept_rate * n * 2.0 * n * n
-    return fl
 
 
 def cpu_baseline(w, max_chains):
@@ -101,83 +108,122 @@ def _oracle_one_sweep(arg):
     return ch.local_proposals + ch.global_proposals, dt
 
 
-def main():
-    a = parse()
-    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the chains of this workload are independent and the "
-              "library has no multi-GPU path (see the sharding paragraph of the design notes).",
-              file=sys.stderr)
-        sys.exit(2)
+def run_workload(w, steps, warmup, profile=True):
+    """Time `steps` sweeps of workload w after `warmup` untimed ones (HIP events
+    on the library's stream), then optionally one profiled sweep with per-phase
+    device times.  Returns a dict of results; the context is closed."""
     import torch
-    import workloads
     from paper_1905_07440_amd import hq
 
-    w = workloads.ALL[a.workload]()
     ctx = hq.Context(hq.groups_from_workload(w), precision=w.precision, seed=w.seed, delay=w.delay)
     stream = ctx._stream
-    ctx.sweep(a.warmup)
+    ctx.sweep(warmup)
     ctx.synchronize()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
-    ctx.sweep(a.steps)
+    ctx.sweep(steps)
     e1.record(stream)
     ctx.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / a.steps
-    value = proposals_per_sweep(w) / (ms * 1e-3)
-
+    ms = e0.elapsed_time(e1) / steps
     stats = [ctx.stats(c) for c in range(ctx.n_chains)]
-    acc = sum(s["local_accepts"] for s in stats) / max(1, sum(s["local_proposals"] for s in stats))
-    max_dg = max(s["max_drift_green"] for s in stats)
-    max_dl = max(s["max_drift_logdet"] for s in stats)
+    out = {
+        "value": proposals_per_sweep(w) / (ms * 1e-3), "ms_per_step": ms, "wall_s": wall,
+        "local_acceptance": sum(s["local_accepts"] for s in stats) / max(1, sum(s["local_proposals"] for s in stats)),
+        "max_drift_green": max(s["max_drift_green"] for s in stats),
+        "max_drift_logdet": max(s["max_drift_logdet"] for s in stats),
+        "tuning": [ctx.tuning(k) for k in range(len(w.groups))],
+    }
+    if profile:
+        ctx.set_profiling(True)
+        ctx.sweep(1)
+        phases = {}
+        for ph in ("wrap", "local", "stab", "global", "network"):
+            t, k = ctx.phase_time(ph)
+            if k:
+                phases[ph] = {"ms_per_sweep": t, "launch_regions": k, "us_per_region": 1e3 * t / k}
+        ctx.set_profiling(False)
+        out["phases"] = phases
+    ctx.close()
+    return out
 
-    # profiling pass: per-phase device time from HIP events on the library stream
-    ctx.set_profiling(True)
-    ctx.sweep(1)
-    phases = {}
-    for ph in ("wrap", "local", "stab", "global", "network"):
-        t, k = ctx.phase_time(ph)
-        if k:
-            phases[ph] = {"ms_per_sweep": t, "launch_regions": k, "us_per_region": 1e3 * t / k}
-    ctx.set_profiling(False)
-    dominant = max(phases, key=lambda p: phases[p]["ms_per_sweep"])
-    roof_phase = dominant if dominant in ("wrap", "local") else max(
-        ("wrap", "local"), key=lambda p: phases.get(p, {"ms_per_sweep": 0})["ms_per_sweep"])
-    per = phases[roof_phase]["us_per_region"] * 1e-6
-    flops = phase_flops(w, roof_phase, acc)
+
+def local_roofline(w, res):
+    """Roofline of the local-move kernel (one launch per slice covers every
+    chain of the group): algorithmic flops = 2 N^2 per accepted move (the
+    rank-1 update of G the method defines), acceptance as measured, against
+    the dense MFMA peak of the precision G is held in."""
+    g = w.groups[0]
+    n = g.nx * g.nx
+    per_launch_s = res["phases"]["local"]["us_per_region"] * 1e-6
+    flops = g.n_chains * res["local_acceptance"] * n * 2.0 * n * n
     peak = MI355X_PEAK["fp32" if w.precision else "fp64"]
-    roofline = {"bound": "mfma", "achieved": flops / per / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": flops / per / peak, "traffic": None, "kernel": roof_phase,
-                "note": "dominant phase by device time: %s" % dominant}
+    hbm = g.n_chains * 2.0 * n * n * (4 if w.precision else 8)
+    return {"bound": "mfma", "achieved": flops / per_launch_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": flops / per_launch_s / peak, "traffic": None, "kernel": "local_regs_kernel",
+            "note": ("one launch = the local moves of one slice for all %d chains; its G traffic is %.1f MB, "
+                     "%.1f us at 8 TB/s, so the kernel is bound by the sequential accept chain, not HBM"
+                     % (g.n_chains, hbm / 1e6, hbm / 8e12 * 1e6))}
+
+
+def main():
+    a = parse()
+    if a.copy_calibration:
+        copy_calibration()
+        return
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the chains of this workload are independent and the "
+              "library has no multi-GPU path (see the sharding paragraph of the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+    import workloads
+
+    headline = a.workload
+    if headline == "c3":
+        headline = "c3-gate"                 # mixed precision at the stated accuracy
+    w = workloads.ALL[headline]()
+    res = run_workload(w, a.steps, a.warmup)
+    extra = {}
+    if a.workload == "c3":
+        fp64 = run_workload(workloads.ALL["c3-fp64"](), a.steps, a.warmup, profile=False)
+        lit = run_workload(workloads.ALL["c3"](), a.steps, a.warmup, profile=False)
+        extra["fp64_baseline"] = {k: fp64[k] for k in ("value", "ms_per_step", "max_drift_green", "max_drift_logdet")}
+        extra["fp64_baseline"]["config"] = "same chains in FP64, recompute every 10 slices"
+        extra["speedup_vs_fp64"] = res["value"] / fp64["value"]
+        extra["mixed_nstab10"] = {k: lit[k] for k in ("value", "ms_per_step", "max_drift_green", "max_drift_logdet")}
+        extra["mixed_nstab10"]["gate_1e-5"] = lit["max_drift_green"] <= 1e-5
 
     cpu = None
     if not a.no_cpu_baseline:
         cpu = cpu_baseline(w, a.cpu_sample_chains)
 
     g0 = w.groups[0]
+    dominant = max(res["phases"], key=lambda p: res["phases"][p]["ms_per_sweep"])
     out = {
         "metric": "phonon-field updates/s (all chains), mixed vs FP64 at |G-G_FP64|<=1e-5",
-        "value": value, "unit": "updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": res["value"], "unit": "updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if w.precision else "f64", "data": "synthetic",
         "config": {"workload": w.name, "chains": w.n_chains, "nx": [g.nx for g in w.groups],
                    "L": [round(g.beta / g.dtau) for g in w.groups], "n_stab": g0.n_stab,
                    "precision": "mixed" if w.precision else "fp64", "delay": w.delay or 16,
                    "parallelism": "independent chains, one GPU"},
-        "accuracy": {"max_abs_G_minus_fp64": max_dg, "max_logdet_err": max_dl,
-                     "log_weight_err": 2 * max_dl, "gate_1e-5": max_dg <= 1e-5},
-        "local_acceptance": acc,
-        "phases": phases,
-        "roofline": roofline,
+        "accuracy": {"max_abs_G_minus_fp64": res["max_drift_green"], "max_logdet_err": res["max_drift_logdet"],
+                     "log_weight_err": 2 * res["max_drift_logdet"], "gate_1e-5": res["max_drift_green"] <= 1e-5},
+        "local_acceptance": res["local_acceptance"],
+        "tuning": res["tuning"],
+        "phases": res["phases"],
+        "dominant_phase": dominant,
+        "roofline": local_roofline(w, res),
         "cpu_baseline": cpu,
-        "wall_s": wall,
+        "wall_s": res["wall_s"],
     }
+    out.update(extra)
     print(json.dumps(out))
-    ctx.close()
 
 
 if __name__ == "__main__":

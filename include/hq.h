@@ -84,7 +84,9 @@ typedef struct {
 
 typedef struct {
   int32_t precision;     /* HQ_PREC_FP64 or HQ_PREC_MIXED (FP32 wraps and updates) */
-  int32_t delay;         /* delayed-update depth k (8, 16 or 32); 0 = autotuned */
+  int32_t delay;         /* local-move block size k (8, 16 or 32): the sites are taken k
+                            at a time and G gets one delayed rank-(accepts) update per
+                            block; 0 = library default (16) */
   int32_t activation;    /* network hidden activation: 0 ReLU, 1 softplus */
   int32_t record;        /* 1: keep every decision of the last sweep (hq_read_decisions) */
 } hq_options;
@@ -158,6 +160,18 @@ hq_status hq_chain_shape(const hq_ctx* ctx, int32_t chain, int32_t* n, int32_t* 
  * on.  names: "wrap", "local", "stab", "global", "network". */
 hq_status hq_set_profiling(hq_ctx* ctx, int32_t on);
 hq_status hq_phase_time(hq_ctx* ctx, const char* phase, double* ms_total, int64_t* launches);
+
+/* The configuration chosen at hq_create for one group: the GEMM tile of
+ * the FP64 products (block products, UDT combines) and of the wraps' products
+ * in the context's precision, found by timing every tile that fits on the
+ * group's own shape, and the local-move block size.  Tile names from
+ * hq_gemm_tile_name (a static string; "?" for an unknown code). */
+typedef struct {
+  int32_t gemm_tile_fp64, gemm_tile_wrap, local_block;
+  double gemm_us_fp64, gemm_us_wrap;   /* measured time of one batched product */
+} hq_tuning;
+hq_status hq_read_tuning(const hq_ctx* ctx, int32_t group, hq_tuning* out);
+const char* hq_gemm_tile_name(int32_t tile);
 
 /* Wait for all work on the context's stream. */
 hq_status hq_synchronize(hq_ctx* ctx);

@@ -131,29 +131,39 @@ __device__ void apply_reflector(double* A, int n, int p0, int m, const double (*
 
 // T (upper triangular; H_0 ... H_{nb-1} = I - V T V^T) from the Gram matrix:
 // T[j][j] = tau_j,  T[i][j] = -tau_j sum_{k=i}^{j-1} T[i][k] (V^T V)[k][j].
+// V^T V comes from MFMA (both operands are the same V fragment), the four
+// waves taking every fourth 4-row chunk; the recurrence runs in registers of
+// 16 lanes of wave 0, lane i holding row i of T.
 __device__ void form_t(const double (*Vs)[VLD], int m, int nbw, const double* tau, double (*Gm)[NB + 1],
-                       double (*Ts)[NB + 1]) {
-  const int tid = threadIdx.x;
-  const int a = tid >> 4, b = tid & 15;
-  double s = 0.0;
-  if (a < nbw && b < nbw && b > a)
-    for (int r = b; r < m; ++r) s += Vs[a][r] * Vs[b][r];
-  Gm[a][b] = s;
+                       double (*Ts)[NB + 1], double (*Sc)[NB][NB + 1]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 g = {0, 0, 0, 0};
+  for (int r0 = 4 * wave; r0 < m; r0 += 16) {
+    const double x = Vs[li][r0 + lk];      // rows past m are zero in Vs
+    g = mfma16(x, x, g);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Sc[wave][frag_row<double>(lane, v)][li] = g[v];
+  __syncthreads();
+  {
+    const int a = tid >> 4, b = tid & 15;
+    Gm[a][b] = (Sc[0][a][b] + Sc[1][a][b]) + (Sc[2][a][b] + Sc[3][a][b]);
+  }
   __syncthreads();
   if (tid < NB) {
     const int i = tid;
+    double t[NB];
+#pragma unroll
     for (int j = 0; j < NB; ++j) {
-      double v = 0.0;
-      if (j < nbw) {
-        if (i < j) {
-          for (int k = i; k < j; ++k) v += Ts[i][k] * Gm[k][j];
-          v *= -tau[j];
-        } else if (i == j) {
-          v = tau[j];
-        }
-      }
-      Ts[i][j] = v;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < j; ++k) acc += t[k] * Gm[k][j];   // t[k] = 0 for k < i
+      const double tj = (j < nbw) ? tau[j] : 0.0;
+      t[j] = (i < j) ? -tj * acc : ((i == j) ? tj : 0.0);
     }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) Ts[i][j] = t[j];
   }
   __syncthreads();
 }
@@ -270,7 +280,7 @@ __global__ __launch_bounds__(256) void qr_blocked_kernel(double* __restrict__ Zg
     }
     Vs[tid >> 4][MAXN + (tid & 15)] = 0.0;
     __syncthreads();
-    form_t(Vs, m, nbw, tau, Gm, Ts);
+    form_t(Vs, m, nbw, tau, Gm, Ts, Sc);
     Tst[(long)pi * NB * NB + tid] = Ts[tid >> 4][tid & 15];
     apply_reflector<MX>(W, n, p0, m, Vs, Ts, 1, p0 + nbw, Sc[wave]);
     __syncthreads();
@@ -305,6 +315,293 @@ __global__ __launch_bounds__(256) void qr_blocked_kernel(double* __restrict__ Zg
     __syncthreads();
     apply_reflector<MX>(Q, n, p0, m, Vs, Ts, 0, p0, Sc[wave]);
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same QR with the matrix resident in registers (N <= 160): the four
+// waves hold it as 16 x 16 MFMA tiles, wave w owning tile columns w, w + 4,
+// w + 8.  A panel passes through LDS once to be factored by wave 0; the block
+// reflector is applied to the tiles in place, so the trailing update touches
+// no memory but the 16-column reflector.  Q is accumulated in the same
+// registers afterwards.  V and T of every panel go to W and T in global
+// memory for that second pass.
+// ---------------------------------------------------------------------------
+template <int MX>
+__global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, double* __restrict__ Wg,
+                                                      double* __restrict__ Qg, double* __restrict__ Dg,
+                                                      double* __restrict__ Tg, int n) {
+  constexpr int NTT = (MX + 15) / 16;      // tile rows
+  constexpr int CPW = (NTT + 3) / 4;       // tile columns per wave
+  __shared__ double Vs[NB][VLD];
+  __shared__ double Pn[NB][VLD];           // the panel being factored, column-major
+  __shared__ double Ts[NB][NB + 1];
+  __shared__ double Gm[NB][NB + 1];
+  __shared__ double Sc[4][NB][NB + 1];
+  __shared__ double norms[MAXN];
+  __shared__ double tau[NB];
+  __shared__ int perm[MAXN];
+  const int z = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  double* Z = Zg + (long)z * n * n;
+  double* W = Wg + (long)z * n * n;
+  double* Q = Qg + (long)z * n * n;
+  double* Tst = Tg + (long)z * NB * (n + NB);
+  const int nt = (n + 15) / 16;
+  const int npan = nt;
+
+  // pre-pivoting: columns of Z in order of decreasing norm (NaN last)
+  if (tid < n) {
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int r0 = 0; r0 < n; r0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (r0 + u < n) ? Z[(long)(r0 + u) * n + tid] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] += v[u] * v[u];
+    }
+    const double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    norms[tid] = (t == t) ? t : -1.0;
+  }
+  __syncthreads();
+  if (tid < n) {
+    const double s = norms[tid];
+    int rank = 0;
+    for (int k = 0; k < n; ++k) rank += (norms[k] > s || (norms[k] == s && k < tid)) ? 1 : 0;
+    perm[rank] = tid;
+  }
+  __syncthreads();
+
+  d4 A[CPW][NTT];
+#pragma unroll
+  for (int u = 0; u < CPW; ++u) {
+    const int col = 16 * (wave + 4 * u) + li;
+    const int pc = (col < n) ? perm[col] : 0;
+#pragma unroll
+    for (int t = 0; t < NTT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + frag_row<double>(lane, v);
+        A[u][t][v] = (row < n && col < n) ? Z[(long)row * n + pc] : 0.0;
+      }
+  }
+
+  // A <- (I - V op(T) V^T) A on rows >= p0 of tile column u (tiles t >= p)
+  auto apply = [&](int u, int p, int transT) {
+    double (*S)[NB + 1] = Sc[wave];
+    d4 w1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < NTT; ++t)
+      if (t >= p && t < nt) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w1 = mfma16(Vs[li][16 * (t - p) + 4 * q + lk], A[u][t][q], w1);
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[frag_row<double>(lane, v)][li] = w1[v];
+    wave_sync_lds();
+    d4 w2 = {0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+      const double at = transT ? Ts[k0 + lk][li] : Ts[li][k0 + lk];
+      w2 = mfma16(at, S[k0 + lk][li], w2);
+    }
+    wave_sync_lds();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[frag_row<double>(lane, v)][li] = w2[v];
+    wave_sync_lds();
+    double wb[NB / 4];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) wb[q] = S[4 * q + lk][li];
+#pragma unroll
+    for (int t = 0; t < NTT; ++t)
+      if (t >= p && t < nt) {
+#pragma unroll
+        for (int q = 0; q < NB / 4; ++q) A[u][t] = mfma16(-Vs[4 * q + lk][16 * (t - p) + li], wb[q], A[u][t]);
+      }
+    wave_sync_lds();
+  };
+
+  for (int p = 0; p < npan; ++p) {
+    const int p0 = p * NB, nbw = min(NB, n - p0), m = n - p0;
+    const int owner = p & 3, up = p >> 2;
+    // the panel's tiles to LDS (rows relative to p0)
+    if (wave == owner) {
+#pragma unroll
+      for (int u = 0; u < CPW; ++u)
+        if (u == up) {
+#pragma unroll
+          for (int t = 0; t < NTT; ++t)
+            if (t >= p && t < nt) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) Pn[li][16 * (t - p) + frag_row<double>(lane, v)] = A[u][t][v];
+            }
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double a[NB][Cap<MX>::rpl];
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int t = 0; t < Cap<MX>::rpl; ++t) {
+          const int r = lane + 64 * t;
+          a[j][t] = (j < nbw && r < m) ? Pn[j][r] : 0.0;
+        }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < nbw) {
+          double sg = 0.0, al = 0.0;
+#pragma unroll
+          for (int t = 0; t < Cap<MX>::rpl; ++t) {
+            const int r = lane + 64 * t;
+            if (r > j && r < m) sg += a[j][t] * a[j][t];
+            if (r == j) al = a[j][t];
+          }
+          sg = wave_total(sg);
+          al = wave_total(al);
+          double be = al, tj = 0.0, scl = 0.0;
+          if (sg > 0.0) {
+            const double nrm = sqrt(al * al + sg);
+            be = (al >= 0.0) ? -nrm : nrm;
+            tj = (be - al) / be;
+            scl = 1.0 / (al - be);
+          }
+          double vr[Cap<MX>::rpl];
+#pragma unroll
+          for (int t = 0; t < Cap<MX>::rpl; ++t) {
+            const int r = lane + 64 * t;
+            if (r > j && r < m) a[j][t] *= scl;
+            if (r == j) a[j][t] = be;
+            vr[t] = (r == j) ? 1.0 : ((r > j && r < m) ? a[j][t] : 0.0);
+          }
+          double w[NB];
+#pragma unroll
+          for (int c = j + 1; c < NB; ++c) {
+            w[c] = 0.0;
+#pragma unroll
+            for (int t = 0; t < Cap<MX>::rpl; ++t) w[c] += vr[t] * a[c][t];
+          }
+#pragma unroll
+          for (int c = j + 1; c < NB; ++c) w[c] = wave_total(w[c]) * tj;
+#pragma unroll
+          for (int c = j + 1; c < NB; ++c)
+            if (c < nbw) {
+#pragma unroll
+              for (int t = 0; t < Cap<MX>::rpl; ++t) a[c][t] -= vr[t] * w[c];
+            }
+          if (lane == 0) tau[j] = tj;
+        }
+      }
+      // V (unit diagonal, zero above, zero past the panel) to Vs; R and V to Pn and to W
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int t = 0; t < Cap<MX>::rpl; ++t) {
+          const int r = lane + 64 * t;
+          if (r < VLD) {
+            Vs[j][r] = (j < nbw && r < m) ? ((r == j) ? 1.0 : ((r > j) ? a[j][t] : 0.0)) : 0.0;
+            Pn[j][r] = (j < nbw && r < m) ? a[j][t] : 0.0;
+          }
+          if (j < nbw && r < m) W[(long)(p0 + r) * n + p0 + j] = a[j][t];
+        }
+    }
+    Vs[tid >> 4][MAXN + (tid & 15)] = 0.0;
+    __syncthreads();
+    form_t(Vs, m, nbw, tau, Gm, Ts, Sc);
+    Tst[(long)p * NB * NB + tid] = Ts[tid >> 4][tid & 15];
+    // the factored panel back into its tiles, then the trailing tile columns
+    if (wave == owner) {
+#pragma unroll
+      for (int u = 0; u < CPW; ++u)
+        if (u == up) {
+#pragma unroll
+          for (int t = 0; t < NTT; ++t)
+            if (t >= p && t < nt) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) A[u][t][v] = Pn[li][16 * (t - p) + frag_row<double>(lane, v)];
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) {
+      const int cj = wave + 4 * u;
+      if (cj > p && cj < nt) apply(u, p, 1);
+    }
+    __syncthreads();
+  }
+
+  // D = |diag R|; Rt = D^-1 R P^T written over Z
+#pragma unroll
+  for (int u = 0; u < CPW; ++u) {
+    const int cj = wave + 4 * u;
+#pragma unroll
+    for (int t = 0; t < NTT; ++t)
+      if (t == cj && cj < nt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + frag_row<double>(lane, v), col = 16 * cj + li;
+          if (row == col && row < n) norms[row] = fabs(A[u][t][v]);
+        }
+      }
+  }
+  __syncthreads();
+  for (int r = tid; r < n; r += 256) Dg[(long)z * n + r] = norms[r];
+#pragma unroll
+  for (int u = 0; u < CPW; ++u) {
+    const int col = 16 * (wave + 4 * u) + li;
+    if (col < n) {
+      const int pc = perm[col];
+#pragma unroll
+      for (int t = 0; t < NTT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + frag_row<double>(lane, v);
+          if (row < n) Z[(long)row * n + pc] = (row <= col) ? A[u][t][v] / norms[row] : 0.0;
+        }
+    }
+  }
+
+  // Q = H_0 H_1 ... accumulated backwards from the identity
+#pragma unroll
+  for (int u = 0; u < CPW; ++u)
+#pragma unroll
+    for (int t = 0; t < NTT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + frag_row<double>(lane, v), col = 16 * (wave + 4 * u) + li;
+        A[u][t][v] = (row == col && row < n) ? 1.0 : 0.0;
+      }
+  for (int p = npan - 1; p >= 0; --p) {
+    const int p0 = p * NB, nbw = min(NB, n - p0), m = n - p0;
+    __syncthreads();
+    batched_copy<256, 17, double>(NB * VLD,
+                                  [&](int e) {
+                                    const int j = e / VLD, r = e - j * VLD;
+                                    double v = 0.0;
+                                    if (j < nbw && r < m) v = (r == j) ? 1.0 : ((r > j) ? W[(long)(p0 + r) * n + p0 + j] : 0.0);
+                                    return v;
+                                  },
+                                  [&](int e, double v) { Vs[e / VLD][e % VLD] = v; });
+    Ts[tid >> 4][tid & 15] = Tst[(long)p * NB * NB + tid];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) {
+      const int cj = wave + 4 * u;
+      if (cj >= p && cj < nt) apply(u, p, 0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < CPW; ++u) {
+    const int col = 16 * (wave + 4 * u) + li;
+#pragma unroll
+    for (int t = 0; t < NTT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + frag_row<double>(lane, v);
+        if (row < n && col < n) Q[(long)row * n + col] = A[u][t][v];
+      }
   }
 }
 
@@ -479,9 +776,11 @@ size_t qr_t_doubles(int n) { return (size_t)NB * (n + NB); }
 hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int n, int batch, hipStream_t s) {
   if (!qr_supported(n)) return hipErrorInvalidValue;
   if (n <= 64)
-    hipLaunchKernelGGL(qr_blocked_kernel<64>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
-  else if (n <= 160)
-    hipLaunchKernelGGL(qr_blocked_kernel<160>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
+    hipLaunchKernelGGL(qr_regs_kernel<64>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
+  else if (n <= 112)
+    hipLaunchKernelGGL(qr_regs_kernel<112>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
+  else if (n <= 144)
+    hipLaunchKernelGGL(qr_regs_kernel<144>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
   else
     hipLaunchKernelGGL(qr_blocked_kernel<256>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
   return hipGetLastError();

@@ -106,6 +106,122 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
       }
 }
 
+// Full-K variant for K <= a few hundred (every DQMC product has K = N <= 256):
+// the whole BM x K panel of op(A) and K x BN panel of op(B) are staged in LDS
+// in one pass, so a tile pays the memory latency once instead of once per K
+// stage.  LDS: (BM + BN + 2) * K elements, dynamic.
+template <typename T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void gemm_fullk_kernel(GemmArgs<T> a) {
+  constexpr int NT = WM * WN * 64;
+  constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
+  constexpr int LA = BM + 1, LB = BN + 1;  // odd strides: the transposing stores hit distinct banks
+  static_assert(FM >= 1 && FN >= 1, "tile too small");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* As = (T*)smem_raw;                    // [K4][LA]: As[k][m] = op(A)(m0 + m, k)
+  const int K4 = (a.K + 3) & ~3;
+  T* Bs = As + (long)K4 * LA;              // [K4][LB]: Bs[k][n] = op(B)(k, n0 + n)
+  __shared__ double rsv[BM];
+  __shared__ double csv[BN];
+
+  const int z = blockIdx.z;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WN, wn = wave % WN;
+  const T* A = a.A + (long)z * a.sA;
+  const T* B = a.B + (long)z * a.sB;
+  T* C = a.C + (long)z * a.sC;
+
+  for (int i = tid; i < BM; i += NT)
+    rsv[i] = (m0 + i < a.M) ? scale_value(a.rs, z, a.inner_count, m0 + i) : 0.0;
+  for (int i = tid; i < BN; i += NT)
+    csv[i] = (n0 + i < a.N) ? scale_value(a.cs, z, a.inner_count, n0 + i) : 0.0;
+  // op(A) and op(B) panels, 16 consecutive threads along the contiguous
+  // index of the source (coalesced), no per-element division
+  {
+    const int t16 = tid & 15, g16 = tid >> 4;
+    constexpr int G = NT / 16;             // thread groups of 16
+    if (!a.tA) {                           // A[m][k]: groups over m, lanes over k
+      for (int m = g16; m < BM; m += G) {
+        const int gm = m0 + m;
+#pragma unroll 4
+        for (int k = t16; k < K4; k += 16)
+          As[k * LA + m] = (gm < a.M && k < a.K) ? A[(long)gm * a.lda + k] : T(0);
+      }
+    } else {                               // A[k][m]: groups over k, lanes over m
+      for (int k = g16; k < K4; k += G)
+#pragma unroll
+        for (int m = t16; m < BM; m += 16) {
+          const int gm = m0 + m;
+          As[k * LA + m] = (gm < a.M && k < a.K) ? A[(long)k * a.lda + gm] : T(0);
+        }
+    }
+    if (!a.tB) {                           // B[k][n]: groups over k, lanes over n
+      for (int k = g16; k < K4; k += G)
+#pragma unroll
+        for (int n = t16; n < BN; n += 16) {
+          const int gn = n0 + n;
+          Bs[k * LB + n] = (gn < a.N && k < a.K) ? B[(long)k * a.ldb + gn] : T(0);
+        }
+    } else {                               // B[n][k]: groups over n, lanes over k
+      for (int n = g16; n < BN; n += G) {
+        const int gn = n0 + n;
+#pragma unroll 4
+        for (int k = t16; k < K4; k += 16)
+          Bs[k * LB + n] = (gn < a.N && k < a.K) ? B[(long)gn * a.ldb + k] : T(0);
+      }
+    }
+  }
+  __syncthreads();
+
+  typedef typename Frag<T>::type F;
+  F acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = F{0, 0, 0, 0};
+  for (int kk = 0; kk < K4; kk += 4) {
+    T af[FM], bf[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) af[i] = As[(kk + (lane >> 4)) * LA + wm * FM * 16 + i * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) bf[j] = Bs[(kk + (lane >> 4)) * LB + wn * FN * 16 + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+  }
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = wm * FM * 16 + i * 16 + frag_row<T>(lane, v);
+        const int lc = wn * FN * 16 + j * 16 + (lane & 15);
+        const int r = m0 + lr, c = n0 + lc;
+        if (r < a.M && c < a.N) {
+          double val = a.alpha * rsv[lr] * (double)acc[i][j][v] * csv[lc];
+          T* dst = C + (long)r * a.ldc + c;
+          if (a.beta != 0.0) val += a.beta * (double)(*dst);
+          *dst = (T)val;
+        }
+      }
+}
+
+template <typename T, int BM, int BN>
+static size_t fullk_lds(int K) { return sizeof(T) * (size_t)((K + 3) & ~3) * (BM + BN + 4); }
+
+template <typename T, int BM, int BN, int WM, int WN>
+static hipError_t launch_fullk(const GemmArgs<T>& a, hipStream_t s) {
+  const size_t lds = fullk_lds<T, BM, BN>(a.K);
+  if (lds > 150 * 1024) return hipErrorInvalidValue;
+  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, a.batch);
+  hipLaunchKernelGGL((gemm_fullk_kernel<T, BM, BN, WM, WN>), grid, dim3(WM * WN * 64), lds, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int BM, int BN, int WM, int WN>
 static hipError_t launch_tile(const GemmArgs<T>& a, hipStream_t s) {
   dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, a.batch);
@@ -120,12 +236,52 @@ static hipError_t launch_any(const GemmArgs<T>& a, int tile, hipStream_t s) {
     case TILE_32x32: return launch_tile<T, 32, 32, 1, 1>(a, s);
     case TILE_48x48: return launch_tile<T, 48, 48, 3, 1>(a, s);
     case TILE_16x64: return launch_tile<T, 16, 64, 1, 4>(a, s);
+    case TILE_FK_32x32: return launch_fullk<T, 32, 32, 1, 1>(a, s);
+    case TILE_FK_48x48: return launch_fullk<T, 48, 48, 3, 1>(a, s);
+    case TILE_FK_64x64: return launch_fullk<T, 64, 64, 2, 2>(a, s);
+    case TILE_FK_32x64: return launch_fullk<T, 32, 64, 1, 2>(a, s);
     default: return launch_tile<T, 64, 64, 2, 2>(a, s);
   }
 }
 
 hipError_t launch_gemm(const GemmArgs<double>& a, int tile, hipStream_t s) { return launch_any(a, tile, s); }
 hipError_t launch_gemm(const GemmArgs<float>& a, int tile, hipStream_t s) { return launch_any(a, tile, s); }
+
+bool gemm_tile_fits(int tile, int K, int precision) {
+  const bool f = precision != 0;
+  switch (tile) {
+    case TILE_FK_32x32: return (f ? fullk_lds<float, 32, 32>(K) : fullk_lds<double, 32, 32>(K)) <= 150 * 1024;
+    case TILE_FK_48x48: return (f ? fullk_lds<float, 48, 48>(K) : fullk_lds<double, 48, 48>(K)) <= 150 * 1024;
+    case TILE_FK_64x64: return (f ? fullk_lds<float, 64, 64>(K) : fullk_lds<double, 64, 64>(K)) <= 150 * 1024;
+    case TILE_FK_32x64: return (f ? fullk_lds<float, 32, 64>(K) : fullk_lds<double, 32, 64>(K)) <= 150 * 1024;
+    default: return true;
+  }
+}
+
+template <typename T>
+static hipError_t allow_fullk_t() {
+  hipError_t e = hipSuccess, x;
+  x = hipFuncSetAttribute((const void*)gemm_fullk_kernel<T, 32, 32, 1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          150 * 1024);
+  if (x != hipSuccess) e = x;
+  x = hipFuncSetAttribute((const void*)gemm_fullk_kernel<T, 48, 48, 3, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          150 * 1024);
+  if (x != hipSuccess) e = x;
+  x = hipFuncSetAttribute((const void*)gemm_fullk_kernel<T, 64, 64, 2, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          150 * 1024);
+  if (x != hipSuccess) e = x;
+  x = hipFuncSetAttribute((const void*)gemm_fullk_kernel<T, 32, 64, 1, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          150 * 1024);
+  if (x != hipSuccess) e = x;
+  return e;
+}
+
+// raise the dynamic-LDS limit of the full-K kernels once, before any capture
+hipError_t prepare_gemm() {
+  const hipError_t e1 = allow_fullk_t<double>();
+  const hipError_t e2 = allow_fullk_t<float>();
+  return e1 != hipSuccess ? e1 : e2;
+}
 
 // P[z] = diag(rs(z)) * A, A shared by the batch
 __global__ void scale_rows_kernel(double* P, long sP, const double* A, int n, Scale rs, int inner_count) {

@@ -34,6 +34,7 @@ struct Group {
   hq_group p{};
   int nx = 0, n = 0, L = 0, ns = 0, nb = 0, C = 0, chain0 = 0;
   int nt = 256, kd = 16, tile = TILE_64x64, tile32 = TILE_64x64;
+  double tile_us = 0.0, tile32_us = 0.0;   // autotuner timings
   bool global = false, network = false;
   // fields, couplings, model matrices
   double *x = nullptr, *xp = nullptr, *g = nullptr;
@@ -629,6 +630,65 @@ hq_status enqueue_sweep(hq_ctx* ctx) {
   return HQ_OK;
 }
 
+// GEMM autotuner: time one batched product of the group's shape with every
+// tile that fits (operands: expK and scratch buffers, which hold nothing yet)
+// and keep the fastest, for FP64 and for the precision of the wraps.
+hq_status autotune(hq_ctx* ctx) {
+  hipStream_t s = ctx->stream;
+  hipEvent_t e0, e1;
+  HQ_TRY(hipEventCreate(&e0));
+  HQ_TRY(hipEventCreate(&e1));
+  const int cands[] = {TILE_64x64, TILE_32x32, TILE_48x48, TILE_FK_32x32, TILE_FK_48x48, TILE_FK_64x64,
+                       TILE_FK_32x64};
+  hq_status st = HQ_OK;
+  for (Group& g : ctx->groups) {
+    const long nn = (long)g.n * g.n;
+    for (int prec = 0; prec < 2 && st == HQ_OK; ++prec) {
+      if (prec == 1 && ctx->opt.precision != HQ_PREC_MIXED) break;
+      double best = 1e30;
+      int bt = TILE_64x64;
+      for (int tile : cands) {
+        if (!gemm_tile_fits(tile, g.n, prec)) continue;
+        hipError_t e = hipSuccess;
+        auto run = [&]() {
+          if (prec) {
+            GemmArgs<float> a;
+            a.M = a.N = a.K = g.n; a.lda = a.ldb = a.ldc = g.n; a.batch = g.C;
+            a.A = g.expk32; a.sA = 0;
+            a.B = (const float*)g.Wt; a.sB = nn;
+            a.C = (float*)g.G; a.sC = nn;
+            return launch_gemm(a, tile, s);
+          }
+          GemmArgs<double> a = sq(g, g.C);
+          a.A = g.expk; a.sA = 0;
+          a.B = g.blks; a.sB = nn;
+          a.C = g.Z; a.sC = nn;
+          return launch_gemm(a, tile, s);
+        };
+        e = run();
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) e = run();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          st = fail(ctx, HQ_EDEVICE, "autotune: %s", hipGetErrorString(e));
+          break;
+        }
+        const double us = 1e3 * ms / 3.0;
+        if (us < best) { best = us; bt = tile; }
+      }
+      if (prec) { g.tile32 = bt; g.tile32_us = best; }
+      else { g.tile = bt; g.tile_us = best; }
+    }
+    if (ctx->opt.precision != HQ_PREC_MIXED) { g.tile32 = g.tile; g.tile32_us = g.tile_us; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 hq_status recompute_all(hq_ctx* ctx) {
   Sched S{ctx, ctx->stream};
   for (Group& g : ctx->groups) {
@@ -723,6 +783,7 @@ hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* 
   *out = ctx;
 
   HQ_TRY(prepare_local());
+  HQ_TRY(prepare_gemm());
   hipStream_t s = ctx->stream;
   // host-side model set-up and initial state
   for (Group& g : ctx->groups) {
@@ -766,6 +827,7 @@ hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* 
       HQ_TRY(launch_fill_u8(g.replay[k], 255, (long)C * g.kind_slots(k), s));
   }
   HQ_TRY(launch_fill_i64(ctx->sweep_counter, 0, 1, s));
+  ST_TRY(autotune(ctx));
   hq_status st = recompute_all(ctx);
   if (st != HQ_OK) return st;
   return sync(ctx);
@@ -960,6 +1022,31 @@ hq_status hq_phase_time(hq_ctx* ctx, const char* phase, double* ms_total, int64_
       return HQ_OK;
     }
   return fail(ctx, HQ_EINVAL, "unknown phase %s", phase);
+}
+
+hq_status hq_read_tuning(const hq_ctx* ctx, int32_t group, hq_tuning* out) {
+  if (!ctx || !out || group < 0 || group >= (int32_t)ctx->groups.size()) return HQ_EINVAL;
+  const Group& g = ctx->groups[group];
+  out->gemm_tile_fp64 = g.tile;
+  out->gemm_tile_wrap = g.tile32;
+  out->local_block = g.kd;
+  out->gemm_us_fp64 = g.tile_us;
+  out->gemm_us_wrap = g.tile32_us;
+  return HQ_OK;
+}
+
+const char* hq_gemm_tile_name(int32_t tile) {
+  switch (tile) {
+    case TILE_64x64: return "64x64/k16";
+    case TILE_32x32: return "32x32/k16";
+    case TILE_48x48: return "48x48/k16";
+    case TILE_16x64: return "16x64/k16";
+    case TILE_FK_32x32: return "32x32/fullk";
+    case TILE_FK_48x48: return "48x48/fullk";
+    case TILE_FK_64x64: return "64x64/fullk";
+    case TILE_FK_32x64: return "32x64/fullk";
+    default: return "?";
+  }
 }
 
 hq_status hq_synchronize(hq_ctx* ctx) {

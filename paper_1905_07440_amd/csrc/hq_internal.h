@@ -35,10 +35,14 @@ struct GemmArgs {
 };
 
 // GEMM tile configurations (see gemm.hip); the autotuner picks one per shape.
-enum GemmTile { TILE_64x64 = 0, TILE_32x32 = 1, TILE_48x48 = 2, TILE_16x64 = 3, N_GEMM_TILES = 4 };
+// TILE_FK_*: the whole K extent staged at once (needs K small enough for LDS).
+enum GemmTile { TILE_64x64 = 0, TILE_32x32 = 1, TILE_48x48 = 2, TILE_16x64 = 3, TILE_FK_32x32 = 4, TILE_FK_48x48 = 5,
+                TILE_FK_64x64 = 6, TILE_FK_32x64 = 7, N_GEMM_TILES = 8 };
 
 hipError_t launch_gemm(const GemmArgs<double>& a, int tile, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs<float>& a, int tile, hipStream_t s);
+bool gemm_tile_fits(int tile, int K, int precision);
+hipError_t prepare_gemm();
 
 // P[z] = diag(rs(z)) * A  (A shared), used for the first slice of a block product
 hipError_t launch_scale_rows(double* P, long sP, const double* A, int n, Scale rs, int batch,

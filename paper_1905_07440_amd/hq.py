@@ -61,11 +61,17 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("gemm_tile_fp64", ctypes.c_int32), ("gemm_tile_wrap", ctypes.c_int32),
+                ("local_block", ctypes.c_int32), ("gemm_us_fp64", ctypes.c_double),
+                ("gemm_us_wrap", ctypes.c_double)]
+
+
 EXPORTS = [
     "hq_workspace_bytes", "hq_create", "hq_set_fields", "hq_set_network", "hq_sweep",
     "hq_recompute", "hq_read_green", "hq_read_fields", "hq_read_stats", "hq_read_decisions",
     "hq_set_replay", "hq_num_chains", "hq_chain_shape", "hq_set_profiling", "hq_phase_time",
-    "hq_synchronize", "hq_last_error", "hq_destroy",
+    "hq_read_tuning", "hq_gemm_tile_name", "hq_synchronize", "hq_last_error", "hq_destroy",
 ]
 
 _lib = None
@@ -99,13 +105,17 @@ def load(path=LIB_PATH):
     lib.hq_chain_shape.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.hq_set_profiling.argtypes = [P, I32]
     lib.hq_phase_time.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)]
+    lib.hq_read_tuning.argtypes = [P, I32, ctypes.POINTER(Tuning)]
+    lib.hq_gemm_tile_name.argtypes = [I32]
+    lib.hq_gemm_tile_name.restype = ctypes.c_char_p
     lib.hq_synchronize.argtypes = [P]
     lib.hq_last_error.argtypes = [P]
     lib.hq_last_error.restype = ctypes.c_char_p
     lib.hq_destroy.argtypes = [P]
     lib.hq_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("hq_workspace_bytes", "hq_num_chains", "hq_last_error", "hq_destroy"):
+        if name not in ("hq_workspace_bytes", "hq_num_chains", "hq_last_error", "hq_destroy",
+                        "hq_gemm_tile_name"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -221,6 +231,15 @@ class Context:
         ms, k = ctypes.c_double(), ctypes.c_int64()
         self._check(self._lib.hq_phase_time(self._ctx, phase.encode(), ctypes.byref(ms), ctypes.byref(k)))
         return ms.value, k.value
+
+    def tuning(self, group):
+        """The autotuner's choices for one group (GEMM tiles by name, timings in us)."""
+        t = Tuning()
+        self._check(self._lib.hq_read_tuning(self._ctx, group, ctypes.byref(t)))
+        name = self._lib.hq_gemm_tile_name
+        return {"gemm_tile_fp64": name(t.gemm_tile_fp64).decode(), "gemm_us_fp64": t.gemm_us_fp64,
+                "gemm_tile_wrap": name(t.gemm_tile_wrap).decode(), "gemm_us_wrap": t.gemm_us_wrap,
+                "local_block": t.local_block}
 
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx:

@@ -60,9 +60,9 @@ def holstein_8x8_batched_global():
                     [Lattice(nx=8, n_chains=64, g=1.2, beta=8.0, n_stab=8, global_width=1.0)])
 
 
-def holstein_12x12_mixed(precision=1):
-    return Workload("holstein-12x12-L120-%s-128chains" % ("mixed" if precision else "fp64"), 3,
-                    [Lattice(nx=12, n_chains=128, g=1.5, beta=12.0, n_stab=10)],
+def holstein_12x12_mixed(precision=1, n_stab=10):
+    return Workload("holstein-12x12-L120-%s-nstab%d-128chains" % ("mixed" if precision else "fp64", n_stab), 3,
+                    [Lattice(nx=12, n_chains=128, g=1.5, beta=12.0, n_stab=n_stab)],
                     precision=precision)
 
 
@@ -82,6 +82,9 @@ ALL = {
     "c2": holstein_8x8_batched_global,
     "c3": holstein_12x12_mixed,
     "c3-fp64": lambda: holstein_12x12_mixed(0),
+    # mixed precision with the FP64 recompute every 6 slices: the largest
+    # interval (a divisor of L = 120) whose drift stays within 1e-5
+    "c3-gate": lambda: holstein_12x12_mixed(1, n_stab=6),
     "c4": holstein_uneven_batch,
     "c5": holstein_16x16_network,
 }
