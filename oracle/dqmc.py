@@ -1,17 +1,29 @@
 """The conventional DQMC sweep of the Holstein model (paper: Determinant quantum
 Monte Carlo, Local Updates intro, Benchmarks protocol), plain and serial in FP64.
 
-One sweep:
+One sweep visits every slice once.  G_l = (I + B_l...B_0 B_{L-1}...B_{l+1})^-1
+is the Green's function "at slice l", the one whose local moves at slice l
+are rank-1 updates.  Upward (even sweeps, and every sweep of a chain with
+block moves):
   for l = 0..L-1:
-      wrap      G <- B_l G B_l^-1, so G = (I + B_l...B_0 B_{L-1}...B_{l+1})^-1
+      wrap      G <- B_l G B_l^-1              (G_{l-1} -> G_l)
       for i = 0..N-1: local move x[l,i] += d, d ~ U(-w, w)
           det ratio of one spin  r = 1 + delta (1 - G_ii), delta = exp(-dtau g d) - 1
           Metropolis ratio       R = r^2 exp(-(S_b(x') - S_b(x)))      (W'/W)
           accept iff u < R; then G <- G - (delta/r) G[:,i] (e_i - G[i,:])   (rank 1)
-      if (l+1) % n_stab == 0: recompute G and log|det M| from scratch (UDT chain)
-  then, if block moves are enabled, for i = 0..N-1: shift x[:,i] by d ~ U(-w_g, w_g)
-      and accept with exp(2 (log|det M'| - log|det M|) - dS_b), the determinant
-      evaluated from scratch (no fast update exists for block moves).
+      if (l+1) % n_stab == 0: recompute G_l and log|det M| from scratch (UDT chain)
+Downward (odd sweeps of a chain without block moves):
+  for l = L-1..0:
+      the same N local moves at slice l
+      unwrap    G <- B_l^-1 G B_l             (G_l -> G_{l-1})
+      if l % n_stab == 0: recompute G_{l-1} and log|det M| from scratch
+Both end at G_{L-1}, the state every sweep starts from.  The paper fixes no
+order; alternating lets an implementation reuse the products of the previous
+sweep (the blocks above slice l in an upward sweep are exactly those the
+downward sweep has just updated).  Then, if block moves are enabled, for
+i = 0..N-1: shift x[:,i] by d ~ U(-w_g, w_g) and accept with
+exp(2 (log|det M'| - log|det M|) - dS_b), the determinant evaluated from
+scratch (no fast update exists for block moves).
 
 The rank-1 form follows from det(I + (I+Delta) A) = det(I + A) det(I + Delta(I - G))
 with Delta = delta e_i e_i^T and A the cyclic product that starts at B_l.
@@ -73,6 +85,11 @@ class Chain:
         dvec = np.exp(-self.p.dtau * self.p.g * self.x[l])
         self.G = (dvec[:, None] * (self.expk @ self.G @ self.expkinv)) / dvec[None, :]
 
+    def unwrap(self, l):
+        """G <- B_l^-1 G B_l, from the slice-l Green's function to slice l-1's."""
+        dvec = np.exp(-self.p.dtau * self.p.g * self.x[l])
+        self.G = self.expkinv @ ((self.G / dvec[:, None]) * dvec[None, :]) @ self.expk
+
     def local_move(self, l, i):
         p, x, G = self.p, self.x, self.G
         L = x.shape[0]
@@ -104,14 +121,26 @@ class Chain:
         self.max_drift_logdet = max(self.max_drift_logdet, abs(self.logdet - ld_rec))
         self.G, self.logdet = g_rec, ld_rec
 
+    def downward(self):
+        """Whether this sweep runs downward: odd sweeps, when there are no block moves."""
+        return self.p.global_width == 0.0 and self.sweep_index % 2 == 1
+
     def local_sweep(self):
         p = self.p
-        for l in range(p.L):
-            self.wrap(l)
+        if not self.downward():
+            for l in range(p.L):
+                self.wrap(l)
+                for i in range(p.n):
+                    self.local_move(l, i)
+                if (l + 1) % p.n_stab == 0:
+                    self.recompute(l)
+            return
+        for l in range(p.L - 1, -1, -1):
             for i in range(p.n):
                 self.local_move(l, i)
-            if (l + 1) % p.n_stab == 0:
-                self.recompute(l)
+            self.unwrap(l)
+            if l % p.n_stab == 0:
+                self.recompute(l - 1)
 
     def global_sweep(self):
         p, L = self.p, self.p.L

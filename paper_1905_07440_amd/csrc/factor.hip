@@ -66,6 +66,46 @@ __device__ inline double wave_total(double v) {
   return lane_value(v, 63);
 }
 
+// totals over the 64 lanes of 16 values at once, returned wave-uniform: a
+// butterfly in which every exchange halves the values a lane carries (lanes
+// l and l ^ 32 keep the lower and upper eight, and so on), 17 exchanges in
+// all instead of 16 separate six-step reductions.  Afterwards lane l holds
+// the total of value (l >> 2) & 15.
+__device__ inline void wave_totals16(const double (&v)[16], double (&t)[16]) {
+  const int lane = threadIdx.x & 63;
+  double a8[8], a4[4], a2[2];
+  {
+    const bool h = (lane & 32) != 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double keep = h ? v[8 + i] : v[i], send = h ? v[i] : v[8 + i];
+      a8[i] = keep + __shfl_xor(send, 32, 64);
+    }
+  }
+  {
+    const bool h = (lane & 16) != 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double keep = h ? a8[4 + i] : a8[i], send = h ? a8[i] : a8[4 + i];
+      a4[i] = keep + __shfl_xor(send, 16, 64);
+    }
+  }
+  {
+    const bool h = (lane & 8) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double keep = h ? a4[2 + i] : a4[i], send = h ? a4[i] : a4[2 + i];
+      a2[i] = keep + __shfl_xor(send, 8, 64);
+    }
+  }
+  const bool h = (lane & 4) != 0;
+  double a1 = (h ? a2[1] : a2[0]) + __shfl_xor(h ? a2[0] : a2[1], 4, 64);
+  a1 += __shfl_xor(a1, 2, 64);
+  a1 += __shfl_xor(a1, 1, 64);
+#pragma unroll
+  for (int c = 0; c < 16; ++c) t[c] = lane_value(a1, 4 * c);
+}
+
 // ---------------------------------------------------------------------------
 // A <- A - V op(T) (V^T A) on rows [p0, n) and columns [c_begin, n),
 // op(T) = T^T (transT) or T.  V: Vs[k][r] (r relative to p0, zero outside the
@@ -452,15 +492,29 @@ __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, d
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (j < nbw) {
-          double sg = 0.0, al = 0.0;
+          // every sum the column needs in one butterfly: slot 0 the squared
+          // norm below the diagonal, slot c the dot of that tail with column
+          // j + c; the reflector's scale enters afterwards, since
+          // v^T a_c = a_c[j] + scl * (tail . a_c[tail])
+          double tail[Cap<MX>::rpl];       // column j below the diagonal, zero elsewhere
 #pragma unroll
           for (int t = 0; t < Cap<MX>::rpl; ++t) {
             const int r = lane + 64 * t;
-            if (r > j && r < m) sg += a[j][t] * a[j][t];
-            if (r == j) al = a[j][t];
+            tail[t] = (r > j && r < m) ? a[j][t] : 0.0;
           }
-          sg = wave_total(sg);
-          al = wave_total(al);
+          double part[16];
+#pragma unroll
+          for (int c = 0; c < 16; ++c) {
+            part[c] = 0.0;
+            if (j + c < NB) {
+#pragma unroll
+              for (int t = 0; t < Cap<MX>::rpl; ++t) part[c] += tail[t] * a[(j + c) % NB][t];
+            }
+          }
+          double tot[16];
+          wave_totals16(part, tot);
+          const double sg = tot[0];
+          const double al = lane_value(a[j][0], j);      // row j of the panel lives in lane j
           double be = al, tj = 0.0, scl = 0.0;
           if (sg > 0.0) {
             const double nrm = sqrt(al * al + sg);
@@ -472,24 +526,15 @@ __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, d
 #pragma unroll
           for (int t = 0; t < Cap<MX>::rpl; ++t) {
             const int r = lane + 64 * t;
-            if (r > j && r < m) a[j][t] *= scl;
-            if (r == j) a[j][t] = be;
-            vr[t] = (r == j) ? 1.0 : ((r > j && r < m) ? a[j][t] : 0.0);
-          }
-          double w[NB];
-#pragma unroll
-          for (int c = j + 1; c < NB; ++c) {
-            w[c] = 0.0;
-#pragma unroll
-            for (int t = 0; t < Cap<MX>::rpl; ++t) w[c] += vr[t] * a[c][t];
+            vr[t] = (r == j) ? 1.0 : tail[t] * scl;
+            if (r >= j) a[j][t] = (r == j) ? be : vr[t];
           }
 #pragma unroll
-          for (int c = j + 1; c < NB; ++c) w[c] = wave_total(w[c]) * tj;
+          for (int c = 1; c < 16; ++c)
+            if (j + c < nbw) {
+              const double w = tj * (lane_value(a[j + c][0], j) + scl * tot[c]);
 #pragma unroll
-          for (int c = j + 1; c < NB; ++c)
-            if (c < nbw) {
-#pragma unroll
-              for (int t = 0; t < Cap<MX>::rpl; ++t) a[c][t] -= vr[t] * w[c];
+              for (int t = 0; t < Cap<MX>::rpl; ++t) a[j + c][t] -= vr[t] * w;
             }
           if (lane == 0) tau[j] = tj;
         }

@@ -1,6 +1,6 @@
 // Batched dense products on MFMA for the wraps, block products and UDT
-// combines of the DQMC sweep.  C = alpha * diag(rs) op(A) op(B) diag(cs)
-// + beta * C, row-major, one workgroup per (tile, batch entry).
+// combines of the DQMC sweep.  C = alpha * diag(rs) op(A) diag(ks) op(B)
+// diag(cs) + beta * C, row-major, one workgroup per (tile, batch entry).
 //
 // FP64 uses v_mfma_f64_16x16x4f64, FP32 uses v_mfma_f32_16x16x4f32 with
 // FP32 accumulation.  A workgroup tile of BM x BN is split over WM x WN
@@ -32,6 +32,7 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
   __shared__ T Bs[BK][BN + PAD];
   __shared__ double rsv[BM];
   __shared__ double csv[BN];
+  __shared__ double ksv[256];
 
   const int z = blockIdx.z;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
@@ -45,6 +46,10 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
     rsv[i] = (m0 + i < a.M) ? scale_value(a.rs, z, a.inner_count, m0 + i) : 0.0;
   for (int i = tid; i < BN; i += NT)
     csv[i] = (n0 + i < a.N) ? scale_value(a.cs, z, a.inner_count, n0 + i) : 0.0;
+  const bool kscale = a.ks.v != nullptr;
+  if (kscale)
+    for (int i = tid; i < a.K; i += NT) ksv[i] = scale_value(a.ks, z, a.inner_count, i);
+  __syncthreads();
 
   typedef typename Frag<T>::type F;
   F acc[FM][FN];
@@ -69,7 +74,10 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
       if (a.tB) { k = e % BK; n = e / BK; } else { n = e % BN; k = e / BN; }
       const int gn = n0 + n, gk = k0 + k;
       T v = 0;
-      if (gn < a.N && gk < a.K) v = a.tB ? B[(long)gn * a.ldb + gk] : B[(long)gk * a.ldb + gn];
+      if (gn < a.N && gk < a.K) {
+        v = a.tB ? B[(long)gn * a.ldb + gk] : B[(long)gk * a.ldb + gn];
+        if (kscale) v = (T)((double)v * ksv[gk]);
+      }
       Bs[k][n] = v;
     }
     __syncthreads();
@@ -122,6 +130,7 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_fullk_kernel(GemmArgs<T> a)
   T* Bs = As + (long)K4 * LA;              // [K4][LB]: Bs[k][n] = op(B)(k, n0 + n)
   __shared__ double rsv[BM];
   __shared__ double csv[BN];
+  __shared__ double ksv[256];
 
   const int z = blockIdx.z;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
@@ -136,6 +145,10 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_fullk_kernel(GemmArgs<T> a)
     rsv[i] = (m0 + i < a.M) ? scale_value(a.rs, z, a.inner_count, m0 + i) : 0.0;
   for (int i = tid; i < BN; i += NT)
     csv[i] = (n0 + i < a.N) ? scale_value(a.cs, z, a.inner_count, n0 + i) : 0.0;
+  const bool kscale = a.ks.v != nullptr;
+  if (kscale)
+    for (int i = tid; i < a.K; i += NT) ksv[i] = scale_value(a.ks, z, a.inner_count, i);
+  __syncthreads();
   // op(A) and op(B) panels, 16 consecutive threads along the contiguous
   // index of the source (coalesced), no per-element division
   {
@@ -161,14 +174,16 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_fullk_kernel(GemmArgs<T> a)
 #pragma unroll
         for (int n = t16; n < BN; n += 16) {
           const int gn = n0 + n;
-          Bs[k * LB + n] = (gn < a.N && k < a.K) ? B[(long)k * a.ldb + gn] : T(0);
+          Bs[k * LB + n] = (gn < a.N && k < a.K) ? (T)((double)B[(long)k * a.ldb + gn] * (kscale ? ksv[k] : 1.0))
+                                                 : T(0);
         }
     } else {                               // B[n][k]: groups over n, lanes over k
       for (int n = g16; n < BN; n += G) {
         const int gn = n0 + n;
 #pragma unroll 4
         for (int k = t16; k < K4; k += 16)
-          Bs[k * LB + n] = (gn < a.N && k < a.K) ? B[(long)gn * a.ldb + k] : T(0);
+          Bs[k * LB + n] = (gn < a.N && k < a.K) ? (T)((double)B[(long)gn * a.ldb + k] * (kscale ? ksv[k] : 1.0))
+                                                 : T(0);
       }
     }
   }
@@ -232,6 +247,7 @@ static hipError_t launch_tile(const GemmArgs<T>& a, hipStream_t s) {
 template <typename T>
 static hipError_t launch_any(const GemmArgs<T>& a, int tile, hipStream_t s) {
   if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
+  if (a.ks.v && a.K > 256) return hipErrorInvalidValue;   // the inner scale is staged in LDS
   switch (tile) {
     case TILE_32x32: return launch_tile<T, 32, 32, 1, 1>(a, s);
     case TILE_48x48: return launch_tile<T, 48, 48, 3, 1>(a, s);

@@ -48,6 +48,8 @@ struct Group {
   double *blk = nullptr, *blkp = nullptr, *blks = nullptr;     // [C][nb][n][n]
   double *RU = nullptr, *RD = nullptr, *RT = nullptr;          // [C][nb][n][n], [C][nb][n]
   double *LU = nullptr, *LD = nullptr, *LT[2] = {nullptr, nullptr};
+  double *SU = nullptr, *SD = nullptr, *ST = nullptr;          // left stack [nb][C][n][n], [nb][C][n]
+  bool alternate = false;        // sweeps alternate upward / downward (local moves only)
   double *Z = nullptr, *Rt = nullptr, *M = nullptr, *Minv = nullptr, *Xm = nullptr, *Tq = nullptr;
   double *dLbinv = nullptr, *dLs = nullptr, *dRbinv = nullptr, *dRs = nullptr, *sumlog = nullptr;
   double *logdet = nullptr, *logdet_new = nullptr, *shift = nullptr;
@@ -97,8 +99,12 @@ struct hq_ctx {
   int n_chains = 0;
   bool broken = false;
   std::string err;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // one captured graph per (direction, stack rebuild) and the host's view of
+  // the sweep state: the next sweep's index and which UDT stack is current
+  hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int64_t sweep_index = 0;
+  bool left_valid = false, right_valid = false;
   bool profiling = false;
   // per-phase event timing (profiling mode runs the schedule eagerly)
   struct Phase { const char* name; double ms; int64_t launches; };
@@ -106,6 +112,11 @@ struct hq_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<int> pending_phase;
   std::vector<hipEvent_t> event_pool;
+  // groups of different lattices run as concurrent branches of the sweep
+  // graph: one side stream per group, forked from and joined to `stream`
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
 };
 
 namespace {
@@ -194,6 +205,9 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
     g.LD = cv.take<double>(C * n);
     g.LT[0] = cv.take<double>(C * nn);
     g.LT[1] = cv.take<double>(C * nn);
+    g.SU = cv.take<double>(C * nb * nn);
+    g.SD = cv.take<double>(C * nb * n);
+    g.ST = cv.take<double>(C * nb * nn);
     g.Z = cv.take<double>(C * nn);
     g.Rt = cv.take<double>(C * nn);
     g.M = cv.take<double>(C * nn);
@@ -253,6 +267,7 @@ bool build_groups(const hq_group* gp, int ng, const hq_options& o, std::vector<G
     g.chain0 = chain0;
     g.global = gp[k].global_width > 0.0 && gp[k].proposal == HQ_PROPOSAL_DQMC;
     g.network = gp[k].proposal == HQ_PROPOSAL_NETWORK;
+    g.alternate = !g.global && !g.network;
     g.nt = g.n <= 64 ? 64 : 256;
     g.kd = o.delay ? o.delay : 16;
     g.tile = g.n <= 32 ? TILE_32x32 : TILE_64x64;
@@ -404,8 +419,8 @@ hq_status combine(Sched& S, Group& g, const double* A, long sA, int tA, const do
 
 // G = (I + L R)^-1 and log|det|, L = U_L D_L T_L, R = T_R^T D_R U_R^T
 // (identity R when UR == nullptr).  Results in g.Gnew, g.logdet_new.
-hq_status merge(Sched& S, Group& g, const double* UL, const double* DL, const double* TL, const double* UR, long sUR,
-                const double* DR, long sDR, const double* TR, long sTR) {
+hq_status merge(Sched& S, Group& g, const double* UL, long sUL, const double* DL, const double* TL, long sTL,
+                const double* UR, long sUR, const double* DR, long sDR, const double* TR, long sTR) {
   const long nn = (long)g.n * g.n;
   const int n = g.n;
   SCHED_TRY(launch_dsplit(DL, g.dLbinv, g.dLs, g.sumlog, 0, n, g.C, S.s));
@@ -421,14 +436,14 @@ hq_status merge(Sched& S, Group& g, const double* UL, const double* DL, const do
     TR = g.ident; sTR = 0;
   }
   GemmArgs<double> a = sq(g, g.C);                 // M = Db_L^-1 (U_L^T U_R) Db_R^-1
-  a.A = UL; a.sA = nn; a.tA = 1;
+  a.A = UL; a.sA = sUL; a.tA = 1;
   a.B = UR; a.sB = sUR;
   a.C = g.M; a.sC = nn;
   a.rs.v = g.dLbinv; a.rs.so = n;
   a.cs.v = rb; a.cs.so = n;
   SCHED_TRY(launch_gemm(a, g.tile, S.s));
   GemmArgs<double> b = sq(g, g.C);                 // M += Ds_L (T_L T_R^T) Ds_R
-  b.A = TL; b.sA = nn;
+  b.A = TL; b.sA = sTL;
   b.B = TR; b.sB = sTR; b.tB = 1;
   b.C = g.M; b.sC = nn;
   b.beta = 1.0;
@@ -439,7 +454,7 @@ hq_status merge(Sched& S, Group& g, const double* UL, const double* DL, const do
   SCHED_TRY(launch_gj(g.M, g.Minv, rb, g.dLbinv, g.sumlog, g.logdet_new, n, g.C, S.s));
   GemmArgs<double> c = sq(g, g.C);                 // X = Minv U_L^T (Minv over M)
   c.A = g.M; c.sA = nn;
-  c.B = UL; c.sB = nn; c.tB = 1;
+  c.B = UL; c.sB = sUL; c.tB = 1;
   c.C = g.Xm; c.sC = nn;
   SCHED_TRY(launch_gemm(c, g.tile, S.s));
   GemmArgs<double> d = sq(g, g.C);                 // G = U_R X
@@ -463,7 +478,7 @@ hq_status from_scratch(Sched& S, Group& g, const double* xs, double* blocks) {
                    g.LT[1 - t], nn));
     t = 1 - t;
   }
-  return merge(S, g, g.LU, g.LD, g.LT[t], nullptr, 0, nullptr, 0, nullptr, 0);
+  return merge(S, g, g.LU, nn, g.LD, g.LT[t], nn, nullptr, 0, nullptr, 0, nullptr, 0);
 }
 
 hq_status wrap(Sched& S, Group& g, int slice) {
@@ -513,16 +528,93 @@ hq_status local(Sched& S, Group& g, int slice) {
   return HQ_OK;
 }
 
-hq_status stab_point(Sched& S, Group& g, int b, int& t) {
+// G <- B_l^-1 G B_l = expK^-1 D_l^-1 G D_l expK (downward sweeps): the inner
+// scale D^-1 on G's rows and the column scale D in the first product, then expK
+hq_status unwrap(Sched& S, Group& g, int slice) {
+  const long nn = (long)g.n * g.n;
+  Scale ks, cs;
+  ks.v = g.x; ks.so = (long)g.L * g.n; ks.off = (long)slice * g.n; ks.coef = g.g; ks.cmul = g.p.dtau;
+  cs = ks; cs.cmul = -g.p.dtau;
+  if (S.ctx->opt.precision == HQ_PREC_MIXED) {
+    GemmArgs<float> a;
+    a.M = a.N = a.K = g.n; a.lda = a.ldb = a.ldc = g.n; a.batch = g.C;
+    a.A = g.expkinv32; a.sA = 0;
+    a.B = (const float*)g.G; a.sB = nn;
+    a.C = (float*)g.Wt; a.sC = nn;
+    a.ks = ks; a.cs = cs;
+    SCHED_TRY(launch_gemm(a, g.tile32, S.s));
+    GemmArgs<float> b = a;
+    b.A = (const float*)g.Wt; b.sA = nn;
+    b.B = g.expk32; b.sB = 0;
+    b.C = (float*)g.G; b.sC = nn;
+    b.ks = Scale(); b.cs = Scale();
+    SCHED_TRY(launch_gemm(b, g.tile32, S.s));
+  } else {
+    GemmArgs<double> a = sq(g, g.C);
+    a.A = g.expkinv; a.sA = 0;
+    a.B = (const double*)g.G; a.sB = nn;
+    a.C = (double*)g.Wt; a.sC = nn;
+    a.ks = ks; a.cs = cs;
+    SCHED_TRY(launch_gemm(a, g.tile, S.s));
+    GemmArgs<double> b = a;
+    b.A = (const double*)g.Wt; b.sA = nn;
+    b.B = g.expk; b.sB = 0;
+    b.C = (double*)g.G; b.sC = nn;
+    b.ks = Scale(); b.cs = Scale();
+    SCHED_TRY(launch_gemm(b, g.tile, S.s));
+  }
+  return HQ_OK;
+}
+
+// stack entries, all chains of the group contiguous per entry
+struct Udt { double *U, *D, *T; long sU, sD, sT; };
+Udt left_entry(Group& g, int b) {       // L_b = C_b ... C_0; b = -1: identity
+  const long nn = (long)g.n * g.n;
+  if (b < 0) return {g.ident, g.ones, g.ident, 0, g.n, 0};
+  return {g.SU + (long)b * g.C * nn, g.SD + (long)b * g.C * g.n, g.ST + (long)b * g.C * nn, nn, g.n, nn};
+}
+Udt right_entry(Group& g, int b) {      // R_b^T with R_b = C_{nb-1} ... C_{b+1}; R_{nb-1} = identity
+  const long nn = (long)g.n * g.n;
+  return {g.RU + (long)b * g.C * nn, g.RD + (long)b * g.C * g.n, g.RT + (long)b * g.C * nn, nn, g.n, nn};
+}
+
+// upward stabilisation after block b: C_b from the new fields, L_b = C_b L_{b-1},
+// G = (I + L_b R_b)^-1
+hq_status stab_up(Sched& S, Group& g, int b) {
   const long nn = (long)g.n * g.n;
   ST_TRY(block_products(S, g, g.x, g.blk + b * nn, (long)g.nb * nn, g.Z, b, 1));
-  ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 0, g.LU, nn, g.LD, g.n, g.LT[t], nn, g.LU, nn, g.LD, g.n,
-                 g.LT[1 - t], nn));
-  t = 1 - t;
-  // right stack entry b lives at RU[b] etc. in [nb][C] order (contiguous per b)
-  ST_TRY(merge(S, g, g.LU, g.LD, g.LT[t], g.RU + (long)b * g.C * nn, nn, g.RD + (long)b * g.C * g.n, g.n,
-               g.RT + (long)b * g.C * nn, nn));
+  const Udt in = left_entry(g, b - 1), out = left_entry(g, b), r = right_entry(g, b);
+  ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 0, in.U, in.sU, in.D, in.sD, in.T, in.sT, out.U, out.sU, out.D,
+                 out.sD, out.T, out.sT));
+  ST_TRY(merge(S, g, out.U, out.sU, out.D, out.T, out.sT, r.U, r.sU, r.D, r.sD, r.T, r.sT));
   SCHED_TRY(launch_stab_finish(g.G, S.ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.n, g.C, 1, S.s));
+  return HQ_OK;
+}
+
+// downward stabilisation after block b (G unwrapped to slice b*ns - 1):
+// C_b from the new fields, R_{b-1}^T = C_b^T R_b^T, G = (I + L_{b-1} R_{b-1})^-1.
+// For b = 0 the full product goes to the scratch UDT (LU, LD, LT[0]).
+hq_status stab_down(Sched& S, Group& g, int b) {
+  const long nn = (long)g.n * g.n;
+  ST_TRY(block_products(S, g, g.x, g.blk + b * nn, (long)g.nb * nn, g.Z, b, 1));
+  const Udt in = right_entry(g, b);
+  const Udt out = (b > 0) ? right_entry(g, b - 1) : Udt{g.LU, g.LD, g.LT[0], nn, g.n, nn};
+  ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 1, in.U, in.sU, in.D, in.sD, in.T, in.sT, out.U, out.sU, out.D,
+                 out.sD, out.T, out.sT));
+  const Udt l = left_entry(g, b - 1);
+  ST_TRY(merge(S, g, l.U, l.sU, l.D, l.T, l.sT, out.U, out.sU, out.D, out.sD, out.T, out.sT));
+  SCHED_TRY(launch_stab_finish(g.G, S.ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.n, g.C, 1, S.s));
+  return HQ_OK;
+}
+
+// every left stack entry from the cached block products
+hq_status left_stack(Sched& S, Group& g) {
+  const long nn = (long)g.n * g.n;
+  for (int b = 0; b < g.nb; ++b) {
+    const Udt in = left_entry(g, b - 1), out = left_entry(g, b);
+    ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 0, in.U, in.sU, in.D, in.sD, in.T, in.sT, out.U, out.sU,
+                   out.D, out.sD, out.T, out.sT));
+  }
   return HQ_OK;
 }
 
@@ -587,45 +679,96 @@ hq_status network_sweep(Sched& S, Group& g) {
   return HQ_OK;
 }
 
-hq_status sweep_group(Sched& S, Group& g) {
+enum { DIR_UP = 0, DIR_DOWN = 1 };
+
+// One sweep of a group.  Upward: wrap and local moves slice by slice, FP64
+// stabilisation after every block against the right stack (rebuilt first
+// unless the previous downward sweep left it valid); then the block moves.
+// Downward (alternating groups, odd sweeps): local moves and unwrap slice by
+// slice from the top, stabilisation against the left stack the previous
+// upward sweep left behind (or a rebuilt one).
+hq_status sweep_group(Sched& S, Group& g, int dir, bool rebuild) {
   if (g.network) {
     ST_TRY(begin_phase(S, PH_NETWORK));
     ST_TRY(network_sweep(S, g));
     return end_phase(S);
   }
-  ST_TRY(begin_phase(S, PH_STAB));
-  ST_TRY(right_stack(S, g));
-  SCHED_TRY(launch_identity(g.LU, g.LD, g.LT[0], g.n, g.C, S.s));
-  ST_TRY(end_phase(S));
-  int t = 0;
-  for (int b = 0; b < g.nb; ++b) {
-    for (int k = 0; k < g.ns; ++k) {
-      const int slice = b * g.ns + k;
-      ST_TRY(begin_phase(S, PH_WRAP));
-      ST_TRY(wrap(S, g, slice));
+  if (!g.alternate || dir == DIR_UP) {
+    if (!g.alternate || rebuild) {
+      ST_TRY(begin_phase(S, PH_STAB));
+      ST_TRY(right_stack(S, g));
       ST_TRY(end_phase(S));
+    }
+    for (int b = 0; b < g.nb; ++b) {
+      for (int k = 0; k < g.ns; ++k) {
+        const int slice = b * g.ns + k;
+        ST_TRY(begin_phase(S, PH_WRAP));
+        ST_TRY(wrap(S, g, slice));
+        ST_TRY(end_phase(S));
+        ST_TRY(begin_phase(S, PH_LOCAL));
+        ST_TRY(local(S, g, slice));
+        ST_TRY(end_phase(S));
+      }
+      ST_TRY(begin_phase(S, PH_STAB));
+      ST_TRY(stab_up(S, g, b));
+      ST_TRY(end_phase(S));
+    }
+    if (g.global) {
+      ST_TRY(begin_phase(S, PH_GLOBAL));
+      ST_TRY(global_moves(S, g));
+      ST_TRY(end_phase(S));
+    }
+    return HQ_OK;
+  }
+  ST_TRY(begin_phase(S, PH_STAB));
+  if (rebuild) ST_TRY(left_stack(S, g));
+  const Udt top = right_entry(g, g.nb - 1);
+  SCHED_TRY(launch_identity(top.U, top.D, top.T, g.n, g.C, S.s));
+  ST_TRY(end_phase(S));
+  for (int b = g.nb - 1; b >= 0; --b) {
+    for (int k = g.ns - 1; k >= 0; --k) {
+      const int slice = b * g.ns + k;
       ST_TRY(begin_phase(S, PH_LOCAL));
       ST_TRY(local(S, g, slice));
       ST_TRY(end_phase(S));
+      ST_TRY(begin_phase(S, PH_WRAP));
+      ST_TRY(unwrap(S, g, slice));
+      ST_TRY(end_phase(S));
     }
     ST_TRY(begin_phase(S, PH_STAB));
-    ST_TRY(stab_point(S, g, b, t));
-    ST_TRY(end_phase(S));
-  }
-  if (g.global) {
-    ST_TRY(begin_phase(S, PH_GLOBAL));
-    ST_TRY(global_moves(S, g));
+    ST_TRY(stab_down(S, g, b));
     ST_TRY(end_phase(S));
   }
   return HQ_OK;
 }
 
-hq_status enqueue_sweep(hq_ctx* ctx) {
+hq_status enqueue_group(hq_ctx* ctx, Group& g, hipStream_t s, int dir, bool rebuild) {
+  Sched S{ctx, s};
+  ST_TRY(sweep_group(S, g, dir, rebuild));
+  for (int k : {HQ_KIND_LOCAL, HQ_KIND_GLOBAL, HQ_KIND_NN, HQ_KIND_CUMULATIVE})
+    SCHED_TRY(launch_fill_u8(g.replay[k], 255, (long)g.C * g.kind_slots(k), S.s));
+  return HQ_OK;
+}
+
+// One sweep of every group.  Groups share nothing but the read-only network
+// and the sweep counter, so with more than one group each runs on its own
+// stream (a parallel branch once captured) and the counter is advanced after
+// the join.  The profiling mode keeps one stream so that its events time
+// each phase alone.
+hq_status enqueue_sweep(hq_ctx* ctx, int dir, bool rebuild) {
+  const bool fork = !ctx->profiling && ctx->groups.size() > 1;
+  if (!fork) {
+    for (Group& g : ctx->groups) ST_TRY(enqueue_group(ctx, g, ctx->stream, dir, rebuild));
+  } else {
+    HQ_TRY(hipEventRecord(ctx->fork, ctx->stream));
+    for (size_t k = 0; k < ctx->groups.size(); ++k) {
+      HQ_TRY(hipStreamWaitEvent(ctx->side[k], ctx->fork, 0));
+      ST_TRY(enqueue_group(ctx, ctx->groups[k], ctx->side[k], dir, rebuild));
+      HQ_TRY(hipEventRecord(ctx->join[k], ctx->side[k]));
+    }
+    for (size_t k = 0; k < ctx->groups.size(); ++k) HQ_TRY(hipStreamWaitEvent(ctx->stream, ctx->join[k], 0));
+  }
   Sched S{ctx, ctx->stream};
-  for (Group& g : ctx->groups) ST_TRY(sweep_group(S, g));
-  for (Group& g : ctx->groups)
-    for (int k : {HQ_KIND_LOCAL, HQ_KIND_GLOBAL, HQ_KIND_NN, HQ_KIND_CUMULATIVE})
-      SCHED_TRY(launch_fill_u8(g.replay[k], 255, (long)g.C * g.kind_slots(k), S.s));
   SCHED_TRY(launch_add_i64(ctx->sweep_counter, 1, S.s));
   return HQ_OK;
 }
@@ -784,6 +927,17 @@ hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* 
 
   HQ_TRY(prepare_local());
   HQ_TRY(prepare_gemm());
+  if (ctx->groups.size() > 1) {
+    HQ_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    for (size_t k = 0; k < ctx->groups.size(); ++k) {
+      hipStream_t side = nullptr;
+      hipEvent_t ev = nullptr;
+      HQ_TRY(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+      ctx->side.push_back(side);
+      HQ_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      ctx->join.push_back(ev);
+    }
+  }
   hipStream_t s = ctx->stream;
   // host-side model set-up and initial state
   for (Group& g : ctx->groups) {
@@ -840,6 +994,7 @@ hq_status hq_set_fields(hq_ctx* ctx, int32_t chain, const double* x_host, int64_
   if (!g || !x_host || n != (int64_t)g->L * g->n) return fail(ctx, HQ_EINVAL, "bad chain or field count");
   for (int64_t k = 0; k < n; ++k)
     if (!std::isfinite(x_host[k])) return fail(ctx, HQ_EINVAL, "non-finite field");
+  ctx->left_valid = ctx->right_valid = false;
   HQ_TRY(hipMemcpyAsync(g->x + (long)lc * n, x_host, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   Sched S{ctx, ctx->stream};
   ST_TRY(from_scratch(S, *g, g->x, g->blk));
@@ -863,26 +1018,37 @@ hq_status hq_sweep(hq_ctx* ctx, int32_t n_sweeps) {
   if (n_sweeps < 0) return fail(ctx, HQ_EINVAL, "n_sweeps < 0");
   for (const Group& g : ctx->groups)
     if (g.network && !ctx->net_loaded) return fail(ctx, HQ_EINVAL, "network proposals need hq_set_network first");
-  if (ctx->profiling) {
-    for (int k = 0; k < n_sweeps; ++k) ST_TRY(enqueue_sweep(ctx));
-    return collect_profile(ctx);
+  for (int k = 0; k < n_sweeps; ++k) {
+    const int dir = (ctx->sweep_index % 2 == 1) ? DIR_DOWN : DIR_UP;
+    const bool rebuild = (dir == DIR_UP) ? !ctx->right_valid : !ctx->left_valid;
+    if (ctx->profiling) {
+      ST_TRY(enqueue_sweep(ctx, dir, rebuild));
+    } else {
+      hipGraphExec_t& ex = ctx->exec[dir][rebuild ? 1 : 0];
+      if (!ex) {
+        HQ_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        hq_status st = enqueue_sweep(ctx, dir, rebuild);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+        if (st != HQ_OK) return st;
+        if (e != hipSuccess) return fail(ctx, HQ_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        ctx->graph[dir][rebuild ? 1 : 0] = graph;
+        HQ_TRY(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0));
+      }
+      HQ_TRY(hipGraphLaunch(ex, ctx->stream));
+    }
+    ctx->sweep_index += 1;
+    // an upward sweep leaves every left stack entry current, a downward one every right entry
+    ctx->left_valid = (dir == DIR_UP);
+    ctx->right_valid = (dir == DIR_DOWN);
   }
-  if (!ctx->exec) {
-    HQ_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    hq_status st = enqueue_sweep(ctx);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
-    if (st != HQ_OK) return st;
-    if (e != hipSuccess) return fail(ctx, HQ_EDEVICE, "graph capture: %s", hipGetErrorString(e));
-    ctx->graph = graph;
-    HQ_TRY(hipGraphInstantiate(&ctx->exec, graph, nullptr, nullptr, 0));
-  }
-  for (int k = 0; k < n_sweeps; ++k) HQ_TRY(hipGraphLaunch(ctx->exec, ctx->stream));
+  if (ctx->profiling) return collect_profile(ctx);
   return HQ_OK;
 }
 
 hq_status hq_recompute(hq_ctx* ctx) {
   ST_TRY(check_ctx(ctx));
+  ctx->left_valid = ctx->right_valid = false;
   ST_TRY(recompute_all(ctx));
   return sync(ctx);
 }
@@ -973,12 +1139,15 @@ hq_status hq_set_replay(hq_ctx* ctx, int32_t chain, int32_t kind, const uint8_t*
     return fail(ctx, HQ_EINVAL, "bad chain or kind");
   const long slots = g->kind_slots(kind);
   if (!(band >= 0) || (n != 0 && (n != slots || !bits))) return fail(ctx, HQ_EINVAL, "expected %ld bits", slots);
-  if (g->band[kind] != band && ctx->exec) {
-    // the band is a kernel argument: rebuild the graph
-    hipGraphExecDestroy(ctx->exec);
-    hipGraphDestroy(ctx->graph);
-    ctx->exec = nullptr;
-    ctx->graph = nullptr;
+  if (g->band[kind] != band) {
+    // the band is a kernel argument: the captured graphs are rebuilt on next use
+    for (int d = 0; d < 2; ++d)
+      for (int r = 0; r < 2; ++r) {
+        if (ctx->exec[d][r]) (void)hipGraphExecDestroy(ctx->exec[d][r]);
+        if (ctx->graph[d][r]) (void)hipGraphDestroy(ctx->graph[d][r]);
+        ctx->exec[d][r] = nullptr;
+        ctx->graph[d][r] = nullptr;
+      }
   }
   g->band[kind] = band;
   if (n == 0) {
@@ -1059,10 +1228,19 @@ const char* hq_last_error(const hq_ctx* ctx) { return ctx ? ctx->err.c_str() : "
 void hq_destroy(hq_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
-  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  for (int d = 0; d < 2; ++d)
+    for (int r = 0; r < 2; ++r) {
+      if (ctx->exec[d][r]) (void)hipGraphExecDestroy(ctx->exec[d][r]);
+      if (ctx->graph[d][r]) (void)hipGraphDestroy(ctx->graph[d][r]);
+    }
   for (auto& pe : ctx->pending) { (void)hipEventDestroy(pe.first); (void)hipEventDestroy(pe.second); }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  for (auto st : ctx->side) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (auto e : ctx->join) (void)hipEventDestroy(e);
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   delete ctx;
 }
 

@@ -20,7 +20,7 @@ struct Scale {
   int invert = 0;
 };
 
-// C[z] = alpha * diag(rs) * op(A[z]) * op(B[z]) * diag(cs) + beta * C[z]
+// C[z] = alpha * diag(rs) * op(A[z]) * diag(ks) * op(B[z]) * diag(cs) + beta * C[z]
 // for z in [0, batch); matrices row-major.  op = transpose when trans != 0.
 // Matrix pointers advance by the stride per batch entry (stride 0 = shared).
 template <typename T>
@@ -30,7 +30,7 @@ struct GemmArgs {
   const T* B = nullptr; long ldb = 0, sB = 0; int tB = 0;
   T* C = nullptr; long ldc = 0, sC = 0;
   double alpha = 1.0, beta = 0.0;
-  Scale rs, cs;
+  Scale rs, cs, ks;                        // ks: on the inner index, K <= 256
   int batch = 1, inner_count = 1;
 };
 

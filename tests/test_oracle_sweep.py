@@ -61,6 +61,46 @@ def test_wrap_matches_recompute():
         assert np.max(np.abs(ch.G - G_ref)) < 1e-12
 
 
+def test_unwrap_matches_recompute():
+    """B_l^-1 G_l B_l = G_{l-1}, both from scratch."""
+    p = small_params()
+    ch = dqmc.Chain(p, seed=8, chain=0)
+    for l in range(p.L):
+        ch.G, _ = udt.green_and_logdet(p, ch.expk, ch.x, (l + 1) % p.L)   # G_l, fresh
+        ch.unwrap(l)
+        G_ref, _ = udt.green_and_logdet(p, ch.expk, ch.x, l)             # G_{l-1}
+        assert np.max(np.abs(ch.G - G_ref)) < 1e-12
+
+
+def test_downward_sweep_tracks_recompute():
+    """A downward sweep: after the moves of slice l the tracked G equals G_l from
+    scratch; its slice order and recompute points are as documented."""
+    p = small_params(g=1.5, local_width=1.0)
+    ch = dqmc.Chain(p, seed=3, chain=1)
+    ch.sweep()
+    assert ch.downward()
+    seen = []
+    orig = ch.local_move
+
+    def spy(l, i):
+        if i == 0:
+            G_ref, _ = udt.green_and_logdet(p, ch.expk, ch.x, (l + 1) % p.L)
+            assert np.max(np.abs(ch.G - G_ref)) < 1e-10
+            seen.append(l)
+        return orig(l, i)
+
+    ch.local_move = spy
+    ch.sweep()
+    assert seen == list(range(p.L - 1, -1, -1))
+    G_ref, ld_ref = udt.green_and_logdet(p, ch.expk, ch.x, 0)
+    assert np.max(np.abs(ch.G - G_ref)) < 1e-13 and abs(ch.logdet - ld_ref) < 1e-12
+    assert ch.max_drift_g < 1e-10
+    # block moves keep every sweep upward
+    q = dqmc.Chain(small_params(global_width=1.0), seed=3, chain=1)
+    q.sweep()
+    assert not q.downward()
+
+
 def test_sweep_invariants_and_decision_log():
     p = small_params(beta=4.0, n_stab=10)
     ch = dqmc.Chain(p, seed=1, chain=0)
@@ -136,10 +176,12 @@ def test_sampling_two_slice_atomic_limit():
     """t = 0, N = 1, L = 2: the chain samples W(x0, x1) = exp(-S_b) (1 + e^{-dtau g (x0+x1)})^2.
 
     Moments of x0 + x1 from the Markov chain against 2-D quadrature of the explicit weight."""
-    p = Params(nx=1, t=0.0, mu=0.0, beta=0.2, dtau=0.1, g=1.5, omega=1.0, n_stab=2, local_width=1.5)
+    # a stiff oscillator (Omega = 5) keeps the autocorrelation far below the bin length; with
+    # Omega = 1 the sum x0 + x1 random-walks for hundreds of sweeps and binned errors undercount
+    p = Params(nx=1, t=0.0, mu=0.0, beta=0.2, dtau=0.1, g=1.5, omega=5.0, n_stab=2, local_width=1.0)
     ch = dqmc.Chain(p, seed=17, chain=0, x=np.zeros((2, 1)))
     samples = []
-    for _ in range(6000):
+    for _ in range(12000):
         ch.sweep()
         samples.append(float(ch.x[0, 0] + ch.x[1, 0]))
     samples = samples[200:]
