@@ -116,6 +116,9 @@ def run_workload(w, steps, warmup, profile=True):
     from paper_1905_07440_amd import hq
 
     ctx = hq.Context(hq.groups_from_workload(w), precision=w.precision, seed=w.seed, delay=w.delay)
+    if any(g.proposal == 1 for g in w.groups):
+        import workloads
+        ctx.set_network(workloads.random_network(1001))   # seeded random weights, no trained set
     stream = ctx._stream
     ctx.sweep(warmup)
     ctx.synchronize()
@@ -138,6 +141,11 @@ def run_workload(w, steps, warmup, profile=True):
         "max_drift_logdet": max(s["max_drift_logdet"] for s in stats),
         "tuning": [ctx.tuning(k) for k in range(len(w.groups))],
     }
+    c0, by_group = 0, []
+    for g in w.groups:
+        by_group.append(max(s["max_drift_green"] for s in stats[c0:c0 + g.n_chains]))
+        c0 += g.n_chains
+    out["max_drift_green_by_group"] = by_group
     if profile:
         ctx.set_profiling(True)
         ctx.sweep(1)
@@ -159,6 +167,8 @@ def local_roofline(w, res):
     the dense MFMA peak of the precision G is held in."""
     g = w.groups[0]
     n = g.nx * g.nx
+    if "local" not in res["phases"]:
+        return None            # network groups: proposals come from the network kernel, no local-move launches
     per_launch_s = res["phases"]["local"]["us_per_region"] * 1e-6
     flops = g.n_chains * res["local_acceptance"] * n * 2.0 * n * n
     peak = MI355X_PEAK["fp32" if w.precision else "fp64"]
@@ -212,7 +222,9 @@ def main():
                    "L": [round(g.beta / g.dtau) for g in w.groups], "n_stab": g0.n_stab,
                    "precision": "mixed" if w.precision else "fp64", "delay": w.delay or 16,
                    "parallelism": "independent chains, one GPU"},
-        "accuracy": {"max_abs_G_minus_fp64": res["max_drift_green"], "max_logdet_err": res["max_drift_logdet"],
+        "accuracy": {"max_abs_G_minus_fp64": res["max_drift_green"],
+                     "max_abs_G_minus_fp64_by_group": res["max_drift_green_by_group"],
+                     "max_logdet_err": res["max_drift_logdet"],
                      "log_weight_err": 2 * res["max_drift_logdet"], "gate_1e-5": res["max_drift_green"] <= 1e-5},
         "local_acceptance": res["local_acceptance"],
         "tuning": res["tuning"],

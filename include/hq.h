@@ -171,6 +171,15 @@ typedef struct {
   double gemm_us_fp64, gemm_us_wrap;   /* measured time of one batched product */
 } hq_tuning;
 hq_status hq_read_tuning(const hq_ctx* ctx, int32_t group, hq_tuning* out);
+
+/* Pin one group's GEMM tiles in place of the autotuner's choice (for
+ * reproducible timings and for testing every tile).  Codes are those of
+ * hq_read_tuning, 0 .. 10.  HQ_EINVAL, with nothing changed, for an unknown
+ * code, a tile that does not fit the group's N in that precision, or, in FP64
+ * precision, tile_wrap != tile_fp64.  Waits for the context's stream; the
+ * sweep graphs are captured again on the next hq_sweep.  The timings that
+ * hq_read_tuning reports become 0. */
+hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t tile_wrap);
 const char* hq_gemm_tile_name(int32_t tile);
 
 /* Wait for all work on the context's stream. */

@@ -225,6 +225,143 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_fullk_kernel(GemmArgs<T> a)
       }
 }
 
+// Register-prefetch variant: every thread loads its share of the whole
+// BM x K panel of op(A) and K x BN panel of op(B) into registers at once (one
+// memory latency for the tile), then the K extent passes through two small
+// LDS buffers 16 at a time.  LDS stays small, so many tiles share a CU.
+// KC = number of 16-wide K chunks the registers can hold (K <= 16 KC).
+template <typename T, int BM, int BN, int WM, int WN, int KC>
+__global__ __launch_bounds__(WM * WN * 64) void gemm_regpf_kernel(GemmArgs<T> a) {
+  constexpr int NT = WM * WN * 64;
+  constexpr int BK = 16;
+  constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
+  constexpr int PA = BM * BK / NT, PB = BN * BK / NT;   // elements per thread per chunk
+  static_assert(PA * NT == BM * BK && PB * NT == BN * BK, "tile must split evenly");
+  constexpr int PAD = 1;
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
+  __shared__ double rsv[BM];
+  __shared__ double csv[BN];
+  __shared__ double ksv[256];
+
+  const int z = blockIdx.z;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave / WN, wn = wave % WN;
+  const T* A = a.A + (long)z * a.sA;
+  const T* B = a.B + (long)z * a.sB;
+  T* C = a.C + (long)z * a.sC;
+  const int nchunk = (a.K + BK - 1) / BK;
+
+  for (int i = tid; i < BM; i += NT)
+    rsv[i] = (m0 + i < a.M) ? scale_value(a.rs, z, a.inner_count, m0 + i) : 0.0;
+  for (int i = tid; i < BN; i += NT)
+    csv[i] = (n0 + i < a.N) ? scale_value(a.cs, z, a.inner_count, n0 + i) : 0.0;
+  const bool kscale = a.ks.v != nullptr;
+  if (kscale)
+    for (int i = tid; i < a.K; i += NT) ksv[i] = scale_value(a.ks, z, a.inner_count, i);
+
+  // element e of a chunk -> (row, k) with consecutive threads on the source's contiguous index
+  auto a_pos = [&](int e, int& m, int& k) {
+    if (a.tA) { m = e % BM; k = e / BM; } else { m = e / BK; k = e % BK; }
+  };
+  auto b_pos = [&](int e, int& k, int& n) {
+    if (a.tB) { n = e / BK; k = e % BK; } else { k = e / BN; n = e % BN; }
+  };
+  T ra[KC][PA], rb[KC][PB];
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      int m, k;
+      a_pos(tid + NT * q, m, k);
+      const int gm = m0 + m, gk = BK * c + k;
+      ra[c][q] = (c < nchunk && gm < a.M && gk < a.K) ? (a.tA ? A[(long)gk * a.lda + gm] : A[(long)gm * a.lda + gk])
+                                                      : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      int k, n;
+      b_pos(tid + NT * q, k, n);
+      const int gn = n0 + n, gk = BK * c + k;
+      rb[c][q] = (c < nchunk && gn < a.N && gk < a.K) ? (a.tB ? B[(long)gn * a.ldb + gk] : B[(long)gk * a.ldb + gn])
+                                                      : T(0);
+    }
+  }
+  __syncthreads();                         // rsv, csv, ksv
+
+  typedef typename Frag<T>::type F;
+  F acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = F{0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < KC; ++c) {
+    if (c < nchunk) {                      // the same for every thread
+      const int buf = c & 1;
+#pragma unroll
+      for (int q = 0; q < PA; ++q) {
+        int m, k;
+        a_pos(tid + NT * q, m, k);
+        As[buf][k][m] = ra[c][q];
+      }
+#pragma unroll
+      for (int q = 0; q < PB; ++q) {
+        int k, n;
+        b_pos(tid + NT * q, k, n);
+        const int gk = BK * c + k;        // rb is 0 past K; ksv is only written below K
+        Bs[buf][k][n] = (kscale && gk < a.K) ? (T)((double)rb[c][q] * ksv[gk]) : rb[c][q];
+      }
+      __syncthreads();                     // buffer c & 1 is complete; buffer (c+1) & 1 was read before the last barrier
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        T af[FM], bf[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) af[i] = As[buf][kk + (lane >> 4)][wm * FM * 16 + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bf[j] = Bs[buf][kk + (lane >> 4)][wn * FN * 16 + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = wm * FM * 16 + i * 16 + frag_row<T>(lane, v);
+        const int lc = wn * FN * 16 + j * 16 + (lane & 15);
+        const int r = m0 + lr, c = n0 + lc;
+        if (r < a.M && c < a.N) {
+          double val = a.alpha * rsv[lr] * (double)acc[i][j][v] * csv[lc];
+          T* dst = C + (long)r * a.ldc + c;
+          if (a.beta != 0.0) val += a.beta * (double)(*dst);
+          *dst = (T)val;
+        }
+      }
+}
+
+template <typename T, int BM, int BN, int WM, int WN>
+static hipError_t launch_regpf(const GemmArgs<T>& a, hipStream_t s) {
+  if (a.K > 256) return hipErrorInvalidValue;
+  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, a.batch);
+  if (a.K <= 160) {
+    hipLaunchKernelGGL((gemm_regpf_kernel<T, BM, BN, WM, WN, 10>), grid, dim3(WM * WN * 64), 0, s, a);
+  } else {
+    // a single-wave tile would need 256 K values per thread: it only takes K <= 160
+    if constexpr (WM * WN == 1) return hipErrorInvalidValue;
+    else hipLaunchKernelGGL((gemm_regpf_kernel<T, BM, BN, WM, WN, 16>), grid, dim3(WM * WN * 64), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 template <typename T, int BM, int BN>
 static size_t fullk_lds(int K) { return sizeof(T) * (size_t)((K + 3) & ~3) * (BM + BN + 4); }
 
@@ -256,6 +393,9 @@ static hipError_t launch_any(const GemmArgs<T>& a, int tile, hipStream_t s) {
     case TILE_FK_48x48: return launch_fullk<T, 48, 48, 3, 1>(a, s);
     case TILE_FK_64x64: return launch_fullk<T, 64, 64, 2, 2>(a, s);
     case TILE_FK_32x64: return launch_fullk<T, 32, 64, 1, 2>(a, s);
+    case TILE_PF_48x48: return launch_regpf<T, 48, 48, 3, 1>(a, s);
+    case TILE_PF_64x64: return launch_regpf<T, 64, 64, 2, 2>(a, s);
+    case TILE_PF_32x32: return launch_regpf<T, 32, 32, 1, 1>(a, s);
     default: return launch_tile<T, 64, 64, 2, 2>(a, s);
   }
 }
@@ -270,6 +410,9 @@ bool gemm_tile_fits(int tile, int K, int precision) {
     case TILE_FK_48x48: return (f ? fullk_lds<float, 48, 48>(K) : fullk_lds<double, 48, 48>(K)) <= 150 * 1024;
     case TILE_FK_64x64: return (f ? fullk_lds<float, 64, 64>(K) : fullk_lds<double, 64, 64>(K)) <= 150 * 1024;
     case TILE_FK_32x64: return (f ? fullk_lds<float, 32, 64>(K) : fullk_lds<double, 32, 64>(K)) <= 150 * 1024;
+    case TILE_PF_48x48:
+    case TILE_PF_64x64: return K <= 256;
+    case TILE_PF_32x32: return K <= 160;
     default: return true;
   }
 }

@@ -782,7 +782,7 @@ hq_status autotune(hq_ctx* ctx) {
   HQ_TRY(hipEventCreate(&e0));
   HQ_TRY(hipEventCreate(&e1));
   const int cands[] = {TILE_64x64, TILE_32x32, TILE_48x48, TILE_FK_32x32, TILE_FK_48x48, TILE_FK_64x64,
-                       TILE_FK_32x64};
+                       TILE_FK_32x64, TILE_PF_48x48, TILE_PF_64x64, TILE_PF_32x32};
   hq_status st = HQ_OK;
   for (Group& g : ctx->groups) {
     const long nn = (long)g.n * g.n;
@@ -1131,6 +1131,18 @@ hq_status hq_read_decisions(hq_ctx* ctx, int32_t chain, int32_t kind, uint8_t* a
   return HQ_OK;
 }
 
+// Captured sweeps bake in kernel arguments and launch shapes; after a change
+// of either they are captured again on the next hq_sweep.
+static void drop_graphs(hq_ctx* ctx) {
+  for (int d = 0; d < 2; ++d)
+    for (int r = 0; r < 2; ++r) {
+      if (ctx->exec[d][r]) (void)hipGraphExecDestroy(ctx->exec[d][r]);
+      if (ctx->graph[d][r]) (void)hipGraphDestroy(ctx->graph[d][r]);
+      ctx->exec[d][r] = nullptr;
+      ctx->graph[d][r] = nullptr;
+    }
+}
+
 hq_status hq_set_replay(hq_ctx* ctx, int32_t chain, int32_t kind, const uint8_t* bits, int64_t n, double band) {
   ST_TRY(check_ctx(ctx));
   int lc = 0;
@@ -1139,16 +1151,8 @@ hq_status hq_set_replay(hq_ctx* ctx, int32_t chain, int32_t kind, const uint8_t*
     return fail(ctx, HQ_EINVAL, "bad chain or kind");
   const long slots = g->kind_slots(kind);
   if (!(band >= 0) || (n != 0 && (n != slots || !bits))) return fail(ctx, HQ_EINVAL, "expected %ld bits", slots);
-  if (g->band[kind] != band) {
-    // the band is a kernel argument: the captured graphs are rebuilt on next use
-    for (int d = 0; d < 2; ++d)
-      for (int r = 0; r < 2; ++r) {
-        if (ctx->exec[d][r]) (void)hipGraphExecDestroy(ctx->exec[d][r]);
-        if (ctx->graph[d][r]) (void)hipGraphDestroy(ctx->graph[d][r]);
-        ctx->exec[d][r] = nullptr;
-        ctx->graph[d][r] = nullptr;
-      }
-  }
+  // the band is a kernel argument: the captured graphs are rebuilt on next use
+  if (g->band[kind] != band) drop_graphs(ctx);
   g->band[kind] = band;
   if (n == 0) {
     HQ_TRY(launch_fill_u8(g->replay[kind] + lc * slots, 255, slots, ctx->stream));
@@ -1204,6 +1208,25 @@ hq_status hq_read_tuning(const hq_ctx* ctx, int32_t group, hq_tuning* out) {
   return HQ_OK;
 }
 
+hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t tile_wrap) {
+  ST_TRY(check_ctx(ctx));
+  if (group < 0 || group >= (int32_t)ctx->groups.size()) return fail(ctx, HQ_EINVAL, "bad group %d", group);
+  Group& g = ctx->groups[group];
+  const bool mixed = ctx->opt.precision == HQ_PREC_MIXED;
+  if (tile_fp64 < 0 || tile_fp64 >= N_GEMM_TILES || !gemm_tile_fits(tile_fp64, g.n, 0))
+    return fail(ctx, HQ_EINVAL, "GEMM tile %d does not fit FP64 products of size %d", tile_fp64, g.n);
+  if (tile_wrap < 0 || tile_wrap >= N_GEMM_TILES || !gemm_tile_fits(tile_wrap, g.n, mixed ? 1 : 0))
+    return fail(ctx, HQ_EINVAL, "GEMM tile %d does not fit the wraps' products of size %d", tile_wrap, g.n);
+  if (!mixed && tile_wrap != tile_fp64)
+    return fail(ctx, HQ_EINVAL, "in FP64 precision the wraps use the FP64 tile");
+  HQ_TRY(hipStreamSynchronize(ctx->stream));
+  drop_graphs(ctx);
+  g.tile = tile_fp64;
+  g.tile32 = tile_wrap;
+  g.tile_us = g.tile32_us = 0.0;
+  return HQ_OK;
+}
+
 const char* hq_gemm_tile_name(int32_t tile) {
   switch (tile) {
     case TILE_64x64: return "64x64/k16";
@@ -1214,6 +1237,9 @@ const char* hq_gemm_tile_name(int32_t tile) {
     case TILE_FK_48x48: return "48x48/fullk";
     case TILE_FK_64x64: return "64x64/fullk";
     case TILE_FK_32x64: return "32x64/fullk";
+    case TILE_PF_48x48: return "48x48/prefetch";
+    case TILE_PF_64x64: return "64x64/prefetch";
+    case TILE_PF_32x32: return "32x32/prefetch";
     default: return "?";
   }
 }

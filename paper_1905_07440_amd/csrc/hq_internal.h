@@ -36,8 +36,10 @@ struct GemmArgs {
 
 // GEMM tile configurations (see gemm.hip); the autotuner picks one per shape.
 // TILE_FK_*: the whole K extent staged at once (needs K small enough for LDS).
+// TILE_PF_*: each thread prefetches its whole share of K into registers.
 enum GemmTile { TILE_64x64 = 0, TILE_32x32 = 1, TILE_48x48 = 2, TILE_16x64 = 3, TILE_FK_32x32 = 4, TILE_FK_48x48 = 5,
-                TILE_FK_64x64 = 6, TILE_FK_32x64 = 7, N_GEMM_TILES = 8 };
+                TILE_FK_64x64 = 6, TILE_FK_32x64 = 7, TILE_PF_48x48 = 8, TILE_PF_64x64 = 9, TILE_PF_32x32 = 10,
+                N_GEMM_TILES = 11 };
 
 hipError_t launch_gemm(const GemmArgs<double>& a, int tile, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs<float>& a, int tile, hipStream_t s);

@@ -67,11 +67,18 @@ class Tuning(ctypes.Structure):
                 ("gemm_us_wrap", ctypes.c_double)]
 
 
+N_GEMM_TILES = 11
+
+def tile_name(code):
+    """Name of a GEMM tile code ("?" for an unknown one)."""
+    return load().hq_gemm_tile_name(code).decode()
+
+
 EXPORTS = [
     "hq_workspace_bytes", "hq_create", "hq_set_fields", "hq_set_network", "hq_sweep",
     "hq_recompute", "hq_read_green", "hq_read_fields", "hq_read_stats", "hq_read_decisions",
     "hq_set_replay", "hq_num_chains", "hq_chain_shape", "hq_set_profiling", "hq_phase_time",
-    "hq_read_tuning", "hq_gemm_tile_name", "hq_synchronize", "hq_last_error", "hq_destroy",
+    "hq_read_tuning", "hq_set_tuning", "hq_gemm_tile_name", "hq_synchronize", "hq_last_error", "hq_destroy",
 ]
 
 _lib = None
@@ -106,6 +113,7 @@ def load(path=LIB_PATH):
     lib.hq_set_profiling.argtypes = [P, I32]
     lib.hq_phase_time.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)]
     lib.hq_read_tuning.argtypes = [P, I32, ctypes.POINTER(Tuning)]
+    lib.hq_set_tuning.argtypes = [P, I32, I32, I32]
     lib.hq_gemm_tile_name.argtypes = [I32]
     lib.hq_gemm_tile_name.restype = ctypes.c_char_p
     lib.hq_synchronize.argtypes = [P]
@@ -231,6 +239,12 @@ class Context:
         ms, k = ctypes.c_double(), ctypes.c_int64()
         self._check(self._lib.hq_phase_time(self._ctx, phase.encode(), ctypes.byref(ms), ctypes.byref(k)))
         return ms.value, k.value
+
+    def set_tuning(self, group, tile_fp64, tile_wrap=None):
+        """Pin a group's GEMM tiles (codes 0 .. N_GEMM_TILES-1; the wraps take
+        tile_fp64 when tile_wrap is None)."""
+        self._check(self._lib.hq_set_tuning(self._ctx, group, tile_fp64,
+                                            tile_fp64 if tile_wrap is None else tile_wrap))
 
     def tuning(self, group):
         """The autotuner's choices for one group (GEMM tiles by name, timings in us)."""

@@ -164,8 +164,10 @@ def test_batched_8x8_full_size_sampled(hq):
     ctx.close()
 
 
-def _mixed_replay_case(hq, gr, chains_to_check, seed, sweeps=1):
+def _mixed_replay_case(hq, gr, chains_to_check, seed, sweeps=1, setup=None):
     ctx = make_ctx(hq, [gr], precision=1, seed=seed, delay=32)
+    if setup is not None:
+        setup(ctx)
     oracles = {c: dqmc.Chain(params_of(gr), seed, c) for c in chains_to_check}
     for s in range(sweeps):
         for c, ch in oracles.items():
@@ -196,6 +198,54 @@ def test_mixed_12x12_full_size_sampled(hq):
     say("12x12 x128 mixed full size")
     _mixed_replay_case(hq, dict(nx=g.nx, chains=g.n_chains, g=g.g, beta=g.beta, n_stab=g.n_stab),
                        (0, 127), seed=w.seed)
+
+
+_TILE_CASE = dict(nx=10, chains=2, g=1.3, beta=2.0, n_stab=5)
+_tile_oracle = {}
+
+
+@pytest.mark.parametrize("tile", range(11))
+def test_every_gemm_tile_fp64(hq, tile):
+    """Each GEMM tile pinned in turn (N = 100: whole tiles plus a ragged edge
+    for the 32, 48 and 64 tiles), an upward and a downward sweep in FP64."""
+    say("FP64 sweeps with GEMM tile %s" % hq.tile_name(tile))
+    gr = _TILE_CASE
+    ctx = make_ctx(hq, [gr], seed=13)
+    ctx.set_tuning(0, tile)
+    assert ctx.tuning(0)["gemm_tile_fp64"] == hq.tile_name(tile)
+    ctx.sweep(2)
+    if not _tile_oracle:
+        for c in range(2):
+            ch = dqmc.Chain(params_of(gr), 13, c)
+            ch.sweep(); ch.sweep()
+            _tile_oracle[c] = ch
+    for c in range(2):
+        assert_state(ctx, c, _tile_oracle[c], TOL64, "tile %d chain %d" % (tile, c))
+    ctx.close()
+
+
+@pytest.mark.parametrize("tile", range(11))
+def test_every_gemm_tile_mixed_wraps(hq, tile):
+    """Each tile pinned for the FP32 wraps of a mixed-precision sweep."""
+    say("mixed sweep with FP32 GEMM tile %s" % hq.tile_name(tile))
+    _mixed_replay_case(hq, dict(_TILE_CASE, n_stab=4), (0,), seed=13,
+                       sweeps=2, setup=lambda ctx: ctx.set_tuning(0, 0, tile))
+
+
+def test_set_tuning_rejects_bad_tiles(hq):
+    say("set_tuning errors")
+    ctx = make_ctx(hq, [dict(nx=16, chains=1, beta=0.4, n_stab=2)])
+    with pytest.raises(hq.HQError):
+        ctx.set_tuning(0, hq.N_GEMM_TILES)
+    with pytest.raises(hq.HQError):
+        ctx.set_tuning(0, 0, 1)                 # FP64 wraps must use the FP64 tile
+    with pytest.raises(hq.HQError):
+        ctx.set_tuning(0, 10)                   # 32x32 prefetch holds K <= 160; here K = 256
+    with pytest.raises(hq.HQError):
+        ctx.set_tuning(1, 0)
+    ctx.sweep(1)
+    assert ctx.stats(0)["local_proposals"] == 256 * 4
+    ctx.close()
 
 
 def test_uneven_groups_per_chain_coupling(hq):
