@@ -5,7 +5,8 @@
 // FP64 uses v_mfma_f64_16x16x4f64, FP32 uses v_mfma_f32_16x16x4f32 with
 // FP32 accumulation.  A workgroup tile of BM x BN is split over WM x WN
 // waves, each computing FM x FN fragments of 16 x 16; K advances in stages
-// of BK = 16 staged through LDS.  Edges are zero-padded on load and masked
+// of BK = 16 through two LDS buffers, the next stage's loads in flight while
+// the current one is multiplied.  Edges are zero-padded on load and masked
 // on store, so any M, N, K works.
 #include "hq_device.h"
 #include "hq_internal.h"
@@ -21,26 +22,32 @@ __device__ inline double scale_value(const Scale& s, int z, int inner_count, int
   return v;
 }
 
+// K staged 16 at a time through two LDS buffers: while the waves multiply
+// out of one buffer, every thread's loads of the next 16-wide K chunk are in
+// flight, and one barrier per chunk separates the two.
 template <typename T, int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
   constexpr int NT = WM * WN * 64;
   constexpr int BK = 16;
   constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
-  constexpr int PAD = 2;
+  constexpr int PA = (BM * BK + NT - 1) / NT, PB = (BN * BK + NT - 1) / NT;   // loads per thread per chunk
+  constexpr int PAD = 1;
   static_assert(FM >= 1 && FN >= 1, "tile too small");
-  __shared__ T As[BK][BM + PAD];
-  __shared__ T Bs[BK][BN + PAD];
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
   __shared__ double rsv[BM];
   __shared__ double csv[BN];
   __shared__ double ksv[256];
 
   const int z = blockIdx.z;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
   const T* A = a.A + (long)z * a.sA;
   const T* B = a.B + (long)z * a.sB;
   T* C = a.C + (long)z * a.sC;
+  const int nchunk = (a.K + BK - 1) / BK;
 
   for (int i = tid; i < BM; i += NT)
     rsv[i] = (m0 + i < a.M) ? scale_value(a.rs, z, a.inner_count, m0 + i) : 0.0;
@@ -49,7 +56,52 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
   const bool kscale = a.ks.v != nullptr;
   if (kscale)
     for (int i = tid; i < a.K; i += NT) ksv[i] = scale_value(a.ks, z, a.inner_count, i);
-  __syncthreads();
+
+  // chunk element e -> (row, k), consecutive threads on the source's contiguous index
+  auto a_pos = [&](int e, int& m, int& k) {
+    if (a.tA) { m = e % BM; k = e / BM; } else { m = e / BK; k = e % BK; }
+  };
+  auto b_pos = [&](int e, int& k, int& n) {
+    if (a.tB) { n = e / BK; k = e % BK; } else { k = e / BN; n = e % BN; }
+  };
+  T ra[PA], rb[PB];
+  auto load = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      const int e = tid + NT * q;
+      int m, k;
+      a_pos(e, m, k);
+      const int gm = m0 + m, gk = BK * c + k;
+      ra[q] = (e < BM * BK && gm < a.M && gk < a.K) ? (a.tA ? A[(long)gk * a.lda + gm] : A[(long)gm * a.lda + gk])
+                                                    : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int e = tid + NT * q;
+      int k, n;
+      b_pos(e, k, n);
+      const int gn = n0 + n, gk = BK * c + k;
+      rb[q] = (e < BN * BK && gn < a.N && gk < a.K) ? (a.tB ? B[(long)gn * a.ldb + gk] : B[(long)gk * a.ldb + gn])
+                                                    : T(0);
+    }
+  };
+  auto store = [&](int c, int buf) {
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      const int e = tid + NT * q;
+      int m, k;
+      a_pos(e, m, k);
+      if (e < BM * BK) As[buf][k][m] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int e = tid + NT * q;
+      int k, n;
+      b_pos(e, k, n);
+      const int gk = BK * c + k;           // rb is 0 past K; ksv is only written below K
+      if (e < BN * BK) Bs[buf][k][n] = (kscale && gk < a.K) ? (T)((double)rb[q] * ksv[gk]) : rb[q];
+    }
+  };
 
   typedef typename Frag<T>::type F;
   F acc[FM][FN];
@@ -58,41 +110,27 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = F{0, 0, 0, 0};
 
-  for (int k0 = 0; k0 < a.K; k0 += BK) {
-    // stage A: As[k][m] = op(A)(m0+m, k0+k)
-    for (int e = tid; e < BM * BK; e += NT) {
-      int m, k;
-      if (a.tA) { m = e % BM; k = e / BM; } else { k = e % BK; m = e / BK; }
-      const int gm = m0 + m, gk = k0 + k;
-      T v = 0;
-      if (gm < a.M && gk < a.K) v = a.tA ? A[(long)gk * a.lda + gm] : A[(long)gm * a.lda + gk];
-      As[k][m] = v;
-    }
-    // stage B: Bs[k][n] = op(B)(k0+k, n0+n)
-    for (int e = tid; e < BN * BK; e += NT) {
-      int n, k;
-      if (a.tB) { k = e % BK; n = e / BK; } else { n = e % BN; k = e / BN; }
-      const int gn = n0 + n, gk = k0 + k;
-      T v = 0;
-      if (gn < a.N && gk < a.K) {
-        v = a.tB ? B[(long)gn * a.ldb + gk] : B[(long)gk * a.ldb + gn];
-        if (kscale) v = (T)((double)v * ksv[gk]);
-      }
-      Bs[k][n] = v;
-    }
-    __syncthreads();
+  load(0);
+  __syncthreads();                         // rsv, csv, ksv
+  store(0, 0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunk) load(c + 1);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T af[FM], bf[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = As[kk + (lane >> 4)][wm * FM * 16 + i * 16 + (lane & 15)];
+      for (int i = 0; i < FM; ++i) af[i] = As[buf][kk + (lane >> 4)][wm * FM * 16 + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = Bs[kk + (lane >> 4)][wn * FN * 16 + j * 16 + (lane & 15)];
+      for (int j = 0; j < FN; ++j) bf[j] = Bs[buf][kk + (lane >> 4)][wn * FN * 16 + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
     }
+    // buffer buf ^ 1 was last read before the previous barrier
+    if (c + 1 < nchunk) store(c + 1, buf ^ 1);
     __syncthreads();
   }
 
@@ -386,7 +424,7 @@ static hipError_t launch_any(const GemmArgs<T>& a, int tile, hipStream_t s) {
   if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
   if (a.ks.v && a.K > 256) return hipErrorInvalidValue;   // the inner scale is staged in LDS
   switch (tile) {
-    case TILE_32x32: return launch_tile<T, 32, 32, 1, 1>(a, s);
+    case TILE_32x32: return launch_tile<T, 32, 32, 2, 2>(a, s);
     case TILE_48x48: return launch_tile<T, 48, 48, 3, 1>(a, s);
     case TILE_16x64: return launch_tile<T, 16, 64, 1, 4>(a, s);
     case TILE_FK_32x32: return launch_fullk<T, 32, 32, 1, 1>(a, s);
