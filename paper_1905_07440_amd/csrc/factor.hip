@@ -66,44 +66,89 @@ __device__ inline double wave_total(double v) {
   return lane_value(v, 63);
 }
 
+// 1 / x by the hardware estimate and two Newton steps (x finite, nonzero,
+// not subnormal): within an ulp or so of the correctly rounded quotient
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
+// maximum over the 64 lanes of an unsigned key, returned uniform (the same
+// exchange pattern as wave_total)
+template <int CTRL, int ROWMASK = 0xF>
+__device__ inline uint32_t dpp_move_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xF, false);
+}
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, dpp_move_u32<0xB1>(v));
+  v = max(v, dpp_move_u32<0x4E>(v));
+  v = max(v, dpp_move_u32<0x141>(v));
+  v = max(v, dpp_move_u32<0x140>(v));
+  v = max(v, dpp_move_u32<0x142, 0xA>(v));
+  v = max(v, dpp_move_u32<0x143, 0xC>(v));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // totals over the 64 lanes of 16 values at once, returned wave-uniform: a
-// butterfly in which every exchange halves the values a lane carries (lanes
-// l and l ^ 32 keep the lower and upper eight, and so on), 17 exchanges in
-// all instead of 16 separate six-step reductions.  Afterwards lane l holds
-// the total of value (l >> 2) & 15.
+// butterfly in which every exchange halves the values a lane carries, 15
+// exchanges in all instead of 16 separate six-step reductions, none through
+// LDS.  Lane halves (bit 5) and row pairs (bit 4) trade through the
+// permlane swaps: after swapping the upper lanes of x with the lower lanes of
+// y, x + y is, on every lane, the kept value plus the partner's matching one.
+// Bit 3 pairs lanes by a row rotation of 8 and bit 2 by the half-row mirror
+// (lane ^ 7), whose partners agree on every bit already reduced.  Afterwards
+// lane l holds the total of value (l >> 2) & 15.
+__device__ inline double swap_sum32(double lo_half, double hi_half) {
+  // x: values the lower lanes keep; y: values the upper lanes keep
+  const auto l = __builtin_amdgcn_permlane32_swap(__double2loint(lo_half), __double2loint(hi_half), false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(__double2hiint(lo_half), __double2hiint(hi_half), false, false);
+  return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
+__device__ inline double swap_sum16(double lo_half, double hi_half) {
+  const auto l = __builtin_amdgcn_permlane16_swap(__double2loint(lo_half), __double2loint(hi_half), false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(__double2hiint(lo_half), __double2hiint(hi_half), false, false);
+  return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
 __device__ inline void wave_totals16(const double (&v)[16], double (&t)[16]) {
   const int lane = threadIdx.x & 63;
   double a8[8], a4[4], a2[2];
-  {
-    const bool h = (lane & 32) != 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const double keep = h ? v[8 + i] : v[i], send = h ? v[i] : v[8 + i];
-      a8[i] = keep + __shfl_xor(send, 32, 64);
-    }
-  }
-  {
-    const bool h = (lane & 16) != 0;
+  for (int i = 0; i < 8; ++i) a8[i] = swap_sum32(v[i], v[8 + i]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double keep = h ? a8[4 + i] : a8[i], send = h ? a8[i] : a8[4 + i];
-      a4[i] = keep + __shfl_xor(send, 16, 64);
-    }
-  }
+  for (int i = 0; i < 4; ++i) a4[i] = swap_sum16(a8[i], a8[4 + i]);
   {
     const bool h = (lane & 8) != 0;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const double keep = h ? a4[2 + i] : a4[i], send = h ? a4[i] : a4[2 + i];
-      a2[i] = keep + __shfl_xor(send, 8, 64);
+      a2[i] = keep + dpp_move<0x128>(send);          // row_ror:8, lane ^ 8 within the row
     }
   }
   const bool h = (lane & 4) != 0;
-  double a1 = (h ? a2[1] : a2[0]) + __shfl_xor(h ? a2[0] : a2[1], 4, 64);
-  a1 += __shfl_xor(a1, 2, 64);
-  a1 += __shfl_xor(a1, 1, 64);
+  double a1 = (h ? a2[1] : a2[0]) + dpp_move<0x141>(h ? a2[0] : a2[1]);   // row_half_mirror, lane ^ 7
+  a1 += dpp_move<0xB1>(a1);                           // quad_perm [1,0,3,2]
+  a1 += dpp_move<0x4E>(a1);                           // quad_perm [2,3,0,1]
 #pragma unroll
   for (int c = 0; c < 16; ++c) t[c] = lane_value(a1, 4 * c);
+}
+
+// the same for 8 values: afterwards lane l holds the total of value (l >> 3) & 7
+__device__ inline void wave_totals8(const double (&v)[8], double (&t)[8]) {
+  const int lane = threadIdx.x & 63;
+  double a4[4], a2[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) a4[i] = swap_sum32(v[i], v[4 + i]);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) a2[i] = swap_sum16(a4[i], a4[2 + i]);
+  const bool h = (lane & 8) != 0;
+  double a1 = (h ? a2[1] : a2[0]) + dpp_move<0x128>(h ? a2[0] : a2[1]);   // row_ror:8, lane ^ 8
+  a1 += dpp_move<0x141>(a1);                          // row_half_mirror, lane ^ 7
+  a1 += dpp_move<0xB1>(a1);                           // quad_perm [1,0,3,2]
+  a1 += dpp_move<0x4E>(a1);                           // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int c = 0; c < 8; ++c) t[c] = lane_value(a1, 8 * c);
 }
 
 // ---------------------------------------------------------------------------
@@ -186,26 +231,33 @@ __device__ void form_t(const double (*Vs)[VLD], int m, int nbw, const double* ta
 #pragma unroll
   for (int v = 0; v < 4; ++v) Sc[wave][frag_row<double>(lane, v)][li] = g[v];
   __syncthreads();
-  {
-    const int a = tid >> 4, b = tid & 15;
-    Gm[a][b] = (Sc[0][a][b] + Sc[1][a][b]) + (Sc[2][a][b] + Sc[3][a][b]);
-  }
+  // T by recursive doubling (one element per thread): with T_1, T_2 the
+  // factors of two adjacent groups of b reflectors, the factor of the pair is
+  // [[T_1, -T_1 (V_1^T V_2) T_2], [0, T_2]]; start from T_jj = tau_j
+  const int a = tid >> 4, b = tid & 15;
+  Gm[a][b] = (Sc[0][a][b] + Sc[1][a][b]) + (Sc[2][a][b] + Sc[3][a][b]);
+  Ts[a][b] = (a == b && a < nbw) ? tau[a] : 0.0;
   __syncthreads();
-  if (tid < NB) {
-    const int i = tid;
-    double t[NB];
+  double (*X)[NB + 1] = Sc[0];             // V_1^T V_2 T_2, reusing the Gram partials' space
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      double acc = 0.0;
+  for (int w = 1; w < NB; w *= 2) {
+    const int o = a & ~(2 * w - 1);        // first row of this pair of groups
+    const bool upper = (a - o) < w && (b & ~(2 * w - 1)) == o && (b - o) >= w;
+    if (upper) {
+      double x = 0.0;
 #pragma unroll
-      for (int k = 0; k < j; ++k) acc += t[k] * Gm[k][j];   // t[k] = 0 for k < i
-      const double tj = (j < nbw) ? tau[j] : 0.0;
-      t[j] = (i < j) ? -tj * acc : ((i == j) ? tj : 0.0);
+      for (int k = 0; k < w; ++k) x += Gm[a][o + w + k] * Ts[o + w + k][b];
+      X[a][b] = x;
     }
+    __syncthreads();
+    if (upper) {
+      double t = 0.0;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) Ts[i][j] = t[j];
+      for (int k = 0; k < w; ++k) t += Ts[a][o + k] * X[o + k][b];
+      Ts[a][b] = -t;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 template <int MX>
@@ -380,6 +432,7 @@ __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, d
   __shared__ double Sc[4][NB][NB + 1];
   __shared__ double norms[MAXN];
   __shared__ double tau[NB];
+  __shared__ double Colj[2][MAXN];         // panel column j, alternating per column
   __shared__ int perm[MAXN];
   const int z = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -480,76 +533,99 @@ __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, d
         }
     }
     __syncthreads();
-    if (wave == 0) {
-      double a[NB][Cap<MX>::rpl];
+    // the panel is factored by all four waves: wave w holds panel columns
+    // w, w + 4, w + 8, w + 12 (one row per lane and slot).  Column j goes to
+    // every wave through LDS; each wave reduces the column's norm below the
+    // diagonal together with its dots against its own columns in one
+    // butterfly, forms the same reflector, and updates its own columns.
+    {
+      constexpr int RPL = Cap<MX>::rpl;
+      double a[4][RPL];
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int t = 0; t < Cap<MX>::rpl; ++t) {
-          const int r = lane + 64 * t;
-          a[j][t] = (j < nbw && r < m) ? Pn[j][r] : 0.0;
+        for (int t = 0; t < RPL; ++t) {
+          const int r = lane + 64 * t, c = wave + 4 * q;
+          a[q][t] = (c < nbw && r < m) ? Pn[c][r] : 0.0;
         }
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (j < nbw) {
-          // every sum the column needs in one butterfly: slot 0 the squared
-          // norm below the diagonal, slot c the dot of that tail with column
-          // j + c; the reflector's scale enters afterwards, since
-          // v^T a_c = a_c[j] + scl * (tail . a_c[tail])
-          double tail[Cap<MX>::rpl];       // column j below the diagonal, zero elsewhere
+          const int jq = j >> 2;
+          if (wave == (j & 3)) {
 #pragma unroll
-          for (int t = 0; t < Cap<MX>::rpl; ++t) {
-            const int r = lane + 64 * t;
-            tail[t] = (r > j && r < m) ? a[j][t] : 0.0;
-          }
-          double part[16];
-#pragma unroll
-          for (int c = 0; c < 16; ++c) {
-            part[c] = 0.0;
-            if (j + c < NB) {
-#pragma unroll
-              for (int t = 0; t < Cap<MX>::rpl; ++t) part[c] += tail[t] * a[(j + c) % NB][t];
+            for (int t = 0; t < RPL; ++t) {
+              const int r = lane + 64 * t;
+              if (r < MAXN) Colj[j & 1][r] = a[jq][t];
             }
           }
-          double tot[16];
-          wave_totals16(part, tot);
+          __syncthreads();
+          // slot 0: the squared norm of column j below the diagonal; slot
+          // 1 + q: the dot of that tail with own column w + 4q (if right of
+          // j).  The reflector's scale enters afterwards, since
+          // v^T a_c = a_c[j] + scl * (tail . a_c[tail])
+          double tail[RPL];
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            const int r = lane + 64 * t;
+            tail[t] = (r > j && r < m) ? Colj[j & 1][r] : 0.0;
+          }
+          double part[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) part[c] = 0.0;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) part[0] += tail[t] * tail[t];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (wave + 4 * q > j) {
+#pragma unroll
+              for (int t = 0; t < RPL; ++t) part[1 + q] += tail[t] * a[q][t];
+            }
+          double tot[8];
+          wave_totals8(part, tot);
           const double sg = tot[0];
-          const double al = lane_value(a[j][0], j);      // row j of the panel lives in lane j
+          const double al = Colj[j & 1][j];
           double be = al, tj = 0.0, scl = 0.0;
           if (sg > 0.0) {
             const double nrm = sqrt(al * al + sg);
             be = (al >= 0.0) ? -nrm : nrm;
-            tj = (be - al) / be;
-            scl = 1.0 / (al - be);
+            tj = (be - al) * rcp_nr(be);
+            scl = rcp_nr(al - be);             // |al - be| = |al| + nrm > 0
           }
-          double vr[Cap<MX>::rpl];
+          double vr[RPL];
 #pragma unroll
-          for (int t = 0; t < Cap<MX>::rpl; ++t) {
+          for (int t = 0; t < RPL; ++t) {
             const int r = lane + 64 * t;
             vr[t] = (r == j) ? 1.0 : tail[t] * scl;
-            if (r >= j) a[j][t] = (r == j) ? be : vr[t];
           }
 #pragma unroll
-          for (int c = 1; c < 16; ++c)
-            if (j + c < nbw) {
-              const double w = tj * (lane_value(a[j + c][0], j) + scl * tot[c]);
+          for (int q = 0; q < 4; ++q)
+            if (wave + 4 * q > j) {
+              const double w = tj * (lane_value(a[q][0], j) + scl * tot[1 + q]);   // row j lives in lane j
 #pragma unroll
-              for (int t = 0; t < Cap<MX>::rpl; ++t) a[j + c][t] -= vr[t] * w;
+              for (int t = 0; t < RPL; ++t) a[q][t] -= vr[t] * w;
             }
-          if (lane == 0) tau[j] = tj;
+          if (wave == (j & 3)) {
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+              const int r = lane + 64 * t;
+              if (r >= j) a[jq][t] = (r == j) ? be : vr[t];
+            }
+          }
+          if (tid == 0) tau[j] = tj;
         }
       }
       // V (unit diagonal, zero above, zero past the panel) to Vs; R and V to Pn and to W
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int t = 0; t < Cap<MX>::rpl; ++t) {
-          const int r = lane + 64 * t;
+        for (int t = 0; t < RPL; ++t) {
+          const int r = lane + 64 * t, c = wave + 4 * q;
           if (r < VLD) {
-            Vs[j][r] = (j < nbw && r < m) ? ((r == j) ? 1.0 : ((r > j) ? a[j][t] : 0.0)) : 0.0;
-            Pn[j][r] = (j < nbw && r < m) ? a[j][t] : 0.0;
+            Vs[c][r] = (c < nbw && r < m) ? ((r == c) ? 1.0 : ((r > c) ? a[q][t] : 0.0)) : 0.0;
+            Pn[c][r] = (c < nbw && r < m) ? a[q][t] : 0.0;
           }
-          if (j < nbw && r < m) W[(long)(p0 + r) * n + p0 + j] = a[j][t];
+          if (c < nbw && r < m) W[(long)(p0 + r) * n + p0 + c] = a[q][t];
         }
     }
     Vs[tid >> 4][MAXN + (tid & 15)] = 0.0;
@@ -814,6 +890,235 @@ __global__ __launch_bounds__(256) void inv_blocked_kernel(double* __restrict__ M
   }
 }
 
+// ---------------------------------------------------------------------------
+// Gauss-Jordan inversion with the matrix held in registers (N <= MX <= 144):
+// the same elimination as inv_blocked_kernel, panel by panel, but every
+// column tile lives in the accumulators of the wave that owns it (tile column
+// c belongs to wave c % 4), so the trailing rank-16 update of a panel never
+// leaves the CU.  Per panel: the owner hands the panel to wave 0 through LDS,
+// wave 0 eliminates its 16 columns, and each wave fetches the panel's pivot
+// rows of its own columns through a per-wave LDS copy of the tile column.
+// ---------------------------------------------------------------------------
+template <int MX>
+__global__ __launch_bounds__(256) void gj_regs_kernel(double* __restrict__ Mg, double* __restrict__ Wg,
+                                                      const double* __restrict__ rsg,
+                                                      const double* __restrict__ csg,
+                                                      const double* __restrict__ base,
+                                                      double* __restrict__ logdet, int n) {
+  constexpr int NTT = (MX + 15) / 16;      // tile rows (and tile columns)
+  constexpr int CPW = (NTT + 3) / 4;       // tile columns per wave
+  constexpr int RPL = Cap<MX>::rpl;
+  static_assert(4 * NTT <= 64, "pivot-row flags hold 64 rows per lane");
+  __shared__ double Pn[NB][VLD];           // the panel, column-major; after elimination its F
+  __shared__ double Cs[4][NTT * 16][NB + 1];   // per-wave copy of one tile column
+  __shared__ int perm[MAXN];               // perm[j]: pivot row of column j
+  __shared__ int pinv[MAXN];
+  __shared__ double pivot[MAXN];           // pivot value of column j
+  __shared__ double Colj[2][MAXN];         // panel column j, alternating per column
+  __shared__ double rsl[MAXN], csl[MAXN];
+  __shared__ double part[4];
+  const int z = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  double* M = Mg + (long)z * n * n;
+  double* W = Wg + (long)z * n * n;
+  const int nt = (n + 15) / 16;
+  for (int i = tid; i < n; i += 256) {
+    rsl[i] = rsg[(long)z * n + i];
+    csl[i] = csg[(long)z * n + i];
+  }
+
+  d4 A[CPW][NTT];
+#pragma unroll
+  for (int u = 0; u < CPW; ++u) {
+    const int col = 16 * (wave + 4 * u) + li;
+#pragma unroll
+    for (int t = 0; t < NTT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + frag_row<double>(lane, v);
+        A[u][t][v] = (row < n && col < n) ? M[(long)row * n + col] : 0.0;
+      }
+  }
+  bool used[RPL];                          // rows of this lane already pivoted (same in every wave)
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) used[t] = false;
+
+  for (int p = 0; p < nt; ++p) {
+    const int p0 = p * NB, nbw = min(NB, n - p0);
+    const int owner = p & 3, up = p >> 2;
+    if (wave == owner) {
+#pragma unroll
+      for (int u = 0; u < CPW; ++u)
+        if (u == up) {
+#pragma unroll
+          for (int t = 0; t < NTT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Pn[li][16 * t + frag_row<double>(lane, v)] = A[u][t][v];
+        }
+    }
+    __syncthreads();
+    // the panel is eliminated by all four waves: wave w holds panel columns
+    // w, w + 4, w + 8, w + 12 (one row per lane and slot); column j goes to
+    // every wave through LDS, every wave finds the same pivot and updates
+    // its own columns
+    {
+      double a[4][RPL];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int r = lane + 64 * t;
+          a[q][t] = (r < n) ? Pn[wave + 4 * q][r] : 0.0;
+        }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < nbw) {
+          const int jq = j >> 2;
+          if (wave == (j & 3)) {
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+              const int r = lane + 64 * t;
+              if (r < MAXN) Colj[j & 1][r] = a[jq][t];
+            }
+          }
+          __syncthreads();
+          double aj[RPL];
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            const int r = lane + 64 * t;
+            aj[t] = (r < MAXN) ? Colj[j & 1][r] : 0.0;
+          }
+          // pivot: the unused row of largest |a|, found as the largest key
+          // (|a| rounded to FP32 with its low 9 bits replaced by 511 - row, so
+          // near-equal magnitudes go to the lower row); used rows key 0
+          uint32_t key = 0;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            const int r = lane + 64 * t;
+            const uint32_t kt = (__float_as_uint((float)fabs(aj[t])) & ~0x1FFu) | (uint32_t)(511 - r);
+            if (r < n && !used[t]) key = max(key, kt);
+          }
+          key = wave_max_u32(key);
+          const int pr = 511 - (int)(key & 0x1FFu), pl = pr & 63, pt = pr >> 6;
+          double pmine = 0.0;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) pmine = (t == pt) ? aj[t] : pmine;
+          const double pj = lane_value(pmine, pl);
+          const double ip = rcp_nr(pj);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (wave + 4 * q == j) {
+              // column j becomes -a / pivot, 1 / pivot on the pivot row
+#pragma unroll
+              for (int t = 0; t < RPL; ++t) a[q][t] = (lane + 64 * t == pr) ? ip : -aj[t] * ip;
+            } else {
+              // the pivot row's entry of this column, broadcast from its lane
+              double mine = 0.0;
+#pragma unroll
+              for (int t = 0; t < RPL; ++t) mine = (t == pt) ? a[q][t] : mine;
+              const double wp = lane_value(mine, pl) * ip;
+#pragma unroll
+              for (int t = 0; t < RPL; ++t) a[q][t] = (lane + 64 * t == pr) ? wp : fma(-aj[t], wp, a[q][t]);
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < RPL; ++t)
+            if (lane + 64 * t == pr) used[t] = true;
+          if (tid == 0) {
+            perm[p0 + j] = pr;
+            pinv[pr] = p0 + j;
+            pivot[p0 + j] = pj;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int r = lane + 64 * t, c = wave + 4 * q;
+          if (r < 16 * NTT) Pn[c][r] = (c < nbw) ? a[q][t] : 0.0;
+        }
+    }
+    __syncthreads();
+    // rows of this lane (bit 4t + v for row 16t + frag_row(lane, v)) that became pivots in this panel
+    uint64_t pm = 0;
+    for (int k = 0; k < nbw; ++k) {
+      const int r = perm[p0 + k];
+      if ((r & 3) == lk) pm |= 1ull << (4 * (r >> 4) + ((r & 15) >> 2));
+    }
+    if (wave == owner) {
+#pragma unroll
+      for (int u = 0; u < CPW; ++u)
+        if (u == up) {
+#pragma unroll
+          for (int t = 0; t < NTT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) A[u][t][v] = Pn[li][16 * t + frag_row<double>(lane, v)];
+        }
+    }
+    // every other column: rows outside the panel's pivots keep their value,
+    // then all rows gain F * (old pivot rows)
+#pragma unroll
+    for (int u = 0; u < CPW; ++u) {
+      const int cj = wave + 4 * u;
+      if (cj != p && cj < nt) {
+#pragma unroll
+        for (int t = 0; t < NTT; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Cs[wave][16 * t + frag_row<double>(lane, v)][li] = A[u][t][v];
+        wave_sync_lds();
+        double b[NB / 4];
+#pragma unroll
+        for (int q = 0; q < NB / 4; ++q) b[q] = (4 * q + lk < nbw) ? Cs[wave][perm[p0 + 4 * q + lk]][li] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NTT; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if ((pm >> (4 * t + v)) & 1) A[u][t][v] = 0.0;
+#pragma unroll
+        for (int t = 0; t < NTT; ++t)
+          if (t < nt) {
+#pragma unroll
+            for (int q = 0; q < NB / 4; ++q) A[u][t] = mfma16(Pn[4 * q + lk][16 * t + li], b[q], A[u][t]);
+          }
+        wave_sync_lds();                    // Cs is rewritten by the next tile column
+      }
+    }
+    __syncthreads();                        // Pn is rewritten by the next panel
+  }
+
+  // M^-1[j][perm[k]] = W[perm[j]][k]: each element straight from its
+  // register to its permuted place, scaled, over M
+#pragma unroll
+  for (int u = 0; u < CPW; ++u) {
+    const int col = 16 * (wave + 4 * u) + li;
+    if (col < n) {
+      const int pk = perm[col];
+      const double cv = csl[pk];
+#pragma unroll
+      for (int t = 0; t < NTT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + frag_row<double>(lane, v);
+          if (row < n) {
+            const int j = pinv[row];
+            M[(long)j * n + pk] = rsl[j] * A[u][t][v] * cv;
+          }
+        }
+    }
+  }
+  // log|det M| = sum of log|pivot|
+  double lg = 0.0;
+  for (int i = tid; i < n; i += 256) lg += log(fabs(pivot[i]));
+  lg = wave_total(lg);
+  if (lane == 0) part[wave] = lg;
+  __syncthreads();
+  if (tid == 0) logdet[z] = base[z] + ((part[0] + part[1]) + (part[2] + part[3]));
+  (void)W;
+}
+
 bool qr_supported(int n) { return n >= 1 && n <= MAXN; }
 bool gj_supported(int n) { return n >= 1 && n <= MAXN; }
 size_t qr_t_doubles(int n) { return (size_t)NB * (n + NB); }
@@ -835,9 +1140,11 @@ hipError_t launch_gj(double* M, double* W, const double* rs, const double* cs, c
                      int n, int batch, hipStream_t s) {
   if (!gj_supported(n)) return hipErrorInvalidValue;
   if (n <= 64)
-    hipLaunchKernelGGL(inv_blocked_kernel<64>, dim3(batch), dim3(256), 0, s, M, W, rs, cs, base, logdet, n);
-  else if (n <= 160)
-    hipLaunchKernelGGL(inv_blocked_kernel<160>, dim3(batch), dim3(256), 0, s, M, W, rs, cs, base, logdet, n);
+    hipLaunchKernelGGL(gj_regs_kernel<64>, dim3(batch), dim3(256), 0, s, M, W, rs, cs, base, logdet, n);
+  else if (n <= 112)
+    hipLaunchKernelGGL(gj_regs_kernel<112>, dim3(batch), dim3(256), 0, s, M, W, rs, cs, base, logdet, n);
+  else if (n <= 144)
+    hipLaunchKernelGGL(gj_regs_kernel<144>, dim3(batch), dim3(256), 0, s, M, W, rs, cs, base, logdet, n);
   else
     hipLaunchKernelGGL(inv_blocked_kernel<256>, dim3(batch), dim3(256), 0, s, M, W, rs, cs, base, logdet, n);
   return hipGetLastError();

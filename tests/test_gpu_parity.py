@@ -248,6 +248,87 @@ def test_set_tuning_rejects_bad_tiles(hq):
     ctx.close()
 
 
+def test_uneven_batch_full_size_sampled(hq):
+    """The uneven batch at full size (6x6, 8x8, 10x10, 16x16 x 32 chains, L = 100,
+    mixed, g per chain): the first chain of each of the three smaller lattices
+    swept beside the oracle with the tie band replayed; the 16x16 lattice (an
+    oracle sweep there takes most of a minute) through its initial state and,
+    after the sweep, the oracle's from-scratch log|det| of the GPU's own
+    fields, the recompute of G from those fields and the drift gate."""
+    from oracle.model import chain_coupling
+    from oracle.udt import green_and_logdet
+    w = workloads.holstein_uneven_batch()
+    say("uneven batch full size, one sweep")
+    groups = [dict(nx=g.nx, chains=g.n_chains, beta=g.beta, n_stab=g.n_stab, g_range=g.g_range) for g in w.groups]
+    ctx = make_ctx(hq, groups, precision=1, seed=w.seed, delay=w.delay)
+    oracles = {}
+    for k, gr in enumerate(groups[:3]):
+        c = 32 * k
+        oracles[c] = dqmc.Chain(params_of(gr, g=chain_coupling(w.seed, c, 0.8, 1.6)), w.seed, c)
+    c16 = 96
+    p16 = params_of(groups[3], g=chain_coupling(w.seed, c16, 0.8, 1.6))
+    ch16 = dqmc.Chain(p16, w.seed, c16)
+    assert np.array_equal(ctx.fields(c16), ch16.x)
+    assert rel_g(ctx.green(c16), ch16.G) <= TOL_MIXED
+    assert abs(ctx.stats(c16)["logdet"] - ch16.logdet) <= TOL64 * max(1.0, abs(ch16.logdet))
+    for c, ch in oracles.items():
+        ch.sweep()
+        ctx.set_replay(c, hq.KIND_LOCAL, oracle_local_bits(ch, 0), BAND_MIXED)
+    ctx.sweep(1)
+    for c, ch in oracles.items():
+        st = ctx.stats(c)
+        assert st["replay_mismatches"] == 0, "chain %d" % c
+        assert np.array_equal(ctx.fields(c), ch.x), "chain %d" % c
+        assert rel_g(ctx.green(c), ch.G) <= TOL_MIXED, "chain %d" % c
+        assert abs(st["logdet"] - ch.logdet) <= TOL64 * max(1.0, abs(ch.logdet)), "chain %d" % c
+        assert st["local_accepts"] == ch.local_accepts, "chain %d" % c
+    st = ctx.stats(c16)
+    x16 = ctx.fields(c16)
+    _, ld = green_and_logdet(p16, ch16.expk, x16, 0)
+    assert abs(st["logdet"] - ld) <= TOL64 * max(1.0, abs(ld))
+    assert st["max_drift_green"] <= TOL_MIXED
+    assert 0 < st["local_accepts"] < st["local_proposals"] == 256 * 100
+    G_swept = ctx.green(c16)
+    ctx.recompute()
+    assert rel_g(G_swept, ctx.green(c16)) <= TOL_MIXED
+    ctx.close()
+
+
+def test_network_full_size_sampled(hq):
+    """The network workload at full size (64 chains of 16x16, L = 160): chains 0
+    and 63 swept beside the oracle's network sweep, inner decisions replayed
+    inside the tie band, cumulative accept and state compared."""
+    w = workloads.holstein_16x16_network()
+    g = w.groups[0]
+    say("network 16x16 x64 full size, one sweep")
+    gr = dict(nx=g.nx, chains=g.n_chains, g=g.g, beta=g.beta, n_stab=g.n_stab, proposal=1)
+    net = workloads.random_network(1001)
+    ctx = make_ctx(hq, [gr], seed=w.seed)
+    ctx.set_network(net)
+    p = params_of(gr)
+    nets = {c: nnmc.NNChain(dqmc.Chain(p, w.seed, c), net) for c in (0, 63)}
+    for c, nn in nets.items():
+        nn.sweep()
+        bits = np.zeros(p.L * p.n, dtype=np.uint8)
+        cum = np.zeros(1, dtype=np.uint8)
+        for kind, sw, slot, acc, _ in nn.decisions:
+            if kind == philox.KIND_NN:
+                bits[slot] = acc
+            if kind == philox.KIND_CUMULATIVE:
+                cum[0] = acc
+        ctx.set_replay(c, hq.KIND_NN, bits, BAND_MIXED)
+        ctx.set_replay(c, hq.KIND_CUMULATIVE, cum, BAND_MIXED)
+    ctx.sweep(1)
+    for c, nn in nets.items():
+        st = ctx.stats(c)
+        assert st["replay_mismatches"] == 0, "chain %d" % c
+        assert np.array_equal(ctx.fields(c), nn.c.x), "chain %d" % c
+        assert abs(st["logdet"] - nn.c.logdet) <= TOL64 * max(1.0, abs(nn.c.logdet)), "chain %d" % c
+        assert st["cumulative_accepts"] == nn.cumulative_accepts
+        assert st["nn_accepts"] == nn.inner_accepts
+    ctx.close()
+
+
 def test_uneven_groups_per_chain_coupling(hq):
     """Two lattice sizes in one context, g per chain from U(0.8, 1.6)."""
     say("uneven groups 4x4 + 6x6")

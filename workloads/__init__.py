@@ -66,9 +66,11 @@ def holstein_12x12_mixed(precision=1, n_stab=10):
                     precision=precision)
 
 
-def holstein_uneven_batch():
-    return Workload("holstein-uneven-6/8/10/16-L100-mixed-4x32chains", 4,
-                    [Lattice(nx=n, n_chains=32, beta=10.0, n_stab=10, g_range=(0.8, 1.6))
+def holstein_uneven_batch(n_stab=5):
+    # FP32 wraps drift past 1e-5 within 10 slices on every lattice of this
+    # batch (3e-5 .. 7e-5), so the recompute interval is 5, a divisor of L = 100
+    return Workload("holstein-uneven-6/8/10/16-L100-mixed-nstab%d-4x32chains" % n_stab, 4,
+                    [Lattice(nx=n, n_chains=32, beta=10.0, n_stab=n_stab, g_range=(0.8, 1.6))
                      for n in (6, 8, 10, 16)], precision=1)
 
 
