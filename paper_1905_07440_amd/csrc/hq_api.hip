@@ -54,7 +54,7 @@ struct Group {
   double *dLbinv = nullptr, *dLs = nullptr, *dRbinv = nullptr, *dRs = nullptr, *sumlog = nullptr;
   double *logdet = nullptr, *logdet_new = nullptr, *shift = nullptr;
   int64_t* counters = nullptr;
-  double *drift = nullptr, *obs = nullptr, *lastpc = nullptr;
+  double *drift = nullptr, *dpart = nullptr, *obs = nullptr, *lastpc = nullptr;
   int* flags = nullptr;
   int64_t* replay_counts = nullptr;
   float* log_margin[N_KIND_SLOTS] = {};
@@ -224,6 +224,7 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
     g.shift = cv.take<double>(C);
     g.counters = cv.take<int64_t>(C * N_COUNTERS);
     g.drift = cv.take<double>(C * 5);
+    g.dpart = cv.take<double>((long)stab_part_doubles(C));
     g.obs = cv.take<double>(C * 5);
     g.lastpc = cv.take<double>(C * 2);
     g.flags = cv.take<int>(C);
@@ -587,7 +588,8 @@ hq_status stab_up(Sched& S, Group& g, int b) {
   ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 0, in.U, in.sU, in.D, in.sD, in.T, in.sT, out.U, out.sU, out.D,
                  out.sD, out.T, out.sT));
   ST_TRY(merge(S, g, out.U, out.sU, out.D, out.T, out.sT, r.U, r.sU, r.D, r.sD, r.T, r.sT));
-  SCHED_TRY(launch_stab_finish(g.G, S.ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.n, g.C, 1, S.s));
+  SCHED_TRY(launch_stab_finish(g.G, S.ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.dpart, g.n,
+                               g.C, 1, S.s));
   return HQ_OK;
 }
 
@@ -603,7 +605,8 @@ hq_status stab_down(Sched& S, Group& g, int b) {
                  out.sD, out.T, out.sT));
   const Udt l = left_entry(g, b - 1);
   ST_TRY(merge(S, g, l.U, l.sU, l.D, l.T, l.sT, out.U, out.sU, out.D, out.sD, out.T, out.sT));
-  SCHED_TRY(launch_stab_finish(g.G, S.ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.n, g.C, 1, S.s));
+  SCHED_TRY(launch_stab_finish(g.G, S.ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.dpart, g.n,
+                               g.C, 1, S.s));
   return HQ_OK;
 }
 
@@ -836,7 +839,7 @@ hq_status recompute_all(hq_ctx* ctx) {
   Sched S{ctx, ctx->stream};
   for (Group& g : ctx->groups) {
     ST_TRY(from_scratch(S, g, g.x, g.blk));
-    SCHED_TRY(launch_stab_finish(g.G, ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.n, g.C, 0,
+    SCHED_TRY(launch_stab_finish(g.G, ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.dpart, g.n, g.C, 0,
                                  S.s));
   }
   return HQ_OK;
@@ -998,7 +1001,7 @@ hq_status hq_set_fields(hq_ctx* ctx, int32_t chain, const double* x_host, int64_
   HQ_TRY(hipMemcpyAsync(g->x + (long)lc * n, x_host, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   Sched S{ctx, ctx->stream};
   ST_TRY(from_scratch(S, *g, g->x, g->blk));
-  SCHED_TRY(launch_stab_finish(g->G, ctx->opt.precision, g->Gnew, g->logdet, g->logdet_new, g->drift, g->n, g->C, 0,
+  SCHED_TRY(launch_stab_finish(g->G, ctx->opt.precision, g->Gnew, g->logdet, g->logdet_new, g->drift, g->dpart, g->n, g->C, 0,
                                ctx->stream));
   return sync(ctx);
 }
@@ -1084,11 +1087,13 @@ hq_status hq_read_stats(hq_ctx* ctx, int32_t chain, hq_stats* out) {
   int lc = 0;
   Group* g = find_chain(ctx, chain, lc);
   if (!g || !out) return fail(ctx, HQ_EINVAL, "bad chain");
-  ObsArgs a;
+  ObsArgs a;                                // this chain only
+  const long nn = (long)g->n * g->n;
+  const size_t gsz = ctx->opt.precision == HQ_PREC_MIXED ? sizeof(float) : sizeof(double);
   a.n = g->n; a.L = g->L; a.nx = g->nx;
-  a.G = g->G; a.precision = ctx->opt.precision; a.x = g->x;
-  a.out = g->obs; a.flags = g->flags; a.logdet = g->logdet;
-  HQ_TRY(launch_observables(a, g->C, ctx->stream));
+  a.G = (const char*)g->G + lc * nn * gsz; a.precision = ctx->opt.precision; a.x = g->x + (long)lc * g->L * g->n;
+  a.out = g->obs + lc * 5; a.flags = g->flags + lc; a.logdet = g->logdet + lc;
+  HQ_TRY(launch_observables(a, 1, ctx->stream));
   ST_TRY(sync(ctx));
   double ld = 0, gg = 0, dr[5], ob[5];
   int64_t cnt[N_COUNTERS], rc[2];

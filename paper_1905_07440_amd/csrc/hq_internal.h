@@ -101,9 +101,11 @@ hipError_t launch_identity(double* U, double* D, double* T, int n, int batch, hi
 // dbinv = 1/max(D,1), ds = min(D,1), sumlog[z] (+)= sum log max(D,1)
 hipError_t launch_dsplit(const double* D, double* dbinv, double* ds, double* sumlog, int accumulate,
                          int n, int batch, hipStream_t s);
-// drift of the tracked state against the recomputed one, then replace it
+// drift of the tracked state against the recomputed one, then replace it;
+// part: stab_part_doubles(batch) of scratch
+size_t stab_part_doubles(int batch);
 hipError_t launch_stab_finish(void* G, int precision, const double* Gnew, double* logdet,
-                              const double* logdet_new, double* drift, int n, int batch,
+                              const double* logdet_new, double* drift, double* part, int n, int batch,
                               int record_drift, hipStream_t s);
 hipError_t launch_copy_f64_to_f32(float* dst, const double* src, long count, hipStream_t s);
 hipError_t launch_copy_f32_to_f64(double* dst, const float* src, long count, hipStream_t s);

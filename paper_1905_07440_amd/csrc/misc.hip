@@ -51,45 +51,72 @@ hipError_t launch_dsplit(const double* D, double* dbinv, double* ds, double* sum
 // FP64 recomputation, then the tracked state is replaced by it.
 // drift[z] = {max |dG|, max |dlogdet|, last |dG|, last |dlogdet|, flags}
 // ---------------------------------------------------------------------------
+// Stabilisation finish in two launches.  The copy of the recomputed G over
+// the tracked one is spread over STAB_SPLIT workgroups per chain (one per
+// CU would leave most of each CU's memory pipeline idle); each writes its
+// share's max |G_tracked - G_new| and non-finite flag to part[z][k].  The
+// second launch folds the parts per chain and updates drift and log det.
+constexpr int STAB_SPLIT = 8;
+
 template <typename T>
-__global__ void stab_finish_kernel(T* G, const double* Gnew, double* logdet, const double* logdet_new,
-                                   double* drift, int n, int record) {
+__global__ __launch_bounds__(256) void stab_copy_kernel(T* G, const double* Gnew, double* part, int n, int record) {
   __shared__ double red[4];
-  const int z = blockIdx.x;
-  T* g = G + (long)z * n * n;
-  const double* gn = Gnew + (long)z * n * n;
+  const int k = blockIdx.x, z = blockIdx.y;
+  const long nn = (long)n * n;
+  const long e0 = nn * k / STAB_SPLIT, e1 = nn * (k + 1) / STAB_SPLIT;
+  T* g = G + z * nn;
+  const double* gn = Gnew + z * nn;
   double mx = 0.0, bad = 0.0;
-  batched_copy<256, 16, double>(n * n, [&](int e) { return gn[e]; },
-                                [&](int e, double v) {
-                                  if (!isfinite(v)) bad = 1.0;
-                                  if (record) mx = fmax(mx, fabs((double)g[e] - v));
-                                  g[e] = (T)v;
-                                });
+  batched_copy<256, 8, double>((int)(e1 - e0), [&](int e) { return gn[e0 + e]; },
+                               [&](int e, double v) {
+                                 if (!isfinite(v)) bad = 1.0;
+                                 if (record) mx = fmax(mx, fabs((double)g[e0 + e] - v));
+                                 g[e0 + e] = (T)v;
+                               });
   mx = block_max<256>(mx, red);
   bad = block_max<256>(bad, red);
   if (threadIdx.x == 0) {
-    const double ldn = logdet_new[z];
-    double* dr = drift + (long)z * 5;
-    if (record) {
-      const double dl = fabs(logdet[z] - ldn);
-      dr[0] = fmax(dr[0], mx);
-      dr[1] = fmax(dr[1], dl);
-      dr[2] = mx;
-      dr[3] = dl;
-    }
-    if (bad > 0.0 || !isfinite(ldn)) dr[4] = 1.0;
-    logdet[z] = ldn;
+    part[(z * STAB_SPLIT + k) * 2] = mx;
+    part[(z * STAB_SPLIT + k) * 2 + 1] = bad;
   }
 }
 
+__global__ void stab_fold_kernel(const double* part, double* logdet, const double* logdet_new, double* drift,
+                                 int chains, int record) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= chains) return;
+  double mx = 0.0, bad = 0.0;
+  for (int k = 0; k < STAB_SPLIT; ++k) {
+    mx = fmax(mx, part[(z * STAB_SPLIT + k) * 2]);
+    bad = fmax(bad, part[(z * STAB_SPLIT + k) * 2 + 1]);
+  }
+  const double ldn = logdet_new[z];
+  double* dr = drift + (long)z * 5;
+  if (record) {
+    const double dl = fabs(logdet[z] - ldn);
+    dr[0] = fmax(dr[0], mx);
+    dr[1] = fmax(dr[1], dl);
+    dr[2] = mx;
+    dr[3] = dl;
+  }
+  if (bad > 0.0 || !isfinite(ldn)) dr[4] = 1.0;
+  logdet[z] = ldn;
+}
+
+size_t stab_part_doubles(int batch) { return (size_t)batch * STAB_SPLIT * 2; }
+
 hipError_t launch_stab_finish(void* G, int precision, const double* Gnew, double* logdet, const double* logdet_new,
-                              double* drift, int n, int batch, int record_drift, hipStream_t s) {
+                              double* drift, double* part, int n, int batch, int record_drift, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  const dim3 grid(STAB_SPLIT, batch);
   if (precision)
-    hipLaunchKernelGGL(stab_finish_kernel<float>, dim3(batch), dim3(256), 0, s, (float*)G, Gnew, logdet,
-                       logdet_new, drift, n, record_drift);
+    hipLaunchKernelGGL(stab_copy_kernel<float>, grid, dim3(256), 0, s, (float*)G, Gnew, part, n, record_drift);
   else
-    hipLaunchKernelGGL(stab_finish_kernel<double>, dim3(batch), dim3(256), 0, s, (double*)G, Gnew, logdet,
-                       logdet_new, drift, n, record_drift);
+    hipLaunchKernelGGL(stab_copy_kernel<double>, grid, dim3(256), 0, s, (double*)G, Gnew, part, n, record_drift);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(stab_fold_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, part, logdet, logdet_new, drift,
+                     batch, record_drift);
   return hipGetLastError();
 }
 
