@@ -473,11 +473,235 @@ static hipError_t allow_fullk_t() {
   return e;
 }
 
+// ---------------------------------------------------------------------------
+// Both products of a wrap in one launch:
+//   G' = diag(rs2) (A1 diag(ks1) G diag(cs1)) A2 diag(cs2)
+// with A1, A2 shared by the batch.  Two workgroups per chain split the rows
+// of G' (tile rows [0, h0) and [h0, nt)); each forms its rows of the middle
+// product X = A1 diag(ks1) G diag(cs1) in MFMA accumulators, parks them in
+// LDS, and multiplies them by A2 streamed in 16-row chunks.  G is read once
+// and G' written once, instead of a round trip of X through HBM.  Every
+// workgroup reads all of G, so G' goes to a different buffer.
+// ---------------------------------------------------------------------------
+constexpr int WRAP_WAVES = 8;
+
+// K advances in chunks of BK = 16
+template <typename T> struct WrapBK { static constexpr int v = 16; };
+
+template <typename T, int MAXT>
+struct WrapLds {
+  static constexpr int BK = WrapBK<T>::v;
+  static constexpr int RTM = (MAXT + 1) / 2;     // tile rows of the larger half
+  static constexpr int KP = (16 * MAXT + BK - 1) / BK * BK;   // columns of X, padded to whole chunks
+  static constexpr int LDA = 16 * RTM + 1;       // A1 chunk, [k][local row]
+  static constexpr int LDB = 16 * MAXT + 1;      // G / A2 chunks, [k][col]
+  static constexpr int LDX = KP + 1;             // X, [row][col]
+  static constexpr size_t bytes() { return sizeof(T) * ((size_t)2 * BK * LDA + 2 * BK * LDB + 16 * RTM * LDX); }
+};
+
+template <typename T, int MAXT>
+__global__ __launch_bounds__(64 * WRAP_WAVES) void wrap_fused_kernel(WrapArgs<T> w) {
+  typedef WrapLds<T, MAXT> Lay;
+  constexpr int NT = 64 * WRAP_WAVES;
+  constexpr int BK = Lay::BK, RTM = Lay::RTM, LDA = Lay::LDA, LDB = Lay::LDB, LDX = Lay::LDX;
+  // output tiles per wave: wave w takes tile column w in every tile row (its
+  // B values are shared by those tiles), and with nine tile columns wave w
+  // also takes tile (w, 8)
+  static_assert(MAXT <= WRAP_WAVES + 1, "one tile column per wave, plus one shared column");
+  constexpr int TPW = RTM + (MAXT > WRAP_WAVES ? 1 : 0);
+  constexpr int PA = (16 * RTM * BK + NT - 1) / NT;                  // A1 loads per thread per chunk
+  constexpr int PB = (BK * 16 * MAXT + NT - 1) / NT;                 // G / A2 loads per thread per chunk
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* As = (T*)smem;                        // [2][BK][LDA]
+  T* Bs = As + 2 * BK * LDA;               // [2][BK][LDB]
+  T* Xs = Bs + 2 * BK * LDB;               // [16 RTM][LDX]
+  __shared__ double ksv[16 * MAXT], c1v[16 * MAXT], c2v[16 * MAXT], r2v[16 * RTM];
+
+  const int n = w.n, nt = (n + 15) / 16;
+  const int nch = (16 * nt + BK - 1) / BK;  // chunks per product
+  const int part = blockIdx.x, z = blockIdx.y;
+  const int h0 = (nt + 1) / 2;
+  const int t0 = part == 0 ? 0 : h0, nrt = part == 0 ? h0 : nt - h0;
+  const int r0 = 16 * t0, R = 16 * nrt;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const T* G = w.Gin + (long)z * w.sG;
+  T* Go = w.Gout + (long)z * w.sG;
+  for (int i = tid; i < 16 * MAXT; i += NT) {
+    ksv[i] = (i < n) ? scale_value(w.ks1, z, 1, i) : 0.0;
+    c1v[i] = (i < n) ? scale_value(w.cs1, z, 1, i) : 0.0;
+    c2v[i] = (i < n) ? scale_value(w.cs2, z, 1, i) : 0.0;
+  }
+  for (int i = tid; i < 16 * RTM; i += NT) r2v[i] = (i < R && r0 + i < n) ? scale_value(w.rs2, z, 1, r0 + i) : 0.0;
+  // X columns past the last tile meet zero rows of A2 but must not hold stale values
+  for (int e = tid; e < 16 * RTM * LDX; e += NT) Xs[e] = T(0);
+
+  // the output tiles of this wave: tile rows trs (local), tile columns tcs
+  int trs[TPW], tcs[TPW];
+  bool own[TPW];
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) {
+    if (s < RTM) {
+      trs[s] = s;
+      tcs[s] = wave;
+      own[s] = s < nrt && wave < nt;
+    } else {
+      trs[s] = wave;
+      tcs[s] = WRAP_WAVES;
+      own[s] = wave < nrt && WRAP_WAVES < nt;
+    }
+  }
+  typedef typename Frag<T>::type F;
+  F acc[TPW];
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) acc[s] = F{0, 0, 0, 0};
+  T ra[PA], rb[PB];
+  // stage 1 chunk c: A1 rows r0 .. r0 + R, columns BK c ..; G rows BK c .., all columns
+  auto load1 = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      const int e = tid + NT * q, m = e / BK, k = e % BK, gk = BK * c + k;
+      ra[q] = (m < R && r0 + m < n && gk < n) ? w.A1[(long)(r0 + m) * n + gk] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int e = tid + NT * q, k = e / (16 * MAXT), col = e % (16 * MAXT), gk = BK * c + k;
+      rb[q] = (k < BK && col < n && gk < n) ? G[(long)gk * n + col] : T(0);
+    }
+  };
+  auto store1 = [&](int c, int buf) {
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      const int e = tid + NT * q, m = e / BK, k = e % BK;
+      if (m < 16 * RTM) As[(buf * BK + k) * LDA + m] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int e = tid + NT * q, k = e / (16 * MAXT), col = e % (16 * MAXT), gk = BK * c + k;
+      if (k < BK) Bs[(buf * BK + k) * LDB + col] = (gk < n) ? (T)((double)rb[q] * ksv[gk] * c1v[col]) : T(0);
+    }
+  };
+  // stage 2 chunk c: A2 rows BK c .., all columns
+  auto load2 = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int e = tid + NT * q, k = e / (16 * MAXT), col = e % (16 * MAXT), gk = BK * c + k;
+      rb[q] = (k < BK && col < n && gk < n) ? w.A2[(long)gk * n + col] : T(0);
+    }
+  };
+  auto store2 = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int e = tid + NT * q, k = e / (16 * MAXT), col = e % (16 * MAXT);
+      if (k < BK) Bs[(buf * BK + k) * LDB + col] = rb[q];
+    }
+  };
+
+  load1(0);
+  __syncthreads();                         // scales
+  store1(0, 0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) load1(c + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+#pragma unroll
+      for (int s = 0; s < TPW; ++s)
+        if (own[s]) {
+          const T a = As[(buf * BK + kk + lk) * LDA + 16 * trs[s] + li];
+          const T b = Bs[(buf * BK + kk + lk) * LDB + 16 * tcs[s] + li];
+          acc[s] = mfma16(a, b, acc[s]);
+        }
+    }
+    if (c + 1 < nch) store1(c + 1, buf ^ 1);   // buffer buf ^ 1 was last read before the previous barrier
+    __syncthreads();
+  }
+  // X to LDS, row-major; the accumulators start over for G'
+#pragma unroll
+  for (int s = 0; s < TPW; ++s) {
+    if (own[s]) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Xs[(16 * trs[s] + frag_row<T>(lane, v)) * LDX + 16 * tcs[s] + li] = acc[s][v];
+    }
+    acc[s] = F{0, 0, 0, 0};
+  }
+  load2(0);
+  store2(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) load2(c + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+#pragma unroll
+      for (int s = 0; s < TPW; ++s)
+        if (own[s]) {
+          const T a = Xs[(16 * trs[s] + li) * LDX + BK * c + kk + lk];
+          const T b = Bs[(buf * BK + kk + lk) * LDB + 16 * tcs[s] + li];
+          acc[s] = mfma16(a, b, acc[s]);
+        }
+    }
+    if (c + 1 < nch) store2(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < TPW; ++s)
+    if (own[s]) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = 16 * trs[s] + frag_row<T>(lane, v), col = 16 * tcs[s] + li;
+        if (r0 + lr < n && col < n) Go[(long)(r0 + lr) * n + col] = (T)(r2v[lr] * (double)acc[s][v] * c2v[col]);
+      }
+    }
+}
+
+template <typename T, int MAXT>
+static hipError_t launch_wrap_t(const WrapArgs<T>& w, hipStream_t s) {
+  const size_t lds = WrapLds<T, MAXT>::bytes();
+  hipLaunchKernelGGL((wrap_fused_kernel<T, MAXT>), dim3(2, w.batch), dim3(64 * WRAP_WAVES), lds, s, w);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_wrap_any(const WrapArgs<T>& w, hipStream_t s) {
+  if (w.batch <= 0) return hipSuccess;
+  if (!wrap_fused_supported(w.n, sizeof(T) == 4)) return hipErrorInvalidValue;
+  if (w.n <= 64) return launch_wrap_t<T, 4>(w, s);
+  if (w.n <= 112) return launch_wrap_t<T, 7>(w, s);
+  return launch_wrap_t<T, 9>(w, s);
+}
+
+bool wrap_fused_supported(int n, bool fp32) {
+  (void)fp32;
+  return n >= 1 && n <= 144;
+}
+hipError_t launch_wrap_fused(const WrapArgs<double>& w, hipStream_t s) { return launch_wrap_any(w, s); }
+hipError_t launch_wrap_fused(const WrapArgs<float>& w, hipStream_t s) { return launch_wrap_any(w, s); }
+
+template <typename T>
+static hipError_t allow_wrap_t() {
+  hipError_t e = hipSuccess, x;
+  x = hipFuncSetAttribute((const void*)wrap_fused_kernel<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)WrapLds<T, 4>::bytes());
+  if (x != hipSuccess) e = x;
+  x = hipFuncSetAttribute((const void*)wrap_fused_kernel<T, 7>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)WrapLds<T, 7>::bytes());
+  if (x != hipSuccess) e = x;
+  x = hipFuncSetAttribute((const void*)wrap_fused_kernel<T, 9>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)WrapLds<T, 9>::bytes());
+  if (x != hipSuccess) e = x;
+  return e;
+}
+
 // raise the dynamic-LDS limit of the full-K kernels once, before any capture
 hipError_t prepare_gemm() {
   const hipError_t e1 = allow_fullk_t<double>();
   const hipError_t e2 = allow_fullk_t<float>();
-  return e1 != hipSuccess ? e1 : e2;
+  const hipError_t e3 = allow_wrap_t<double>();
+  const hipError_t e4 = allow_wrap_t<float>();
+  return e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e3 != hipSuccess ? e3 : e4));
 }
 
 // P[z] = diag(rs(z)) * A, A shared by the batch

@@ -35,6 +35,8 @@ struct Group {
   int nx = 0, n = 0, L = 0, ns = 0, nb = 0, C = 0, chain0 = 0;
   int nt = 256, kd = 16, tile = TILE_64x64, tile32 = TILE_64x64;
   double tile_us = 0.0, tile32_us = 0.0;   // autotuner timings
+  bool fused_wrap = false;                 // both wrap products in one launch (autotuner's choice)
+  double wrap_us = 0.0;                    // measured time of one wrap as chosen
   bool global = false, network = false;
   // fields, couplings, model matrices
   double *x = nullptr, *xp = nullptr, *g = nullptr;
@@ -43,6 +45,9 @@ struct Group {
   // Green's functions
   void* G = nullptr;             // [C][n][n], precision of the context
   void* Wt = nullptr;            // wrap temporary, same precision
+  // A fused wrap writes G' into Wt and the two buffers trade places; G0 is
+  // where G lives between sweeps
+  void* G0 = nullptr;
   double* Gnew = nullptr;        // [C][n][n]
   // block products and UDT stacks
   double *blk = nullptr, *blkp = nullptr, *blks = nullptr;     // [C][nb][n][n]
@@ -193,6 +198,7 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
     g.expk32 = cv.take<float>(nn);
     g.expkinv32 = cv.take<float>(nn);
     g.G = cv.take<char>(C * nn * ts);
+    g.G0 = g.G;
     g.Wt = cv.take<char>(C * nn * ts);
     g.Gnew = cv.take<double>(C * nn);
     g.blk = cv.take<double>(C * nb * nn);
@@ -482,11 +488,38 @@ hq_status from_scratch(Sched& S, Group& g, const double* xs, double* blocks) {
   return merge(S, g, g.LU, nn, g.LD, g.LT[t], nn, nullptr, 0, nullptr, 0, nullptr, 0);
 }
 
+// one launch for both products of a wrap: Wt = diag(rs2) (A1 diag(ks1) G diag(cs1)) A2 diag(cs2),
+// then G and Wt trade places
+template <typename T>
+hq_status fused_wrap(Sched& S, Group& g, const T* A1, const T* A2, Scale ks1, Scale cs1, Scale rs2, Scale cs2) {
+  WrapArgs<T> w;
+  w.n = g.n; w.batch = g.C;
+  w.A1 = A1; w.A2 = A2;
+  w.Gin = (const T*)g.G; w.Gout = (T*)g.Wt; w.sG = (long)g.n * g.n;
+  w.ks1 = ks1; w.cs1 = cs1; w.rs2 = rs2; w.cs2 = cs2;
+  SCHED_TRY(launch_wrap_fused(w, S.s));
+  std::swap(g.G, g.Wt);
+  return HQ_OK;
+}
+
+// G back in G0 at the end of a group's sweep (after an odd number of fused wraps)
+hq_status settle_g(Sched& S, Group& g) {
+  if (g.G == g.G0) return HQ_OK;
+  const size_t ts = S.ctx->opt.precision == HQ_PREC_MIXED ? sizeof(float) : sizeof(double);
+  SCHED_TRY(launch_copy_u32((uint32_t*)g.G0, (const uint32_t*)g.G, (long)g.C * g.n * g.n * (long)(ts / 4), S.s));
+  std::swap(g.G, g.Wt);
+  return HQ_OK;
+}
+
 hq_status wrap(Sched& S, Group& g, int slice) {
   const long nn = (long)g.n * g.n;
   Scale rs, cs;
   rs.v = g.x; rs.so = (long)g.L * g.n; rs.off = (long)slice * g.n; rs.coef = g.g; rs.cmul = -g.p.dtau;
   cs = rs; cs.cmul = g.p.dtau;
+  if (g.fused_wrap) {
+    if (S.ctx->opt.precision == HQ_PREC_MIXED) return fused_wrap<float>(S, g, g.expk32, g.expkinv32, Scale(), Scale(), rs, cs);
+    return fused_wrap<double>(S, g, g.expk, g.expkinv, Scale(), Scale(), rs, cs);
+  }
   if (S.ctx->opt.precision == HQ_PREC_MIXED) {
     GemmArgs<float> a;
     a.M = a.N = a.K = g.n; a.lda = a.ldb = a.ldc = g.n; a.batch = g.C;
@@ -536,6 +569,10 @@ hq_status unwrap(Sched& S, Group& g, int slice) {
   Scale ks, cs;
   ks.v = g.x; ks.so = (long)g.L * g.n; ks.off = (long)slice * g.n; ks.coef = g.g; ks.cmul = g.p.dtau;
   cs = ks; cs.cmul = -g.p.dtau;
+  if (g.fused_wrap) {
+    if (S.ctx->opt.precision == HQ_PREC_MIXED) return fused_wrap<float>(S, g, g.expkinv32, g.expk32, ks, cs, Scale(), Scale());
+    return fused_wrap<double>(S, g, g.expkinv, g.expk, ks, cs, Scale(), Scale());
+  }
   if (S.ctx->opt.precision == HQ_PREC_MIXED) {
     GemmArgs<float> a;
     a.M = a.N = a.K = g.n; a.lda = a.ldb = a.ldc = g.n; a.batch = g.C;
@@ -747,7 +784,12 @@ hq_status sweep_group(Sched& S, Group& g, int dir, bool rebuild) {
 
 hq_status enqueue_group(hq_ctx* ctx, Group& g, hipStream_t s, int dir, bool rebuild) {
   Sched S{ctx, s};
-  ST_TRY(sweep_group(S, g, dir, rebuild));
+  hq_status st = sweep_group(S, g, dir, rebuild);
+  if (st == HQ_OK) st = settle_g(S, g);
+  if (st != HQ_OK) {
+    if (g.G != g.G0) std::swap(g.G, g.Wt);   // the enqueue failed part-way: keep the buffers' roles
+    return st;
+  }
   for (int k : {HQ_KIND_LOCAL, HQ_KIND_GLOBAL, HQ_KIND_NN, HQ_KIND_CUMULATIVE})
     SCHED_TRY(launch_fill_u8(g.replay[k], 255, (long)g.C * g.kind_slots(k), S.s));
   return HQ_OK;
@@ -829,6 +871,37 @@ hq_status autotune(hq_ctx* ctx) {
       else { g.tile = bt; g.tile_us = best; }
     }
     if (ctx->opt.precision != HQ_PREC_MIXED) { g.tile32 = g.tile; g.tile32_us = g.tile_us; }
+    // the wrap: both products in one launch, or two tiled products
+    g.fused_wrap = false;
+    g.wrap_us = 2.0 * g.tile32_us;
+    const bool mixed = ctx->opt.precision == HQ_PREC_MIXED;
+    if (st == HQ_OK && wrap_fused_supported(g.n, mixed)) {
+      auto run = [&]() {
+        if (mixed) {
+          WrapArgs<float> w;
+          w.n = g.n; w.batch = g.C; w.A1 = g.expk32; w.A2 = g.expkinv32;
+          w.Gin = (const float*)g.G; w.Gout = (float*)g.Wt; w.sG = nn;
+          return launch_wrap_fused(w, s);
+        }
+        WrapArgs<double> w;
+        w.n = g.n; w.batch = g.C; w.A1 = g.expk; w.A2 = g.expkinv;
+        w.Gin = (const double*)g.G; w.Gout = (double*)g.Wt; w.sG = nn;
+        return launch_wrap_fused(w, s);
+      };
+      hipError_t e = run();
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int k = 0; k < 3 && e == hipSuccess; ++k) e = run();
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = fail(ctx, HQ_EDEVICE, "autotune: %s", hipGetErrorString(e));
+      } else if (1e3 * ms / 3.0 < g.wrap_us) {
+        g.fused_wrap = true;
+        g.wrap_us = 1e3 * ms / 3.0;
+      }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1210,10 +1283,12 @@ hq_status hq_read_tuning(const hq_ctx* ctx, int32_t group, hq_tuning* out) {
   out->local_block = g.kd;
   out->gemm_us_fp64 = g.tile_us;
   out->gemm_us_wrap = g.tile32_us;
+  out->wrap_fused = g.fused_wrap ? 1 : 0;
+  out->wrap_us = g.wrap_us;
   return HQ_OK;
 }
 
-hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t tile_wrap) {
+hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t tile_wrap, int32_t wrap_fused) {
   ST_TRY(check_ctx(ctx));
   if (group < 0 || group >= (int32_t)ctx->groups.size()) return fail(ctx, HQ_EINVAL, "bad group %d", group);
   Group& g = ctx->groups[group];
@@ -1224,11 +1299,14 @@ hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t t
     return fail(ctx, HQ_EINVAL, "GEMM tile %d does not fit the wraps' products of size %d", tile_wrap, g.n);
   if (!mixed && tile_wrap != tile_fp64)
     return fail(ctx, HQ_EINVAL, "in FP64 precision the wraps use the FP64 tile");
+  if ((wrap_fused != 0 && wrap_fused != 1) || (wrap_fused && !wrap_fused_supported(g.n, mixed)))
+    return fail(ctx, HQ_EINVAL, "no fused wrap for N = %d", g.n);
   HQ_TRY(hipStreamSynchronize(ctx->stream));
   drop_graphs(ctx);
   g.tile = tile_fp64;
   g.tile32 = tile_wrap;
-  g.tile_us = g.tile32_us = 0.0;
+  g.fused_wrap = wrap_fused != 0;
+  g.tile_us = g.tile32_us = g.wrap_us = 0.0;
   return HQ_OK;
 }
 

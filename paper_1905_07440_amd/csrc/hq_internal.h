@@ -41,6 +41,23 @@ enum GemmTile { TILE_64x64 = 0, TILE_32x32 = 1, TILE_48x48 = 2, TILE_16x64 = 3, 
                 TILE_FK_64x64 = 6, TILE_FK_32x64 = 7, TILE_PF_48x48 = 8, TILE_PF_64x64 = 9, TILE_PF_32x32 = 10,
                 N_GEMM_TILES = 11 };
 
+// Both products of a wrap for every chain in one launch (gemm.hip):
+//   Gout[z] = diag(rs2) (A1 diag(ks1) Gin[z] diag(cs1)) A2 diag(cs2)
+// A1, A2 shared by the batch (n x n, row-major); Gout must not overlap Gin.
+template <typename T>
+struct WrapArgs {
+  int n = 0, batch = 0;
+  const T* A1 = nullptr;
+  const T* A2 = nullptr;
+  const T* Gin = nullptr;
+  T* Gout = nullptr;
+  long sG = 0;
+  Scale ks1, cs1, rs2, cs2;
+};
+bool wrap_fused_supported(int n, bool fp32);
+hipError_t launch_wrap_fused(const WrapArgs<double>& w, hipStream_t s);
+hipError_t launch_wrap_fused(const WrapArgs<float>& w, hipStream_t s);
+
 hipError_t launch_gemm(const GemmArgs<double>& a, int tile, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs<float>& a, int tile, hipStream_t s);
 bool gemm_tile_fits(int tile, int K, int precision);
@@ -182,6 +199,7 @@ struct CumulativeArgs {
 };
 hipError_t launch_cumulative(const CumulativeArgs& a, int chains, hipStream_t s);
 hipError_t launch_copy_f64(double* dst, const double* src, long count, hipStream_t s);
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, long count, hipStream_t s);
 
 // counters layout per chain
 enum { CNT_LOCAL_P = 0, CNT_LOCAL_A, CNT_GLOBAL_P, CNT_GLOBAL_A, CNT_NN_P, CNT_NN_A, CNT_CUM_P,

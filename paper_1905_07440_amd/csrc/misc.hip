@@ -131,6 +131,10 @@ __global__ void f32_to_f64_kernel(double* d, const float* s, long n) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) d[e] = (double)s[e];
 }
+__global__ void copy_u32_kernel(uint32_t* d, const uint32_t* s, long n) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) d[e] = s[e];
+}
 __global__ void copy_f64_kernel(double* d, const double* s, long n) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) d[e] = s[e];
@@ -156,6 +160,11 @@ static inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
 hipError_t launch_copy_f64_to_f32(float* dst, const double* src, long count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(f64_to_f32_kernel, dim3(nblk(count)), dim3(256), 0, s, dst, src, count);
+  return hipGetLastError();
+}
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_u32_kernel, dim3(nblk(count)), dim3(256), 0, s, dst, src, count);
   return hipGetLastError();
 }
 hipError_t launch_copy_f32_to_f64(double* dst, const float* src, long count, hipStream_t s) {

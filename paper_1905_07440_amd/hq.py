@@ -64,7 +64,8 @@ class Stats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("gemm_tile_fp64", ctypes.c_int32), ("gemm_tile_wrap", ctypes.c_int32),
                 ("local_block", ctypes.c_int32), ("gemm_us_fp64", ctypes.c_double),
-                ("gemm_us_wrap", ctypes.c_double)]
+                ("gemm_us_wrap", ctypes.c_double), ("wrap_fused", ctypes.c_int32),
+                ("wrap_us", ctypes.c_double)]
 
 
 N_GEMM_TILES = 11
@@ -113,7 +114,7 @@ def load(path=LIB_PATH):
     lib.hq_set_profiling.argtypes = [P, I32]
     lib.hq_phase_time.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)]
     lib.hq_read_tuning.argtypes = [P, I32, ctypes.POINTER(Tuning)]
-    lib.hq_set_tuning.argtypes = [P, I32, I32, I32]
+    lib.hq_set_tuning.argtypes = [P, I32, I32, I32, I32]
     lib.hq_gemm_tile_name.argtypes = [I32]
     lib.hq_gemm_tile_name.restype = ctypes.c_char_p
     lib.hq_synchronize.argtypes = [P]
@@ -240,11 +241,12 @@ class Context:
         self._check(self._lib.hq_phase_time(self._ctx, phase.encode(), ctypes.byref(ms), ctypes.byref(k)))
         return ms.value, k.value
 
-    def set_tuning(self, group, tile_fp64, tile_wrap=None):
+    def set_tuning(self, group, tile_fp64, tile_wrap=None, wrap_fused=False):
         """Pin a group's GEMM tiles (codes 0 .. N_GEMM_TILES-1; the wraps take
-        tile_fp64 when tile_wrap is None)."""
+        tile_fp64 when tile_wrap is None) and the wrap's form (one fused launch
+        or two tiled products)."""
         self._check(self._lib.hq_set_tuning(self._ctx, group, tile_fp64,
-                                            tile_fp64 if tile_wrap is None else tile_wrap))
+                                            tile_fp64 if tile_wrap is None else tile_wrap, int(wrap_fused)))
 
     def tuning(self, group):
         """The autotuner's choices for one group (GEMM tiles by name, timings in us)."""
@@ -253,7 +255,7 @@ class Context:
         name = self._lib.hq_gemm_tile_name
         return {"gemm_tile_fp64": name(t.gemm_tile_fp64).decode(), "gemm_us_fp64": t.gemm_us_fp64,
                 "gemm_tile_wrap": name(t.gemm_tile_wrap).decode(), "gemm_us_wrap": t.gemm_us_wrap,
-                "local_block": t.local_block}
+                "wrap_fused": bool(t.wrap_fused), "wrap_us": t.wrap_us, "local_block": t.local_block}
 
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx:

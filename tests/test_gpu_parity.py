@@ -232,6 +232,32 @@ def test_every_gemm_tile_mixed_wraps(hq, tile):
                        sweeps=2, setup=lambda ctx: ctx.set_tuning(0, 0, tile))
 
 
+@pytest.mark.parametrize("nx", [3, 8, 10, 12])
+def test_fused_wrap_fp64(hq, nx):
+    """Both wrap products in one launch (one instantiation per lattice-size
+    class, ragged N = 9 and 100 included), an upward and a downward sweep;
+    L = 9 and n_stab = 3 put the stabilisation points and the end of the sweep
+    after odd numbers of wraps, where G sits in the other buffer."""
+    say("FP64 fused wrap nx=%d" % nx)
+    gr = dict(nx=nx, chains=2, g=1.2, beta=0.9, n_stab=3)
+    ctx = make_ctx(hq, [gr], seed=15)
+    ctx.set_tuning(0, 0, 0, wrap_fused=True)
+    assert ctx.tuning(0)["wrap_fused"]
+    ctx.sweep(2)
+    for c in range(2):
+        ch = dqmc.Chain(params_of(gr), 15, c)
+        ch.sweep(); ch.sweep()
+        assert_state(ctx, c, ch, TOL64, "fused wrap nx=%d chain %d" % (nx, c))
+    ctx.close()
+
+
+@pytest.mark.parametrize("nx", [5, 12])
+def test_fused_wrap_mixed(hq, nx):
+    say("mixed fused wrap nx=%d" % nx)
+    _mixed_replay_case(hq, dict(nx=nx, chains=1, g=1.3, beta=0.9, n_stab=3), (0,), seed=16, sweeps=2,
+                       setup=lambda ctx: ctx.set_tuning(0, 0, 0, wrap_fused=True))
+
+
 def test_set_tuning_rejects_bad_tiles(hq):
     say("set_tuning errors")
     ctx = make_ctx(hq, [dict(nx=16, chains=1, beta=0.4, n_stab=2)])
@@ -243,6 +269,8 @@ def test_set_tuning_rejects_bad_tiles(hq):
         ctx.set_tuning(0, 10)                   # 32x32 prefetch holds K <= 160; here K = 256
     with pytest.raises(hq.HQError):
         ctx.set_tuning(1, 0)
+    with pytest.raises(hq.HQError):
+        ctx.set_tuning(0, 0, 0, wrap_fused=True)   # N = 256: no fused wrap
     ctx.sweep(1)
     assert ctx.stats(0)["local_proposals"] == 256 * 4
     ctx.close()
