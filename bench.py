@@ -160,6 +160,26 @@ def run_workload(w, steps, warmup, profile=True):
     return out
 
 
+# HBM bytes per launch of the local-move kernel from the FETCH_SIZE / WRITE_SIZE
+# counter runs on the mixed 12x12 workload, scaled by the same counters on a
+# plain copy (profiles/local_regs_kernel_12x12_mixed_traffic.txt); valid only
+# for the kernel source those runs measured
+LOCAL_TRAFFIC = {"sha1": "2837df4eec3c9a09f0671f3777a19fa6f298e832", "bytes": 22773499,
+                 "workload": "holstein-12x12-L120-mixed-nstab6-128chains"}
+
+
+def measured_traffic(w):
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1905_07440_amd", "csrc", "local.hip")
+    try:
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if sha != LOCAL_TRAFFIC["sha1"] or w.name != LOCAL_TRAFFIC["workload"]:
+        return None
+    return LOCAL_TRAFFIC["bytes"]
+
+
 def local_roofline(w, res):
     """Roofline of the local-move kernel (one launch per slice covers every
     chain of the group): algorithmic flops = 2 N^2 per accepted move (the
@@ -174,7 +194,7 @@ def local_roofline(w, res):
     peak = MI355X_PEAK["fp32" if w.precision else "fp64"]
     hbm = g.n_chains * 2.0 * n * n * (4 if w.precision else 8)
     return {"bound": "mfma", "achieved": flops / per_launch_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": flops / per_launch_s / peak, "traffic": None, "kernel": "local_regs_kernel",
+            "frac": flops / per_launch_s / peak, "traffic": measured_traffic(w), "kernel": "local_regs_kernel",
             "note": ("one launch = the local moves of one slice for all %d chains; its G traffic is %.1f MB, "
                      "%.1f us at 8 TB/s, so the kernel is bound by the sequential accept chain, not HBM"
                      % (g.n_chains, hbm / 1e6, hbm / 8e12 * 1e6))}
