@@ -13,6 +13,21 @@
 
 namespace hq {
 
+// Workgroups are dealt to the eight XCDs in turn (workgroup g runs on XCD
+// g mod 8), each XCD with its own L2.  The grid is one-dimensional and is
+// read so that all tiles of one batch entry land on the same XCD: XCD x
+// takes entries x, x + 8, ..., tile by tile, and the entry's operands are
+// fetched into that L2 once.  Returns false for the padding workgroups of a
+// batch that is not a multiple of 8.
+constexpr int N_XCD = 8;
+__device__ inline bool xcd_tile(int tiles, int batch, int& z, int& tile) {
+  const int g = blockIdx.x, x = g % N_XCD, k = g / N_XCD;
+  z = N_XCD * (k / tiles) + x;
+  tile = k % tiles;
+  return z < batch;
+}
+inline unsigned xcd_grid(int tiles, int batch) { return (unsigned)(N_XCD * ((batch + N_XCD - 1) / N_XCD) * tiles); }
+
 __device__ inline double scale_value(const Scale& s, int z, int inner_count, int i) {
   if (!s.v) return 1.0;
   const int outer = z / inner_count, inner = z - outer * inner_count;
@@ -39,8 +54,10 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
   __shared__ double csv[BN];
   __shared__ double ksv[256];
 
-  const int z = blockIdx.z;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tn = (a.N + BN - 1) / BN, tm = (a.M + BM - 1) / BM;
+  int z, tile;
+  if (!xcd_tile(tn * tm, a.batch, z, tile)) return;
+  const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
@@ -170,8 +187,10 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_fullk_kernel(GemmArgs<T> a)
   __shared__ double csv[BN];
   __shared__ double ksv[256];
 
-  const int z = blockIdx.z;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tn = (a.N + BN - 1) / BN, tm = (a.M + BM - 1) / BM;
+  int z, tile;
+  if (!xcd_tile(tn * tm, a.batch, z, tile)) return;
+  const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
@@ -282,8 +301,10 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_regpf_kernel(GemmArgs<T> a)
   __shared__ double csv[BN];
   __shared__ double ksv[256];
 
-  const int z = blockIdx.z;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tn = (a.N + BN - 1) / BN, tm = (a.M + BM - 1) / BM;
+  int z, tile;
+  if (!xcd_tile(tn * tm, a.batch, z, tile)) return;
+  const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
@@ -389,7 +410,7 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_regpf_kernel(GemmArgs<T> a)
 template <typename T, int BM, int BN, int WM, int WN>
 static hipError_t launch_regpf(const GemmArgs<T>& a, hipStream_t s) {
   if (a.K > 256) return hipErrorInvalidValue;
-  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, a.batch);
+  const dim3 grid(xcd_grid(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch));
   if (a.K <= 160) {
     hipLaunchKernelGGL((gemm_regpf_kernel<T, BM, BN, WM, WN, 10>), grid, dim3(WM * WN * 64), 0, s, a);
   } else {
@@ -407,14 +428,14 @@ template <typename T, int BM, int BN, int WM, int WN>
 static hipError_t launch_fullk(const GemmArgs<T>& a, hipStream_t s) {
   const size_t lds = fullk_lds<T, BM, BN>(a.K);
   if (lds > 150 * 1024) return hipErrorInvalidValue;
-  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, a.batch);
+  const dim3 grid(xcd_grid(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch));
   hipLaunchKernelGGL((gemm_fullk_kernel<T, BM, BN, WM, WN>), grid, dim3(WM * WN * 64), lds, s, a);
   return hipGetLastError();
 }
 
 template <typename T, int BM, int BN, int WM, int WN>
 static hipError_t launch_tile(const GemmArgs<T>& a, hipStream_t s) {
-  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, a.batch);
+  const dim3 grid(xcd_grid(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch));
   hipLaunchKernelGGL((gemm_kernel<T, BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s, a);
   return hipGetLastError();
 }
@@ -519,7 +540,8 @@ __global__ __launch_bounds__(64 * WRAP_WAVES) void wrap_fused_kernel(WrapArgs<T>
 
   const int n = w.n, nt = (n + 15) / 16;
   const int nch = (16 * nt + BK - 1) / BK;  // chunks per product
-  const int part = blockIdx.x, z = blockIdx.y;
+  int z, part;
+  if (!xcd_tile(2, w.batch, z, part)) return;
   const int h0 = (nt + 1) / 2;
   const int t0 = part == 0 ? 0 : h0, nrt = part == 0 ? h0 : nt - h0;
   const int r0 = 16 * t0, R = 16 * nrt;
@@ -660,7 +682,7 @@ __global__ __launch_bounds__(64 * WRAP_WAVES) void wrap_fused_kernel(WrapArgs<T>
 template <typename T, int MAXT>
 static hipError_t launch_wrap_t(const WrapArgs<T>& w, hipStream_t s) {
   const size_t lds = WrapLds<T, MAXT>::bytes();
-  hipLaunchKernelGGL((wrap_fused_kernel<T, MAXT>), dim3(2, w.batch), dim3(64 * WRAP_WAVES), lds, s, w);
+  hipLaunchKernelGGL((wrap_fused_kernel<T, MAXT>), dim3(xcd_grid(2, w.batch)), dim3(64 * WRAP_WAVES), lds, s, w);
   return hipGetLastError();
 }
 
