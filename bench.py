@@ -200,6 +200,44 @@ def local_roofline(w, res):
                      % (g.n_chains, hbm / 1e6, hbm / 8e12 * 1e6))}
 
 
+def sweep_roofline(w, res):
+    """The whole sweep against the MFMA peaks: the dense operation counts of
+    the scheme as built, per sweep of all chains (N = sites, L = slices,
+    n_s = recompute interval, 2N^3 per product):
+      wraps           4 N^3 L                        (FP32 in mixed precision)
+      local updates   2 N^2 per accepted move        (FP32 in mixed precision)
+      stabilisation   per point: (n_s - 1) block-product steps 2N^3 each, a
+                      combine (product 2N^3, QR with explicit Q (8/3)N^3,
+                      triangular product 2N^3) and a merge (four products
+                      8N^3, Gauss-Jordan 2N^3): 2 N^3 n_s + (44/3) N^3
+      block moves     per proposal: all block products, L/n_s combines and a
+                      merge from scratch
+    T_roof = F32 / P32 + F64 / P64; frac = T_roof / measured time."""
+    f32 = f64 = 0.0
+    for g in w.groups:
+        if g.proposal:
+            return None
+        n = g.nx * g.nx
+        L = round(g.beta / g.dtau)
+        ns = g.n_stab
+        n3 = float(n) ** 3
+        wraps = 4.0 * n3 * L
+        upd = 2.0 * n * n * res["local_acceptance"] * n * L
+        stab = (L / ns) * (2.0 * n3 * ns + 44.0 / 3.0 * n3)
+        glob = 0.0
+        if g.global_width > 0:
+            glob = n * (2.0 * n3 * (ns - 1) * (L / ns) + (L / ns) * (4.0 + 8.0 / 3.0) * n3 + 10.0 * n3)
+        if w.precision:
+            f32 += g.n_chains * (wraps + upd)
+            f64 += g.n_chains * (stab + glob)
+        else:
+            f64 += g.n_chains * (wraps + upd + stab + glob)
+    t = f32 / MI355X_PEAK["fp32"] + f64 / MI355X_PEAK["fp64"]
+    return {"fp32_gflop": f32 / 1e9, "fp64_gflop": f64 / 1e9, "t_roof_ms": t * 1e3,
+            "frac": t * 1e3 / res["ms_per_step"], "peaks_tflops": {"fp32": MI355X_PEAK["fp32"] / 1e12,
+                                                               "fp64": MI355X_PEAK["fp64"] / 1e12}}
+
+
 def main():
     a = parse()
     if a.copy_calibration:
@@ -251,6 +289,7 @@ def main():
         "phases": res["phases"],
         "dominant_phase": dominant,
         "roofline": local_roofline(w, res),
+        "sweep_roofline": sweep_roofline(w, res),
         "cpu_baseline": cpu,
         "wall_s": res["wall_s"],
     }
