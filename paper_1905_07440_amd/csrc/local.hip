@@ -360,10 +360,14 @@ __device__ inline void walk_strips(int npw, int base, int cnt, int blk, const T*
       if (acc) {
         const int i = base + q;
         const T coef = (T)delta * recip((T)r);
-        // G[i, S] and G[S, i] as wave-uniform values
+        // G[i, S] and G[S, i] as wave-uniform values.  Site k reads only
+        // column and row k of the strips, so once the first half of the
+        // block is walked its columns are no longer updated (the loop bounds
+        // stay fixed per half, which keeps the register allocation compact).
         T nb[K], ci[K];
+        const int k0 = (q < K / 2) ? 0 : K / 2;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = k0; k < K; ++k) {
           nb[k] = ((k == q) ? T(1) : T(0)) - bcast(rq, l0 + k);
           ci[k] = bcast(cq, l0 + k);
         }
@@ -377,7 +381,7 @@ __device__ inline void walk_strips(int npw, int base, int cnt, int blk, const T*
             Bp[j * KL + m] = nr;
           }
 #pragma unroll
-          for (int k = 0; k < K; ++k) {
+          for (int k = k0; k < K; ++k) {
             cs[t][k] -= na * nb[k];
             rs[t][k] -= (coef * ci[k]) * nr;
           }
@@ -713,15 +717,17 @@ __global__ __launch_bounds__(256) void local_stream_kernel(LocalArgs a) {
 // ---------------------------------------------------------------------------
 static const size_t kMaxLds = 160 * 1024;
 
-// tile-grid classes of the register form: N <= 16 * NT.  Beyond N = 144 the
-// tiles plus the working registers exceed the register file, and the
-// streamed form takes over.
+// tile-grid classes of the register form: N <= 16 * NT.  Up to N = 144 the
+// tiles and the walker's strips fit the register file with room to spare;
+// an FP32 G of N = 256 fills the accumulators (64 tiles a wave) and the
+// walker spills some of its strips, which still beats streaming G from
+// memory.  FP64 beyond N = 144 takes the streamed form.
 static int reg_class(int n, int precision) {
-  (void)precision;
   const int nt = pad16(n) / 16;
   if (nt <= 4) return 4;
   if (nt <= 7) return 7;
   if (nt <= 9) return 9;
+  if (nt <= 16 && precision) return 16;
   return 0;
 }
 
@@ -732,7 +738,8 @@ static size_t lds_t(int n, bool regs) {
 
 static bool use_regs(int n, int precision, int kd) {
   if (kd != 16 && kd != 32) return false;
-  if (!reg_class(n, precision)) return false;
+  const int rc = reg_class(n, precision);
+  if (!rc || (rc == 16 && kd != 16)) return false;   // N > 144: blocks of 16 only
   const size_t b = precision ? (kd == 16 ? lds_t<float, 16>(n, true) : lds_t<float, 32>(n, true))
                              : (kd == 16 ? lds_t<double, 16>(n, true) : lds_t<double, 32>(n, true));
   return b <= kMaxLds;
@@ -767,6 +774,9 @@ static hipError_t launch_k(const LocalArgs& a, int precision, int chains, hipStr
         case 4: return launch_regs<T, K, 4>(a, chains, s);
         case 7: return launch_regs<T, K, 7>(a, chains, s);
         case 9: return launch_regs<T, K, 9>(a, chains, s);
+        case 16:
+          if constexpr (sizeof(T) == 4 && K == 16) return launch_regs<T, K, 16>(a, chains, s);
+          break;
         default: break;
       }
       return hipErrorInvalidValue;
@@ -797,6 +807,9 @@ static hipError_t allow_all_t() {
   HQ_ALLOW(local_regs_kernel<T, 32, 4>);
   HQ_ALLOW(local_regs_kernel<T, 32, 7>);
   HQ_ALLOW(local_regs_kernel<T, 32, 9>);
+  if constexpr (sizeof(T) == 4) {
+    HQ_ALLOW(local_regs_kernel<T, 16, 16>);
+  }
 #undef HQ_ALLOW
   return e;
 }

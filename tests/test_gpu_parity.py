@@ -191,6 +191,13 @@ def test_mixed_12x12_small(hq):
     _mixed_replay_case(hq, dict(nx=12, chains=2, g=1.5, beta=2.0, n_stab=10), (0, 1), seed=3, sweeps=2)
 
 
+def test_mixed_16x16_register_form(hq):
+    """N = 256 in mixed precision: G in the accumulators of four waves (64
+    tiles each), an upward and a downward sweep."""
+    say("16x16 mixed, register form")
+    _mixed_replay_case(hq, dict(nx=16, chains=1, g=1.2, beta=0.4, n_stab=2), (0,), seed=8, sweeps=2)
+
+
 def test_mixed_12x12_full_size_sampled(hq):
     """128 chains of 12x12, L = 120 (the mixed workload at full size); chains 0 and 127 vs the oracle."""
     w = workloads.holstein_12x12_mixed()
