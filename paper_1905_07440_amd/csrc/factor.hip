@@ -152,6 +152,192 @@ __device__ inline void wave_totals8(const double (&v)[8], double (&t)[8]) {
 }
 
 // ---------------------------------------------------------------------------
+// Householder factorisation of one panel of 16 columns (rows relative to the
+// panel's diagonal block, m of them) by all four waves: wave w holds panel
+// columns w, w + 4, w + 8, w + 12, one row per lane and slot.  Column j goes
+// to every wave through LDS (Colj, alternating per column); each wave reduces
+// the column's norm below the diagonal together with its dots against its
+// own columns in one butterfly, forms the same reflector, and updates its own
+// columns.  load(c, r) gives the panel; store(c, r, v) receives R on and
+// above the diagonal and the reflectors below it, for every c < 16 and every
+// row slot r; tau[j] the reflectors' scales.
+// ---------------------------------------------------------------------------
+template <int RPL, typename Load, typename Store>
+__device__ inline void factor_panel(int nbw, int m, double (*Colj)[MAXN], double* tau, Load load, Store store) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double a[4][RPL];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int r = lane + 64 * t, c = wave + 4 * q;
+      a[q][t] = (c < nbw && r < m) ? load(c, r) : 0.0;
+    }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < nbw) {
+      const int jq = j >> 2;
+      if (wave == (j & 3)) {
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int r = lane + 64 * t;
+          if (r < MAXN) Colj[j & 1][r] = a[jq][t];
+        }
+      }
+      __syncthreads();
+      // slot 0: the squared norm of column j below the diagonal; slot 1 + q:
+      // the dot of that tail with own column w + 4q (if right of j).  The
+      // reflector's scale enters afterwards, since
+      // v^T a_c = a_c[j] + scl * (tail . a_c[tail])
+      double tail[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = lane + 64 * t;
+        tail[t] = (r > j && r < m) ? Colj[j & 1][r] : 0.0;
+      }
+      double part[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) part[c] = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) part[0] += tail[t] * tail[t];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (wave + 4 * q > j) {
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) part[1 + q] += tail[t] * a[q][t];
+        }
+      double tot[8];
+      wave_totals8(part, tot);
+      const double sg = tot[0];
+      const double al = Colj[j & 1][j];
+      double be = al, tj = 0.0, scl = 0.0;
+      if (sg > 0.0) {
+        const double nrm = sqrt(al * al + sg);
+        be = (al >= 0.0) ? -nrm : nrm;
+        tj = (be - al) * rcp_nr(be);
+        scl = rcp_nr(al - be);             // |al - be| = |al| + nrm > 0
+      }
+      double vr[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = lane + 64 * t;
+        vr[t] = (r == j) ? 1.0 : tail[t] * scl;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (wave + 4 * q > j) {
+          const double w = tj * (lane_value(a[q][0], j) + scl * tot[1 + q]);   // row j lives in lane j
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) a[q][t] -= vr[t] * w;
+        }
+      if (wave == (j & 3)) {
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int r = lane + 64 * t;
+          if (r >= j) a[jq][t] = (r == j) ? be : vr[t];
+        }
+      }
+      if (tid == 0) tau[j] = tj;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) store(wave + 4 * q, lane + 64 * t, a[q][t]);
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Jordan elimination of one panel of 16 columns (all n rows) by all four
+// waves: wave w holds panel columns w, w + 4, w + 8, w + 12, one row per lane
+// and slot.  Column j goes to every wave through LDS; every wave finds the
+// same pivot (the unused row of largest |a| by a DPP maximum over 32-bit keys:
+// |a| rounded to FP32 with its low 9 bits replaced by 511 - row, so
+// near-equal magnitudes go to the lower row) and updates its own columns:
+// rows other than the pivot row lose a multiple of it, the pivot row is
+// divided by the pivot, and column j becomes -a / pivot with 1 / pivot on the
+// pivot row.  used[] marks this lane's pivoted rows (the same in every wave).
+// load(c, r) gives the panel (called for c < nbw, r < n only); store(c, r, v)
+// receives it eliminated, for every c < 16 and row slot r;
+// perm[p0 + j], pinv[row] and pivot[p0 + j] record the pivots.
+// ---------------------------------------------------------------------------
+template <int RPL, typename Load, typename Store>
+__device__ inline void eliminate_panel(int p0, int nbw, int n, double (*Colj)[MAXN], bool (&used)[RPL], int* perm,
+                                       int* pinv, double* pivot, Load load, Store store) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double a[4][RPL];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int r = lane + 64 * t, c = wave + 4 * q;
+      a[q][t] = (r < n && c < nbw) ? load(c, r) : 0.0;
+    }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < nbw) {
+      const int jq = j >> 2;
+      if (wave == (j & 3)) {
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int r = lane + 64 * t;
+          if (r < MAXN) Colj[j & 1][r] = a[jq][t];
+        }
+      }
+      __syncthreads();
+      double aj[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = lane + 64 * t;
+        aj[t] = (r < MAXN) ? Colj[j & 1][r] : 0.0;
+      }
+      uint32_t key = 0;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = lane + 64 * t;
+        const uint32_t kt = (__float_as_uint((float)fabs(aj[t])) & ~0x1FFu) | (uint32_t)(511 - r);
+        if (r < n && !used[t]) key = max(key, kt);
+      }
+      key = wave_max_u32(key);
+      const int pr = 511 - (int)(key & 0x1FFu), pl = pr & 63, pt = pr >> 6;
+      double pmine = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) pmine = (t == pt) ? aj[t] : pmine;
+      const double pj = lane_value(pmine, pl);
+      const double ip = rcp_nr(pj);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (wave + 4 * q == j) {
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) a[q][t] = (lane + 64 * t == pr) ? ip : -aj[t] * ip;
+        } else {
+          // the pivot row's entry of this column, broadcast from its lane
+          double mine = 0.0;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) mine = (t == pt) ? a[q][t] : mine;
+          const double wp = lane_value(mine, pl) * ip;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) a[q][t] = (lane + 64 * t == pr) ? wp : fma(-aj[t], wp, a[q][t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < RPL; ++t)
+        if (lane + 64 * t == pr) used[t] = true;
+      if (tid == 0) {
+        perm[p0 + j] = pr;
+        pinv[pr] = p0 + j;
+        pivot[p0 + j] = pj;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) store(wave + 4 * q, lane + 64 * t, a[q][t]);
+}
+
+// ---------------------------------------------------------------------------
 // A <- A - V op(T) (V^T A) on rows [p0, n) and columns [c_begin, n),
 // op(T) = T^T (transT) or T.  V: Vs[k][r] (r relative to p0, zero outside the
 // panel's rows), T: Ts.  Each wave takes 16-column strips and holds a strip in
@@ -270,9 +456,10 @@ __global__ __launch_bounds__(256) void qr_blocked_kernel(double* __restrict__ Zg
   __shared__ double Sc[4][NB][NB + 1];
   __shared__ double norms[MAXN];
   __shared__ double tau[NB];
+  __shared__ double Colj[2][MAXN];         // panel column j, alternating per column
   __shared__ int perm[MAXN];
   const int z = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, wave = tid >> 6;
   double* Z = Zg + (long)z * n * n;
   double* W = Wg + (long)z * n * n;
   double* Q = Qg + (long)z * n * n;
@@ -306,70 +493,13 @@ __global__ __launch_bounds__(256) void qr_blocked_kernel(double* __restrict__ Zg
 
   for (int pi = 0; pi < npan; ++pi) {
     const int p0 = pi * NB, nbw = min(NB, n - p0), m = n - p0;
-    if (wave == 0) {
-      double a[NB][Cap<MX>::rpl];
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int t = 0; t < Cap<MX>::rpl; ++t) {
-          const int r = lane + 64 * t;
-          a[j][t] = (j < nbw && r < m) ? W[(long)(p0 + r) * n + p0 + j] : 0.0;
-        }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < nbw) {
-          double sg = 0.0, al = 0.0;
-#pragma unroll
-          for (int t = 0; t < Cap<MX>::rpl; ++t) {
-            const int r = lane + 64 * t;
-            if (r > j && r < m) sg += a[j][t] * a[j][t];
-            if (r == j) al = a[j][t];
-          }
-          sg = wave_total(sg);
-          al = wave_total(al);
-          double be = al, tj = 0.0, scl = 0.0;
-          if (sg > 0.0) {
-            const double nrm = sqrt(al * al + sg);
-            be = (al >= 0.0) ? -nrm : nrm;
-            tj = (be - al) / be;
-            scl = 1.0 / (al - be);
-          }
-          double vr[Cap<MX>::rpl];
-#pragma unroll
-          for (int t = 0; t < Cap<MX>::rpl; ++t) {
-            const int r = lane + 64 * t;
-            if (r > j && r < m) a[j][t] *= scl;
-            if (r == j) a[j][t] = be;
-            vr[t] = (r == j) ? 1.0 : ((r > j && r < m) ? a[j][t] : 0.0);
-          }
-          double w[NB];
-#pragma unroll
-          for (int c = j + 1; c < NB; ++c) {
-            w[c] = 0.0;
-#pragma unroll
-            for (int t = 0; t < Cap<MX>::rpl; ++t) w[c] += vr[t] * a[c][t];
-          }
-#pragma unroll
-          for (int c = j + 1; c < NB; ++c) w[c] = wave_total(w[c]) * tj;
-#pragma unroll
-          for (int c = j + 1; c < NB; ++c)
-            if (c < nbw) {
-#pragma unroll
-              for (int t = 0; t < Cap<MX>::rpl; ++t) a[c][t] -= vr[t] * w[c];
-            }
-          if (lane == 0) tau[j] = tj;
-        }
-      }
-      // V to LDS (unit diagonal, zero above and below the panel rows); R and V back to W
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int t = 0; t < Cap<MX>::rpl; ++t) {
-          const int r = lane + 64 * t;
-          Vs[j][r] = (j < nbw && r < m) ? ((r == j) ? 1.0 : ((r > j) ? a[j][t] : 0.0)) : 0.0;
-          if (j < nbw && r < m) W[(long)(p0 + r) * n + p0 + j] = a[j][t];
-        }
-    }
+    factor_panel<Cap<MX>::rpl>(
+        nbw, m, Colj, tau, [&](int c, int r) { return W[(long)(p0 + r) * n + p0 + c]; },
+        [&](int c, int r, double v) {
+          // V to LDS (unit diagonal, zero above and below the panel rows); R and V back to W
+          if (r < VLD) Vs[c][r] = (c < nbw && r < m) ? ((r == c) ? 1.0 : ((r > c) ? v : 0.0)) : 0.0;
+          if (c < nbw && r < m) W[(long)(p0 + r) * n + p0 + c] = v;
+        });
     Vs[tid >> 4][MAXN + (tid & 15)] = 0.0;
     __syncthreads();
     form_t(Vs, m, nbw, tau, Gm, Ts, Sc);
@@ -533,101 +663,17 @@ __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, d
         }
     }
     __syncthreads();
-    // the panel is factored by all four waves: wave w holds panel columns
-    // w, w + 4, w + 8, w + 12 (one row per lane and slot).  Column j goes to
-    // every wave through LDS; each wave reduces the column's norm below the
-    // diagonal together with its dots against its own columns in one
-    // butterfly, forms the same reflector, and updates its own columns.
-    {
-      constexpr int RPL = Cap<MX>::rpl;
-      double a[4][RPL];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int r = lane + 64 * t, c = wave + 4 * q;
-          a[q][t] = (c < nbw && r < m) ? Pn[c][r] : 0.0;
-        }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < nbw) {
-          const int jq = j >> 2;
-          if (wave == (j & 3)) {
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) {
-              const int r = lane + 64 * t;
-              if (r < MAXN) Colj[j & 1][r] = a[jq][t];
-            }
-          }
-          __syncthreads();
-          // slot 0: the squared norm of column j below the diagonal; slot
-          // 1 + q: the dot of that tail with own column w + 4q (if right of
-          // j).  The reflector's scale enters afterwards, since
-          // v^T a_c = a_c[j] + scl * (tail . a_c[tail])
-          double tail[RPL];
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            const int r = lane + 64 * t;
-            tail[t] = (r > j && r < m) ? Colj[j & 1][r] : 0.0;
-          }
-          double part[8];
-#pragma unroll
-          for (int c = 0; c < 8; ++c) part[c] = 0.0;
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) part[0] += tail[t] * tail[t];
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (wave + 4 * q > j) {
-#pragma unroll
-              for (int t = 0; t < RPL; ++t) part[1 + q] += tail[t] * a[q][t];
-            }
-          double tot[8];
-          wave_totals8(part, tot);
-          const double sg = tot[0];
-          const double al = Colj[j & 1][j];
-          double be = al, tj = 0.0, scl = 0.0;
-          if (sg > 0.0) {
-            const double nrm = sqrt(al * al + sg);
-            be = (al >= 0.0) ? -nrm : nrm;
-            tj = (be - al) * rcp_nr(be);
-            scl = rcp_nr(al - be);             // |al - be| = |al| + nrm > 0
-          }
-          double vr[RPL];
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            const int r = lane + 64 * t;
-            vr[t] = (r == j) ? 1.0 : tail[t] * scl;
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (wave + 4 * q > j) {
-              const double w = tj * (lane_value(a[q][0], j) + scl * tot[1 + q]);   // row j lives in lane j
-#pragma unroll
-              for (int t = 0; t < RPL; ++t) a[q][t] -= vr[t] * w;
-            }
-          if (wave == (j & 3)) {
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) {
-              const int r = lane + 64 * t;
-              if (r >= j) a[jq][t] = (r == j) ? be : vr[t];
-            }
-          }
-          if (tid == 0) tau[j] = tj;
-        }
-      }
-      // V (unit diagonal, zero above, zero past the panel) to Vs; R and V to Pn and to W
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int r = lane + 64 * t, c = wave + 4 * q;
+    // the panel is factored by all four waves
+    factor_panel<Cap<MX>::rpl>(
+        nbw, m, Colj, tau, [&](int c, int r) { return Pn[c][r]; },
+        [&](int c, int r, double v) {
+          // V (unit diagonal, zero above, zero past the panel) to Vs; R and V to Pn and to W
           if (r < VLD) {
-            Vs[c][r] = (c < nbw && r < m) ? ((r == c) ? 1.0 : ((r > c) ? a[q][t] : 0.0)) : 0.0;
-            Pn[c][r] = (c < nbw && r < m) ? a[q][t] : 0.0;
+            Vs[c][r] = (c < nbw && r < m) ? ((r == c) ? 1.0 : ((r > c) ? v : 0.0)) : 0.0;
+            Pn[c][r] = (c < nbw && r < m) ? v : 0.0;
           }
-          if (c < nbw && r < m) W[(long)(p0 + r) * n + p0 + c] = a[q][t];
-        }
-    }
+          if (c < nbw && r < m) W[(long)(p0 + r) * n + p0 + c] = v;
+        });
     Vs[tid >> 4][MAXN + (tid & 15)] = 0.0;
     __syncthreads();
     form_t(Vs, m, nbw, tau, Gm, Ts, Sc);
@@ -740,7 +786,9 @@ __global__ __launch_bounds__(256) void inv_blocked_kernel(double* __restrict__ M
   __shared__ int perm[MAXN];              // perm[j]: pivot row of column j
   __shared__ int pinv[MAXN];
   __shared__ int panel_of[MAXN];          // panel in which a row became a pivot row
-  __shared__ double logp[MAXN];
+  __shared__ double pivot[MAXN];           // pivot value of column j
+  __shared__ double Colj[2][MAXN];         // panel column j, alternating per column
+  __shared__ double part[4];
   const int z = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -750,86 +798,20 @@ __global__ __launch_bounds__(256) void inv_blocked_kernel(double* __restrict__ M
   panel_of[tid] = -1;
   __syncthreads();
   const int npan = (n + NB - 1) / NB;
-  bool used[Cap<MX>::rpl];                         // wave 0: rows of this lane already pivoted
+  bool used[Cap<MX>::rpl];                         // rows of this lane already pivoted (same in every wave)
 #pragma unroll
   for (int t = 0; t < Cap<MX>::rpl; ++t) used[t] = false;
 
   for (int pi = 0; pi < npan; ++pi) {
     const int p0 = pi * NB, nbw = min(NB, n - p0);
-    if (wave == 0) {
-      double a[NB][Cap<MX>::rpl];
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int t = 0; t < Cap<MX>::rpl; ++t) {
-          const int r = lane + 64 * t;
-          a[j][t] = (j < nbw && r < n) ? W[(long)r * n + p0 + j] : 0.0;
-        }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < nbw) {
-          // pivot: largest |a| among unused rows, first index on ties; first unused row if none compares
-          double best = -1.0;
-          int bi = MAXN, fu = MAXN;
-#pragma unroll
-          for (int t = 0; t < Cap<MX>::rpl; ++t) {
-            const int r = lane + 64 * t;
-            if (r < n && !used[t]) {
-              fu = min(fu, r);
-              const double v = fabs(a[j][t]);
-              if (v > best || (v == best && r < bi)) { best = v; bi = r; }
-            }
-          }
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) {
-            const double ob = __shfl_xor(best, o, 64);
-            const int oi = __shfl_xor(bi, o, 64);
-            fu = min(fu, __shfl_xor(fu, o, 64));
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-          }
-          if (bi >= n) bi = (fu < n) ? fu : 0;
-          const int p = __builtin_amdgcn_readfirstlane(bi), pl = p & 63, pt = p >> 6;
-          double prow[NB];
-#pragma unroll
-          for (int c = 0; c < NB; ++c) {
-            double mine = 0.0;
-#pragma unroll
-            for (int t = 0; t < Cap<MX>::rpl; ++t) mine = (t == pt) ? a[c][t] : mine;
-            prow[c] = lane_value(mine, pl);
-          }
-          const double ip = 1.0 / prow[j];
-#pragma unroll
-          for (int t = 0; t < Cap<MX>::rpl; ++t) {
-            const int r = lane + 64 * t;
-            const bool isp = (r == p);
-            const double aj = a[j][t];
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-              if (c != j) {
-                const double wp = prow[c] * ip;
-                a[c][t] = isp ? wp : a[c][t] - aj * wp;
-              }
-            }
-            a[j][t] = isp ? ip : -aj * ip;
-            if (isp) used[t] = true;
-          }
-          if (lane == 0) {
-            perm[p0 + j] = p;
-            pinv[p] = p0 + j;
-            panel_of[p] = pi;
-            logp[p0 + j] = log(fabs(prow[j]));
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int t = 0; t < Cap<MX>::rpl; ++t) {
-          const int r = lane + 64 * t;
-          Fs[j][r] = (j < nbw && r < n) ? a[j][t] : 0.0;
-          if (j < nbw && r < n) W[(long)r * n + p0 + j] = a[j][t];
-        }
-    }
+    eliminate_panel<Cap<MX>::rpl>(
+        p0, nbw, n, Colj, used, perm, pinv, pivot, [&](int c, int r) { return W[(long)r * n + p0 + c]; },
+        [&](int c, int r, double v) {
+          if (r < VLD - NB) Fs[c][r] = (c < nbw && r < n) ? v : 0.0;
+          if (c < nbw && r < n) W[(long)r * n + p0 + c] = v;
+        });
+    __syncthreads();
+    for (int j = tid; j < nbw; j += 256) panel_of[perm[p0 + j]] = pi;
     Fs[tid >> 4][MAXN + (tid & 15)] = 0.0;
     __syncthreads();
     // rank-NB update of every column outside the panel, all rows
@@ -883,11 +865,13 @@ __global__ __launch_bounds__(256) void inv_blocked_kernel(double* __restrict__ M
                                   const int j = pinv[r], pk = perm[k];
                                   M[(long)j * n + pk] = rs[j] * v * cs[pk];
                                 });
-  if (tid == 0) {
-    double s = 0.0;
-    for (int j = 0; j < n; ++j) s += logp[j];
-    logdet[z] = base[z] + s;
-  }
+  // log|det M| = sum of log|pivot|
+  double lg = 0.0;
+  for (int i = tid; i < n; i += 256) lg += log(fabs(pivot[i]));
+  lg = wave_total(lg);
+  if (lane == 0) part[wave] = lg;
+  __syncthreads();
+  if (tid == 0) logdet[z] = base[z] + ((part[0] + part[1]) + (part[2] + part[3]));
 }
 
 // ---------------------------------------------------------------------------
@@ -959,88 +943,12 @@ __global__ __launch_bounds__(256) void gj_regs_kernel(double* __restrict__ Mg, d
         }
     }
     __syncthreads();
-    // the panel is eliminated by all four waves: wave w holds panel columns
-    // w, w + 4, w + 8, w + 12 (one row per lane and slot); column j goes to
-    // every wave through LDS, every wave finds the same pivot and updates
-    // its own columns
-    {
-      double a[4][RPL];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int r = lane + 64 * t;
-          a[q][t] = (r < n) ? Pn[wave + 4 * q][r] : 0.0;
-        }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < nbw) {
-          const int jq = j >> 2;
-          if (wave == (j & 3)) {
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) {
-              const int r = lane + 64 * t;
-              if (r < MAXN) Colj[j & 1][r] = a[jq][t];
-            }
-          }
-          __syncthreads();
-          double aj[RPL];
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            const int r = lane + 64 * t;
-            aj[t] = (r < MAXN) ? Colj[j & 1][r] : 0.0;
-          }
-          // pivot: the unused row of largest |a|, found as the largest key
-          // (|a| rounded to FP32 with its low 9 bits replaced by 511 - row, so
-          // near-equal magnitudes go to the lower row); used rows key 0
-          uint32_t key = 0;
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            const int r = lane + 64 * t;
-            const uint32_t kt = (__float_as_uint((float)fabs(aj[t])) & ~0x1FFu) | (uint32_t)(511 - r);
-            if (r < n && !used[t]) key = max(key, kt);
-          }
-          key = wave_max_u32(key);
-          const int pr = 511 - (int)(key & 0x1FFu), pl = pr & 63, pt = pr >> 6;
-          double pmine = 0.0;
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) pmine = (t == pt) ? aj[t] : pmine;
-          const double pj = lane_value(pmine, pl);
-          const double ip = rcp_nr(pj);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if (wave + 4 * q == j) {
-              // column j becomes -a / pivot, 1 / pivot on the pivot row
-#pragma unroll
-              for (int t = 0; t < RPL; ++t) a[q][t] = (lane + 64 * t == pr) ? ip : -aj[t] * ip;
-            } else {
-              // the pivot row's entry of this column, broadcast from its lane
-              double mine = 0.0;
-#pragma unroll
-              for (int t = 0; t < RPL; ++t) mine = (t == pt) ? a[q][t] : mine;
-              const double wp = lane_value(mine, pl) * ip;
-#pragma unroll
-              for (int t = 0; t < RPL; ++t) a[q][t] = (lane + 64 * t == pr) ? wp : fma(-aj[t], wp, a[q][t]);
-            }
-          }
-#pragma unroll
-          for (int t = 0; t < RPL; ++t)
-            if (lane + 64 * t == pr) used[t] = true;
-          if (tid == 0) {
-            perm[p0 + j] = pr;
-            pinv[pr] = p0 + j;
-            pivot[p0 + j] = pj;
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int r = lane + 64 * t, c = wave + 4 * q;
-          if (r < 16 * NTT) Pn[c][r] = (c < nbw) ? a[q][t] : 0.0;
-        }
-    }
+    // the panel is eliminated by all four waves
+    eliminate_panel<RPL>(
+        p0, nbw, n, Colj, used, perm, pinv, pivot, [&](int c, int r) { return Pn[c][r]; },
+        [&](int c, int r, double v) {
+          if (r < 16 * NTT) Pn[c][r] = (c < nbw) ? v : 0.0;
+        });
     __syncthreads();
     // rows of this lane (bit 4t + v for row 16t + frag_row(lane, v)) that became pivots in this panel
     uint64_t pm = 0;

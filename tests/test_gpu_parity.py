@@ -191,6 +191,20 @@ def test_mixed_12x12_small(hq):
     _mixed_replay_case(hq, dict(nx=12, chains=2, g=1.5, beta=2.0, n_stab=10), (0, 1), seed=3, sweeps=2)
 
 
+@pytest.mark.parametrize("nx", [13, 16])
+def test_large_lattice_fp64(hq, nx):
+    """N = 169 (panels with a ragged last one) and 256 in FP64: the streamed
+    local form and the L2-resident QR and Gauss-Jordan kernels."""
+    say("FP64 %dx%d" % (nx, nx))
+    gr = dict(nx=nx, chains=1, g=1.1, beta=0.4, n_stab=2)
+    ctx = make_ctx(hq, [gr], seed=12)
+    ctx.sweep(2)
+    ch = dqmc.Chain(params_of(gr), 12, 0)
+    ch.sweep(); ch.sweep()
+    assert_state(ctx, 0, ch, TOL64, "%dx%d" % (nx, nx))
+    ctx.close()
+
+
 def test_mixed_16x16_register_form(hq):
     """N = 256 in mixed precision: G in the accumulators of four waves (64
     tiles each), an upward and a downward sweep."""
