@@ -28,6 +28,14 @@ __device__ inline bool xcd_tile(int tiles, int batch, int& z, int& tile) {
 }
 inline unsigned xcd_grid(int tiles, int batch) { return (unsigned)(N_XCD * ((batch + N_XCD - 1) / N_XCD) * tiles); }
 
+// offset of batch entry z: z * s, or, with split > 0 entries per group,
+// (z / split) * so + (z % split) * s
+__device__ inline long batch_offset(int z, int split, long s, long so) {
+  if (split <= 0) return (long)z * s;
+  const int o = z / split;
+  return (long)o * so + (long)(z - o * split) * s;
+}
+
 __device__ inline double scale_value(const Scale& s, int z, int inner_count, int i) {
   if (!s.v) return 1.0;
   const int outer = z / inner_count, inner = z - outer * inner_count;
@@ -61,9 +69,9 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
-  const T* A = a.A + (long)z * a.sA;
-  const T* B = a.B + (long)z * a.sB;
-  T* C = a.C + (long)z * a.sC;
+  const T* A = a.A + batch_offset(z, a.split, a.sA, a.sAo);
+  const T* B = a.B + batch_offset(z, a.split, a.sB, a.sBo);
+  T* C = a.C + batch_offset(z, a.split, a.sC, a.sCo);
   const int nchunk = (a.K + BK - 1) / BK;
 
   for (int i = tid; i < BM; i += NT)
@@ -194,9 +202,9 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_fullk_kernel(GemmArgs<T> a)
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
-  const T* A = a.A + (long)z * a.sA;
-  const T* B = a.B + (long)z * a.sB;
-  T* C = a.C + (long)z * a.sC;
+  const T* A = a.A + batch_offset(z, a.split, a.sA, a.sAo);
+  const T* B = a.B + batch_offset(z, a.split, a.sB, a.sBo);
+  T* C = a.C + batch_offset(z, a.split, a.sC, a.sCo);
 
   for (int i = tid; i < BM; i += NT)
     rsv[i] = (m0 + i < a.M) ? scale_value(a.rs, z, a.inner_count, m0 + i) : 0.0;
@@ -308,9 +316,9 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_regpf_kernel(GemmArgs<T> a)
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
-  const T* A = a.A + (long)z * a.sA;
-  const T* B = a.B + (long)z * a.sB;
-  T* C = a.C + (long)z * a.sC;
+  const T* A = a.A + batch_offset(z, a.split, a.sA, a.sAo);
+  const T* B = a.B + batch_offset(z, a.split, a.sB, a.sBo);
+  T* C = a.C + batch_offset(z, a.split, a.sC, a.sCo);
   const int nchunk = (a.K + BK - 1) / BK;
 
   for (int i = tid; i < BM; i += NT)

@@ -54,6 +54,12 @@ struct Group {
   double *RU = nullptr, *RD = nullptr, *RT = nullptr;          // [C][nb][n][n], [C][nb][n]
   double *LU = nullptr, *LD = nullptr, *LT[2] = {nullptr, nullptr};
   double *SU = nullptr, *SD = nullptr, *ST = nullptr;          // left stack [nb][C][n][n], [nb][C][n]
+  // from-scratch products by pairwise UDT merges (groups with block moves or
+  // the network): UDT pairs [C][nb] (ping-pong), the merged middle factors
+  // [C][nb/2], and the QR's scratch for a batch of C * nb
+  bool tree = false;
+  double *tU[2] = {nullptr, nullptr}, *tT[2] = {nullptr, nullptr}, *tD[2] = {nullptr, nullptr};
+  double *tX = nullptr, *tUp = nullptr, *tDp = nullptr, *tQW = nullptr, *tQT = nullptr;
   bool alternate = false;        // sweeps alternate upward / downward (local moves only)
   double *Z = nullptr, *Rt = nullptr, *M = nullptr, *Minv = nullptr, *Xm = nullptr, *Tq = nullptr;
   double *dLbinv = nullptr, *dLs = nullptr, *dRbinv = nullptr, *dRs = nullptr, *sumlog = nullptr;
@@ -246,6 +252,20 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
     if (g.network) {
       g.sum_y = cv.take<double>(C * L * n);
       g.nn_acc = cv.take<uint8_t>(C * L * n);
+    }
+    g.tree = (g.global || g.network) && nb > 1;
+    if (g.tree) {
+      const long half = (nb + 1) / 2;
+      for (int k = 0; k < 2; ++k) {
+        g.tU[k] = cv.take<double>(C * nb * nn);
+        g.tT[k] = cv.take<double>(C * nb * nn);
+        g.tD[k] = cv.take<double>(C * nb * n);
+      }
+      g.tX = cv.take<double>(C * half * nn);
+      g.tUp = cv.take<double>(C * half * nn);
+      g.tDp = cv.take<double>(C * half * n);
+      g.tQW = cv.take<double>(C * nb * nn);
+      g.tQT = cv.take<double>(C * nb * (long)qr_t_doubles(g.n));
     }
   }
   if (ctx) {
@@ -472,12 +492,76 @@ hq_status merge(Sched& S, Group& g, const double* UL, long sUL, const double* DL
   return HQ_OK;
 }
 
+// U D T factors of a set of matrices, with per-chain strides
+struct Udt { double *U, *D, *T; long sU, sD, sT; };
+
+// The product C_{nb-1} ... C_0 of a group's block products as one UDT per
+// chain by pairwise merges, log2(nb) levels deep instead of nb: every block
+// is factored at once, then level by level
+//   (U_a D_a T_a)(U_b D_b T_b) = (U_a U') D' (T' T_b),  U' D' T' = QR-UDT of D_a (T_a U_b) D_b
+// with a the later block of each pair; an unpaired last block passes to the
+// next level.  Returns pointers to the [C][1] result.
+hq_status tree_product(Sched& S, Group& g, const double* blocks, Udt& out) {
+  const long nn = (long)g.n * g.n;
+  const int n = g.n, C = g.C;
+  int cur = 0, m = g.nb;
+  // level 0: Z = C_b (copied: the QR writes its triangular factor over its input)
+  SCHED_TRY(launch_copy_f64(g.tT[0], blocks, (long)C * g.nb * nn, S.s));
+  SCHED_TRY(launch_qr(g.tT[0], g.tQW, g.tU[0], g.tD[0], g.tQT, n, C * g.nb, S.s));
+  while (m > 1) {
+    const int pairs = m / 2, m2 = (m + 1) / 2, nxt = 1 - cur;
+    const double *U = g.tU[cur], *T = g.tT[cur], *D = g.tD[cur];
+    // X = diag(D_a) (T_a U_b) diag(D_b), a = 2j + 1, b = 2j; X is [C][pairs]
+    GemmArgs<double> x = sq(g, C * pairs);
+    x.split = pairs;
+    x.A = T + nn; x.sA = 2 * nn; x.sAo = (long)m * nn;
+    x.B = U; x.sB = 2 * nn; x.sBo = (long)m * nn;
+    x.C = g.tX; x.sC = nn; x.sCo = (long)pairs * nn;
+    x.rs.v = D + n; x.rs.so = (long)m * n; x.rs.si = 2L * n;
+    x.cs.v = D; x.cs.so = (long)m * n; x.cs.si = 2L * n;
+    x.inner_count = pairs;
+    SCHED_TRY(launch_gemm(x, g.tile, S.s));
+    SCHED_TRY(launch_qr(g.tX, g.tQW, g.tUp, g.tDp, g.tQT, n, C * pairs, S.s));
+    // U_next = U_a U', T_next = T' T_b, D_next = D'; entries [C][m2]
+    GemmArgs<double> u = sq(g, C * pairs);
+    u.split = pairs;
+    u.A = U + nn; u.sA = 2 * nn; u.sAo = (long)m * nn;
+    u.B = g.tUp; u.sB = nn; u.sBo = (long)pairs * nn;
+    u.C = g.tU[nxt]; u.sC = nn; u.sCo = (long)m2 * nn;
+    SCHED_TRY(launch_gemm(u, g.tile, S.s));
+    GemmArgs<double> t = sq(g, C * pairs);
+    t.split = pairs;
+    t.A = g.tX; t.sA = nn; t.sAo = (long)pairs * nn;
+    t.B = T; t.sB = 2 * nn; t.sBo = (long)m * nn;
+    t.C = g.tT[nxt]; t.sC = nn; t.sCo = (long)m2 * nn;
+    SCHED_TRY(launch_gemm(t, g.tile, S.s));
+    SCHED_TRY(launch_copy_blocks(g.tD[nxt], (long)m2 * n, n, g.tDp, (long)pairs * n, n, n, C, pairs, S.s));
+    if (m % 2) {                           // the unpaired last block
+      SCHED_TRY(launch_copy_blocks(g.tU[nxt] + (m2 - 1) * nn, (long)m2 * nn, 0, U + (m - 1) * nn, (long)m * nn, 0,
+                                   nn, C, 1, S.s));
+      SCHED_TRY(launch_copy_blocks(g.tT[nxt] + (m2 - 1) * nn, (long)m2 * nn, 0, T + (m - 1) * nn, (long)m * nn, 0,
+                                   nn, C, 1, S.s));
+      SCHED_TRY(launch_copy_blocks(g.tD[nxt] + (long)(m2 - 1) * n, (long)m2 * n, 0, D + (long)(m - 1) * n,
+                                   (long)m * n, 0, n, C, 1, S.s));
+    }
+    cur = nxt;
+    m = m2;
+  }
+  out = {g.tU[cur], g.tD[cur], g.tT[cur], nn, n, nn};
+  return HQ_OK;
+}
+
 // G and log|det M| of the fields xs from scratch: all block products, the
 // left UDT chain over every block, and the merge with an identity right part.
 // Leaves the block products in `blocks`.
 hq_status from_scratch(Sched& S, Group& g, const double* xs, double* blocks) {
   const long nn = (long)g.n * g.n;
   ST_TRY(block_products(S, g, xs, blocks, 0, g.blks, 0, g.nb));
+  if (g.tree) {
+    Udt l;
+    ST_TRY(tree_product(S, g, blocks, l));
+    return merge(S, g, l.U, l.sU, l.D, l.T, l.sT, nullptr, 0, nullptr, 0, nullptr, 0);
+  }
   SCHED_TRY(launch_identity(g.LU, g.LD, g.LT[0], g.n, g.C, S.s));
   int t = 0;
   for (int b = 0; b < g.nb; ++b) {
@@ -605,7 +689,6 @@ hq_status unwrap(Sched& S, Group& g, int slice) {
 }
 
 // stack entries, all chains of the group contiguous per entry
-struct Udt { double *U, *D, *T; long sU, sD, sT; };
 Udt left_entry(Group& g, int b) {       // L_b = C_b ... C_0; b = -1: identity
   const long nn = (long)g.n * g.n;
   if (b < 0) return {g.ident, g.ones, g.ident, 0, g.n, 0};

@@ -22,13 +22,16 @@ struct Scale {
 
 // C[z] = alpha * diag(rs) * op(A[z]) * diag(ks) * op(B[z]) * diag(cs) + beta * C[z]
 // for z in [0, batch); matrices row-major.  op = transpose when trans != 0.
-// Matrix pointers advance by the stride per batch entry (stride 0 = shared).
+// Matrix pointers advance by the stride per batch entry (stride 0 = shared);
+// with split > 0 the batch is read as groups of split entries: entry z sits
+// at (z / split) * sXo + (z % split) * sX.
 template <typename T>
 struct GemmArgs {
   int M = 0, N = 0, K = 0;
   const T* A = nullptr; long lda = 0, sA = 0; int tA = 0;
   const T* B = nullptr; long ldb = 0, sB = 0; int tB = 0;
   T* C = nullptr; long ldc = 0, sC = 0;
+  int split = 0; long sAo = 0, sBo = 0, sCo = 0;
   double alpha = 1.0, beta = 0.0;
   Scale rs, cs, ks;                        // ks: on the inner index, K <= 256
   int batch = 1, inner_count = 1;
@@ -200,6 +203,9 @@ struct CumulativeArgs {
 hipError_t launch_cumulative(const CumulativeArgs& a, int chains, hipStream_t s);
 hipError_t launch_copy_f64(double* dst, const double* src, long count, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, long count, hipStream_t s);
+// dst[o dso + i dsi + e] = src[o sso + i ssi + e] for e < len, o < outer, i < inner
+hipError_t launch_copy_blocks(double* dst, long dso, long dsi, const double* src, long sso, long ssi, long len,
+                              int outer, int inner, hipStream_t s);
 
 // counters layout per chain
 enum { CNT_LOCAL_P = 0, CNT_LOCAL_A, CNT_GLOBAL_P, CNT_GLOBAL_A, CNT_NN_P, CNT_NN_A, CNT_CUM_P,

@@ -157,6 +157,21 @@ __global__ void add_i64_kernel(int64_t* p, int64_t v) {
 
 static inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
 
+// dst[o dso + i dsi + e] = src[o sso + i ssi + e] for e < len, o < outer, i < inner
+__global__ void copy_blocks_kernel(double* dst, long dso, long dsi, const double* src, long sso, long ssi, long len,
+                                   int inner) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = blockIdx.y / inner, i = blockIdx.y - (blockIdx.y / inner) * inner;
+  if (e < len) dst[o * dso + i * dsi + e] = src[o * sso + i * ssi + e];
+}
+hipError_t launch_copy_blocks(double* dst, long dso, long dsi, const double* src, long sso, long ssi, long len,
+                              int outer, int inner, hipStream_t s) {
+  if (len <= 0 || outer <= 0 || inner <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_blocks_kernel, dim3(nblk(len), outer * inner), dim3(256), 0, s, dst, dso, dsi, src, sso,
+                     ssi, len, inner);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy_f64_to_f32(float* dst, const double* src, long count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(f64_to_f32_kernel, dim3(nblk(count)), dim3(256), 0, s, dst, src, count);
