@@ -34,6 +34,7 @@ struct Group {
   hq_group p{};
   int nx = 0, n = 0, L = 0, ns = 0, nb = 0, C = 0, chain0 = 0;
   int nt = 256, kd = 16, tile = TILE_64x64, tile32 = TILE_64x64;
+  int tile_wide = TILE_64x64;              // FP64 products over all blocks of all chains
   double tile_us = 0.0, tile32_us = 0.0;   // autotuner timings
   bool fused_wrap = false;                 // both wrap products in one launch (autotuner's choice)
   double wrap_us = 0.0;                    // measured time of one wrap as chosen
@@ -414,7 +415,7 @@ hq_status block_products(Sched& S, Group& g, const double* xs, double* dst, long
     a.rs = rs;
     a.rs.off = (long)(b0 * g.ns + t) * g.n;
     a.inner_count = nblk;
-    SCHED_TRY(launch_gemm(a, g.tile, S.s));
+    SCHED_TRY(launch_gemm(a, nblk > 2 ? g.tile_wide : g.tile, S.s));
     cur = 1 - cur;
   }
   return HQ_OK;
@@ -520,7 +521,7 @@ hq_status tree_product(Sched& S, Group& g, const double* blocks, Udt& out) {
     x.rs.v = D + n; x.rs.so = (long)m * n; x.rs.si = 2L * n;
     x.cs.v = D; x.cs.so = (long)m * n; x.cs.si = 2L * n;
     x.inner_count = pairs;
-    SCHED_TRY(launch_gemm(x, g.tile, S.s));
+    SCHED_TRY(launch_gemm(x, pairs > 2 ? g.tile_wide : g.tile, S.s));
     SCHED_TRY(launch_qr(g.tX, g.tQW, g.tUp, g.tDp, g.tQT, n, C * pairs, S.s));
     // U_next = U_a U', T_next = T' T_b, D_next = D'; entries [C][m2]
     GemmArgs<double> u = sq(g, C * pairs);
@@ -528,13 +529,13 @@ hq_status tree_product(Sched& S, Group& g, const double* blocks, Udt& out) {
     u.A = U + nn; u.sA = 2 * nn; u.sAo = (long)m * nn;
     u.B = g.tUp; u.sB = nn; u.sBo = (long)pairs * nn;
     u.C = g.tU[nxt]; u.sC = nn; u.sCo = (long)m2 * nn;
-    SCHED_TRY(launch_gemm(u, g.tile, S.s));
+    SCHED_TRY(launch_gemm(u, pairs > 2 ? g.tile_wide : g.tile, S.s));
     GemmArgs<double> t = sq(g, C * pairs);
     t.split = pairs;
     t.A = g.tX; t.sA = nn; t.sAo = (long)pairs * nn;
     t.B = T; t.sB = 2 * nn; t.sBo = (long)m * nn;
     t.C = g.tT[nxt]; t.sC = nn; t.sCo = (long)m2 * nn;
-    SCHED_TRY(launch_gemm(t, g.tile, S.s));
+    SCHED_TRY(launch_gemm(t, pairs > 2 ? g.tile_wide : g.tile, S.s));
     SCHED_TRY(launch_copy_blocks(g.tD[nxt], (long)m2 * n, n, g.tDp, (long)pairs * n, n, n, C, pairs, S.s));
     if (m % 2) {                           // the unpaired last block
       SCHED_TRY(launch_copy_blocks(g.tU[nxt] + (m2 - 1) * nn, (long)m2 * nn, 0, U + (m - 1) * nn, (long)m * nn, 0,
@@ -914,14 +915,25 @@ hq_status autotune(hq_ctx* ctx) {
   hq_status st = HQ_OK;
   for (Group& g : ctx->groups) {
     const long nn = (long)g.n * g.n;
-    for (int prec = 0; prec < 2 && st == HQ_OK; ++prec) {
-      if (prec == 1 && ctx->opt.precision != HQ_PREC_MIXED) break;
+    // prec 0: FP64 products of the group's batch; 1: the wraps' products in
+    // FP32; 2: FP64 products of every block of every chain at once (block
+    // products from scratch), which favour other tiles
+    for (int prec = 0; prec < 3 && st == HQ_OK; ++prec) {
+      if (prec == 1 && ctx->opt.precision != HQ_PREC_MIXED) continue;
+      if (prec == 2 && g.nb < 3) { g.tile_wide = g.tile; continue; }
       double best = 1e30;
       int bt = TILE_64x64;
       for (int tile : cands) {
-        if (!gemm_tile_fits(tile, g.n, prec)) continue;
+        if (!gemm_tile_fits(tile, g.n, prec == 1)) continue;
         hipError_t e = hipSuccess;
         auto run = [&]() {
+          if (prec == 2) {
+            GemmArgs<double> a = sq(g, g.C * g.nb);
+            a.A = g.expk; a.sA = 0;
+            a.B = g.blkp; a.sB = nn;
+            a.C = g.blk; a.sC = nn;
+            return launch_gemm(a, tile, s);
+          }
           if (prec) {
             GemmArgs<float> a;
             a.M = a.N = a.K = g.n; a.lda = a.ldb = a.ldc = g.n; a.batch = g.C;
@@ -950,8 +962,9 @@ hq_status autotune(hq_ctx* ctx) {
         const double us = 1e3 * ms / 3.0;
         if (us < best) { best = us; bt = tile; }
       }
-      if (prec) { g.tile32 = bt; g.tile32_us = best; }
-      else { g.tile = bt; g.tile_us = best; }
+      if (prec == 1) { g.tile32 = bt; g.tile32_us = best; }
+      else if (prec == 0) { g.tile = bt; g.tile_us = best; }
+      else g.tile_wide = bt;
     }
     if (ctx->opt.precision != HQ_PREC_MIXED) { g.tile32 = g.tile; g.tile32_us = g.tile_us; }
     // the wrap: both products in one launch, or two tiled products
@@ -1386,7 +1399,7 @@ hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t t
     return fail(ctx, HQ_EINVAL, "no fused wrap for N = %d", g.n);
   HQ_TRY(hipStreamSynchronize(ctx->stream));
   drop_graphs(ctx);
-  g.tile = tile_fp64;
+  g.tile = g.tile_wide = tile_fp64;
   g.tile32 = tile_wrap;
   g.fused_wrap = wrap_fused != 0;
   g.tile_us = g.tile32_us = g.wrap_us = 0.0;
