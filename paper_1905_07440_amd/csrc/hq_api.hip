@@ -920,7 +920,7 @@ hq_status autotune(hq_ctx* ctx) {
     // products from scratch), which favour other tiles
     for (int prec = 0; prec < 3 && st == HQ_OK; ++prec) {
       if (prec == 1 && ctx->opt.precision != HQ_PREC_MIXED) continue;
-      if (prec == 2 && g.nb < 3) { g.tile_wide = g.tile; continue; }
+      if (prec == 2 && (g.nb < 3 || !g.tree)) { g.tile_wide = g.tile; continue; }   // only recomputes use it
       double best = 1e30;
       int bt = TILE_64x64;
       for (int tile : cands) {
