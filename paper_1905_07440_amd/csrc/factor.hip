@@ -3,26 +3,31 @@
 // The paper defines G through M = I + B_L ... B_1 and refers to the standard
 // DQMC literature for computing it without overflow: the running product is
 // kept as U D T, re-factored with a pivoted QR after every block of n_stab
-// slices, and G comes from one more solve at the end.  Two kernels serve that
-// scheme, one workgroup (4 waves) per matrix, the matrix in global memory
-// (it stays in L2), blocked by panels of NB = 16 columns:
+// slices, and G comes from one more solve at the end.  Two factorizations
+// serve that scheme, one workgroup (4 waves) per matrix, in panels of NB = 16
+// columns:
 //
-//  qr_blocked   Householder QR with the columns pre-sorted by decreasing norm
+//  QR           Householder QR with the columns pre-sorted by decreasing norm
 //               (pre-pivoting keeps the graded scales of Z = (C U) D in order
 //               without per-step pivot searches).  Each panel is factored by
-//               one wave in registers (reductions by shuffles, no barriers);
-//               the block reflector I - V T V^T (compact WY, T from the Gram
-//               matrix V^T V) is applied to the trailing columns with MFMA by
-//               all waves.  Q is accumulated backwards the same way.  Outputs
-//               Q, D = |diag R| and Rt = D^-1 R P^T (over Z), so
-//               Z = Q diag(D) Rt.
-//  inv_blocked  in-place Gauss-Jordan inversion with partial (row) pivoting,
-//               blocked the same way: one wave eliminates a panel (pivot
-//               search over all unused rows), then every other column gets
-//               the rank-NB update
+//               all four waves (factor_panel: one column per step through
+//               LDS, one butterfly per column for the norm and the dots); the
+//               block reflector I - V T V^T (compact WY, T by recursive
+//               doubling from the Gram matrix V^T V) is applied to the
+//               trailing columns with MFMA.  Q is accumulated backwards the
+//               same way.  Outputs Q, D = |diag R| and Rt = D^-1 R P^T (over
+//               Z), so Z = Q diag(D) Rt.
+//  Gauss-Jordan in-place inversion with partial (row) pivoting, blocked the
+//               same way: the four waves eliminate a panel (eliminate_panel:
+//               pivot over all unused rows), then every other column gets the
+//               rank-NB update
 //                   A[r][C] = [r not a pivot row of the panel] A[r][C] + F[r][:] A_old[P][C]
 //               (F: the eliminated panel, P: its pivot rows).  Output
 //               diag(rs) M^-1 diag(cs) (over M) and log|det M|.
+//
+// Up to N = 144 the matrix lives in the accumulators of the four waves
+// (qr_regs_kernel, gj_regs_kernel); beyond, in global memory, where it stays
+// in L2 (qr_blocked_kernel, inv_blocked_kernel).
 #include "hq_device.h"
 #include "hq_internal.h"
 
@@ -31,8 +36,8 @@ namespace hq {
 constexpr int NB = 16;           // panel width
 constexpr int MAXN = 256;        // largest N (lattices up to 16 x 16)
 constexpr int VLD = MAXN + 16;   // panel row length in LDS (zero tail)
-// kernels are instantiated for N <= MX with MX in {64, 160, 256}: panel rows
-// per lane and 16-row tiles per strip are sized for MX
+// kernels are instantiated for N <= MX with MX in {64, 112, 144, 256}: panel
+// rows per lane and 16-row tiles per strip are sized for MX
 template <int MX> struct Cap { enum { rpl = (MX + 63) / 64, tiles = (MX + 15) / 16 }; };
 
 __device__ inline void wave_sync_lds() {
@@ -91,15 +96,14 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// totals over the 64 lanes of 16 values at once, returned wave-uniform: a
-// butterfly in which every exchange halves the values a lane carries, 15
-// exchanges in all instead of 16 separate six-step reductions, none through
-// LDS.  Lane halves (bit 5) and row pairs (bit 4) trade through the
-// permlane swaps: after swapping the upper lanes of x with the lower lanes of
-// y, x + y is, on every lane, the kept value plus the partner's matching one.
-// Bit 3 pairs lanes by a row rotation of 8 and bit 2 by the half-row mirror
-// (lane ^ 7), whose partners agree on every bit already reduced.  Afterwards
-// lane l holds the total of value (l >> 2) & 15.
+// Totals over the 64 lanes of several values at once, returned
+// wave-uniform: a butterfly in which every exchange halves the values a lane
+// carries, none through LDS.  Lane halves (bit 5) and row pairs (bit 4) trade
+// through the permlane swaps: after swapping the upper lanes of x with the
+// lower lanes of y, x + y is, on every lane, the kept value plus the
+// partner's matching one.  Bit 3 pairs lanes by a row rotation of 8 and the
+// last halving by the half-row mirror (lane ^ 7), whose partners agree on
+// every bit already reduced.
 __device__ inline double swap_sum32(double lo_half, double hi_half) {
   // x: values the lower lanes keep; y: values the upper lanes keep
   const auto l = __builtin_amdgcn_permlane32_swap(__double2loint(lo_half), __double2loint(hi_half), false, false);
@@ -111,30 +115,8 @@ __device__ inline double swap_sum16(double lo_half, double hi_half) {
   const auto h = __builtin_amdgcn_permlane16_swap(__double2hiint(lo_half), __double2hiint(hi_half), false, false);
   return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
 }
-__device__ inline void wave_totals16(const double (&v)[16], double (&t)[16]) {
-  const int lane = threadIdx.x & 63;
-  double a8[8], a4[4], a2[2];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) a8[i] = swap_sum32(v[i], v[8 + i]);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) a4[i] = swap_sum16(a8[i], a8[4 + i]);
-  {
-    const bool h = (lane & 8) != 0;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const double keep = h ? a4[2 + i] : a4[i], send = h ? a4[i] : a4[2 + i];
-      a2[i] = keep + dpp_move<0x128>(send);          // row_ror:8, lane ^ 8 within the row
-    }
-  }
-  const bool h = (lane & 4) != 0;
-  double a1 = (h ? a2[1] : a2[0]) + dpp_move<0x141>(h ? a2[0] : a2[1]);   // row_half_mirror, lane ^ 7
-  a1 += dpp_move<0xB1>(a1);                           // quad_perm [1,0,3,2]
-  a1 += dpp_move<0x4E>(a1);                           // quad_perm [2,3,0,1]
-#pragma unroll
-  for (int c = 0; c < 16; ++c) t[c] = lane_value(a1, 4 * c);
-}
-
-// the same for 8 values: afterwards lane l holds the total of value (l >> 3) & 7
+// 8 values: after the butterfly lane l holds the total of value (l >> 3) & 7,
+// and t[c] reads value c from lane 8 c
 __device__ inline void wave_totals8(const double (&v)[8], double (&t)[8]) {
   const int lane = threadIdx.x & 63;
   double a4[4], a2[2];
@@ -400,11 +382,10 @@ __device__ void apply_reflector(double* A, int n, int p0, int m, const double (*
   }
 }
 
-// T (upper triangular; H_0 ... H_{nb-1} = I - V T V^T) from the Gram matrix:
-// T[j][j] = tau_j,  T[i][j] = -tau_j sum_{k=i}^{j-1} T[i][k] (V^T V)[k][j].
-// V^T V comes from MFMA (both operands are the same V fragment), the four
-// waves taking every fourth 4-row chunk; the recurrence runs in registers of
-// 16 lanes of wave 0, lane i holding row i of T.
+// T (upper triangular; H_0 ... H_{nb-1} = I - V T V^T) from the Gram matrix
+// V^T V, which comes from MFMA (both operands are the same V fragment, the
+// four waves taking every fourth 4-row chunk).  T is built by recursive
+// doubling, one element per thread (see below).
 __device__ void form_t(const double (*Vs)[VLD], int m, int nbw, const double* tau, double (*Gm)[NB + 1],
                        double (*Ts)[NB + 1], double (*Sc)[NB][NB + 1]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -541,11 +522,11 @@ __global__ __launch_bounds__(256) void qr_blocked_kernel(double* __restrict__ Zg
 }
 
 // ---------------------------------------------------------------------------
-// The same QR with the matrix resident in registers (N <= 160): the four
+// The same QR with the matrix resident in registers (N <= 144): the four
 // waves hold it as 16 x 16 MFMA tiles, wave w owning tile columns w, w + 4,
-// w + 8.  A panel passes through LDS once to be factored by wave 0; the block
-// reflector is applied to the tiles in place, so the trailing update touches
-// no memory but the 16-column reflector.  Q is accumulated in the same
+// w + 8.  A panel passes through LDS once to be factored by the four waves;
+// the block reflector is applied to the tiles in place, so the trailing
+// update touches no memory but the 16-column reflector.  Q is accumulated in the same
 // registers afterwards.  V and T of every panel go to W and T in global
 // memory for that second pass.
 // ---------------------------------------------------------------------------
@@ -879,9 +860,10 @@ __global__ __launch_bounds__(256) void inv_blocked_kernel(double* __restrict__ M
 // the same elimination as inv_blocked_kernel, panel by panel, but every
 // column tile lives in the accumulators of the wave that owns it (tile column
 // c belongs to wave c % 4), so the trailing rank-16 update of a panel never
-// leaves the CU.  Per panel: the owner hands the panel to wave 0 through LDS,
-// wave 0 eliminates its 16 columns, and each wave fetches the panel's pivot
-// rows of its own columns through a per-wave LDS copy of the tile column.
+// leaves the CU.  Per panel: the owner hands the panel to the four waves
+// through LDS, they eliminate its 16 columns, and each wave fetches the
+// panel's pivot rows of its own columns through a per-wave LDS copy of the
+// tile column.
 // ---------------------------------------------------------------------------
 template <int MX>
 __global__ __launch_bounds__(256) void gj_regs_kernel(double* __restrict__ Mg, double* __restrict__ Wg,
