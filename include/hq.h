@@ -161,30 +161,39 @@ hq_status hq_chain_shape(const hq_ctx* ctx, int32_t chain, int32_t* n, int32_t* 
 hq_status hq_set_profiling(hq_ctx* ctx, int32_t on);
 hq_status hq_phase_time(hq_ctx* ctx, const char* phase, double* ms_total, int64_t* launches);
 
+/* How a wrap G <- B_l G B_l^-1 (B_l = exp(-dtau V_l) exp(-dtau K), paper:
+ * Methods, DQMC) multiplies by exp(-+dtau K):
+ *   HQ_WRAP_TWO    two tiled dense products;
+ *   HQ_WRAP_FUSED  both dense products in one launch (N <= 144);
+ *   HQ_WRAP_KRON   exp(s dtau K) = E1 (x) E1 on the periodic square lattice
+ *                  (E1 of size nx, site index ix + nx iy), applied as two
+ *                  passes of nx-term sums on each side. */
+enum { HQ_WRAP_TWO = 0, HQ_WRAP_FUSED = 1, HQ_WRAP_KRON = 2 };
+
 /* The configuration chosen at hq_create for one group: the GEMM tile of
- * the FP64 products (block products, UDT combines) and of the wraps' products
- * in the context's precision, found by timing every tile that fits on the
- * group's own shape; whether a wrap runs as one fused launch (N <= 144) or as
- * two tiled products, whichever timed faster; and the local-move block size.  Tile names from
- * hq_gemm_tile_name (a static string; "?" for an unknown code). */
+ * the FP64 products (UDT combines and merges) and of the wraps' dense
+ * products in the context's precision, found by timing every tile that fits
+ * on the group's own shape; the wrap form (HQ_WRAP_*) that timed fastest;
+ * and the local-move block size.  Block products always take the Kronecker
+ * form.  Tile names from hq_gemm_tile_name (a static string; "?" for an
+ * unknown code). */
 typedef struct {
   int32_t gemm_tile_fp64, gemm_tile_wrap, local_block;
   double gemm_us_fp64, gemm_us_wrap;   /* measured time of one batched product */
-  int32_t wrap_fused;                  /* 1: both products of a wrap in one launch */
+  int32_t wrap_kind;                   /* HQ_WRAP_* */
   double wrap_us;                      /* measured time of one wrap of all the group's chains */
 } hq_tuning;
 hq_status hq_read_tuning(const hq_ctx* ctx, int32_t group, hq_tuning* out);
 
 /* Pin one group's GEMM tiles and wrap form in place of the autotuner's
  * choice (for reproducible timings and for testing every path).  Tile codes
- * are those of hq_read_tuning, 0 .. 10; wrap_fused 1 runs both products of a
- * wrap in one launch, 0 as two tiled products.  HQ_EINVAL, with nothing
- * changed, for an unknown code, a tile that does not fit the group's N in
- * that precision, in FP64 precision tile_wrap != tile_fp64, or wrap_fused = 1
- * with N > 144.  Waits for the context's stream; the sweep graphs are
- * captured again on the next hq_sweep.  The timings that hq_read_tuning
- * reports become 0. */
-hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t tile_wrap, int32_t wrap_fused);
+ * are those of hq_read_tuning, 0 .. 10; wrap_kind one of HQ_WRAP_*.
+ * HQ_EINVAL, with nothing changed, for an unknown code, a tile that does not
+ * fit the group's N in that precision, in FP64 precision tile_wrap !=
+ * tile_fp64, or HQ_WRAP_FUSED with N > 144.  Waits for the context's
+ * stream; the sweep graphs are captured again on the next hq_sweep.  The
+ * timings that hq_read_tuning reports become 0. */
+hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t tile_wrap, int32_t wrap_kind);
 const char* hq_gemm_tile_name(int32_t tile);
 
 /* Wait for all work on the context's stream. */

@@ -13,38 +13,6 @@
 
 namespace hq {
 
-// Workgroups are dealt to the eight XCDs in turn (workgroup g runs on XCD
-// g mod 8), each XCD with its own L2.  The grid is one-dimensional and is
-// read so that all tiles of one batch entry land on the same XCD: XCD x
-// takes entries x, x + 8, ..., tile by tile, and the entry's operands are
-// fetched into that L2 once.  Returns false for the padding workgroups of a
-// batch that is not a multiple of 8.
-constexpr int N_XCD = 8;
-__device__ inline bool xcd_tile(int tiles, int batch, int& z, int& tile) {
-  const int g = blockIdx.x, x = g % N_XCD, k = g / N_XCD;
-  z = N_XCD * (k / tiles) + x;
-  tile = k % tiles;
-  return z < batch;
-}
-inline unsigned xcd_grid(int tiles, int batch) { return (unsigned)(N_XCD * ((batch + N_XCD - 1) / N_XCD) * tiles); }
-
-// offset of batch entry z: z * s, or, with split > 0 entries per group,
-// (z / split) * so + (z % split) * s
-__device__ inline long batch_offset(int z, int split, long s, long so) {
-  if (split <= 0) return (long)z * s;
-  const int o = z / split;
-  return (long)o * so + (long)(z - o * split) * s;
-}
-
-__device__ inline double scale_value(const Scale& s, int z, int inner_count, int i) {
-  if (!s.v) return 1.0;
-  const int outer = z / inner_count, inner = z - outer * inner_count;
-  double v = s.v[(long)outer * s.so + (long)inner * s.si + s.off + i];
-  if (s.coef) v = exp(s.cmul * s.coef[outer] * v);
-  if (s.invert) v = 1.0 / v;
-  return v;
-}
-
 // K staged 16 at a time through two LDS buffers: while the waves multiply
 // out of one buffer, every thread's loads of the next 16-wide K chunk are in
 // flight, and one barrier per chunk separates the two.
@@ -732,22 +700,6 @@ hipError_t prepare_gemm() {
   const hipError_t e3 = allow_wrap_t<double>();
   const hipError_t e4 = allow_wrap_t<float>();
   return e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e3 != hipSuccess ? e3 : e4));
-}
-
-// P[z] = diag(rs(z)) * A, A shared by the batch
-__global__ void scale_rows_kernel(double* P, long sP, const double* A, int n, Scale rs, int inner_count) {
-  const int z = blockIdx.y;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * n) return;
-  const int r = e / n;
-  P[(long)z * sP + e] = scale_value(rs, z, inner_count, r) * A[e];
-}
-
-hipError_t launch_scale_rows(double* P, long sP, const double* A, int n, Scale rs, int batch,
-                             int inner_count, hipStream_t s) {
-  dim3 grid((n * n + 255) / 256, batch);
-  hipLaunchKernelGGL(scale_rows_kernel, grid, dim3(256), 0, s, P, sP, A, n, rs, inner_count);
-  return hipGetLastError();
 }
 
 }  // namespace hq

@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -30,19 +31,26 @@ namespace {
 
 const int N_KIND_SLOTS = 5;   // indexed by HQ_KIND_* (0, 1, 3, 4 used)
 
+// a wrap G <- B G B^-1 as two tiled dense products, as one fused launch of
+// both dense products, or as two Kronecker passes (left, then right)
+enum { WRAP_TWO = HQ_WRAP_TWO, WRAP_FUSED = HQ_WRAP_FUSED, WRAP_KRON = HQ_WRAP_KRON };
+
 struct Group {
   hq_group p{};
   int nx = 0, n = 0, L = 0, ns = 0, nb = 0, C = 0, chain0 = 0;
   int nt = 256, kd = 16, tile = TILE_64x64, tile32 = TILE_64x64;
   int tile_wide = TILE_64x64;              // FP64 products over all blocks of all chains
   double tile_us = 0.0, tile32_us = 0.0;   // autotuner timings
-  bool fused_wrap = false;                 // both wrap products in one launch (autotuner's choice)
+  int wrap_kind = WRAP_TWO;                // how a wrap is computed (autotuner's choice)
   double wrap_us = 0.0;                    // measured time of one wrap as chosen
   bool global = false, network = false;
   // fields, couplings, model matrices
   double *x = nullptr, *xp = nullptr, *g = nullptr;
   double *expk = nullptr, *expkinv = nullptr, *ident = nullptr, *ones = nullptr;
   float *expk32 = nullptr, *expkinv32 = nullptr;
+  // nx x nx factors E1 of expK = E1 (x) E1 and of expK^-1
+  double *ek1 = nullptr, *ek1inv = nullptr;
+  float *ek1_32 = nullptr, *ek1inv_32 = nullptr;
   // Green's functions
   void* G = nullptr;             // [C][n][n], precision of the context
   void* Wt = nullptr;            // wrap temporary, same precision
@@ -204,6 +212,10 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
     g.ones = cv.take<double>(C * n);
     g.expk32 = cv.take<float>(nn);
     g.expkinv32 = cv.take<float>(nn);
+    g.ek1 = cv.take<double>((long)g.nx * g.nx);
+    g.ek1inv = cv.take<double>((long)g.nx * g.nx);
+    g.ek1_32 = cv.take<float>((long)g.nx * g.nx);
+    g.ek1inv_32 = cv.take<float>((long)g.nx * g.nx);
     g.G = cv.take<char>(C * nn * ts);
     g.G0 = g.G;
     g.Wt = cv.take<char>(C * nn * ts);
@@ -332,6 +344,27 @@ void exp_hopping(const hq_group& p, double sign, std::vector<double>& out) {
     }
 }
 
+// The nx x nx factor E1 of exp(sign * dtau * K) = E1 (x) E1 (site index
+// ix + nx iy): the plane-wave energy splits into -2t cos kx - mu/2 and
+// -2t cos ky - mu/2, and the sine terms of the sum above cancel between k
+// and -k, so E1[a][b] = (1/nx) sum_k cos(k (a - b)) exp(sign dtau (-2t cos k - mu/2)).
+void exp_hopping_1d(const hq_group& p, double sign, std::vector<double>& out) {
+  const int nx = p.nx;
+  std::vector<double> f((size_t)nx, 0.0);
+  const double tw = 2.0 * M_PI / nx;
+  for (int d = 0; d < nx; ++d) {
+    double s = 0.0;
+    for (int m = 0; m < nx; ++m) {
+      const double k = tw * m;
+      s += std::cos(k * d) * std::exp(sign * p.dtau * (-2.0 * p.t * std::cos(k) - 0.5 * p.mu));
+    }
+    f[d] = s / nx;
+  }
+  out.assign((size_t)nx * nx, 0.0);
+  for (int a = 0; a < nx; ++a)
+    for (int b = 0; b < nx; ++b) out[(size_t)a * nx + b] = f[(a - b + nx) % nx];
+}
+
 // ---------------------------------------------------------------------------
 // schedule building blocks (all FP64 unless noted)
 // ---------------------------------------------------------------------------
@@ -388,35 +421,37 @@ GemmArgs<double> sq(const Group& g, int batch) {
 }
 
 // block products C_{c,b} = B_{b ns + ns - 1} ... B_{b ns} of the fields xs for
-// blocks b0 .. b0+nblk-1 of every chain.  dst stride per chain: nb*n*n when
-// nblk == 1 (into the cached array), else dst is [C][nblk][n][n] contiguous.
+// blocks b0 .. b0+nblk-1 of every chain, B_l = diag(exp(-dtau g x_l)) expK,
+// as Kronecker chains from the identity (one launch while ns * n fits the
+// kernel's table of row scales, else chunks through the scratch buffer).
+// dst stride per chain: nb*n*n when nblk == 1 (into the cached array), else
+// dst is [C][nblk][n][n] contiguous.
 hq_status block_products(Sched& S, Group& g, const double* xs, double* dst, long dst_chain_stride, double* scratch,
                          int b0, int nblk) {
   const long nn = (long)g.n * g.n;
-  const int batch = g.C * nblk;
   // with nblk == 1 the batch index is the chain; dst advances by dst_chain_stride
   const long sdst = (nblk == 1) ? dst_chain_stride : nn;
   double* bufs[2] = {dst, scratch};
-  long strides[2] = {sdst, nn};
-  int cur = ((g.ns - 1) % 2 == 0) ? 0 : 1;
-  Scale rs;
-  rs.v = xs;
-  rs.so = (long)g.L * g.n;
-  rs.si = (long)g.ns * g.n;
-  rs.coef = g.g;
-  rs.cmul = -g.p.dtau;
-  rs.off = (long)b0 * g.ns * g.n;
-  SCHED_TRY(launch_scale_rows(bufs[cur], strides[cur], g.expk, g.n, rs, batch, nblk, S.s));
-  for (int t = 1; t < g.ns; ++t) {
-    GemmArgs<double> a = sq(g, batch);
-    a.A = g.expk; a.sA = 0;
-    a.B = bufs[cur]; a.sB = strides[cur];
-    a.C = bufs[1 - cur]; a.sC = strides[1 - cur];
-    a.rs = rs;
-    a.rs.off = (long)(b0 * g.ns + t) * g.n;
-    a.inner_count = nblk;
-    SCHED_TRY(launch_gemm(a, nblk > 2 ? g.tile_wide : g.tile, S.s));
-    cur = 1 - cur;
+  const long strides[2] = {sdst, nn};
+  const int per = KRON_MAX_SCALES / g.n;
+  const int chunks = (g.ns + per - 1) / per;
+  KronArgs<double> a;
+  a.nx = g.nx; a.n = g.n; a.batch = g.C * nblk; a.inner_count = nblk;
+  a.A = g.ek1;
+  a.X = g.ident; a.sX = 0;
+  a.rs.v = xs;
+  a.rs.so = (long)g.L * g.n;
+  a.rs.si = (long)g.ns * g.n;
+  a.rs.coef = g.g;
+  a.rs.cmul = -g.p.dtau;
+  a.rstep = g.n;
+  for (int k = 0, t0 = 0; k < chunks; ++k, t0 += per) {
+    const int out = (chunks - 1 - k) % 2;     // the last chunk lands in dst
+    a.steps = std::min(per, g.ns - t0);
+    a.rs.off = (long)(b0 * g.ns + t0) * g.n;
+    a.Y = bufs[out]; a.sY = strides[out];
+    SCHED_TRY(launch_kron(a, 0, S.s));
+    a.X = bufs[out]; a.sX = strides[out];
   }
   return HQ_OK;
 }
@@ -587,6 +622,25 @@ hq_status fused_wrap(Sched& S, Group& g, const T* A1, const T* A2, Scale ks1, Sc
   return HQ_OK;
 }
 
+// the same with the Kronecker passes: Wt = (A1 (x) A1) diag(ks1) G diag(cs1),
+// G = diag(rs2) Wt (A2 (x) A2) diag(cs2); G stays in place
+template <typename T>
+hq_status kron_wrap(Sched& S, Group& g, const T* A1, const T* A2, Scale ks1, Scale cs1, Scale rs2, Scale cs2) {
+  KronArgs<T> l;
+  l.nx = g.nx; l.n = g.n; l.batch = g.C;
+  l.A = A1;
+  l.X = (const T*)g.G; l.sX = (long)g.n * g.n;
+  l.Y = (T*)g.Wt; l.sY = l.sX;
+  l.ks = ks1; l.cs = cs1;
+  SCHED_TRY(launch_kron(l, 0, S.s));
+  KronArgs<T> r = l;
+  r.A = A2;
+  r.X = (const T*)g.Wt; r.Y = (T*)g.G;
+  r.ks = Scale(); r.cs = cs2; r.rs = rs2;
+  SCHED_TRY(launch_kron(r, 1, S.s));
+  return HQ_OK;
+}
+
 // G back in G0 at the end of a group's sweep (after an odd number of fused wraps)
 hq_status settle_g(Sched& S, Group& g) {
   if (g.G == g.G0) return HQ_OK;
@@ -601,7 +655,11 @@ hq_status wrap(Sched& S, Group& g, int slice) {
   Scale rs, cs;
   rs.v = g.x; rs.so = (long)g.L * g.n; rs.off = (long)slice * g.n; rs.coef = g.g; rs.cmul = -g.p.dtau;
   cs = rs; cs.cmul = g.p.dtau;
-  if (g.fused_wrap) {
+  if (g.wrap_kind == WRAP_KRON) {
+    if (S.ctx->opt.precision == HQ_PREC_MIXED) return kron_wrap<float>(S, g, g.ek1_32, g.ek1inv_32, Scale(), Scale(), rs, cs);
+    return kron_wrap<double>(S, g, g.ek1, g.ek1inv, Scale(), Scale(), rs, cs);
+  }
+  if (g.wrap_kind == WRAP_FUSED) {
     if (S.ctx->opt.precision == HQ_PREC_MIXED) return fused_wrap<float>(S, g, g.expk32, g.expkinv32, Scale(), Scale(), rs, cs);
     return fused_wrap<double>(S, g, g.expk, g.expkinv, Scale(), Scale(), rs, cs);
   }
@@ -654,7 +712,11 @@ hq_status unwrap(Sched& S, Group& g, int slice) {
   Scale ks, cs;
   ks.v = g.x; ks.so = (long)g.L * g.n; ks.off = (long)slice * g.n; ks.coef = g.g; ks.cmul = g.p.dtau;
   cs = ks; cs.cmul = -g.p.dtau;
-  if (g.fused_wrap) {
+  if (g.wrap_kind == WRAP_KRON) {
+    if (S.ctx->opt.precision == HQ_PREC_MIXED) return kron_wrap<float>(S, g, g.ek1inv_32, g.ek1_32, ks, cs, Scale(), Scale());
+    return kron_wrap<double>(S, g, g.ek1inv, g.ek1, ks, cs, Scale(), Scale());
+  }
+  if (g.wrap_kind == WRAP_FUSED) {
     if (S.ctx->opt.precision == HQ_PREC_MIXED) return fused_wrap<float>(S, g, g.expkinv32, g.expk32, ks, cs, Scale(), Scale());
     return fused_wrap<double>(S, g, g.expkinv, g.expk, ks, cs, Scale(), Scale());
   }
@@ -967,12 +1029,31 @@ hq_status autotune(hq_ctx* ctx) {
       else g.tile_wide = bt;
     }
     if (ctx->opt.precision != HQ_PREC_MIXED) { g.tile32 = g.tile; g.tile32_us = g.tile_us; }
-    // the wrap: both products in one launch, or two tiled products
-    g.fused_wrap = false;
+    // the wrap: two tiled products, both products in one launch, or the two
+    // Kronecker passes (G and Wt hold nothing yet)
+    g.wrap_kind = WRAP_TWO;
     g.wrap_us = 2.0 * g.tile32_us;
     const bool mixed = ctx->opt.precision == HQ_PREC_MIXED;
-    if (st == HQ_OK && wrap_fused_supported(g.n, mixed)) {
-      auto run = [&]() {
+    for (int kind : {WRAP_FUSED, WRAP_KRON}) {
+      if (st != HQ_OK) break;
+      if (kind == WRAP_FUSED && !wrap_fused_supported(g.n, mixed)) continue;
+      auto run = [&]() -> hipError_t {
+        if (kind == WRAP_KRON) {
+          if (mixed) {
+            KronArgs<float> k;
+            k.nx = g.nx; k.n = g.n; k.batch = g.C; k.A = g.ek1_32;
+            k.X = (const float*)g.G; k.sX = nn; k.Y = (float*)g.Wt; k.sY = nn;
+            hipError_t e = launch_kron(k, 0, s);
+            k.X = (const float*)g.Wt; k.Y = (float*)g.G;
+            return e != hipSuccess ? e : launch_kron(k, 1, s);
+          }
+          KronArgs<double> k;
+          k.nx = g.nx; k.n = g.n; k.batch = g.C; k.A = g.ek1;
+          k.X = (const double*)g.G; k.sX = nn; k.Y = (double*)g.Wt; k.sY = nn;
+          hipError_t e = launch_kron(k, 0, s);
+          k.X = (const double*)g.Wt; k.Y = (double*)g.G;
+          return e != hipSuccess ? e : launch_kron(k, 1, s);
+        }
         if (mixed) {
           WrapArgs<float> w;
           w.n = g.n; w.batch = g.C; w.A1 = g.expk32; w.A2 = g.expkinv32;
@@ -994,7 +1075,7 @@ hq_status autotune(hq_ctx* ctx) {
       if (e != hipSuccess) {
         st = fail(ctx, HQ_EDEVICE, "autotune: %s", hipGetErrorString(e));
       } else if (1e3 * ms / 3.0 < g.wrap_us) {
-        g.fused_wrap = true;
+        g.wrap_kind = kind;
         g.wrap_us = 1e3 * ms / 3.0;
       }
     }
@@ -1119,6 +1200,10 @@ hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* 
     exp_hopping(g.p, +1.0, eki);
     for (int i = 0; i < n; ++i) id[(size_t)i * n + i] = 1.0;
     std::vector<float> ek32(ek.begin(), ek.end()), eki32(eki.begin(), eki.end());
+    std::vector<double> e1, e1i;
+    exp_hopping_1d(g.p, -1.0, e1);
+    exp_hopping_1d(g.p, +1.0, e1i);
+    std::vector<float> e1_32(e1.begin(), e1.end()), e1i_32(e1i.begin(), e1i.end());
     std::vector<double> x((size_t)C * L * n), gc((size_t)C);
     for (int c = 0; c < C; ++c) {
       const uint64_t chain = (uint64_t)(g.chain0 + c);
@@ -1139,6 +1224,10 @@ hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* 
     HQ_TRY(hipMemcpyAsync(g.expkinv, eki.data(), eki.size() * 8, hipMemcpyHostToDevice, s));
     HQ_TRY(hipMemcpyAsync(g.expk32, ek32.data(), ek32.size() * 4, hipMemcpyHostToDevice, s));
     HQ_TRY(hipMemcpyAsync(g.expkinv32, eki32.data(), eki32.size() * 4, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipMemcpyAsync(g.ek1, e1.data(), e1.size() * 8, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipMemcpyAsync(g.ek1inv, e1i.data(), e1i.size() * 8, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipMemcpyAsync(g.ek1_32, e1_32.data(), e1_32.size() * 4, hipMemcpyHostToDevice, s));
+    HQ_TRY(hipMemcpyAsync(g.ek1inv_32, e1i_32.data(), e1i_32.size() * 4, hipMemcpyHostToDevice, s));
     HQ_TRY(hipMemcpyAsync(g.ident, id.data(), id.size() * 8, hipMemcpyHostToDevice, s));
     HQ_TRY(hipMemcpyAsync(g.ones, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, s));
     HQ_TRY(hipMemcpyAsync(g.x, x.data(), x.size() * 8, hipMemcpyHostToDevice, s));
@@ -1379,12 +1468,12 @@ hq_status hq_read_tuning(const hq_ctx* ctx, int32_t group, hq_tuning* out) {
   out->local_block = g.kd;
   out->gemm_us_fp64 = g.tile_us;
   out->gemm_us_wrap = g.tile32_us;
-  out->wrap_fused = g.fused_wrap ? 1 : 0;
+  out->wrap_kind = g.wrap_kind;
   out->wrap_us = g.wrap_us;
   return HQ_OK;
 }
 
-hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t tile_wrap, int32_t wrap_fused) {
+hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t tile_wrap, int32_t wrap_kind) {
   ST_TRY(check_ctx(ctx));
   if (group < 0 || group >= (int32_t)ctx->groups.size()) return fail(ctx, HQ_EINVAL, "bad group %d", group);
   Group& g = ctx->groups[group];
@@ -1395,13 +1484,15 @@ hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t t
     return fail(ctx, HQ_EINVAL, "GEMM tile %d does not fit the wraps' products of size %d", tile_wrap, g.n);
   if (!mixed && tile_wrap != tile_fp64)
     return fail(ctx, HQ_EINVAL, "in FP64 precision the wraps use the FP64 tile");
-  if ((wrap_fused != 0 && wrap_fused != 1) || (wrap_fused && !wrap_fused_supported(g.n, mixed)))
+  if (wrap_kind != WRAP_TWO && wrap_kind != WRAP_FUSED && wrap_kind != WRAP_KRON)
+    return fail(ctx, HQ_EINVAL, "unknown wrap kind %d", wrap_kind);
+  if (wrap_kind == WRAP_FUSED && !wrap_fused_supported(g.n, mixed))
     return fail(ctx, HQ_EINVAL, "no fused wrap for N = %d", g.n);
   HQ_TRY(hipStreamSynchronize(ctx->stream));
   drop_graphs(ctx);
   g.tile = g.tile_wide = tile_fp64;
   g.tile32 = tile_wrap;
-  g.fused_wrap = wrap_fused != 0;
+  g.wrap_kind = wrap_kind;
   g.tile_us = g.tile32_us = g.wrap_us = 0.0;
   return HQ_OK;
 }

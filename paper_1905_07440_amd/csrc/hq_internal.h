@@ -37,6 +37,38 @@ struct GemmArgs {
   int batch = 1, inner_count = 1;
 };
 
+// Workgroups are dealt to the eight XCDs in turn (workgroup g runs on XCD
+// g mod 8), each XCD with its own L2.  The grid is one-dimensional and is
+// read so that all tiles of one batch entry land on the same XCD: XCD x
+// takes entries x, x + 8, ..., tile by tile, and the entry's operands are
+// fetched into that L2 once.  Returns false for the padding workgroups of a
+// batch that is not a multiple of 8.
+constexpr int N_XCD = 8;
+__device__ inline bool xcd_tile(int tiles, int batch, int& z, int& tile) {
+  const int g = blockIdx.x, x = g % N_XCD, k = g / N_XCD;
+  z = N_XCD * (k / tiles) + x;
+  tile = k % tiles;
+  return z < batch;
+}
+inline unsigned xcd_grid(int tiles, int batch) { return (unsigned)(N_XCD * ((batch + N_XCD - 1) / N_XCD) * tiles); }
+
+// offset of batch entry z: z * s, or, with split > 0 entries per group,
+// (z / split) * so + (z % split) * s
+__device__ inline long batch_offset(int z, int split, long s, long so) {
+  if (split <= 0) return (long)z * s;
+  const int o = z / split;
+  return (long)o * so + (long)(z - o * split) * s;
+}
+
+__device__ inline double scale_value(const Scale& s, int z, int inner_count, int i) {
+  if (!s.v) return 1.0;
+  const int outer = z / inner_count, inner = z - outer * inner_count;
+  double v = s.v[(long)outer * s.so + (long)inner * s.si + s.off + i];
+  if (s.coef) v = exp(s.cmul * s.coef[outer] * v);
+  if (s.invert) v = 1.0 / v;
+  return v;
+}
+
 // GEMM tile configurations (see gemm.hip); the autotuner picks one per shape.
 // TILE_FK_*: the whole K extent staged at once (needs K small enough for LDS).
 // TILE_PF_*: each thread prefetches its whole share of K into registers.
@@ -61,14 +93,31 @@ bool wrap_fused_supported(int n, bool fp32);
 hipError_t launch_wrap_fused(const WrapArgs<double>& w, hipStream_t s);
 hipError_t launch_wrap_fused(const WrapArgs<float>& w, hipStream_t s);
 
+// Products with A (x) A for an nx x nx factor A (kron.hip), the form that
+// exp(s dtau K) takes on the periodic square lattice; site i = ix + nx iy.
+//   side 0: Y[z] = diag(r_{S-1}) (A (x) A) ... diag(r_0) (A (x) A) diag(ks) X[z] diag(cs)
+//           for S = steps, r_t = rs read at rs.off + t * rstep
+//   side 1: Y[z] = diag(rs) X[z] diag(ks) (A (x) A) diag(cs)     (steps = 1)
+// X, Y n x n row-major (n = nx^2 <= 256), advancing by sX, sY per batch
+// entry (sX = 0: one X for the whole batch); Y must not overlap X.  A shared
+// by the batch.  steps * n <= KRON_MAX_SCALES.
+constexpr int KRON_MAX_SCALES = 2048;
+template <typename T>
+struct KronArgs {
+  int nx = 0, n = 0, batch = 0, inner_count = 1;
+  const T* A = nullptr;
+  const T* X = nullptr; long sX = 0;
+  T* Y = nullptr; long sY = 0;
+  Scale rs, ks, cs;
+  int steps = 1; long rstep = 0;
+};
+hipError_t launch_kron(const KronArgs<double>& a, int side, hipStream_t s);
+hipError_t launch_kron(const KronArgs<float>& a, int side, hipStream_t s);
+
 hipError_t launch_gemm(const GemmArgs<double>& a, int tile, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs<float>& a, int tile, hipStream_t s);
 bool gemm_tile_fits(int tile, int K, int precision);
 hipError_t prepare_gemm();
-
-// P[z] = diag(rs(z)) * A  (A shared), used for the first slice of a block product
-hipError_t launch_scale_rows(double* P, long sP, const double* A, int n, Scale rs, int batch,
-                             int inner_count, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // local moves of one slice: one workgroup per chain, sites in blocks of kd

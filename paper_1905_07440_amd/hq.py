@@ -64,11 +64,14 @@ class Stats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("gemm_tile_fp64", ctypes.c_int32), ("gemm_tile_wrap", ctypes.c_int32),
                 ("local_block", ctypes.c_int32), ("gemm_us_fp64", ctypes.c_double),
-                ("gemm_us_wrap", ctypes.c_double), ("wrap_fused", ctypes.c_int32),
+                ("gemm_us_wrap", ctypes.c_double), ("wrap_kind", ctypes.c_int32),
                 ("wrap_us", ctypes.c_double)]
 
 
 N_GEMM_TILES = 11
+# forms of a wrap (HQ_WRAP_*): two tiled dense products, both in one launch,
+# or the Kronecker passes of exp(-+dtau K) = E1 (x) E1
+WRAP_KINDS = ("two", "fused", "kron")
 
 def tile_name(code):
     """Name of a GEMM tile code ("?" for an unknown one)."""
@@ -241,12 +244,15 @@ class Context:
         self._check(self._lib.hq_phase_time(self._ctx, phase.encode(), ctypes.byref(ms), ctypes.byref(k)))
         return ms.value, k.value
 
-    def set_tuning(self, group, tile_fp64, tile_wrap=None, wrap_fused=False):
+    def set_tuning(self, group, tile_fp64, tile_wrap=None, wrap="two"):
         """Pin a group's GEMM tiles (codes 0 .. N_GEMM_TILES-1; the wraps take
-        tile_fp64 when tile_wrap is None) and the wrap's form (one fused launch
-        or two tiled products)."""
+        tile_fp64 when tile_wrap is None) and the wrap's form (one of
+        WRAP_KINDS)."""
+        if wrap not in WRAP_KINDS:
+            raise ValueError("wrap must be one of %s" % (WRAP_KINDS,))
         self._check(self._lib.hq_set_tuning(self._ctx, group, tile_fp64,
-                                            tile_fp64 if tile_wrap is None else tile_wrap, int(wrap_fused)))
+                                            tile_fp64 if tile_wrap is None else tile_wrap,
+                                            WRAP_KINDS.index(wrap)))
 
     def tuning(self, group):
         """The autotuner's choices for one group (GEMM tiles by name, timings in us)."""
@@ -255,7 +261,8 @@ class Context:
         name = self._lib.hq_gemm_tile_name
         return {"gemm_tile_fp64": name(t.gemm_tile_fp64).decode(), "gemm_us_fp64": t.gemm_us_fp64,
                 "gemm_tile_wrap": name(t.gemm_tile_wrap).decode(), "gemm_us_wrap": t.gemm_us_wrap,
-                "wrap_fused": bool(t.wrap_fused), "wrap_us": t.wrap_us, "local_block": t.local_block}
+                "wrap": WRAP_KINDS[t.wrap_kind] if 0 <= t.wrap_kind < len(WRAP_KINDS) else "?",
+                "wrap_us": t.wrap_us, "local_block": t.local_block}
 
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx:

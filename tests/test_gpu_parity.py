@@ -205,6 +205,21 @@ def test_large_lattice_fp64(hq, nx):
     ctx.close()
 
 
+@pytest.mark.parametrize("ns", [9, 10])
+def test_block_product_chunks_16x16(hq, ns):
+    """N = 256 with n_stab slices per block above the 8 row-scale sets that
+    one Kronecker chain launch holds: block products in two chunks (8 + 1,
+    8 + 2) through the scratch buffer."""
+    say("FP64 16x16 n_stab=%d" % ns)
+    gr = dict(nx=16, chains=1, g=1.1, beta=0.1 * 2 * ns, n_stab=ns)
+    ctx = make_ctx(hq, [gr], seed=19)
+    ctx.sweep(2)
+    ch = dqmc.Chain(params_of(gr), 19, 0)
+    ch.sweep(); ch.sweep()
+    assert_state(ctx, 0, ch, TOL64, "16x16 n_stab=%d" % ns)
+    ctx.close()
+
+
 def test_mixed_16x16_register_form(hq):
     """N = 256 in mixed precision: G in the accumulators of four waves (64
     tiles each), an upward and a downward sweep."""
@@ -262,8 +277,8 @@ def test_fused_wrap_fp64(hq, nx):
     say("FP64 fused wrap nx=%d" % nx)
     gr = dict(nx=nx, chains=2, g=1.2, beta=0.9, n_stab=3)
     ctx = make_ctx(hq, [gr], seed=15)
-    ctx.set_tuning(0, 0, 0, wrap_fused=True)
-    assert ctx.tuning(0)["wrap_fused"]
+    ctx.set_tuning(0, 0, 0, wrap="fused")
+    assert ctx.tuning(0)["wrap"] == "fused"
     ctx.sweep(2)
     for c in range(2):
         ch = dqmc.Chain(params_of(gr), 15, c)
@@ -276,7 +291,32 @@ def test_fused_wrap_fp64(hq, nx):
 def test_fused_wrap_mixed(hq, nx):
     say("mixed fused wrap nx=%d" % nx)
     _mixed_replay_case(hq, dict(nx=nx, chains=1, g=1.3, beta=0.9, n_stab=3), (0,), seed=16, sweeps=2,
-                       setup=lambda ctx: ctx.set_tuning(0, 0, 0, wrap_fused=True))
+                       setup=lambda ctx: ctx.set_tuning(0, 0, 0, wrap="fused"))
+
+
+@pytest.mark.parametrize("nx", [2, 3, 5, 8, 12, 16])
+def test_kron_wrap_fp64(hq, nx):
+    """Wraps as Kronecker passes (each padded factor size 4, 8, 12, 16; strips
+    of 16 that are ragged for N = 4, 9, 25), an upward and a downward sweep.
+    Block products take the Kronecker form in every test."""
+    say("FP64 Kronecker wrap nx=%d" % nx)
+    gr = dict(nx=nx, chains=2, g=1.2, beta=0.9, n_stab=3)
+    ctx = make_ctx(hq, [gr], seed=17)
+    ctx.set_tuning(0, 0, 0, wrap="kron")
+    assert ctx.tuning(0)["wrap"] == "kron"
+    ctx.sweep(2)
+    for c in range(2):
+        ch = dqmc.Chain(params_of(gr), 17, c)
+        ch.sweep(); ch.sweep()
+        assert_state(ctx, c, ch, TOL64, "kron wrap nx=%d chain %d" % (nx, c))
+    ctx.close()
+
+
+@pytest.mark.parametrize("nx", [5, 12, 16])
+def test_kron_wrap_mixed(hq, nx):
+    say("mixed Kronecker wrap nx=%d" % nx)
+    _mixed_replay_case(hq, dict(nx=nx, chains=1, g=1.3, beta=0.9, n_stab=3), (0,), seed=18, sweeps=2,
+                       setup=lambda ctx: ctx.set_tuning(0, 0, 0, wrap="kron"))
 
 
 def test_set_tuning_rejects_bad_tiles(hq):
@@ -291,7 +331,8 @@ def test_set_tuning_rejects_bad_tiles(hq):
     with pytest.raises(hq.HQError):
         ctx.set_tuning(1, 0)
     with pytest.raises(hq.HQError):
-        ctx.set_tuning(0, 0, 0, wrap_fused=True)   # N = 256: no fused wrap
+        ctx.set_tuning(0, 0, 0, wrap="fused")   # N = 256: no fused wrap
+    assert ctx._lib.hq_set_tuning(ctx._ctx, 0, 0, 0, 3) != 0   # no such wrap kind
     ctx.sweep(1)
     assert ctx.stats(0)["local_proposals"] == 256 * 4
     ctx.close()

@@ -37,6 +37,23 @@ def random_fields(p, seed, scale=1.0):
     return scale * np.random.default_rng(seed).standard_normal((p.L, p.n))
 
 
+@pytest.mark.parametrize("nx,mu,sign", [(1, 0.2, -1.0), (2, 0.0, -1.0), (3, 0.4, 1.0), (6, -0.3, -1.0), (12, 0.0, 1.0)])
+def test_exp_hopping_is_a_kronecker_square(nx, mu, sign):
+    """The wraps and block products use exp(s dtau K) = E1 (x) E1 with E1 the
+    exponential of the nx-site ring carrying half the chemical potential
+    (site i = ix + nx iy); checked against the oracle's eigen-decomposition of
+    the full K, with E1 from scipy's expm of the ring."""
+    import scipy.linalg
+    p = Params(nx=nx, beta=1.0, mu=mu)
+    ring = np.zeros((nx, nx))
+    for a in range(nx):
+        ring[a, a] -= 0.5 * mu
+        for d in (1, -1):
+            ring[a, (a + d) % nx] -= p.t
+    e1 = scipy.linalg.expm(sign * p.dtau * ring)
+    assert np.allclose(np.kron(e1, e1), model.exp_hopping(p, sign), rtol=0, atol=1e-14)
+
+
 @pytest.mark.parametrize("nx,beta,mu", [(2, 2.0, 0.0), (4, 4.0, 0.0), (4, 8.0, 0.3), (6, 10.0, -0.5)])
 def test_hopping_spectrum_matches_plane_waves(nx, beta, mu):
     p = Params(nx=nx, beta=beta, mu=mu)
