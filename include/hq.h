@@ -167,8 +167,10 @@ hq_status hq_phase_time(hq_ctx* ctx, const char* phase, double* ms_total, int64_
  *   HQ_WRAP_FUSED  both dense products in one launch (N <= 144);
  *   HQ_WRAP_KRON   exp(s dtau K) = E1 (x) E1 on the periodic square lattice
  *                  (E1 of size nx, site index ix + nx iy), applied as two
- *                  passes of nx-term sums on each side. */
-enum { HQ_WRAP_TWO = 0, HQ_WRAP_FUSED = 1, HQ_WRAP_KRON = 2 };
+ *                  passes of nx-term sums on each side, one launch a side;
+ *   HQ_WRAP_KRON_LDS  the same four passes in one launch, the matrix held in
+ *                  LDS (nx <= 12 in mixed precision, nx <= 10 in FP64). */
+enum { HQ_WRAP_TWO = 0, HQ_WRAP_FUSED = 1, HQ_WRAP_KRON = 2, HQ_WRAP_KRON_LDS = 3 };
 
 /* The configuration chosen at hq_create for one group: the GEMM tile of
  * the FP64 products (UDT combines and merges) and of the wraps' dense
@@ -190,7 +192,8 @@ hq_status hq_read_tuning(const hq_ctx* ctx, int32_t group, hq_tuning* out);
  * are those of hq_read_tuning, 0 .. 10; wrap_kind one of HQ_WRAP_*.
  * HQ_EINVAL, with nothing changed, for an unknown code, a tile that does not
  * fit the group's N in that precision, in FP64 precision tile_wrap !=
- * tile_fp64, or HQ_WRAP_FUSED with N > 144.  Waits for the context's
+ * tile_fp64, HQ_WRAP_FUSED with N > 144, or HQ_WRAP_KRON_LDS beyond its
+ * sizes.  Waits for the context's
  * stream; the sweep graphs are captured again on the next hq_sweep.  The
  * timings that hq_read_tuning reports become 0. */
 hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t tile_wrap, int32_t wrap_kind);

@@ -32,8 +32,9 @@ namespace {
 const int N_KIND_SLOTS = 5;   // indexed by HQ_KIND_* (0, 1, 3, 4 used)
 
 // a wrap G <- B G B^-1 as two tiled dense products, as one fused launch of
-// both dense products, or as two Kronecker passes (left, then right)
-enum { WRAP_TWO = HQ_WRAP_TWO, WRAP_FUSED = HQ_WRAP_FUSED, WRAP_KRON = HQ_WRAP_KRON };
+// both dense products, as two Kronecker launches (left, then right), or as
+// one Kronecker launch with G held in LDS
+enum { WRAP_TWO = HQ_WRAP_TWO, WRAP_FUSED = HQ_WRAP_FUSED, WRAP_KRON = HQ_WRAP_KRON, WRAP_KRON_LDS = HQ_WRAP_KRON_LDS };
 
 struct Group {
   hq_group p{};
@@ -641,6 +642,20 @@ hq_status kron_wrap(Sched& S, Group& g, const T* A1, const T* A2, Scale ks1, Sca
   return HQ_OK;
 }
 
+// the four Kronecker passes in one launch, G in LDS; G and Wt trade places
+template <typename T>
+hq_status kron_lds_wrap(Sched& S, Group& g, const T* A1, const T* A2, Scale ks1, Scale cs1, Scale rs2, Scale cs2) {
+  KronWrapArgs<T> w;
+  w.nx = g.nx; w.batch = g.C;
+  w.A1 = A1; w.A2 = A2;
+  w.X = (const T*)g.G; w.sX = (long)g.n * g.n;
+  w.Y = (T*)g.Wt; w.sY = w.sX;
+  w.ks1 = ks1; w.cs1 = cs1; w.rs2 = rs2; w.cs2 = cs2;
+  SCHED_TRY(launch_kron_wrap_lds(w, S.s));
+  std::swap(g.G, g.Wt);
+  return HQ_OK;
+}
+
 // G back in G0 at the end of a group's sweep (after an odd number of fused wraps)
 hq_status settle_g(Sched& S, Group& g) {
   if (g.G == g.G0) return HQ_OK;
@@ -655,6 +670,10 @@ hq_status wrap(Sched& S, Group& g, int slice) {
   Scale rs, cs;
   rs.v = g.x; rs.so = (long)g.L * g.n; rs.off = (long)slice * g.n; rs.coef = g.g; rs.cmul = -g.p.dtau;
   cs = rs; cs.cmul = g.p.dtau;
+  if (g.wrap_kind == WRAP_KRON_LDS) {
+    if (S.ctx->opt.precision == HQ_PREC_MIXED) return kron_lds_wrap<float>(S, g, g.ek1_32, g.ek1inv_32, Scale(), Scale(), rs, cs);
+    return kron_lds_wrap<double>(S, g, g.ek1, g.ek1inv, Scale(), Scale(), rs, cs);
+  }
   if (g.wrap_kind == WRAP_KRON) {
     if (S.ctx->opt.precision == HQ_PREC_MIXED) return kron_wrap<float>(S, g, g.ek1_32, g.ek1inv_32, Scale(), Scale(), rs, cs);
     return kron_wrap<double>(S, g, g.ek1, g.ek1inv, Scale(), Scale(), rs, cs);
@@ -712,6 +731,10 @@ hq_status unwrap(Sched& S, Group& g, int slice) {
   Scale ks, cs;
   ks.v = g.x; ks.so = (long)g.L * g.n; ks.off = (long)slice * g.n; ks.coef = g.g; ks.cmul = g.p.dtau;
   cs = ks; cs.cmul = -g.p.dtau;
+  if (g.wrap_kind == WRAP_KRON_LDS) {
+    if (S.ctx->opt.precision == HQ_PREC_MIXED) return kron_lds_wrap<float>(S, g, g.ek1inv_32, g.ek1_32, ks, cs, Scale(), Scale());
+    return kron_lds_wrap<double>(S, g, g.ek1inv, g.ek1, ks, cs, Scale(), Scale());
+  }
   if (g.wrap_kind == WRAP_KRON) {
     if (S.ctx->opt.precision == HQ_PREC_MIXED) return kron_wrap<float>(S, g, g.ek1inv_32, g.ek1_32, ks, cs, Scale(), Scale());
     return kron_wrap<double>(S, g, g.ek1inv, g.ek1, ks, cs, Scale(), Scale());
@@ -1034,10 +1057,23 @@ hq_status autotune(hq_ctx* ctx) {
     g.wrap_kind = WRAP_TWO;
     g.wrap_us = 2.0 * g.tile32_us;
     const bool mixed = ctx->opt.precision == HQ_PREC_MIXED;
-    for (int kind : {WRAP_FUSED, WRAP_KRON}) {
+    for (int kind : {WRAP_FUSED, WRAP_KRON, WRAP_KRON_LDS}) {
       if (st != HQ_OK) break;
       if (kind == WRAP_FUSED && !wrap_fused_supported(g.n, mixed)) continue;
+      if (kind == WRAP_KRON_LDS && !kron_wrap_lds_supported(g.nx, mixed)) continue;
       auto run = [&]() -> hipError_t {
+        if (kind == WRAP_KRON_LDS) {
+          if (mixed) {
+            KronWrapArgs<float> k;
+            k.nx = g.nx; k.batch = g.C; k.A1 = g.ek1_32; k.A2 = g.ek1inv_32;
+            k.X = (const float*)g.G; k.sX = nn; k.Y = (float*)g.Wt; k.sY = nn;
+            return launch_kron_wrap_lds(k, s);
+          }
+          KronWrapArgs<double> k;
+          k.nx = g.nx; k.batch = g.C; k.A1 = g.ek1; k.A2 = g.ek1inv;
+          k.X = (const double*)g.G; k.sX = nn; k.Y = (double*)g.Wt; k.sY = nn;
+          return launch_kron_wrap_lds(k, s);
+        }
         if (kind == WRAP_KRON) {
           if (mixed) {
             KronArgs<float> k;
@@ -1484,8 +1520,10 @@ hq_status hq_set_tuning(hq_ctx* ctx, int32_t group, int32_t tile_fp64, int32_t t
     return fail(ctx, HQ_EINVAL, "GEMM tile %d does not fit the wraps' products of size %d", tile_wrap, g.n);
   if (!mixed && tile_wrap != tile_fp64)
     return fail(ctx, HQ_EINVAL, "in FP64 precision the wraps use the FP64 tile");
-  if (wrap_kind != WRAP_TWO && wrap_kind != WRAP_FUSED && wrap_kind != WRAP_KRON)
+  if (wrap_kind != WRAP_TWO && wrap_kind != WRAP_FUSED && wrap_kind != WRAP_KRON && wrap_kind != WRAP_KRON_LDS)
     return fail(ctx, HQ_EINVAL, "unknown wrap kind %d", wrap_kind);
+  if (wrap_kind == WRAP_KRON_LDS && !kron_wrap_lds_supported(g.nx, mixed))
+    return fail(ctx, HQ_EINVAL, "no LDS-resident Kronecker wrap for nx = %d", g.nx);
   if (wrap_kind == WRAP_FUSED && !wrap_fused_supported(g.n, mixed))
     return fail(ctx, HQ_EINVAL, "no fused wrap for N = %d", g.n);
   HQ_TRY(hipStreamSynchronize(ctx->stream));

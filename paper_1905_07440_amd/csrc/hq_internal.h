@@ -111,6 +111,21 @@ struct KronArgs {
   Scale rs, ks, cs;
   int steps = 1; long rstep = 0;
 };
+// A whole wrap Y = diag(rs2) (A1 (x) A1) diag(ks1) X diag(cs1) (A2 (x) A2)
+// diag(cs2) in one launch, X resident in LDS (kron.hip): nx <= 12 in FP32,
+// nx <= 10 in FP64.  Y must not overlap X.
+template <typename T>
+struct KronWrapArgs {
+  int nx = 0, batch = 0;
+  const T* A1 = nullptr;
+  const T* A2 = nullptr;
+  const T* X = nullptr; long sX = 0;
+  T* Y = nullptr; long sY = 0;
+  Scale ks1, cs1, rs2, cs2;
+};
+bool kron_wrap_lds_supported(int nx, bool fp32);
+hipError_t launch_kron_wrap_lds(const KronWrapArgs<double>& w, hipStream_t s);
+hipError_t launch_kron_wrap_lds(const KronWrapArgs<float>& w, hipStream_t s);
 hipError_t launch_kron(const KronArgs<double>& a, int side, hipStream_t s);
 hipError_t launch_kron(const KronArgs<float>& a, int side, hipStream_t s);
 

@@ -11,26 +11,28 @@
 // in place of the 2 n^3 of a dense product (6x fewer on 12 x 12, 8x on
 // 16 x 16).  Bandwidth, not arithmetic, bounds these kernels.
 //
+// Each pass of nx-term sums is a set of small products on the matrix cores:
+// for a block b of nx rows (or the nx rows b, nx + b, ...), the 16 x 16
+// output D = F B with F the factor zero-padded to 16 x 16 and B 16 columns of
+// the strip, by ceil(nx / 4) MFMA 16x16x4 steps.  The factor stays in each
+// lane's registers as MFMA operand fragments; every strip element is read
+// from LDS once per pass and written back in place (a block's reads and
+// writes cover the same rows and belong to one wave).
+//
 // side 0 (left):  Y = diag(rs) (A (x) A) diag(ks) X diag(cs), or a chain of
 //   such products with a row scale after each (a block product
 //   B_{s-1} ... B_0 = diag(v_{s-1}) E ... diag(v_0) E from X = I).  One
-//   workgroup per strip of KW columns of one matrix; the strip stays in LDS
-//   through every step of a chain.  Pass 1 contracts kx: a thread takes the
-//   fiber (ky, column c) of nx values X[ky nx + kx][c] (the first straight
-//   from memory, the 16 threads of one ky reading 16 consecutive columns) and
-//   writes its nx sums back in place.  Pass 2 contracts ky: thread (ix, c)
-//   reads its fiber and writes the nx outputs of rows iy nx + ix.
+//   workgroup per strip of KW = 16 columns of one matrix, held in LDS through
+//   every step of a chain; pass 1 contracts kx within each block of rows
+//   ky nx .. ky nx + nx - 1, pass 2 contracts ky across blocks.
 // side 1 (right): Y = diag(rs) X diag(ks) (A (x) A) diag(cs).  One workgroup
-//   per strip of KW rows.  Pass 1 contracts kx over the contiguous runs
-//   X[r][ky nx .. ky nx + nx - 1] (thread (r, ky), consecutive threads on
-//   consecutive runs of a row), pass 2 contracts ky through LDS.
+//   per strip of 16 rows; the strip is the left operand of the products (its
+//   rows the MFMA's M dimension) and the factor the right one.
 //
-// Both are instantiated for each nx (1 .. 16), so that every loop has a
-// compile-time length and no load or LDS access sits behind a branch; the
-// first fibers are requested from memory before the factor and the diagonal
-// scales are set up in LDS.  Workgroups are mapped XCD-aware, so the left and
-// the right pass over one matrix run on the same XCD and the intermediate is
-// read back from that XCD's L2.
+// Strips are loaded and stored with consecutive threads on consecutive
+// elements of a row.  Workgroups are mapped XCD-aware, so the left and the
+// right pass over one matrix run on the same XCD and the intermediate is read
+// back from that XCD's L2.  Kernels are instantiated for each nx (1 .. 16).
 #include "hq_device.h"
 #include "hq_internal.h"
 
@@ -38,169 +40,371 @@ namespace hq {
 
 namespace {
 
-constexpr int KW = 16;          // strip width (columns, or rows for side 1)
-constexpr int KPAD = 16;        // LDS skew between the fibers of consecutive ky
+constexpr int KW = 16;          // strip width: columns (side 0) or rows (side 1)
+constexpr int KPAD = 16;        // LDS skew between consecutive blocks of nx rows (side 0)
 
-// LDS of the left kernel: the skewed strip, the factor, ks, cs and the row
-// scales of every step
-template <typename T, int NX>
-struct LeftLayout {
+template <int NX> struct KronDim {
   static constexpr int N = NX * NX;
-  static constexpr int SN = N * KW + NX * KPAD;
-  static constexpr int AN = (NX * NX + 1) & ~1;      // keeps the doubles 8-byte aligned
-  static size_t bytes(int steps) { return (size_t)(SN + AN) * sizeof(T) + (size_t)(N + KW + steps * N) * sizeof(double); }
+  static constexpr int KS = (NX + 3) / 4;                 // MFMA k-steps per product
+  static constexpr int SN = N * KW + NX * KPAD;           // side-0 strip in LDS
+  static constexpr int LDR = N + 1;                       // side-1 strip row length
 };
 
-__device__ inline int sidx(int r, int j, int blk) { return r * KW + j + blk * KPAD; }
+// side-0 strip element (row r, column c), rows of one block of nx skewed
+template <int NX>
+__device__ inline int lidx(int r, int c) { return r * KW + c + (r / NX) * KPAD; }
+
+// LDS of the left kernel after the strip: ks, cs and the row scales of every step
+template <typename T, int NX>
+size_t left_lds_bytes(int steps) {
+  return (size_t)KronDim<NX>::SN * sizeof(T) + (size_t)(KronDim<NX>::N + KW + steps * KronDim<NX>::N) * sizeof(double);
+}
 
 template <typename T, int NX>
 __global__ __launch_bounds__(256) void kron_left_kernel(KronArgs<T> a) {
-  typedef LeftLayout<T, NX> Lay;
-  constexpr int N = Lay::N;
+  typedef KronDim<NX> D;
+  constexpr int N = D::N, KS = D::KS;
   extern __shared__ __align__(16) unsigned char kron_lds[];
   T* S = (T*)kron_lds;
-  T* As = S + Lay::SN;
-  double* ksv = (double*)(As + Lay::AN);
+  double* ksv = (double*)(S + D::SN);
   double* csv = ksv + N;
   double* rsv = csv + KW;
   constexpr int strips = (N + KW - 1) / KW;
   int z, strip;
   if (!xcd_tile(strips, a.batch, z, strip)) return;
   const int c0 = strip * KW;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int j = tid % KW, f = tid / KW;
-  const bool act = f < NX, col_ok = c0 + j < N;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
   const T* X = a.X + (long)z * a.sX;
-  T v[NX];
-  if (act && col_ok) {
+
+  // the strip's elements, requested before the tables are built
+  constexpr int PER = (N * KW + 255) / 256;
+  T xin[PER];
 #pragma unroll
-    for (int kx = 0; kx < NX; ++kx) v[kx] = X[(long)(f * NX + kx) * N + c0 + j];
-  } else {
-#pragma unroll
-    for (int kx = 0; kx < NX; ++kx) v[kx] = T(0);
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u, r = e / KW, c = e % KW;
+    xin[u] = (e < N * KW && c0 + c < N) ? X[(long)r * N + c0 + c] : T(0);
   }
-  for (int e = tid; e < NX * NX; e += nt) As[e] = a.A[e];
-  for (int i = tid; i < N; i += nt) ksv[i] = scale_value(a.ks, z, a.inner_count, i);
-  if (tid < KW) csv[tid] = col_ok ? scale_value(a.cs, z, a.inner_count, c0 + tid) : 0.0;
+  // factor fragments: lane holds A[li][4 kk + lk] (zero outside nx x nx)
+  T af[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    const int k = 4 * kk + lk;
+    af[kk] = (li < NX && k < NX) ? a.A[li * NX + k] : T(0);
+  }
+  for (int i = tid; i < N; i += 256) ksv[i] = scale_value(a.ks, z, a.inner_count, i);
+  if (tid < KW) csv[tid] = (c0 + tid < N) ? scale_value(a.cs, z, a.inner_count, c0 + tid) : 0.0;
   const int steps = a.steps;
-  for (int e = tid; e < steps * N; e += nt) {
+  for (int e = tid; e < steps * N; e += 256) {
     const int t = e / N, i = e - t * N;
     Scale sc = a.rs;
     sc.off += (long)t * a.rstep;
     rsv[e] = scale_value(sc, z, a.inner_count, i);
   }
   __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u, r = e / KW, c = e % KW;
+    if (e < N * KW) S[lidx<NX>(r, c)] = xin[u] * (T)ksv[r];
+  }
+  __syncthreads();
 
-  T* Y = a.Y + (long)z * a.sY;
   for (int t = 0; t < steps; ++t) {
-    if (act) {                           // pass 1: fiber (ky = f, column c0 + j)
-      if (t == 0) {
+    // pass 1: within block b, D[ix][c] = sum_kx A[ix][kx] S[b nx + kx][c]
+    for (int b = wave; b < NX; b += 4) {
+      typename Frag<T>::type acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int kx = 0; kx < NX; ++kx) v[kx] *= (T)ksv[f * NX + kx];
-      } else {
-#pragma unroll
-        for (int kx = 0; kx < NX; ++kx) v[kx] = S[sidx(f * NX + kx, j, f)];
+      for (int kk = 0; kk < KS; ++kk) {
+        const int k = 4 * kk + lk;
+        const T bv = S[lidx<NX>(b * NX + min(k, NX - 1), li)];
+        acc = mfma16(af[kk], k < NX ? bv : T(0), acc);
       }
 #pragma unroll
-      for (int ix = 0; ix < NX; ++ix) {
-        T s = T(0);
-#pragma unroll
-        for (int kx = 0; kx < NX; ++kx) s = fma(As[ix * NX + kx], v[kx], s);
-        S[sidx(f * NX + ix, j, f)] = s;
+      for (int v = 0; v < 4; ++v) {
+        const int m = frag_row<T>(lane, v);
+        if (m < NX) S[lidx<NX>(b * NX + m, li)] = acc[v];
       }
     }
     __syncthreads();
-    const bool last = t + 1 == steps;
-    if (act) {                           // pass 2: fiber (ix = f, column c0 + j)
-      T h[NX];
+    // pass 2: for ix = b, D[iy][c] = sum_ky A[iy][ky] S[ky nx + b][c], rows scaled
+    const double* rt = rsv + t * N;
+    for (int b = wave; b < NX; b += 4) {
+      typename Frag<T>::type acc = {0, 0, 0, 0};
 #pragma unroll
-      for (int ky = 0; ky < NX; ++ky) h[ky] = S[sidx(ky * NX + f, j, ky)];
-      const double* rt = rsv + t * N;
+      for (int kk = 0; kk < KS; ++kk) {
+        const int k = 4 * kk + lk;
+        const T bv = S[lidx<NX>(min(k, NX - 1) * NX + b, li)];
+        acc = mfma16(af[kk], k < NX ? bv : T(0), acc);
+      }
 #pragma unroll
-      for (int iy = 0; iy < NX; ++iy) {
-        T s = T(0);
-#pragma unroll
-        for (int ky = 0; ky < NX; ++ky) s = fma(As[iy * NX + ky], h[ky], s);
-        const int r = iy * NX + f;
-        if (!last) S[sidx(r, j, iy)] = (T)rt[r] * s;
-        else if (col_ok) Y[(long)r * N + c0 + j] = (T)(rt[r] * csv[j]) * s;
+      for (int v = 0; v < 4; ++v) {
+        const int m = frag_row<T>(lane, v);
+        if (m < NX) {
+          const int r = m * NX + b;
+          S[lidx<NX>(r, li)] = acc[v] * (T)rt[r];
+        }
       }
     }
-    if (!last) __syncthreads();
+    __syncthreads();
+  }
+
+  T* Y = a.Y + (long)z * a.sY;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u, r = e / KW, c = e % KW;
+    if (e < N * KW && c0 + c < N) Y[(long)r * N + c0 + c] = S[lidx<NX>(r, c)] * (T)csv[c];
   }
 }
 
 template <typename T, int NX>
 __global__ __launch_bounds__(256) void kron_right_kernel(KronArgs<T> a) {
-  constexpr int N = NX * NX;
-  constexpr int SP = N + 1;              // LDS row length
-  __shared__ T S[KW * SP];
-  __shared__ T As[NX * NX];
+  typedef KronDim<NX> D;
+  constexpr int N = D::N, KS = D::KS, LDR = D::LDR;
+  __shared__ T S[KW * LDR];
   __shared__ double rsv[KW], ksv[N], csv[N];
   constexpr int strips = (N + KW - 1) / KW;
   int z, strip;
   if (!xcd_tile(strips, a.batch, z, strip)) return;
   const int r0 = strip * KW;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int r = tid / NX, q = tid - r * NX;   // row of the strip; ky (pass 1) or jx (pass 2)
-  const bool row_ok = r < KW && r0 + r < N;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
   const T* X = a.X + (long)z * a.sX;
-  T v[NX];
-  if (row_ok) {
-    const T* xr = X + (long)(r0 + r) * N + q * NX;
+
+  // rows r0 .. r0 + 15 are contiguous in memory
+  constexpr int PER = (N * KW + 255) / 256;
+  T xin[PER];
 #pragma unroll
-    for (int kx = 0; kx < NX; ++kx) v[kx] = xr[kx];
-  } else {
-#pragma unroll
-    for (int kx = 0; kx < NX; ++kx) v[kx] = T(0);
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u, r = e / N;
+    xin[u] = (e < N * KW && r0 + r < N) ? X[(long)r0 * N + e] : T(0);
   }
-  for (int e = tid; e < NX * NX; e += nt) As[e] = a.A[e];
-  for (int i = tid; i < N; i += nt) {
+  // factor fragments: lane holds A[4 kk + lk][li] (zero outside nx x nx)
+  T bf[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    const int k = 4 * kk + lk;
+    bf[kk] = (li < NX && k < NX) ? a.A[k * NX + li] : T(0);
+  }
+  for (int i = tid; i < N; i += 256) {
     ksv[i] = scale_value(a.ks, z, a.inner_count, i);
     csv[i] = scale_value(a.cs, z, a.inner_count, i);
   }
   if (tid < KW) rsv[tid] = (r0 + tid < N) ? scale_value(a.rs, z, a.inner_count, r0 + tid) : 0.0;
   __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u, r = e / N, c = e - r * N;
+    if (e < N * KW) S[r * LDR + c] = xin[u] * (T)ksv[c];
+  }
+  __syncthreads();
 
-  T* Y = a.Y + (long)z * a.sY;
-  if (row_ok) {                          // pass 1: run (row r0 + r, ky = q)
+  // pass 1: within column block b, D[r][jx] = sum_kx S[r][b nx + kx] A[kx][jx]
+  for (int b = wave; b < NX; b += 4) {
+    typename Frag<T>::type acc = {0, 0, 0, 0};
 #pragma unroll
-    for (int kx = 0; kx < NX; ++kx) v[kx] *= (T)ksv[q * NX + kx];
+    for (int kk = 0; kk < KS; ++kk) {
+      const int k = 4 * kk + lk;
+      const T av = S[li * LDR + b * NX + min(k, NX - 1)];
+      acc = mfma16(k < NX ? av : T(0), bf[kk], acc);
+    }
+    if (li < NX) {
 #pragma unroll
-    for (int jx = 0; jx < NX; ++jx) {
-      T s = T(0);
-#pragma unroll
-      for (int kx = 0; kx < NX; ++kx) s = fma(v[kx], As[kx * NX + jx], s);
-      S[r * SP + q * NX + jx] = s;
+      for (int v = 0; v < 4; ++v) S[frag_row<T>(lane, v) * LDR + b * NX + li] = acc[v];
     }
   }
   __syncthreads();
-  if (row_ok) {                          // pass 2: fiber (row r0 + r, jx = q)
-    T h[NX];
+  // pass 2: for jx = b, D[r][jy] = sum_ky S[r][ky nx + b] A[ky][jy]
+  for (int b = wave; b < NX; b += 4) {
+    typename Frag<T>::type acc = {0, 0, 0, 0};
 #pragma unroll
-    for (int ky = 0; ky < NX; ++ky) h[ky] = S[r * SP + ky * NX + q];
-    const double ri = rsv[r];
-    T* yr = Y + (long)(r0 + r) * N + q;
+    for (int kk = 0; kk < KS; ++kk) {
+      const int k = 4 * kk + lk;
+      const T av = S[li * LDR + min(k, NX - 1) * NX + b];
+      acc = mfma16(k < NX ? av : T(0), bf[kk], acc);
+    }
+    if (li < NX) {
 #pragma unroll
-    for (int jy = 0; jy < NX; ++jy) {
-      T s = T(0);
-#pragma unroll
-      for (int ky = 0; ky < NX; ++ky) s = fma(h[ky], As[ky * NX + jy], s);
-      yr[jy * NX] = (T)(ri * csv[jy * NX + q]) * s;
+      for (int v = 0; v < 4; ++v) S[frag_row<T>(lane, v) * LDR + li * NX + b] = acc[v];
     }
   }
+  __syncthreads();
+
+  T* Y = a.Y + (long)z * a.sY;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u, r = e / N, c = e - r * N;
+    if (e < N * KW && r0 + r < N) Y[(long)r0 * N + e] = S[r * LDR + c] * (T)(rsv[r] * csv[c]);
+  }
+}
+
+// A whole wrap in one launch with the matrix resident in LDS (N <= 144 in
+// FP32, N <= 100 in FP64): Y = diag(rs2) (A1 (x) A1) diag(ks1) X diag(cs1)
+// (A2 (x) A2) diag(cs2), one workgroup of 16 waves per matrix.  The four
+// passes (kx and ky of the left product, then of the right one) run over
+// units of one block and one 16-wide tile of the other index, dealt to the
+// waves in turn, two units at a time; each unit reads and writes its own
+// elements only.  The LDS row length is 4 mod 16, so the four 16-lane groups
+// of an MFMA result (rows 4 apart) write to disjoint banks.
+template <int N>
+struct WrapLd { static constexpr int value = N + (20 - N % 16) % 16; };
+
+// one unit of a pass: D = F B (left passes: F the factor, B 16 columns of
+// 16 - padded rows) or D = B F (right passes: B 16 rows); rd(k, x) reads the
+// strip operand (k the contracted index, x the tile index of the lane), wr(m,
+// x, v) stores a result
+template <typename T, int KS, bool LEFT, typename Rd, typename Wr>
+__device__ inline void kron_units2(int u0, int u1, const T* fa, Rd rd, Wr wr) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  typename Frag<T>::type acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  T b0[KS], b1[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    b0[kk] = rd(u0, 4 * kk + lk, li);
+    if (u1 >= 0) b1[kk] = rd(u1, 4 * kk + lk, li);
+  }
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    acc0 = LEFT ? mfma16(fa[kk], b0[kk], acc0) : mfma16(b0[kk], fa[kk], acc0);
+    if (u1 >= 0) acc1 = LEFT ? mfma16(fa[kk], b1[kk], acc1) : mfma16(b1[kk], fa[kk], acc1);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    wr(u0, frag_row<T>(lane, v), li, acc0[v]);
+    if (u1 >= 0) wr(u1, frag_row<T>(lane, v), li, acc1[v]);
+  }
+}
+
+template <typename T, int NX>
+__global__ __launch_bounds__(1024) void kron_wrap_lds_kernel(KronWrapArgs<T> w) {
+  constexpr int N = NX * NX, KS = (NX + 3) / 4, LD = WrapLd<N>::value, NTL = (N + 15) / 16;
+  constexpr int UNITS = NX * NTL;
+  constexpr int PER = (N * N + 1023) / 1024;
+  __shared__ T S[N * LD];
+  __shared__ double rs[N], cs[N];
+  const int z = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const T* X = w.X + (long)z * w.sX;
+  T xin[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 1024 * u;
+    xin[u] = e < N * N ? X[e] : T(0);
+  }
+  T af[KS], bf[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    const int k = 4 * kk + lk;
+    af[kk] = (li < NX && k < NX) ? w.A1[li * NX + k] : T(0);
+    bf[kk] = (li < NX && k < NX) ? w.A2[k * NX + li] : T(0);
+  }
+  for (int i = tid; i < N; i += 1024) {
+    rs[i] = scale_value(w.ks1, z, 1, i);
+    cs[i] = scale_value(w.cs1, z, 1, i);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 1024 * u, r = e / N, c = e - r * N;
+    if (e < N * N) S[r * LD + c] = xin[u] * (T)(rs[r] * cs[c]);
+  }
+  __syncthreads();
+  for (int i = tid; i < N; i += 1024) {      // the output scales, read after the last pass
+    rs[i] = scale_value(w.rs2, z, 1, i);
+    cs[i] = scale_value(w.cs2, z, 1, i);
+  }
+
+  // unit u: block b = u / NTL, tile t = u % NTL (16 columns for the left
+  // passes, 16 rows for the right ones); out-of-range k, columns and rows
+  // read as zero from clamped addresses and are not written
+  auto blk = [](int u) { return u / NTL; };
+  auto t16 = [](int u) { return 16 * (u - (u / NTL) * NTL); };
+  // left product, pass 1: rows b nx + kx -> b nx + ix
+  for (int u = wave; u < UNITS; u += 32) {
+    const int u1 = u + 16 < UNITS ? u + 16 : -1;
+    kron_units2<T, KS, true>(u, u1, af,
+        [&](int uu, int k, int x) {
+          const int c = t16(uu) + x;
+          const T v = S[(blk(uu) * NX + min(k, NX - 1)) * LD + min(c, N - 1)];
+          return (k < NX && c < N) ? v : T(0);
+        },
+        [&](int uu, int m, int x, T v) {
+          const int c = t16(uu) + x;
+          if (m < NX && c < N) S[(blk(uu) * NX + m) * LD + c] = v;
+        });
+  }
+  __syncthreads();
+  // left product, pass 2: rows ky nx + b -> iy nx + b
+  for (int u = wave; u < UNITS; u += 32) {
+    const int u1 = u + 16 < UNITS ? u + 16 : -1;
+    kron_units2<T, KS, true>(u, u1, af,
+        [&](int uu, int k, int x) {
+          const int c = t16(uu) + x;
+          const T v = S[(min(k, NX - 1) * NX + blk(uu)) * LD + min(c, N - 1)];
+          return (k < NX && c < N) ? v : T(0);
+        },
+        [&](int uu, int m, int x, T v) {
+          const int c = t16(uu) + x;
+          if (m < NX && c < N) S[(m * NX + blk(uu)) * LD + c] = v;
+        });
+  }
+  __syncthreads();
+  // right product, pass 1: columns b nx + kx -> b nx + jx
+  for (int u = wave; u < UNITS; u += 32) {
+    const int u1 = u + 16 < UNITS ? u + 16 : -1;
+    kron_units2<T, KS, false>(u, u1, bf,
+        [&](int uu, int k, int x) {
+          const int r = t16(uu) + x;
+          const T v = S[min(r, N - 1) * LD + blk(uu) * NX + min(k, NX - 1)];
+          return (k < NX && r < N) ? v : T(0);
+        },
+        [&](int uu, int m, int x, T v) {
+          const int r = t16(uu) + m;
+          if (x < NX && r < N) S[r * LD + blk(uu) * NX + x] = v;
+        });
+  }
+  __syncthreads();
+  // right product, pass 2: columns ky nx + b -> jy nx + b
+  for (int u = wave; u < UNITS; u += 32) {
+    const int u1 = u + 16 < UNITS ? u + 16 : -1;
+    kron_units2<T, KS, false>(u, u1, bf,
+        [&](int uu, int k, int x) {
+          const int r = t16(uu) + x;
+          const T v = S[min(r, N - 1) * LD + min(k, NX - 1) * NX + blk(uu)];
+          return (k < NX && r < N) ? v : T(0);
+        },
+        [&](int uu, int m, int x, T v) {
+          const int r = t16(uu) + m;
+          if (x < NX && r < N) S[r * LD + x * NX + blk(uu)] = v;
+        });
+  }
+  __syncthreads();
+  T* Y = w.Y + (long)z * w.sY;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 1024 * u, r = e / N, c = e - r * N;
+    if (e < N * N) Y[e] = S[r * LD + c] * (T)(rs[r] * cs[c]);
+  }
+}
+
+template <typename T, int NX>
+hipError_t launch_wrap_lds_t(const KronWrapArgs<T>& w, hipStream_t s) {
+  hipLaunchKernelGGL((kron_wrap_lds_kernel<T, NX>), dim3(w.batch), dim3(1024), 0, s, w);
+  return hipGetLastError();
 }
 
 template <typename T, int NX>
 hipError_t launch_kron_t(const KronArgs<T>& a, int side, hipStream_t s) {
   constexpr int N = NX * NX;
-  const unsigned threads = (unsigned)(64 * ((NX * KW + 63) / 64));
   const dim3 grid(xcd_grid((N + KW - 1) / KW, a.batch));
   if (side == 0) {
-    const size_t lds = LeftLayout<T, NX>::bytes(a.steps);
-    hipLaunchKernelGGL((kron_left_kernel<T, NX>), grid, dim3(threads), lds, s, a);
+    const size_t lds = left_lds_bytes<T, NX>(a.steps);
+    hipLaunchKernelGGL((kron_left_kernel<T, NX>), grid, dim3(256), lds, s, a);
   } else {
-    hipLaunchKernelGGL((kron_right_kernel<T, NX>), grid, dim3(threads), 0, s, a);
+    hipLaunchKernelGGL((kron_right_kernel<T, NX>), grid, dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }
@@ -231,9 +435,38 @@ hipError_t launch_kron_any(const KronArgs<T>& a, int side, hipStream_t s) {
   }
 }
 
+template <typename T>
+hipError_t launch_wrap_lds_any(const KronWrapArgs<T>& w, hipStream_t s) {
+  if (!kron_wrap_lds_supported(w.nx, sizeof(T) == 4) || w.batch < 0 || !w.A1 || !w.A2 || !w.X || !w.Y)
+    return hipErrorInvalidValue;
+  if (w.batch == 0) return hipSuccess;
+  switch (w.nx) {
+    case 1: return launch_wrap_lds_t<T, 1>(w, s);
+    case 2: return launch_wrap_lds_t<T, 2>(w, s);
+    case 3: return launch_wrap_lds_t<T, 3>(w, s);
+    case 4: return launch_wrap_lds_t<T, 4>(w, s);
+    case 5: return launch_wrap_lds_t<T, 5>(w, s);
+    case 6: return launch_wrap_lds_t<T, 6>(w, s);
+    case 7: return launch_wrap_lds_t<T, 7>(w, s);
+    case 8: return launch_wrap_lds_t<T, 8>(w, s);
+    case 9: return launch_wrap_lds_t<T, 9>(w, s);
+    case 10: return launch_wrap_lds_t<T, 10>(w, s);
+    default:
+      if constexpr (sizeof(T) == 4) {
+        if (w.nx == 11) return launch_wrap_lds_t<T, 11>(w, s);
+        return launch_wrap_lds_t<T, 12>(w, s);
+      }
+      return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_kron(const KronArgs<double>& a, int side, hipStream_t s) { return launch_kron_any(a, side, s); }
 hipError_t launch_kron(const KronArgs<float>& a, int side, hipStream_t s) { return launch_kron_any(a, side, s); }
+
+bool kron_wrap_lds_supported(int nx, bool fp32) { return nx >= 1 && nx <= (fp32 ? 12 : 10); }
+hipError_t launch_kron_wrap_lds(const KronWrapArgs<double>& w, hipStream_t s) { return launch_wrap_lds_any(w, s); }
+hipError_t launch_kron_wrap_lds(const KronWrapArgs<float>& w, hipStream_t s) { return launch_wrap_lds_any(w, s); }
 
 }  // namespace hq

@@ -70,8 +70,9 @@ class Tuning(ctypes.Structure):
 
 N_GEMM_TILES = 11
 # forms of a wrap (HQ_WRAP_*): two tiled dense products, both in one launch,
-# or the Kronecker passes of exp(-+dtau K) = E1 (x) E1
-WRAP_KINDS = ("two", "fused", "kron")
+# the Kronecker passes of exp(-+dtau K) = E1 (x) E1 in two launches, or in
+# one launch with G held in LDS
+WRAP_KINDS = ("two", "fused", "kron", "kron_lds")
 
 def tile_name(code):
     """Name of a GEMM tile code ("?" for an unknown one)."""

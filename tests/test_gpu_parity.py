@@ -319,6 +319,31 @@ def test_kron_wrap_mixed(hq, nx):
                        setup=lambda ctx: ctx.set_tuning(0, 0, 0, wrap="kron"))
 
 
+@pytest.mark.parametrize("nx", [2, 3, 7, 10])
+def test_kron_lds_wrap_fp64(hq, nx):
+    """The four Kronecker passes in one launch with G in LDS (ragged 16-wide
+    tiles for N = 4, 9, 49, 100); L = 9 with n_stab = 3 leaves G in the other
+    buffer at stabilisation points and at the end of the sweep."""
+    say("FP64 LDS Kronecker wrap nx=%d" % nx)
+    gr = dict(nx=nx, chains=2, g=1.2, beta=0.9, n_stab=3)
+    ctx = make_ctx(hq, [gr], seed=20)
+    ctx.set_tuning(0, 0, 0, wrap="kron_lds")
+    assert ctx.tuning(0)["wrap"] == "kron_lds"
+    ctx.sweep(2)
+    for c in range(2):
+        ch = dqmc.Chain(params_of(gr), 20, c)
+        ch.sweep(); ch.sweep()
+        assert_state(ctx, c, ch, TOL64, "kron_lds wrap nx=%d chain %d" % (nx, c))
+    ctx.close()
+
+
+@pytest.mark.parametrize("nx", [5, 11, 12])
+def test_kron_lds_wrap_mixed(hq, nx):
+    say("mixed LDS Kronecker wrap nx=%d" % nx)
+    _mixed_replay_case(hq, dict(nx=nx, chains=1, g=1.3, beta=0.9, n_stab=3), (0,), seed=21, sweeps=2,
+                       setup=lambda ctx: ctx.set_tuning(0, 0, 0, wrap="kron_lds"))
+
+
 def test_set_tuning_rejects_bad_tiles(hq):
     say("set_tuning errors")
     ctx = make_ctx(hq, [dict(nx=16, chains=1, beta=0.4, n_stab=2)])
@@ -332,7 +357,9 @@ def test_set_tuning_rejects_bad_tiles(hq):
         ctx.set_tuning(1, 0)
     with pytest.raises(hq.HQError):
         ctx.set_tuning(0, 0, 0, wrap="fused")   # N = 256: no fused wrap
-    assert ctx._lib.hq_set_tuning(ctx._ctx, 0, 0, 0, 3) != 0   # no such wrap kind
+    with pytest.raises(hq.HQError):
+        ctx.set_tuning(0, 0, 0, wrap="kron_lds")   # N = 256: G does not fit in LDS
+    assert ctx._lib.hq_set_tuning(ctx._ctx, 0, 0, 0, 4) != 0   # no such wrap kind
     ctx.sweep(1)
     assert ctx.stats(0)["local_proposals"] == 256 * 4
     ctx.close()
