@@ -208,15 +208,16 @@ def local_roofline(w, res):
 
 
 def sweep_roofline(w, res):
-    """The whole sweep against the MFMA peaks: the dense operation counts of
-    the scheme as built, per sweep of all chains (N = sites, L = slices,
-    n_s = recompute interval, 2N^3 per product):
-      wraps           4 N^3 L                        (FP32 in mixed precision)
+    """The whole sweep against the MFMA peaks: the operation counts of the
+    scheme as built, per sweep of all chains (N = nx^2 sites, L = slices, n_s =
+    recompute interval, 2N^3 per dense product; a product with
+    exp(dtau K) = E1 (x) E1 is two passes of nx-term sums, 4 nx N^2):
+      wraps           8 nx N^2 L                     (FP32 in mixed precision)
       local updates   2 N^2 per accepted move        (FP32 in mixed precision)
-      stabilisation   per point: (n_s - 1) block-product steps 2N^3 each, a
-                      combine (product 2N^3, QR with explicit Q (8/3)N^3,
+      stabilisation   per point: (n_s - 1) block-product steps 4 nx N^2 each,
+                      a combine (product 2N^3, QR with explicit Q (8/3)N^3,
                       triangular product 2N^3) and a merge (four products
-                      8N^3, Gauss-Jordan 2N^3): 2 N^3 n_s + (44/3) N^3
+                      8N^3, Gauss-Jordan 2N^3): 4 nx N^2 (n_s - 1) + (50/3) N^3
       block moves     per proposal: all block products, L/n_s combines and a
                       merge from scratch
     T_roof = F32 / P32 + F64 / P64; frac = T_roof / measured time."""
@@ -224,16 +225,16 @@ def sweep_roofline(w, res):
     for g in w.groups:
         if g.proposal:
             return None
-        n = g.nx * g.nx
+        nx, n = g.nx, g.nx * g.nx
         L = round(g.beta / g.dtau)
         ns = g.n_stab
-        n3 = float(n) ** 3
-        wraps = 4.0 * n3 * L
-        upd = 2.0 * n * n * res["local_acceptance"] * n * L
-        stab = (L / ns) * (2.0 * n3 * ns + 44.0 / 3.0 * n3)
+        n2, n3 = float(n) ** 2, float(n) ** 3
+        wraps = 8.0 * nx * n2 * L
+        upd = 2.0 * n2 * res["local_acceptance"] * n * L
+        stab = (L / ns) * (4.0 * nx * n2 * (ns - 1) + 50.0 / 3.0 * n3)
         glob = 0.0
         if g.global_width > 0:
-            glob = n * (2.0 * n3 * (ns - 1) * (L / ns) + (L / ns) * (4.0 + 8.0 / 3.0) * n3 + 10.0 * n3)
+            glob = n * (4.0 * nx * n2 * (ns - 1) * (L / ns) + (L / ns) * (4.0 + 8.0 / 3.0) * n3 + 10.0 * n3)
         if w.precision:
             f32 += g.n_chains * (wraps + upd)
             f64 += g.n_chains * (stab + glob)

@@ -361,11 +361,10 @@ __device__ inline void walk_strips(int npw, int base, int cnt, int blk, const T*
         const int i = base + q;
         const T coef = (T)delta * recip((T)r);
         // G[i, S] and G[S, i] as wave-uniform values.  Site k reads only
-        // column and row k of the strips, so once the first half of the
-        // block is walked its columns are no longer updated (the loop bounds
-        // stay fixed per half, which keeps the register allocation compact).
+        // column and row k of the strips, so the columns of the sites
+        // already walked are no longer updated: the update runs over k >= q.
         T nb[K], ci[K];
-        const int k0 = (q < K / 2) ? 0 : K / 2;
+        const int k0 = q;                  // a compile-time bound once q is unrolled
 #pragma unroll
         for (int k = k0; k < K; ++k) {
           nb[k] = ((k == q) ? T(1) : T(0)) - bcast(rq, l0 + k);
