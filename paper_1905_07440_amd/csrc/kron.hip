@@ -9,7 +9,8 @@
 // index i = ix + nx iy, (E1 (x) E1)[i][k] = E1[iy][ky] E1[ix][kx], and a
 // product with it is two passes of nx-term sums per element: 4 nx n^2 flops
 // in place of the 2 n^3 of a dense product (6x fewer on 12 x 12, 8x on
-// 16 x 16).  Bandwidth, not arithmetic, bounds these kernels.
+// 16 x 16).  At the sweep's sizes a launch is bound by the latency of one
+// workgroup's load, passes and store rather than by HBM or the matrix cores.
 //
 // Each pass of nx-term sums is a set of small products on the matrix cores:
 // for a block b of nx rows (or the nx rows b, nx + b, ...), the 16 x 16
