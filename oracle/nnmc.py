@@ -1,5 +1,5 @@
-"""Network-proposed local moves and the cumulative update (paper: Local
-Updates; the p_c equation after Global Updates).
+"""Network-proposed local and block moves and the cumulative update (paper:
+Local Updates; Global Updates and the p_c equation after it).
 
 The fully connected network sees the proposed displacement and the fields
 around the spacetime point (i, l): nearest and next-nearest neighbours in
@@ -21,8 +21,27 @@ classes (l mod 4, iy mod 2, ix mod 2), class after class; two points of one
 class are never inside each other's patch (needs Nx even and L % 4 == 0), so
 the moves of a class do not interact and their order within it is immaterial.
 
-Parity: the forward pass is pinned against torch.nn.functional on the same
-weights, the p_c algebra against log W from scratch
+Block moves (paper: Global Updates, and the caption of its network figure).
+A move shifts the whole column x[:, i] by D.  The convolutional network sees
+three channels over the L slices of site i: the column itself and the means
+of the four nearest and of the four diagonal next-nearest neighbours'
+columns.  The paper fixes four layers, sigmoid hidden units and a linear
+output, and leaves the first layer's stride and kernel open; here a circular
+convolution along imaginary time (periodic in l) with 4 output channels,
+kernel 4 and stride 2 (first hidden layer 4 x L/2 units), a dense layer of 32
+units and the output.  Reading of how the move enters: the network is taken
+as a site-local effective energy of the column, so its estimate of the
+fermionic change of log W is y = f(x_i + D) - f(x_i) with the neighbour
+channels unchanged.  Sites are visited by colour classes (iy mod 2, ix mod 2):
+a site's inputs come from its 3 x 3 neighbourhood, which holds no other site
+of its class.
+
+A full sweep: n_u sweeps of network local moves, then n_u sweeps of network
+block moves (if the block width is > 0), then one cumulative accept with the
+sum of every accepted y.
+
+Parity: both forward passes are pinned against torch.nn.functional on the
+same weights, the p_c algebra against log W from scratch
 (tests/test_oracle_nn.py).
 """
 import math
@@ -30,11 +49,80 @@ import math
 import numpy as np
 
 from . import philox
-from .model import local_action_change
+from .model import global_action_change, local_action_change
 from .udt import green_and_logdet
 
 N_IN, N_HID = 45, 64
 N_WEIGHTS = N_HID * N_IN + N_HID + N_HID * N_HID + N_HID + N_HID + 1   # 7169
+
+CNN_C, CNN_K, CNN_S, CNN_H = 4, 4, 2, 32     # conv channels, kernel, stride; dense units
+
+
+def cnn_count(L):
+    """Weights of the block-move network for L slices: 64 L + 117."""
+    if L % CNN_S:
+        raise ValueError("the block-move network needs L divisible by %d" % CNN_S)
+    P = L // CNN_S
+    return CNN_C * 3 * CNN_K + CNN_C + CNN_H * CNN_C * P + CNN_H + CNN_H + 1
+
+
+def unpack_cnn(w, L):
+    """Flat FP32 weights -> (Wc[C,3,K], bc[C], Wd[H, C*P], bd[H], Wo[H], bo) as float64.
+    The dense layer reads the conv output flattened channel-major, index c * P + p."""
+    w = np.asarray(w, dtype=np.float32).astype(np.float64)
+    if w.size != cnn_count(L):
+        raise ValueError("expected %d weights" % cnn_count(L))
+    P = L // CNN_S
+    o = 0
+    Wc = w[o:o + CNN_C * 3 * CNN_K].reshape(CNN_C, 3, CNN_K); o += CNN_C * 3 * CNN_K
+    bc = w[o:o + CNN_C]; o += CNN_C
+    Wd = w[o:o + CNN_H * CNN_C * P].reshape(CNN_H, CNN_C * P); o += CNN_H * CNN_C * P
+    bd = w[o:o + CNN_H]; o += CNN_H
+    Wo = w[o:o + CNN_H]; o += CNN_H
+    bo = w[o]
+    return Wc, bc, Wd, bd, Wo, bo
+
+
+def sigmoid(h):
+    return 1.0 / (1.0 + np.exp(-h))
+
+
+def cnn_forward(weights, inp):
+    """Block-move network on inputs inp[3, L]: circular convolution along l
+    (output position p reads slices S p .. S p + K - 1 mod L), sigmoid, dense
+    sigmoid layer, linear output."""
+    Wc, bc, Wd, bd, Wo, bo = weights
+    L = inp.shape[1]
+    P = L // CNN_S
+    conv = np.empty((CNN_C, P))
+    for c in range(CNN_C):
+        for p in range(P):
+            s = bc[c]
+            for ch in range(3):
+                for k in range(CNN_K):
+                    s += Wc[c, ch, k] * inp[ch, (CNN_S * p + k) % L]
+            conv[c, p] = s
+    h1 = sigmoid(conv).reshape(-1)
+    h2 = sigmoid(Wd @ h1 + bd)
+    return float(Wo @ h2 + bo)
+
+
+def cnn_inputs(nx, x, i):
+    """The three input channels of site i: x[:, i], the mean over its four
+    nearest neighbours and over its four diagonal next-nearest neighbours."""
+    ix, iy = i % nx, i // nx
+    site = lambda dx, dy: (ix + dx) % nx + nx * ((iy + dy) % nx)
+    nn = [site(1, 0), site(-1, 0), site(0, 1), site(0, -1)]
+    nnn = [site(1, 1), site(1, -1), site(-1, 1), site(-1, -1)]
+    return np.stack([x[:, i], x[:, nn].mean(axis=1), x[:, nnn].mean(axis=1)])
+
+
+def cnn_colour_order(nx):
+    """Sites in visiting order: classes (iy mod 2, ix mod 2), then iy, ix."""
+    if nx % 2:
+        raise ValueError("network block moves need even Nx")
+    return [ix + nx * iy for py in range(2) for px in range(2)
+            for iy in range(py, nx, 2) for ix in range(px, nx, 2)]
 
 
 def unpack(w):
@@ -96,14 +184,20 @@ def colour_order(nx, L):
 
 
 class NNChain:
-    """A chain driven by network proposals and exact cumulative accepts."""
+    """A chain driven by network proposals and exact cumulative accepts.
+    cnn: flat block-move network weights (used when the chain's block width
+    is > 0); nu: sweeps of each kind per cumulative accept."""
 
-    def __init__(self, chain, weights_flat, kind=0):
+    def __init__(self, chain, weights_flat, kind=0, cnn=None, nu=1):
         self.c = chain                   # a dqmc.Chain: params, fields, G, log det, seed
         self.weights = unpack(weights_flat)
         self.kind = kind
+        self.nu = nu
+        self.cnn = unpack_cnn(cnn, chain.p.L) if cnn is not None else None
         self.inner_accepts = 0
         self.inner_proposals = 0
+        self.block_accepts = 0
+        self.block_proposals = 0
         self.cumulative_accepts = 0
         self.last_log_pc = 0.0
         self.last_sum_y = 0.0
@@ -114,20 +208,42 @@ class NNChain:
         L, n = p.L, p.n
         xp = c.x.copy()
         sum_y = 0.0
-        for l, i in colour_order(p.nx, L):
-            u0, u1 = philox.uniforms(c.seed, c.chain, c.sweep_index, l * n + i, philox.KIND_NN)
-            d = p.local_width * (2.0 * u0 - 1.0)
-            y = forward(self.weights, patch(p.nx, xp, l, i, d), self.kind)
-            ds = local_action_change(p, xp[l, i], xp[(l - 1) % L, i], xp[(l + 1) % L, i], d)
-            R = math.exp(min(y - ds, 700.0))
-            accept = u1 < R
-            self.decisions.append((philox.KIND_NN, c.sweep_index, l * n + i, accept,
-                                   math.log(u1) - (y - ds) if u1 > 0 else -math.inf))
-            self.inner_proposals += 1
-            if accept:
-                xp[l, i] += d
-                sum_y += y
-                self.inner_accepts += 1
+        for u in range(self.nu):
+            for l, i in colour_order(p.nx, L):
+                slot = u * L * n + l * n + i
+                u0, u1 = philox.uniforms(c.seed, c.chain, c.sweep_index, slot, philox.KIND_NN)
+                d = p.local_width * (2.0 * u0 - 1.0)
+                y = forward(self.weights, patch(p.nx, xp, l, i, d), self.kind)
+                ds = local_action_change(p, xp[l, i], xp[(l - 1) % L, i], xp[(l + 1) % L, i], d)
+                R = math.exp(min(y - ds, 700.0))
+                accept = u1 < R
+                self.decisions.append((philox.KIND_NN, c.sweep_index, slot, accept,
+                                       math.log(u1) - (y - ds) if u1 > 0 else -math.inf))
+                self.inner_proposals += 1
+                if accept:
+                    xp[l, i] += d
+                    sum_y += y
+                    self.inner_accepts += 1
+        if self.cnn is not None and p.global_width > 0:
+            for u in range(self.nu):
+                for i in cnn_colour_order(p.nx):
+                    slot = u * n + i
+                    u0, u1 = philox.uniforms(c.seed, c.chain, c.sweep_index, slot, philox.KIND_NN_GLOBAL)
+                    d = p.global_width * (2.0 * u0 - 1.0)
+                    inp = cnn_inputs(p.nx, xp, i)
+                    moved = inp.copy()
+                    moved[0] += d
+                    y = cnn_forward(self.cnn, moved) - cnn_forward(self.cnn, inp)
+                    ds = global_action_change(p, float(np.sum(xp[:, i])), d, L)
+                    R = math.exp(min(y - ds, 700.0))
+                    accept = u1 < R
+                    self.decisions.append((philox.KIND_NN_GLOBAL, c.sweep_index, slot, accept,
+                                           math.log(u1) - (y - ds) if u1 > 0 else -math.inf))
+                    self.block_proposals += 1
+                    if accept:
+                        xp[:, i] += d
+                        sum_y += y
+                        self.block_accepts += 1
         g_new, ld_new = green_and_logdet(p, c.expk, xp, 0)
         log_pc = 2.0 * (ld_new - c.logdet) - sum_y
         uc, _ = philox.uniforms(c.seed, c.chain, c.sweep_index, 0, philox.KIND_CUMULATIVE)

@@ -7,6 +7,7 @@ import math
 import numpy as np
 import pytest
 import torch
+import torch.nn.functional as F
 
 from oracle import dqmc, model, nnmc
 from oracle.model import Params
@@ -97,3 +98,98 @@ def test_cumulative_ratio_is_exact_weight_ratio_minus_network_path():
     else:
         assert np.array_equal(ch.x, x0)
     assert math.isfinite(nn.last_log_pc)
+
+
+def random_cnn(seed, L, scale=0.2):
+    return (scale * np.random.default_rng(seed).standard_normal(nnmc.cnn_count(L))).astype(np.float32)
+
+
+@pytest.mark.parametrize("L", [8, 20])
+def test_cnn_forward_matches_torch(L):
+    """The block-move network against torch.nn.functional: circular padding
+    on the right by K - 1, conv1d with stride S, sigmoid, channel-major
+    flatten, linear + sigmoid, linear."""
+    w = random_cnn(11, L)
+    Wc, bc, Wd, bd, Wo, bo = nnmc.unpack_cnn(w, L)
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        inp = rng.standard_normal((3, L))
+        t = torch.tensor(inp, dtype=torch.float64)[None]
+        t = torch.cat([t, t[:, :, :nnmc.CNN_K - 1]], dim=2)
+        h = torch.sigmoid(F.conv1d(t, torch.tensor(Wc), torch.tensor(bc), stride=nnmc.CNN_S))
+        h = torch.sigmoid(F.linear(h.reshape(-1), torch.tensor(Wd), torch.tensor(bd)))
+        ref = float(F.linear(h, torch.tensor(Wo)[None], torch.tensor([bo]))[0])
+        assert abs(nnmc.cnn_forward((Wc, bc, Wd, bd, Wo, bo), inp) - ref) < 1e-12
+
+
+def test_cnn_weight_count():
+    assert nnmc.cnn_count(80) == 64 * 80 + 117
+    with pytest.raises(ValueError):
+        nnmc.cnn_count(9)
+
+
+def test_cnn_inputs_are_c4_symmetric():
+    """Rotating the lattice by 90 degrees about site i leaves its three input
+    channels unchanged (the neighbour means are what gives the network C4
+    symmetry); the channels are the column and the hand-summed means."""
+    nx, L = 6, 4
+    x = np.random.default_rng(9).standard_normal((L, nx * nx))
+    i = 2 + nx * 3
+    ix, iy = i % nx, i // nx
+    rot = np.empty_like(x)
+    for jy in range(nx):
+        for jx in range(nx):
+            dx, dy = jx - ix, jy - iy
+            kx, ky = (ix - dy) % nx, (iy + dx) % nx       # (dx, dy) -> (-dy, dx)
+            rot[:, kx + nx * ky] = x[:, jx + nx * jy]
+    assert np.allclose(nnmc.cnn_inputs(nx, x, i), nnmc.cnn_inputs(nx, rot, i), atol=1e-14)
+    inp = nnmc.cnn_inputs(nx, x, i)
+    s = lambda dx, dy: x[:, (ix + dx) % nx + nx * ((iy + dy) % nx)]
+    assert np.allclose(inp[0], x[:, i])
+    assert np.allclose(inp[1], (s(1, 0) + s(-1, 0) + s(0, 1) + s(0, -1)) / 4)
+    assert np.allclose(inp[2], (s(1, 1) + s(1, -1) + s(-1, 1) + s(-1, -1)) / 4)
+
+
+def test_cnn_colour_classes_do_not_interact():
+    nx = 6
+    order = nnmc.cnn_colour_order(nx)
+    assert sorted(order) == list(range(nx * nx))
+    per = nx * nx // 4
+    for k in range(4):
+        cls = order[k * per:(k + 1) * per]
+        for a in cls:
+            for b in cls:
+                if a == b:
+                    continue
+                dx = min((a % nx - b % nx) % nx, (b % nx - a % nx) % nx)
+                dy = min((a // nx - b // nx) % nx, (b // nx - a // nx) % nx)
+                assert max(dx, dy) >= 2, (a, b)
+    with pytest.raises(ValueError):
+        nnmc.cnn_colour_order(5)
+
+
+def test_cumulative_ratio_with_block_moves_and_two_inner_sweeps():
+    """With network block moves and n_u = 2 the sweep's proposal X' follows
+    from the recorded decisions, and log p_c + sum y = 2 dlogdet =
+    (log W(X') - log W(X)) + dS_b."""
+    from oracle import philox
+    p = Params(nx=4, beta=0.8, g=1.2, n_stab=4, local_width=0.5, global_width=0.4)
+    ch = dqmc.Chain(p, seed=7, chain=1)
+    nn = nnmc.NNChain(ch, random_weights(3), cnn=random_cnn(5, p.L), nu=2)
+    x0 = ch.x.copy()
+    lw0 = ch.log_weight()
+    nn.sweep()
+    assert nn.inner_proposals == 2 * p.L * p.n and nn.block_proposals == 2 * p.n
+    xp = x0.copy()
+    for kind, sw, slot, acc, _ in nn.decisions:
+        if kind == philox.KIND_NN and acc:
+            u0, _ = philox.uniforms(7, 1, 0, slot, philox.KIND_NN)
+            r = slot % (p.L * p.n)
+            xp[r // p.n, r % p.n] += p.local_width * (2 * u0 - 1)
+        if kind == philox.KIND_NN_GLOBAL and acc:
+            u0, _ = philox.uniforms(7, 1, 0, slot, philox.KIND_NN_GLOBAL)
+            xp[:, slot % p.n] += p.global_width * (2 * u0 - 1)
+    lw1 = ch.log_weight(xp)
+    dsb = model.bosonic_action(p, xp) - model.bosonic_action(p, x0)
+    assert abs((nn.last_log_pc + nn.last_sum_y) - (lw1 - lw0 + dsb)) < 1e-9
+    assert np.array_equal(ch.x, xp if nn.cumulative_accepts else x0)
