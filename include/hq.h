@@ -64,7 +64,7 @@ typedef enum {
 enum { HQ_PREC_FP64 = 0, HQ_PREC_MIXED = 1 };
 enum { HQ_PROPOSAL_DQMC = 0, HQ_PROPOSAL_NETWORK = 1 };
 /* decision kinds; equal to word 3 of the Philox counter of the draw */
-enum { HQ_KIND_LOCAL = 0, HQ_KIND_GLOBAL = 1, HQ_KIND_NN = 3, HQ_KIND_CUMULATIVE = 4 };
+enum { HQ_KIND_LOCAL = 0, HQ_KIND_GLOBAL = 1, HQ_KIND_NN = 3, HQ_KIND_CUMULATIVE = 4, HQ_KIND_NN_GLOBAL = 6 };
 
 /* One group of chains sharing a lattice and model parameters.  Chains are
  * numbered consecutively over the groups in the order given. */
@@ -79,7 +79,11 @@ typedef struct {
   int32_t n_stab;        /* FP64 recompute every n_stab slices; must divide L */
   int32_t proposal;      /* HQ_PROPOSAL_DQMC or HQ_PROPOSAL_NETWORK */
   double local_width;    /* local move d ~ U(-w, w) */
-  double global_width;   /* 0: no block moves; else one per site per sweep, d ~ U(-w, w) */
+  double global_width;   /* 0: no block moves; else one per site per sweep, d ~ U(-w, w).
+                            Network groups: block moves proposed by the convolutional
+                            network (hq_set_block_network), d ~ U(-w, w) */
+  int32_t nn_sweeps;     /* network groups: n_u sweeps of network local moves, then n_u of
+                            network block moves, per cumulative accept (0 means 1) */
 } hq_group;
 
 typedef struct {
@@ -126,6 +130,19 @@ hq_status hq_set_fields(hq_ctx* ctx, int32_t chain, const double* x_host, int64_
  * W2[64][64], b2[64], W3[64], b3) used by HQ_PROPOSAL_NETWORK groups. */
 hq_status hq_set_network(hq_ctx* ctx, const float* weights, int64_t n);
 
+/* Load the convolutional network of network block moves (paper: "Global
+ * Updates" and the caption of its network figure), for groups with L slices:
+ * n = 64 L + 117 FP32 values Wc[4][3][4], bc[4], Wd[32][2 L], bd[32], Wo[32],
+ * bo.  Input of a move at site i: three channels over l (x[l][i] and the
+ * means of the four nearest and the four diagonal next-nearest neighbours);
+ * a circular convolution along l (output p reads slices 2p .. 2p+3 mod L),
+ * sigmoid; a dense layer of 32 sigmoid units over the conv output flattened
+ * as c*(L/2) + p; a linear output f.  The estimate of a move's fermionic
+ * change of log W is f(x_i + d) - f(x_i).  HQ_EINVAL for odd L or a count
+ * that is not 64 L + 117; a network group with global_width > 0 must have
+ * this L. */
+hq_status hq_set_block_network(hq_ctx* ctx, const float* weights, int64_t n, int32_t L);
+
 /* Run n_sweeps full sweeps of every chain (asynchronous on the stream). */
 hq_status hq_sweep(hq_ctx* ctx, int32_t n_sweeps);
 
@@ -139,8 +156,9 @@ hq_status hq_read_green(hq_ctx* ctx, int32_t chain, double* out, int64_t n);
 hq_status hq_read_fields(hq_ctx* ctx, int32_t chain, double* out, int64_t n);
 hq_status hq_read_stats(hq_ctx* ctx, int32_t chain, hq_stats* out);
 
-/* Decisions of the last sweep for one chain and kind, in slot order (local
- * and network: l*N + i; block: i; cumulative: 0).  accept[k] is 0/1;
+/* Decisions of the last sweep for one chain and kind, in slot order (local:
+ * l*N + i; network local moves: u*L*N + l*N + i and network block moves:
+ * u*N + i for inner sweep u < n_u; block: i; cumulative: 0).  accept[k] is 0/1;
  * margin[k] = ln u - ln R (FP32).  Needs options.record = 1. */
 hq_status hq_read_decisions(hq_ctx* ctx, int32_t chain, int32_t kind,
                             uint8_t* accept, float* margin, int64_t n);

@@ -29,7 +29,8 @@ using namespace hq;
 
 namespace {
 
-const int N_KIND_SLOTS = 5;   // indexed by HQ_KIND_* (0, 1, 3, 4 used)
+const int N_KIND_SLOTS = 7;   // indexed by HQ_KIND_* (0, 1, 3, 4, 6 used)
+const int KINDS[] = {HQ_KIND_LOCAL, HQ_KIND_GLOBAL, HQ_KIND_NN, HQ_KIND_CUMULATIVE, HQ_KIND_NN_GLOBAL};
 
 // a wrap G <- B G B^-1 as two tiled dense products, as one fused launch of
 // both dense products, as two Kronecker launches (left, then right), or as
@@ -84,8 +85,16 @@ struct Group {
   double band[N_KIND_SLOTS] = {};
   double* sum_y = nullptr;
   uint8_t* nn_acc = nullptr;
+  // network block moves (network groups with global_width > 0): n_u inner
+  // sweeps of each kind per cumulative accept
+  int nu = 1;
+  bool cnn = false;
+  double* sum_yb = nullptr;      // [C][n]
+  uint8_t* acc_b = nullptr;      // [C][n]
   long kind_slots(int kind) const {
-    if (kind == HQ_KIND_LOCAL || kind == HQ_KIND_NN) return (long)L * n;
+    if (kind == HQ_KIND_LOCAL) return (long)L * n;
+    if (kind == HQ_KIND_NN) return (long)nu * L * n;
+    if (kind == HQ_KIND_NN_GLOBAL) return (long)nu * n;
     if (kind == HQ_KIND_GLOBAL) return n;
     return 1;
   }
@@ -117,6 +126,9 @@ struct hq_ctx {
   int64_t* sweep_counter = nullptr;
   float* net = nullptr;
   bool net_loaded = false;
+  float* cnn = nullptr;          // block-move network weights, 64 L + 117 floats
+  int cnn_max_L = 0;             // room for the largest L of a group with block-move networks
+  int cnn_L = 0;                 // L the loaded weights are for (0: none)
   int n_chains = 0;
   bool broken = false;
   std::string err;
@@ -177,6 +189,14 @@ bool valid_group(const hq_group& p, const hq_options& o, std::string& why) {
   if (p.proposal != HQ_PROPOSAL_DQMC && p.proposal != HQ_PROPOSAL_NETWORK) { why = "bad proposal"; return false; }
   if (p.proposal == HQ_PROPOSAL_NETWORK && (p.nx % 2 || L % 4)) {
     why = "network proposals need even nx and L divisible by 4";
+    return false;
+  }
+  if (p.proposal == HQ_PROPOSAL_NETWORK && (p.nn_sweeps < 0 || p.nn_sweeps > 64)) {
+    why = "nn_sweeps must be 0 .. 64";
+    return false;
+  }
+  if (p.proposal == HQ_PROPOSAL_NETWORK && p.global_width > 0.0 && cnn_lds_bytes(L) > 65536) {
+    why = "network block moves need 64 L + 117 weights within 64 KB (L <= 254)";
     return false;
   }
   const int n = p.nx * p.nx;
@@ -255,7 +275,7 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
     g.lastpc = cv.take<double>(C * 2);
     g.flags = cv.take<int>(C);
     g.replay_counts = cv.take<int64_t>(C * 2);
-    for (int k : {HQ_KIND_LOCAL, HQ_KIND_GLOBAL, HQ_KIND_NN, HQ_KIND_CUMULATIVE}) {
+    for (int k : KINDS) {
       const long slots = C * g.kind_slots(k);
       g.replay[k] = cv.take<uint8_t>(slots);
       if (o.record) {
@@ -266,6 +286,10 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
     if (g.network) {
       g.sum_y = cv.take<double>(C * L * n);
       g.nn_acc = cv.take<uint8_t>(C * L * n);
+      if (g.cnn) {
+        g.sum_yb = cv.take<double>(C * n);
+        g.acc_b = cv.take<uint8_t>(C * n);
+      }
     }
     g.tree = (g.global || g.network) && nb > 1;
     if (g.tree) {
@@ -282,12 +306,18 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
       g.tQT = cv.take<double>(C * nb * (long)qr_t_doubles(g.n));
     }
   }
+  int cnn_L = 0;
+  for (const Group& g : gs)
+    if (g.cnn) cnn_L = std::max(cnn_L, g.L);
   if (ctx) {
     ctx->sweep_counter = cv.take<int64_t>(1);
     ctx->net = cv.take<float>(7169 + 7);
+    ctx->cnn_max_L = cnn_L;
+    if (cnn_L) ctx->cnn = cv.take<float>(64L * cnn_L + 117);
   } else {
     cv.take<int64_t>(1);
     cv.take<float>(7169 + 7);
+    if (cnn_L) cv.take<float>(64L * cnn_L + 117);
   }
   return cv.off + 256;
 }
@@ -308,6 +338,8 @@ bool build_groups(const hq_group* gp, int ng, const hq_options& o, std::vector<G
     g.chain0 = chain0;
     g.global = gp[k].global_width > 0.0 && gp[k].proposal == HQ_PROPOSAL_DQMC;
     g.network = gp[k].proposal == HQ_PROPOSAL_NETWORK;
+    g.cnn = g.network && gp[k].global_width > 0.0;
+    g.nu = g.network ? std::max(1, (int)gp[k].nn_sweeps) : 1;
     g.alternate = !g.global && !g.network;
     g.nt = g.n <= 64 ? 64 : 256;
     g.kd = o.delay ? o.delay : 16;
@@ -862,17 +894,40 @@ hq_status network_sweep(Sched& S, Group& g) {
   hq_ctx* ctx = S.ctx;
   const long ln = (long)g.L * g.n;
   SCHED_TRY(launch_copy_f64(g.xp, g.x, (long)g.C * ln, S.s));
-  for (int colour = 0; colour < 16; ++colour) {
-    NetArgs a;
-    a.nx = g.nx; a.n = g.n; a.L = g.L; a.colour = colour;
-    a.xp = g.xp; a.g = g.g;
-    a.dtau = g.p.dtau; a.mass = g.p.mass; a.omega = g.p.omega; a.width = g.p.local_width;
-    a.seed = ctx->seed; a.chain0 = g.chain0; a.sweep = ctx->sweep_counter;
-    a.w = ctx->net; a.activation = ctx->opt.activation; a.chains = g.C;
-    a.sum_y = g.sum_y; a.accepted = g.nn_acc; a.counters = g.counters;
-    a.log_margin = g.log_margin[HQ_KIND_NN]; a.log_accept = g.log_accept[HQ_KIND_NN];
-    a.replay = g.replay[HQ_KIND_NN]; a.band = g.band[HQ_KIND_NN]; a.replay_counts = g.replay_counts;
-    SCHED_TRY(launch_network_colour(a, g.C, S.s));
+  SCHED_TRY(launch_fill_f64(g.sum_y, 0.0, (long)g.C * ln, S.s));
+  SCHED_TRY(launch_fill_u8(g.nn_acc, 0, (long)g.C * ln, S.s));
+  for (int u = 0; u < g.nu; ++u)
+    for (int colour = 0; colour < 16; ++colour) {
+      NetArgs a;
+      a.nx = g.nx; a.n = g.n; a.L = g.L; a.colour = colour;
+      a.inner = u; a.nu = g.nu;
+      a.xp = g.xp; a.g = g.g;
+      a.dtau = g.p.dtau; a.mass = g.p.mass; a.omega = g.p.omega; a.width = g.p.local_width;
+      a.seed = ctx->seed; a.chain0 = g.chain0; a.sweep = ctx->sweep_counter;
+      a.w = ctx->net; a.activation = ctx->opt.activation; a.chains = g.C;
+      a.sum_y = g.sum_y; a.accepted = g.nn_acc; a.counters = g.counters;
+      a.log_margin = g.log_margin[HQ_KIND_NN]; a.log_accept = g.log_accept[HQ_KIND_NN];
+      a.replay = g.replay[HQ_KIND_NN]; a.band = g.band[HQ_KIND_NN]; a.replay_counts = g.replay_counts;
+      SCHED_TRY(launch_network_colour(a, g.C, S.s));
+    }
+  if (g.cnn) {
+    SCHED_TRY(launch_fill_f64(g.sum_yb, 0.0, (long)g.C * g.n, S.s));
+    SCHED_TRY(launch_fill_u8(g.acc_b, 0, (long)g.C * g.n, S.s));
+    for (int u = 0; u < g.nu; ++u)
+      for (int colour = 0; colour < 4; ++colour) {
+        CnnArgs a;
+        a.nx = g.nx; a.n = g.n; a.L = g.L; a.colour = colour;
+        a.inner = u; a.nu = g.nu;
+        a.xp = g.xp; a.g = g.g;
+        a.dtau = g.p.dtau; a.mass = g.p.mass; a.omega = g.p.omega; a.width = g.p.global_width;
+        a.seed = ctx->seed; a.chain0 = g.chain0; a.sweep = ctx->sweep_counter;
+        a.w = ctx->cnn; a.chains = g.C;
+        a.sum_y = g.sum_yb; a.accepted = g.acc_b;
+        a.log_margin = g.log_margin[HQ_KIND_NN_GLOBAL]; a.log_accept = g.log_accept[HQ_KIND_NN_GLOBAL];
+        a.replay = g.replay[HQ_KIND_NN_GLOBAL]; a.band = g.band[HQ_KIND_NN_GLOBAL];
+        a.replay_counts = g.replay_counts;
+        SCHED_TRY(launch_cnn_colour(a, g.C, S.s));
+      }
   }
   ST_TRY(from_scratch(S, g, g.xp, g.blkp));
   CumulativeArgs c;
@@ -880,6 +935,7 @@ hq_status network_sweep(Sched& S, Group& g) {
   c.x = g.x; c.xp = g.xp; c.logdet = g.logdet; c.logdet_new = g.logdet_new;
   c.G = g.G; c.precision = ctx->opt.precision; c.Gnew = g.Gnew;
   c.blk = g.blk; c.blkp = g.blkp; c.sum_y = g.sum_y; c.accepted = g.nn_acc;
+  c.sum_yb = g.sum_yb; c.accepted_b = g.acc_b; c.inner = g.nu;
   c.seed = ctx->seed; c.chain0 = g.chain0; c.sweep = ctx->sweep_counter; c.counters = g.counters;
   c.log_margin = g.log_margin[HQ_KIND_CUMULATIVE]; c.log_accept = g.log_accept[HQ_KIND_CUMULATIVE];
   c.replay = g.replay[HQ_KIND_CUMULATIVE]; c.band = g.band[HQ_KIND_CUMULATIVE]; c.replay_counts = g.replay_counts;
@@ -959,7 +1015,7 @@ hq_status enqueue_group(hq_ctx* ctx, Group& g, hipStream_t s, int dir, bool rebu
     if (g.G != g.G0) std::swap(g.G, g.Wt);   // the enqueue failed part-way: keep the buffers' roles
     return st;
   }
-  for (int k : {HQ_KIND_LOCAL, HQ_KIND_GLOBAL, HQ_KIND_NN, HQ_KIND_CUMULATIVE})
+  for (int k : KINDS)
     SCHED_TRY(launch_fill_u8(g.replay[k], 255, (long)g.C * g.kind_slots(k), S.s));
   return HQ_OK;
 }
@@ -1274,7 +1330,7 @@ hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* 
     HQ_TRY(launch_fill_f64(g.drift, 0.0, (long)C * 5, s));
     HQ_TRY(launch_fill_f64(g.lastpc, 0.0, (long)C * 2, s));
     HQ_TRY(launch_fill_i64((int64_t*)g.flags, 0, ((long)C * sizeof(int) + 7) / 8, s));
-    for (int k : {HQ_KIND_LOCAL, HQ_KIND_GLOBAL, HQ_KIND_NN, HQ_KIND_CUMULATIVE})
+    for (int k : KINDS)
       HQ_TRY(launch_fill_u8(g.replay[k], 255, (long)C * g.kind_slots(k), s));
   }
   HQ_TRY(launch_fill_i64(ctx->sweep_counter, 0, 1, s));
@@ -1310,11 +1366,26 @@ hq_status hq_set_network(hq_ctx* ctx, const float* w, int64_t n) {
   return sync(ctx);
 }
 
+hq_status hq_set_block_network(hq_ctx* ctx, const float* w, int64_t n, int32_t L) {
+  ST_TRY(check_ctx(ctx));
+  if (!w || L < 2 || L % 2 || L > ctx->cnn_max_L || n != 64L * L + 117)
+    return fail(ctx, HQ_EINVAL, "block-move network: %lld weights for L = %d (needs 64 L + 117, L even, and a "
+                "network group with block moves of that L)", (long long)n, L);
+  for (int64_t k = 0; k < n; ++k)
+    if (!std::isfinite(w[k])) return fail(ctx, HQ_EINVAL, "non-finite weight");
+  HQ_TRY(hipMemcpyAsync(ctx->cnn, w, n * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+  ctx->cnn_L = L;
+  return sync(ctx);
+}
+
 hq_status hq_sweep(hq_ctx* ctx, int32_t n_sweeps) {
   ST_TRY(check_ctx(ctx));
   if (n_sweeps < 0) return fail(ctx, HQ_EINVAL, "n_sweeps < 0");
-  for (const Group& g : ctx->groups)
+  for (const Group& g : ctx->groups) {
     if (g.network && !ctx->net_loaded) return fail(ctx, HQ_EINVAL, "network proposals need hq_set_network first");
+    if (g.cnn && ctx->cnn_L != g.L)
+      return fail(ctx, HQ_EINVAL, "network block moves need hq_set_block_network for L = %d first", g.L);
+  }
   for (int k = 0; k < n_sweeps; ++k) {
     const int dir = (ctx->sweep_index % 2 == 1) ? DIR_DOWN : DIR_UP;
     const bool rebuild = (dir == DIR_UP) ? !ctx->right_valid : !ctx->left_valid;
@@ -1419,7 +1490,8 @@ hq_status hq_read_decisions(hq_ctx* ctx, int32_t chain, int32_t kind, uint8_t* a
   ST_TRY(check_ctx(ctx));
   int lc = 0;
   Group* g = find_chain(ctx, chain, lc);
-  if (!g || (kind != HQ_KIND_LOCAL && kind != HQ_KIND_GLOBAL && kind != HQ_KIND_NN && kind != HQ_KIND_CUMULATIVE))
+  if (!g || (kind != HQ_KIND_LOCAL && kind != HQ_KIND_GLOBAL && kind != HQ_KIND_NN && kind != HQ_KIND_CUMULATIVE &&
+             kind != HQ_KIND_NN_GLOBAL))
     return fail(ctx, HQ_EINVAL, "bad chain or kind");
   if (!ctx->opt.record) return fail(ctx, HQ_EINVAL, "decisions are only kept with options.record = 1");
   const long slots = g->kind_slots(kind);
@@ -1446,7 +1518,8 @@ hq_status hq_set_replay(hq_ctx* ctx, int32_t chain, int32_t kind, const uint8_t*
   ST_TRY(check_ctx(ctx));
   int lc = 0;
   Group* g = find_chain(ctx, chain, lc);
-  if (!g || (kind != HQ_KIND_LOCAL && kind != HQ_KIND_GLOBAL && kind != HQ_KIND_NN && kind != HQ_KIND_CUMULATIVE))
+  if (!g || (kind != HQ_KIND_LOCAL && kind != HQ_KIND_GLOBAL && kind != HQ_KIND_NN && kind != HQ_KIND_CUMULATIVE &&
+             kind != HQ_KIND_NN_GLOBAL))
     return fail(ctx, HQ_EINVAL, "bad chain or kind");
   const long slots = g->kind_slots(kind);
   if (!(band >= 0) || (n != 0 && (n != slots || !bits))) return fail(ctx, HQ_EINVAL, "expected %ld bits", slots);

@@ -235,6 +235,7 @@ hipError_t launch_observables(const ObsArgs& a, int chains, hipStream_t s);
 // ---------------------------------------------------------------------------
 struct NetArgs {
   int nx = 0, n = 0, L = 0, colour = 0;
+  int inner = 0, nu = 1;        // inner sweep u of n_u: draws and log slots at u*L*n + l*n + i
   double* xp = nullptr;         // [C][L][n] proposal fields (updated in place)
   const double* g = nullptr;
   double dtau = 0, mass = 0, omega = 0, width = 0;
@@ -244,13 +245,32 @@ struct NetArgs {
   const float* w = nullptr;     // 7169 weights
   int activation = 0;
   int chains = 0;
-  double* sum_y = nullptr;      // [C][L*n]: network output of each accepted proposal, else 0
-  uint8_t* accepted = nullptr;  // [C][L*n]
+  double* sum_y = nullptr;      // [C][L*n]: network outputs of the accepted proposals, summed over inner sweeps
+  uint8_t* accepted = nullptr;  // [C][L*n]: accepted proposals, counted over inner sweeps
   int64_t* counters = nullptr;
   float* log_margin = nullptr; uint8_t* log_accept = nullptr;
   const uint8_t* replay = nullptr; double band = 0; int64_t* replay_counts = nullptr;
 };
 hipError_t launch_network_colour(const NetArgs& a, int chains, hipStream_t s);
+// network block moves of one colour class (iy mod 2, ix mod 2) of inner sweep
+// u: one thread per site, the convolutional network's weights in LDS
+struct CnnArgs {
+  int nx = 0, n = 0, L = 0, colour = 0, inner = 0, nu = 1;   // draws and log slots at u*n + i
+  double* xp = nullptr;         // [C][L][n] proposal fields (columns shifted in place)
+  const double* g = nullptr;
+  double dtau = 0, mass = 0, omega = 0, width = 0;
+  uint64_t seed = 0;
+  int chain0 = 0;
+  const int64_t* sweep = nullptr;
+  const float* w = nullptr;     // 64 L + 117 weights
+  int chains = 0;
+  double* sum_y = nullptr;      // [C][n]: outputs of the accepted moves, summed over inner sweeps
+  uint8_t* accepted = nullptr;  // [C][n]: accepted moves, counted over inner sweeps
+  float* log_margin = nullptr; uint8_t* log_accept = nullptr;
+  const uint8_t* replay = nullptr; double band = 0; int64_t* replay_counts = nullptr;
+};
+hipError_t launch_cnn_colour(const CnnArgs& a, int chains, hipStream_t s);
+size_t cnn_lds_bytes(int L);
 struct CumulativeArgs {
   int n = 0, L = 0, nb = 0;
   double* x = nullptr; const double* xp = nullptr;
@@ -258,6 +278,8 @@ struct CumulativeArgs {
   void* G = nullptr; int precision = 0; const double* Gnew = nullptr;
   double* blk = nullptr; const double* blkp = nullptr;
   const double* sum_y = nullptr; const uint8_t* accepted = nullptr;
+  const double* sum_yb = nullptr; const uint8_t* accepted_b = nullptr;   // block moves, [C][n], or null
+  int inner = 1;                // n_u: proposals per slot of each kind
   uint64_t seed = 0; int chain0 = 0; const int64_t* sweep = nullptr;
   int64_t* counters = nullptr;
   float* log_margin = nullptr; uint8_t* log_accept = nullptr;

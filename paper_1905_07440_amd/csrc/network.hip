@@ -1,5 +1,5 @@
-// Network-proposed local moves and the cumulative update (paper: "Local
-// Updates", and the p_c equation at the end of "Global Updates").
+// Network-proposed local and block moves and the cumulative update (paper:
+// "Local Updates", "Global Updates" and the p_c equation at its end).
 //
 // The fully connected network sees the displacement d and the fields of the
 // 3 x 3 spatial patch over slices l-2..l+2 (45 inputs: input
@@ -12,6 +12,16 @@
 // Visiting order: colour classes (l mod 4, iy mod 2, ix mod 2).  No two points
 // of a class lie in each other's patch, so a class is one parallel launch of
 // independent proposals: one thread per point, the weights in LDS.
+//
+// Block moves shift a whole column x[:, i] by d.  The convolutional network
+// sees three channels over l (the column, the means of the four nearest and
+// of the four diagonal next-nearest neighbours' columns): a circular
+// convolution along l (4 channels, kernel 4, stride 2), sigmoid, 32 dense
+// sigmoid units, a linear output f; the estimate of the move's fermionic
+// change is f(x_i + d) - f(x_i).  Sites go by colour classes (iy mod 2,
+// ix mod 2): a site's inputs lie in its 3 x 3 neighbourhood, which holds no
+// other site of its class.  n_u sweeps of local moves, then n_u of block
+// moves, precede one cumulative accept.
 #include "hq_device.h"
 #include "hq_internal.h"
 
@@ -46,7 +56,9 @@ __global__ __launch_bounds__(256) void network_colour_kernel(NetArgs a) {
   const int i = ix + nx * iy;
 
   double* xp = a.xp + (long)c * L * n;
-  const Philox4 rn = philox4x64_10((uint64_t)(a.chain0 + c), (uint64_t)(*a.sweep), (uint64_t)(l * n + i),
+  const long ln = (long)L * n;
+  const long draw = (long)a.inner * ln + (long)l * n + i;
+  const Philox4 rn = philox4x64_10((uint64_t)(a.chain0 + c), (uint64_t)(*a.sweep), (uint64_t)draw,
                                    KIND_NN, a.seed, 0);
   const double u1 = u53(rn.w[1]);
   const double d = a.width * (2.0 * u53(rn.w[0]) - 1.0);
@@ -91,7 +103,7 @@ __global__ __launch_bounds__(256) void network_colour_kernel(NetArgs a) {
   const double lr = (double)y - ds;
   int acc = (u1 < exp(lr)) ? 1 : 0;
   const double margin = log(u1) - lr;
-  const long slot = (long)c * L * n + (long)l * n + i;
+  const long slot = (long)c * a.nu * ln + draw;       // decision log and replay
   if (a.replay) {
     const uint8_t rp = a.replay[slot];
     if (rp != 255) {
@@ -104,14 +116,140 @@ __global__ __launch_bounds__(256) void network_colour_kernel(NetArgs a) {
     }
   }
   if (a.log_margin) { a.log_margin[slot] = (float)margin; a.log_accept[slot] = (uint8_t)acc; }
-  a.sum_y[slot] = acc ? (double)y : 0.0;
-  a.accepted[slot] = (uint8_t)acc;
-  if (acc) xp[(long)l * n + i] = xa + d;
+  const long s2 = (long)c * ln + (long)l * n + i;
+  if (acc) {
+    a.sum_y[s2] += (double)y;
+    a.accepted[s2] += 1;
+    xp[(long)l * n + i] = xa + d;
+  }
 }
 
 hipError_t launch_network_colour(const NetArgs& a, int chains, hipStream_t s) {
   const long items = (long)chains * (a.L / 4) * (a.nx / 2) * (a.nx / 2);
   hipLaunchKernelGGL(network_colour_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+constexpr int CNN_C = 4, CNN_K = 4, CNN_S = 2, CNN_H = 32;
+size_t cnn_lds_bytes(int L) { return (size_t)(64 * L + 117) * sizeof(float); }
+
+__device__ inline float sigm(float h) { return 1.0f / (1.0f + __expf(-h)); }
+
+__global__ __launch_bounds__(256) void cnn_colour_kernel(CnnArgs a) {
+  extern __shared__ float cw[];
+  const int nx = a.nx, n = a.n, L = a.L, P = L / CNN_S;
+  const int nw = 64 * L + 117;
+  for (int e = threadIdx.x; e < nw; e += blockDim.x) cw[e] = a.w[e];
+  __syncthreads();
+  const float* Wc = cw;                                 // [C][3][K]
+  const float* bc = Wc + CNN_C * 3 * CNN_K;             // [C]
+  const float* Wd = bc + CNN_C;                         // [H][C P]
+  const float* bd = Wd + CNN_H * CNN_C * P;             // [H]
+  const float* Wo = bd + CNN_H;                         // [H]
+  const float bo = Wo[CNN_H];
+
+  const int py = (a.colour >> 1) & 1, px = a.colour & 1;
+  const int hx = nx / 2, per_chain = hx * hx;
+  const long item = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = (int)(item / per_chain);
+  if (c >= a.chains) return;
+  const int k = (int)(item - (long)c * per_chain);
+  const int iy = py + 2 * (k / hx), ix = px + 2 * (k % hx);
+  const int i = ix + nx * iy;
+  int nb4[4], dg4[4];
+  nb4[0] = (ix + 1) % nx + nx * iy;          nb4[1] = (ix + nx - 1) % nx + nx * iy;
+  nb4[2] = ix + nx * ((iy + 1) % nx);        nb4[3] = ix + nx * ((iy + nx - 1) % nx);
+  dg4[0] = (ix + 1) % nx + nx * ((iy + 1) % nx);      dg4[1] = (ix + 1) % nx + nx * ((iy + nx - 1) % nx);
+  dg4[2] = (ix + nx - 1) % nx + nx * ((iy + 1) % nx); dg4[3] = (ix + nx - 1) % nx + nx * ((iy + nx - 1) % nx);
+
+  double* xp = a.xp + (long)c * L * n;
+  const long draw = (long)a.inner * n + i;
+  const Philox4 rn = philox4x64_10((uint64_t)(a.chain0 + c), (uint64_t)(*a.sweep), (uint64_t)draw,
+                                   KIND_NN_GLOBAL, a.seed, 0);
+  const double u1 = u53(rn.w[1]);
+  const double d = a.width * (2.0 * u53(rn.w[0]) - 1.0);
+  const float df = (float)d;
+  // the moved evaluation differs only in channel 0: conv + d * sum_k Wc[c][0][k]
+  float shift[CNN_C];
+#pragma unroll
+  for (int ch = 0; ch < CNN_C; ++ch) {
+    float s = 0.0f;
+#pragma unroll
+    for (int kk = 0; kk < CNN_K; ++kk) s += Wc[(ch * 3 + 0) * CNN_K + kk];
+    shift[ch] = df * s;
+  }
+  float z0[CNN_H], z1[CNN_H];
+#pragma unroll
+  for (int h = 0; h < CNN_H; ++h) { z0[h] = bd[h]; z1[h] = bd[h]; }
+  double colsum = 0.0;
+  for (int p = 0; p < P; ++p) {
+    float in0[CNN_K], in1[CNN_K], in2[CNN_K];
+#pragma unroll
+    for (int kk = 0; kk < CNN_K; ++kk) {
+      const int l = (CNN_S * p + kk) % L;
+      const double* row = xp + (long)l * n;
+      const double xi = row[i];
+      if (kk < CNN_S) colsum += xi;                    // each slice once
+      in0[kk] = (float)xi;
+      in1[kk] = (float)(0.25 * (row[nb4[0]] + row[nb4[1]] + row[nb4[2]] + row[nb4[3]]));
+      in2[kk] = (float)(0.25 * (row[dg4[0]] + row[dg4[1]] + row[dg4[2]] + row[dg4[3]]));
+    }
+#pragma unroll
+    for (int ch = 0; ch < CNN_C; ++ch) {
+      float s = bc[ch];
+#pragma unroll
+      for (int kk = 0; kk < CNN_K; ++kk) {
+        s = fmaf(Wc[(ch * 3 + 0) * CNN_K + kk], in0[kk], s);
+        s = fmaf(Wc[(ch * 3 + 1) * CNN_K + kk], in1[kk], s);
+        s = fmaf(Wc[(ch * 3 + 2) * CNN_K + kk], in2[kk], s);
+      }
+      const float h0 = sigm(s), h1 = sigm(s + shift[ch]);
+      const float* wd = Wd + ch * P + p;             // Wd[h][ch P + p], stride C P over h
+#pragma unroll
+      for (int h = 0; h < CNN_H; ++h) {
+        const float wv = wd[(long)h * CNN_C * P];
+        z0[h] = fmaf(wv, h0, z0[h]);
+        z1[h] = fmaf(wv, h1, z1[h]);
+      }
+    }
+  }
+  float f0 = bo, f1 = bo;
+#pragma unroll
+  for (int h = 0; h < CNN_H; ++h) {
+    f0 = fmaf(Wo[h], sigm(z0[h]), f0);
+    f1 = fmaf(Wo[h], sigm(z1[h]), f1);
+  }
+  const float y = f1 - f0;
+  const double g = a.g[c];
+  const double mw2 = a.mass * a.omega * a.omega;
+  const double ds = a.dtau * (mw2 * d * colsum + 0.5 * mw2 * L * d * d - g * L * d);
+  const double lr = (double)y - ds;
+  int acc = (u1 < exp(lr)) ? 1 : 0;
+  const double margin = log(u1) - lr;
+  const long slot = (long)c * a.nu * n + draw;
+  if (a.replay) {
+    const uint8_t rp = a.replay[slot];
+    if (rp != 255) {
+      if (fabs(margin) <= a.band) {
+        if (acc != (int)rp) atomicAdd((unsigned long long*)&a.replay_counts[2 * c], 1ull);
+        acc = rp;
+      } else if (acc != (int)rp) {
+        atomicAdd((unsigned long long*)&a.replay_counts[2 * c + 1], 1ull);
+      }
+    }
+  }
+  if (a.log_margin) { a.log_margin[slot] = (float)margin; a.log_accept[slot] = (uint8_t)acc; }
+  if (acc) {
+    a.sum_y[(long)c * n + i] += (double)y;
+    a.accepted[(long)c * n + i] += 1;
+    for (int l = 0; l < L; ++l) xp[(long)l * n + i] += d;
+  }
+}
+
+hipError_t launch_cnn_colour(const CnnArgs& a, int chains, hipStream_t s) {
+  if (a.L % CNN_S || cnn_lds_bytes(a.L) > 65536 || a.nx % 2) return hipErrorInvalidValue;
+  const long items = (long)chains * (a.nx / 2) * (a.nx / 2);
+  hipLaunchKernelGGL(cnn_colour_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), cnn_lds_bytes(a.L), s, a);
   return hipGetLastError();
 }
 
@@ -123,13 +261,19 @@ __global__ void cumulative_kernel(CumulativeArgs a) {
   const int c = blockIdx.x;
   const int n = a.n, L = a.L;
   const long ln = (long)L * n;
-  double sy = 0.0, na = 0.0;
+  double sy = 0.0, na = 0.0, nbk = 0.0;
   for (long e = threadIdx.x; e < ln; e += blockDim.x) {
     sy += a.sum_y[c * ln + e];
     na += (double)a.accepted[c * ln + e];
   }
+  if (a.sum_yb)
+    for (long e = threadIdx.x; e < n; e += blockDim.x) {
+      sy += a.sum_yb[(long)c * n + e];
+      nbk += (double)a.accepted_b[(long)c * n + e];
+    }
   sy = block_sum<256>(sy, red);
   na = block_sum<256>(na, red);
+  nbk = block_sum<256>(nbk, red);
   if (threadIdx.x == 0) {
     const Philox4 rn = philox4x64_10((uint64_t)(a.chain0 + c), (uint64_t)(*a.sweep), 0, KIND_CUMULATIVE,
                                      a.seed, 0);
@@ -150,8 +294,12 @@ __global__ void cumulative_kernel(CumulativeArgs a) {
     }
     if (a.log_margin) { a.log_margin[c] = (float)margin; a.log_accept[c] = (uint8_t)acc; }
     int64_t* cnt = a.counters + (long)c * N_COUNTERS;
-    cnt[CNT_NN_P] += ln;
+    cnt[CNT_NN_P] += (int64_t)a.inner * ln;
     cnt[CNT_NN_A] += (int64_t)na;
+    if (a.sum_yb) {
+      cnt[CNT_GLOBAL_P] += (int64_t)a.inner * n;
+      cnt[CNT_GLOBAL_A] += (int64_t)nbk;
+    }
     cnt[CNT_CUM_P] += 1;
     cnt[CNT_CUM_A] += acc;
     a.last_log_pc[2 * c] = lpc;
@@ -173,10 +321,10 @@ __global__ void cumulative_kernel(CumulativeArgs a) {
     double* G = (double*)a.G + c * nn;
     batched_copy<256, 16, double>((int)nn, [&](int e) { return gn[e]; }, [&](int e, double v) { G[e] = v; });
   }
-  const long nbk = (long)a.nb * nn;
-  const double* bp = a.blkp + c * nbk;
-  double* bk = a.blk + c * nbk;
-  batched_copy<256, 16, double>((int)nbk, [&](int e) { return bp[e]; }, [&](int e, double v) { bk[e] = v; });
+  const long nblk = (long)a.nb * nn;
+  const double* bp = a.blkp + c * nblk;
+  double* bk = a.blk + c * nblk;
+  batched_copy<256, 16, double>((int)nblk, [&](int e) { return bp[e]; }, [&](int e, double v) { bk[e] = v; });
 }
 
 hipError_t launch_cumulative(const CumulativeArgs& a, int chains, hipStream_t s) {

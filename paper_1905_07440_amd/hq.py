@@ -15,8 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhq.so")
 
 HQ_OK, HQ_EINVAL, HQ_ENOMEM, HQ_EDEVICE, HQ_ESTATE, HQ_ENUMERIC = 0, -1, -2, -3, -4, -5
-KIND_LOCAL, KIND_GLOBAL, KIND_NN, KIND_CUMULATIVE = 0, 1, 3, 4
+KIND_LOCAL, KIND_GLOBAL, KIND_NN, KIND_CUMULATIVE, KIND_NN_GLOBAL = 0, 1, 3, 4, 6
 PREC_FP64, PREC_MIXED = 0, 1
+PROPOSAL_DQMC, PROPOSAL_NETWORK = 0, 1
 
 
 class HQError(RuntimeError):
@@ -34,6 +35,7 @@ class Group(ctypes.Structure):
         ("beta", ctypes.c_double), ("dtau", ctypes.c_double),
         ("n_stab", ctypes.c_int32), ("proposal", ctypes.c_int32),
         ("local_width", ctypes.c_double), ("global_width", ctypes.c_double),
+        ("nn_sweeps", ctypes.c_int32),
     ]
 
 
@@ -80,7 +82,7 @@ def tile_name(code):
 
 
 EXPORTS = [
-    "hq_workspace_bytes", "hq_create", "hq_set_fields", "hq_set_network", "hq_sweep",
+    "hq_workspace_bytes", "hq_create", "hq_set_fields", "hq_set_network", "hq_set_block_network", "hq_sweep",
     "hq_recompute", "hq_read_green", "hq_read_fields", "hq_read_stats", "hq_read_decisions",
     "hq_set_replay", "hq_num_chains", "hq_chain_shape", "hq_set_profiling", "hq_phase_time",
     "hq_read_tuning", "hq_set_tuning", "hq_gemm_tile_name", "hq_synchronize", "hq_last_error", "hq_destroy",
@@ -105,6 +107,7 @@ def load(path=LIB_PATH):
     lib.hq_create.argtypes = [GP, I32, OP, ctypes.c_uint64, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
     lib.hq_set_fields.argtypes = [P, I32, P, I64]
     lib.hq_set_network.argtypes = [P, P, I64]
+    lib.hq_set_block_network.argtypes = [P, P, I64, I32]
     lib.hq_sweep.argtypes = [P, I32]
     lib.hq_recompute.argtypes = [P]
     lib.hq_read_green.argtypes = [P, I32, P, I64]
@@ -135,15 +138,16 @@ def load(path=LIB_PATH):
 
 
 def make_group(nx, n_chains, t=1.0, mu=0.0, mass=1.0, omega=1.0, g=1.0, g_range=None, beta=4.0,
-               dtau=0.1, n_stab=10, proposal=0, local_width=0.5, global_width=0.0):
+               dtau=0.1, n_stab=10, proposal=0, local_width=0.5, global_width=0.0, nn_sweeps=1):
     lo, hi = (g_range if g_range is not None else (0.0, 0.0))
     return Group(nx, n_chains, t, mu, mass, omega, g, lo, hi, beta, dtau, n_stab, proposal,
-                 local_width, global_width)
+                 local_width, global_width, nn_sweeps)
 
 
 def groups_from_workload(w):
     return [make_group(gr.nx, gr.n_chains, gr.t, gr.mu, gr.mass, gr.omega, gr.g, gr.g_range, gr.beta,
-                       gr.dtau, gr.n_stab, gr.proposal, gr.local_width, gr.global_width)
+                       gr.dtau, gr.n_stab, gr.proposal, gr.local_width, gr.global_width,
+                       getattr(gr, "nn_sweeps", 1))
             for gr in w.groups]
 
 
@@ -214,6 +218,12 @@ class Context:
         w = np.ascontiguousarray(w, dtype=np.float32)
         self._check(self._lib.hq_set_network(self._ctx, w.ctypes.data, w.size))
 
+    def set_block_network(self, w, L):
+        """Weights of the block-move network (64 L + 117 FP32 values) for the
+        network groups with block moves, all of which have L slices."""
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(self._lib.hq_set_block_network(self._ctx, w.ctypes.data, w.size, L))
+
     def stats(self, chain):
         s = Stats()
         st = self._lib.hq_read_stats(self._ctx, chain, ctypes.byref(s))
@@ -221,9 +231,19 @@ class Context:
             self._check(st)
         return s.as_dict()
 
+    def _inner_sweeps(self, chain):
+        k = 0
+        for gr in self._groups:
+            if chain < k + gr.n_chains:
+                return max(1, gr.nn_sweeps) if gr.proposal == PROPOSAL_NETWORK else 1
+            k += gr.n_chains
+        raise HQError(HQ_EINVAL, "no chain %d" % chain)
+
     def decisions(self, chain, kind):
         n, L = self.shape(chain)
-        slots = {KIND_LOCAL: n * L, KIND_NN: n * L, KIND_GLOBAL: n, KIND_CUMULATIVE: 1}[kind]
+        nu = self._inner_sweeps(chain)
+        slots = {KIND_LOCAL: n * L, KIND_NN: nu * n * L, KIND_GLOBAL: n, KIND_CUMULATIVE: 1,
+                 KIND_NN_GLOBAL: nu * n}[kind]
         acc = np.empty(slots, dtype=np.uint8)
         margin = np.empty(slots, dtype=np.float32)
         self._check(self._lib.hq_read_decisions(self._ctx, chain, kind, acc.ctypes.data,

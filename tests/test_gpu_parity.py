@@ -54,7 +54,8 @@ def make_ctx(hq, groups, precision=0, seed=1, delay=0, record=True):
                         mass=gr.get("mass", 1.0), omega=gr.get("omega", 1.0), g=gr.get("g", 1.0),
                         g_range=gr.get("g_range"), beta=gr["beta"], dtau=gr.get("dtau", 0.1),
                         n_stab=gr["n_stab"], proposal=gr.get("proposal", 0),
-                        local_width=gr.get("local_width", 0.5), global_width=gr.get("global_width", 0.0))
+                        local_width=gr.get("local_width", 0.5), global_width=gr.get("global_width", 0.0),
+                        nn_sweeps=gr.get("nn_sweeps", 1))
           for gr in groups]
     return hq.Context(hg, precision=precision, seed=seed, delay=delay, record=record)
 
@@ -548,6 +549,52 @@ def test_invalid_arguments(hq):
     ctx.close()
     with pytest.raises(hq.HQError):
         make_ctx(hq, [dict(nx=4, chains=1, beta=2.0, n_stab=5, proposal=1)]).sweep(1)   # no network loaded
+
+
+@pytest.mark.parametrize("nu", [1, 2])
+def test_network_block_moves_and_inner_sweeps(hq, nu):
+    """Network local moves and network block moves (the convolutional network
+    over the column and its neighbour means), n_u sweeps of each per
+    cumulative accept, on 4x4 (L = 8): inner decisions of both kinds replayed
+    inside the tie band, fields, log det and every counter against the oracle."""
+    say("network block moves 4x4 n_u=%d" % nu)
+    gr = dict(nx=4, chains=2, g=1.2, beta=0.8, n_stab=4, proposal=1, global_width=0.4, nn_sweeps=nu)
+    p = params_of(gr)
+    w = workloads.random_network(17, scale=0.1)
+    cw = (0.2 * np.random.default_rng(23).standard_normal(nnmc.cnn_count(p.L))).astype(np.float32)
+    ctx = make_ctx(hq, [gr], seed=6)
+    ctx.set_network(w)
+    with pytest.raises(hq.HQError):
+        ctx.sweep(1)                                   # block moves need their network first
+    with pytest.raises(hq.HQError):
+        ctx.set_block_network(cw[:-1], p.L)
+    ctx.set_block_network(cw, p.L)
+    nets = [nnmc.NNChain(dqmc.Chain(p, 6, c), w, cnn=cw, nu=nu) for c in range(2)]
+    for s in range(3):
+        for c, nn in enumerate(nets):
+            nn.sweep()
+            bits = {philox.KIND_NN: np.zeros(nu * p.L * p.n, dtype=np.uint8),
+                    philox.KIND_NN_GLOBAL: np.zeros(nu * p.n, dtype=np.uint8),
+                    philox.KIND_CUMULATIVE: np.zeros(1, dtype=np.uint8)}
+            for kind, sw, slot, acc, _ in nn.decisions:
+                if sw == s:
+                    bits[kind][slot] = acc
+            ctx.set_replay(c, hq.KIND_NN, bits[philox.KIND_NN], BAND_MIXED)
+            ctx.set_replay(c, hq.KIND_NN_GLOBAL, bits[philox.KIND_NN_GLOBAL], BAND_MIXED)
+            ctx.set_replay(c, hq.KIND_CUMULATIVE, bits[philox.KIND_CUMULATIVE], BAND_MIXED)
+        ctx.sweep(1)
+        for c, nn in enumerate(nets):
+            st = ctx.stats(c)
+            assert st["replay_mismatches"] == 0
+            assert np.array_equal(ctx.fields(c), nn.c.x), "sweep %d chain %d" % (s, c)
+            assert abs(st["logdet"] - nn.c.logdet) <= TOL64 * max(1.0, abs(nn.c.logdet))
+            assert st["cumulative_accepts"] == nn.cumulative_accepts
+            assert st["nn_proposals"] == nn.inner_proposals and st["nn_accepts"] == nn.inner_accepts
+            assert st["global_proposals"] == nn.block_proposals and st["global_accepts"] == nn.block_accepts
+            acc, margin = ctx.decisions(c, hq.KIND_NN_GLOBAL)
+            assert acc.size == nu * p.n and np.all(np.isfinite(margin))
+    assert sum(nn.block_accepts for nn in nets) > 0
+    ctx.close()
 
 
 def test_network_proposals_and_cumulative_update(hq):
