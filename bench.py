@@ -62,8 +62,13 @@ def proposals_per_sweep(w):
     for g in w.groups:
         L = round(g.beta / g.dtau)
         n = g.nx * g.nx
+        if g.proposal == 1:
+            total += g.n_chains * g.nn_sweeps * n * L
+            if g.global_width > 0:
+                total += g.n_chains * g.nn_sweeps * n
+            continue
         total += g.n_chains * n * L
-        if g.global_width > 0 and g.proposal == 0:
+        if g.global_width > 0:
             total += g.n_chains * n
     return total
 
@@ -126,6 +131,9 @@ def run_workload(w, steps, warmup, profile=True):
     if any(g.proposal == 1 for g in w.groups):
         import workloads
         ctx.set_network(workloads.random_network(1001))   # seeded random weights, no trained set
+        blocks = {round(g.beta / g.dtau) for g in w.groups if g.proposal == 1 and g.global_width > 0}
+        for L in blocks:
+            ctx.set_block_network(workloads.random_block_network(1002, L), L)
     stream = ctx._stream
     ctx.sweep(warmup)
     ctx.synchronize()

@@ -135,6 +135,10 @@ size_t cnn_lds_bytes(int L) { return (size_t)(64 * L + 117) * sizeof(float); }
 
 __device__ inline float sigm(float h) { return 1.0f / (1.0f + __expf(-h)); }
 
+// one wave per site: the lanes take the conv positions p = lane, lane + 64,
+// ... and accumulate partial dense sums for both evaluations (moved and
+// unmoved column); a halving butterfly leaves the total of dense unit h of
+// the unmoved evaluation in lane h and of the moved one in lane 32 + h
 __global__ __launch_bounds__(256) void cnn_colour_kernel(CnnArgs a) {
   extern __shared__ float cw[];
   const int nx = a.nx, n = a.n, L = a.L, P = L / CNN_S;
@@ -148,11 +152,12 @@ __global__ __launch_bounds__(256) void cnn_colour_kernel(CnnArgs a) {
   const float* Wo = bd + CNN_H;                         // [H]
   const float bo = Wo[CNN_H];
 
+  const int lane = threadIdx.x & 63;
   const int py = (a.colour >> 1) & 1, px = a.colour & 1;
   const int hx = nx / 2, per_chain = hx * hx;
-  const long item = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long item = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);   // one site per wave
   const int c = (int)(item / per_chain);
-  if (c >= a.chains) return;
+  if (c >= a.chains) return;                            // whole waves; no barrier follows
   const int k = (int)(item - (long)c * per_chain);
   const int iy = py + 2 * (k / hx), ix = px + 2 * (k % hx);
   const int i = ix + nx * iy;
@@ -178,11 +183,11 @@ __global__ __launch_bounds__(256) void cnn_colour_kernel(CnnArgs a) {
     for (int kk = 0; kk < CNN_K; ++kk) s += Wc[(ch * 3 + 0) * CNN_K + kk];
     shift[ch] = df * s;
   }
-  float z0[CNN_H], z1[CNN_H];
+  float v[2 * CNN_H];                                   // partial dense sums: unmoved, then moved
 #pragma unroll
-  for (int h = 0; h < CNN_H; ++h) { z0[h] = bd[h]; z1[h] = bd[h]; }
+  for (int h = 0; h < 2 * CNN_H; ++h) v[h] = 0.0f;
   double colsum = 0.0;
-  for (int p = 0; p < P; ++p) {
+  for (int p = lane; p < P; p += 64) {
     float in0[CNN_K], in1[CNN_K], in2[CNN_K];
 #pragma unroll
     for (int kk = 0; kk < CNN_K; ++kk) {
@@ -208,18 +213,31 @@ __global__ __launch_bounds__(256) void cnn_colour_kernel(CnnArgs a) {
 #pragma unroll
       for (int h = 0; h < CNN_H; ++h) {
         const float wv = wd[(long)h * CNN_C * P];
-        z0[h] = fmaf(wv, h0, z0[h]);
-        z1[h] = fmaf(wv, h1, z1[h]);
+        v[h] = fmaf(wv, h0, v[h]);
+        v[CNN_H + h] = fmaf(wv, h1, v[CNN_H + h]);
       }
     }
   }
-  float f0 = bo, f1 = bo;
+  // halving butterfly: at width w the lanes with bit w keep the upper half
 #pragma unroll
-  for (int h = 0; h < CNN_H; ++h) {
-    f0 = fmaf(Wo[h], sigm(z0[h]), f0);
-    f1 = fmaf(Wo[h], sigm(z1[h]), f1);
+  for (int w = 32; w >= 1; w >>= 1) {
+    const bool up = (lane & w) != 0;
+#pragma unroll
+    for (int j = 0; j < w; ++j) {
+      const float send = up ? v[j] : v[j + w];
+      const float keep = up ? v[j + w] : v[j];
+      v[j] = keep + __shfl_xor(send, w);
+    }
   }
+  const int h = lane & (CNN_H - 1);
+  float t = Wo[h] * sigm(v[0] + bd[h]);
+#pragma unroll
+  for (int w = 16; w >= 1; w >>= 1) t += __shfl_xor(t, w);   // within each half of the wave
+  const float f0 = bo + __shfl(t, 0), f1 = bo + __shfl(t, 32);
   const float y = f1 - f0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) colsum += __shfl_xor(colsum, w);
+
   const double g = a.g[c];
   const double mw2 = a.mass * a.omega * a.omega;
   const double ds = a.dtau * (mw2 * d * colsum + 0.5 * mw2 * L * d * d - g * L * d);
@@ -231,25 +249,28 @@ __global__ __launch_bounds__(256) void cnn_colour_kernel(CnnArgs a) {
     const uint8_t rp = a.replay[slot];
     if (rp != 255) {
       if (fabs(margin) <= a.band) {
-        if (acc != (int)rp) atomicAdd((unsigned long long*)&a.replay_counts[2 * c], 1ull);
+        if (lane == 0 && acc != (int)rp) atomicAdd((unsigned long long*)&a.replay_counts[2 * c], 1ull);
         acc = rp;
-      } else if (acc != (int)rp) {
+      } else if (lane == 0 && acc != (int)rp) {
         atomicAdd((unsigned long long*)&a.replay_counts[2 * c + 1], 1ull);
       }
     }
   }
-  if (a.log_margin) { a.log_margin[slot] = (float)margin; a.log_accept[slot] = (uint8_t)acc; }
-  if (acc) {
-    a.sum_y[(long)c * n + i] += (double)y;
-    a.accepted[(long)c * n + i] += 1;
-    for (int l = 0; l < L; ++l) xp[(long)l * n + i] += d;
+  if (lane == 0) {
+    if (a.log_margin) { a.log_margin[slot] = (float)margin; a.log_accept[slot] = (uint8_t)acc; }
+    if (acc) {
+      a.sum_y[(long)c * n + i] += (double)y;
+      a.accepted[(long)c * n + i] += 1;
+    }
   }
+  if (acc)
+    for (int l = lane; l < L; l += 64) xp[(long)l * n + i] += d;
 }
 
 hipError_t launch_cnn_colour(const CnnArgs& a, int chains, hipStream_t s) {
   if (a.L % CNN_S || cnn_lds_bytes(a.L) > 65536 || a.nx % 2) return hipErrorInvalidValue;
-  const long items = (long)chains * (a.nx / 2) * (a.nx / 2);
-  hipLaunchKernelGGL(cnn_colour_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), cnn_lds_bytes(a.L), s, a);
+  const long sites = (long)chains * (a.nx / 2) * (a.nx / 2);   // one wave each, four per workgroup
+  hipLaunchKernelGGL(cnn_colour_kernel, dim3((unsigned)((sites + 3) / 4)), dim3(256), cnn_lds_bytes(a.L), s, a);
   return hipGetLastError();
 }
 

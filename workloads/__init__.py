@@ -30,6 +30,7 @@ class Lattice:
     global_width: float = 0.0
     g_range: Optional[Tuple[float, float]] = None   # per-chain g ~ U(lo, hi)
     proposal: int = 0                              # 0 exact DQMC, 1 network + cumulative
+    nn_sweeps: int = 1                             # network: inner sweeps of each kind per cumulative accept
 
 
 @dataclass
@@ -79,6 +80,14 @@ def holstein_16x16_network():
                     [Lattice(nx=16, n_chains=64, g=1.2, beta=16.0, n_stab=10, proposal=1)])
 
 
+def holstein_16x16_network_block():
+    # the paper's full network sweep: network local moves at every (i, l),
+    # then a network block move at every site, then one cumulative accept
+    return Workload("holstein-16x16-L160-network-blockmoves-64chains", 5,
+                    [Lattice(nx=16, n_chains=64, g=1.2, beta=16.0, n_stab=10, proposal=1,
+                             global_width=1.0)])
+
+
 ALL = {
     "c1": holstein_4x4_single,
     "c2": holstein_8x8_batched_global,
@@ -89,6 +98,7 @@ ALL = {
     "c3-gate": lambda: holstein_12x12_mixed(1, n_stab=6),
     "c4": holstein_uneven_batch,
     "c5": holstein_16x16_network,
+    "c5-block": holstein_16x16_network_block,
 }
 
 
@@ -114,3 +124,8 @@ def random_fields(seed, L, n, scale=1.0):
 def random_network(seed, scale=0.2):
     """A random flat FP32 weight vector of the 45-64-64-1 network (7169 values)."""
     return (scale * np.random.default_rng(seed).standard_normal(7169)).astype(np.float32)
+
+
+def random_block_network(seed, L, scale=0.05):
+    """A random flat FP32 weight vector of the block-move network for L slices (64 L + 117 values)."""
+    return (scale * np.random.default_rng(seed).standard_normal(64 * L + 117)).astype(np.float32)
