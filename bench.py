@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--cpu-sample-chains", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (reference for HBM byte counters)")
+    ap.add_argument("--autocorr", type=int, default=0, metavar="SWEEPS",
+                    help="instead of the throughput line: SWEEPS measured sweeps (>= 128) of the workload, "
+                         "S_CDW of every chain after each, and the integrated autocorrelation time")
     return ap.parse_args()
 
 
@@ -254,6 +257,54 @@ def sweep_roofline(w, res):
                                                                "fp64": MI355X_PEAK["fp64"] / 1e12}}
 
 
+def autocorr_run(w, sweeps, warmup):
+    """The paper's figure of merit beside raw throughput: the integrated
+    autocorrelation time of S_CDW(pi, pi) (binning over sweeps, pooled over
+    the chains) and the independent samples per second it implies.  Time per
+    sweep from the graph replays alone (the per-sweep reads of S_CDW are
+    outside the timed sweeps)."""
+    import numpy as np
+    import torch
+    from paper_1905_07440_amd import autocorr, hq
+
+    ctx = hq.Context(hq.groups_from_workload(w), precision=w.precision, seed=w.seed, delay=w.delay)
+    if any(g.proposal == 1 for g in w.groups):
+        ctx.set_network(workloads_mod().random_network(1001))
+        blocks = {round(g.beta / g.dtau) for g in w.groups if g.proposal == 1 and g.global_width > 0}
+        for L in blocks:
+            ctx.set_block_network(workloads_mod().random_block_network(1002, L), L)
+    ctx.sweep(warmup)
+    ctx.synchronize()
+    C = w.n_chains
+    series = np.empty((C, sweeps))
+    stream = ctx._stream
+    t_ms = 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for s in range(sweeps):
+        e0.record(stream)
+        ctx.sweep(1)
+        e1.record(stream)
+        e1.synchronize()
+        t_ms += e0.elapsed_time(e1)
+        for c in range(C):
+            series[c, s] = ctx.stats(c)["s_cdw"]
+    ctx.close()
+    tau = autocorr.tau_int_chains(series)
+    ms = t_ms / sweeps
+    return {"metric": "independent S_CDW samples/s", "value": C * 1e3 / ms / (2.0 * tau),
+            "unit": "samples/s", "tau_int_sweeps": tau, "ms_per_sweep": ms, "sweeps": sweeps,
+            "warmup": warmup, "chains": C, "s_cdw_mean": float(series.mean()),
+            "estimator": "binning, tau_B = B var(bin means) / (2 var(x)) at the largest B with >= 64 bins, "
+                         "variances pooled over chains",
+            "config": {"workload": w.name}, "data": "synthetic (seeded random initial fields; random "
+                                                   "network weights for network workloads)"}
+
+
+def workloads_mod():
+    import workloads
+    return workloads
+
+
 def main():
     a = parse()
     if a.copy_calibration:
@@ -270,6 +321,12 @@ def main():
     if headline == "c3":
         headline = "c3-gate"                 # mixed precision at the stated accuracy
     w = workloads.ALL[headline]()
+    if a.autocorr:
+        if a.autocorr < 128:
+            print("--autocorr needs at least 128 sweeps", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps(autocorr_run(w, a.autocorr, a.warmup)))
+        return
     res = run_workload(w, a.steps, a.warmup)
     extra = {}
     if a.workload == "c3":
