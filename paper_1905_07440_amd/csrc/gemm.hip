@@ -1,5 +1,6 @@
-// Batched dense products on MFMA for the wraps, block products and UDT
-// combines of the DQMC sweep.  C = alpha * diag(rs) op(A) diag(ks) op(B)
+// Batched dense products on MFMA for the UDT combines and merges of the DQMC
+// sweep, the pairwise merges of a from-scratch recompute, and the dense wrap
+// forms (the products with exp(dtau K) otherwise take its Kronecker form).  C = alpha * diag(rs) op(A) diag(ks) op(B)
 // diag(cs) + beta * C, row-major, one workgroup per (tile, batch entry).
 //
 // FP64 uses v_mfma_f64_16x16x4f64, FP32 uses v_mfma_f32_16x16x4f32 with

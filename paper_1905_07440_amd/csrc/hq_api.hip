@@ -56,8 +56,9 @@ struct Group {
   // Green's functions
   void* G = nullptr;             // [C][n][n], precision of the context
   void* Wt = nullptr;            // wrap temporary, same precision
-  // A fused wrap writes G' into Wt and the two buffers trade places; G0 is
-  // where G lives between sweeps
+  // A one-launch wrap (fused dense, or Kronecker with G in LDS) writes G'
+  // into Wt and the two buffers trade places; G0 is where G lives between
+  // sweeps
   void* G0 = nullptr;
   double* Gnew = nullptr;        // [C][n][n]
   // block products and UDT stacks
@@ -688,7 +689,7 @@ hq_status kron_lds_wrap(Sched& S, Group& g, const T* A1, const T* A2, Scale ks1,
   return HQ_OK;
 }
 
-// G back in G0 at the end of a group's sweep (after an odd number of fused wraps)
+// G back in G0 at the end of a group's sweep (after an odd number of one-launch wraps)
 hq_status settle_g(Sched& S, Group& g) {
   if (g.G == g.G0) return HQ_OK;
   const size_t ts = S.ctx->opt.precision == HQ_PREC_MIXED ? sizeof(float) : sizeof(double);

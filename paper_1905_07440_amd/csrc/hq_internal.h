@@ -7,7 +7,7 @@
 
 namespace hq {
 
-// Diagonal scaling used by the GEMM epilogue and the block products:
+// Diagonal scaling used by the GEMM epilogue and the Kronecker products:
 //   value(z, i) = v[outer*so + inner*si + off + i]            (plain)
 //   value(z, i) = exp(cmul * coef[outer] * v[...])             (coef != null)
 // with outer = z / inner_count, inner = z % inner_count for batch entry z.
