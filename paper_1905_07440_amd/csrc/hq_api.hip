@@ -490,6 +490,9 @@ hq_status block_products(Sched& S, Group& g, const double* xs, double* dst, long
   return HQ_OK;
 }
 
+hq_status combine_tail(Sched& S, Group& g, const double* Tin, long sT, double* Uout, long sUo, double* Dout, long sDo,
+                       double* Tout, long sTo);
+
 // (Uout, Dout, Tout) = QR-UDT of op(A) * Uin * diag(Din) combined with Tin.
 // A, Uin, Tin advance by the given per-chain strides.
 hq_status combine(Sched& S, Group& g, const double* A, long sA, int tA, const double* Uin, long sU, const double* Din,
@@ -502,6 +505,13 @@ hq_status combine(Sched& S, Group& g, const double* A, long sA, int tA, const do
   a.C = g.Z; a.sC = nn;
   a.cs.v = Din; a.cs.so = sD;
   SCHED_TRY(launch_gemm(a, g.tile, S.s));
+  return combine_tail(S, g, Tin, sT, Uout, sUo, Dout, sDo, Tout, sTo);
+}
+
+// the part of a combine after Z: QR-UDT of Z, Tout = Rt Tin
+hq_status combine_tail(Sched& S, Group& g, const double* Tin, long sT, double* Uout, long sUo, double* Dout, long sDo,
+                       double* Tout, long sTo) {
+  const long nn = (long)g.n * g.n;
   // Q and D go straight into the UDT arrays, which are contiguous per chain;
   // Rt comes back over Z
   if (sUo != nn || sDo != g.n) return fail(S.ctx, HQ_EINVAL, "internal: strided QR output");
@@ -818,14 +828,48 @@ Udt right_entry(Group& g, int b) {      // R_b^T with R_b = C_{nb-1} ... C_{b+1}
   return {g.RU + (long)b * g.C * nn, g.RD + (long)b * g.C * g.n, g.RT + (long)b * g.C * nn, nn, g.n, nn};
 }
 
+// A combine straight from the fields, for groups whose cached block products
+// are read only by stack rebuilds: Z = C_b U_in diag(D_in) (upward) or
+// C_b^T U_in diag(D_in) (downward) by the Kronecker chain applied to U_in,
+// C_b = B_{(b+1)ns-1} ... B_{b ns}, B_l = diag(v_l) E, and C_b^T = E diag(v_{b ns})
+// ... E diag(v_{(b+1)ns-1}) (E symmetric); then the QR-UDT of Z as in combine.
+// The block product itself is not formed.
+hq_status chain_combine(Sched& S, Group& g, int b, bool down, const Udt& in, const Udt& out) {
+  const long nn = (long)g.n * g.n;
+  const int per = KRON_MAX_SCALES / g.n;
+  const int chunks = (g.ns + per - 1) / per;
+  double* bufs[2] = {g.Z, g.blks};           // the last chunk lands in Z
+  KronArgs<double> a;
+  a.nx = g.nx; a.n = g.n; a.batch = g.C; a.inner_count = 1;
+  a.A = g.ek1;
+  a.X = in.U; a.sX = in.sU;
+  a.rs.v = g.x; a.rs.so = (long)g.L * g.n; a.rs.coef = g.g; a.rs.cmul = -g.p.dtau;
+  a.pre = down ? 1 : 0;
+  a.rstep = down ? -(long)g.n : (long)g.n;
+  for (int k = 0, t0 = 0; k < chunks; ++k, t0 += per) {
+    const int o = (chunks - 1 - k) % 2;
+    a.steps = std::min(per, g.ns - t0);
+    a.rs.off = (long)(down ? b * g.ns + g.ns - 1 - t0 : b * g.ns + t0) * g.n;
+    if (k + 1 == chunks) { a.cs.v = in.D; a.cs.so = in.sD; }
+    a.Y = bufs[o]; a.sY = nn;
+    SCHED_TRY(launch_kron(a, 0, S.s));
+    a.X = bufs[o]; a.sX = nn;
+  }
+  return combine_tail(S, g, in.T, in.sT, out.U, out.sU, out.D, out.sD, out.T, out.sT);
+}
+
 // upward stabilisation after block b: C_b from the new fields, L_b = C_b L_{b-1},
 // G = (I + L_b R_b)^-1
 hq_status stab_up(Sched& S, Group& g, int b) {
   const long nn = (long)g.n * g.n;
-  ST_TRY(block_products(S, g, g.x, g.blk + b * nn, (long)g.nb * nn, g.Z, b, 1));
   const Udt in = left_entry(g, b - 1), out = left_entry(g, b), r = right_entry(g, b);
-  ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 0, in.U, in.sU, in.D, in.sD, in.T, in.sT, out.U, out.sU, out.D,
-                 out.sD, out.T, out.sT));
+  if (g.alternate) {
+    ST_TRY(chain_combine(S, g, b, false, in, out));
+  } else {
+    ST_TRY(block_products(S, g, g.x, g.blk + b * nn, (long)g.nb * nn, g.Z, b, 1));
+    ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 0, in.U, in.sU, in.D, in.sD, in.T, in.sT, out.U, out.sU,
+                   out.D, out.sD, out.T, out.sT));
+  }
   ST_TRY(merge(S, g, out.U, out.sU, out.D, out.T, out.sT, r.U, r.sU, r.D, r.sD, r.T, r.sT));
   SCHED_TRY(launch_stab_finish(g.G, S.ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.dpart, g.n,
                                g.C, 1, S.s));
@@ -837,11 +881,15 @@ hq_status stab_up(Sched& S, Group& g, int b) {
 // For b = 0 the full product goes to the scratch UDT (LU, LD, LT[0]).
 hq_status stab_down(Sched& S, Group& g, int b) {
   const long nn = (long)g.n * g.n;
-  ST_TRY(block_products(S, g, g.x, g.blk + b * nn, (long)g.nb * nn, g.Z, b, 1));
   const Udt in = right_entry(g, b);
   const Udt out = (b > 0) ? right_entry(g, b - 1) : Udt{g.LU, g.LD, g.LT[0], nn, g.n, nn};
-  ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 1, in.U, in.sU, in.D, in.sD, in.T, in.sT, out.U, out.sU, out.D,
-                 out.sD, out.T, out.sT));
+  if (g.alternate) {
+    ST_TRY(chain_combine(S, g, b, true, in, out));
+  } else {
+    ST_TRY(block_products(S, g, g.x, g.blk + b * nn, (long)g.nb * nn, g.Z, b, 1));
+    ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 1, in.U, in.sU, in.D, in.sD, in.T, in.sT, out.U, out.sU,
+                   out.D, out.sD, out.T, out.sT));
+  }
   const Udt l = left_entry(g, b - 1);
   ST_TRY(merge(S, g, l.U, l.sU, l.D, l.T, l.sT, out.U, out.sU, out.D, out.sD, out.T, out.sT));
   SCHED_TRY(launch_stab_finish(g.G, S.ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.dpart, g.n,
@@ -852,6 +900,8 @@ hq_status stab_down(Sched& S, Group& g, int b) {
 // every left stack entry from the cached block products
 hq_status left_stack(Sched& S, Group& g) {
   const long nn = (long)g.n * g.n;
+  // the sweeps of alternating groups do not keep the block products current
+  if (g.alternate) ST_TRY(block_products(S, g, g.x, g.blk, (long)g.nb * nn, g.blks, 0, g.nb));
   for (int b = 0; b < g.nb; ++b) {
     const Udt in = left_entry(g, b - 1), out = left_entry(g, b);
     ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 0, in.U, in.sU, in.D, in.sD, in.T, in.sT, out.U, out.sU,
@@ -862,6 +912,7 @@ hq_status left_stack(Sched& S, Group& g) {
 
 hq_status right_stack(Sched& S, Group& g) {
   const long nn = (long)g.n * g.n;
+  if (g.alternate) ST_TRY(block_products(S, g, g.x, g.blk, (long)g.nb * nn, g.blks, 0, g.nb));
   const long eU = (long)g.C * nn, eD = (long)g.C * g.n;   // one stack entry, all chains
   SCHED_TRY(launch_identity(g.RU + (g.nb - 1) * eU, g.RD + (g.nb - 1) * eD, g.RT + (g.nb - 1) * eU, g.n, g.C, S.s));
   for (int b = g.nb - 2; b >= 0; --b) {

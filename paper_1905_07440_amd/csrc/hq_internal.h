@@ -96,7 +96,9 @@ hipError_t launch_wrap_fused(const WrapArgs<float>& w, hipStream_t s);
 // Products with A (x) A for an nx x nx factor A (kron.hip), the form that
 // exp(s dtau K) takes on the periodic square lattice; site i = ix + nx iy.
 //   side 0: Y[z] = diag(r_{S-1}) (A (x) A) ... diag(r_0) (A (x) A) diag(ks) X[z] diag(cs)
-//           for S = steps, r_t = rs read at rs.off + t * rstep
+//           for S = steps, r_t = rs read at rs.off + t * rstep (rstep may be
+//           negative); with pre = 1 each scale comes before its product:
+//           Y[z] = (A (x) A) diag(r_{S-1}) ... (A (x) A) diag(r_0) diag(ks) X[z] diag(cs)
 //   side 1: Y[z] = diag(rs) X[z] diag(ks) (A (x) A) diag(cs)     (steps = 1)
 // X, Y n x n row-major (n = nx^2 <= 256), advancing by sX, sY per batch
 // entry (sX = 0: one X for the whole batch); Y must not overlap X.  A shared
@@ -110,6 +112,7 @@ struct KronArgs {
   T* Y = nullptr; long sY = 0;
   Scale rs, ks, cs;
   int steps = 1; long rstep = 0;
+  int pre = 0;
 };
 // A whole wrap Y = diag(rs2) (A1 (x) A1) diag(ks1) X diag(cs1) (A2 (x) A2)
 // diag(cs2) in one launch, X resident in LDS (kron.hip): nx <= 12 in FP32,

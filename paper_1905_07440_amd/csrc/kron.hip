@@ -22,7 +22,9 @@
 //
 // side 0 (left):  Y = diag(rs) (A (x) A) diag(ks) X diag(cs), or a chain of
 //   such products with a row scale after each (a block product
-//   B_{s-1} ... B_0 = diag(v_{s-1}) E ... diag(v_0) E from X = I).  One
+//   B_{s-1} ... B_0 = diag(v_{s-1}) E ... diag(v_0) E applied to X), or
+//   before each (the transposed product E diag(v_0) ... E diag(v_{s-1}) X,
+//   scales taken in descending order).  One
 //   workgroup per strip of KW = 16 columns of one matrix, held in LDS through
 //   every step of a chain; pass 1 contracts kx within each block of rows
 //   ky nx .. ky nx + nx - 1, pass 2 contracts ky across blocks.
@@ -111,14 +113,19 @@ __global__ __launch_bounds__(256) void kron_left_kernel(KronArgs<T> a) {
   }
   __syncthreads();
 
+  const bool pre = a.pre != 0;
   for (int t = 0; t < steps; ++t) {
+    const double* rt = rsv + t * N;
     // pass 1: within block b, D[ix][c] = sum_kx A[ix][kx] S[b nx + kx][c]
+    // (rows scaled first in the pre-scaled form)
     for (int b = wave; b < NX; b += 4) {
       typename Frag<T>::type acc = {0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk) {
         const int k = 4 * kk + lk;
-        const T bv = S[lidx<NX>(b * NX + min(k, NX - 1), li)];
+        const int row = b * NX + min(k, NX - 1);
+        T bv = S[lidx<NX>(row, li)];
+        if (pre) bv *= (T)rt[row];
         acc = mfma16(af[kk], k < NX ? bv : T(0), acc);
       }
 #pragma unroll
@@ -128,8 +135,8 @@ __global__ __launch_bounds__(256) void kron_left_kernel(KronArgs<T> a) {
       }
     }
     __syncthreads();
-    // pass 2: for ix = b, D[iy][c] = sum_ky A[iy][ky] S[ky nx + b][c], rows scaled
-    const double* rt = rsv + t * N;
+    // pass 2: for ix = b, D[iy][c] = sum_ky A[iy][ky] S[ky nx + b][c], rows
+    // scaled after (the post-scaled form)
     for (int b = wave; b < NX; b += 4) {
       typename Frag<T>::type acc = {0, 0, 0, 0};
 #pragma unroll
@@ -143,7 +150,7 @@ __global__ __launch_bounds__(256) void kron_left_kernel(KronArgs<T> a) {
         const int m = frag_row<T>(lane, v);
         if (m < NX) {
           const int r = m * NX + b;
-          S[lidx<NX>(r, li)] = acc[v] * (T)rt[r];
+          S[lidx<NX>(r, li)] = pre ? acc[v] : acc[v] * (T)rt[r];
         }
       }
     }
