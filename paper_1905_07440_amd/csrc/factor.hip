@@ -144,8 +144,8 @@ __device__ inline void wave_totals8(const double (&v)[8], double (&t)[8]) {
 // above the diagonal and the reflectors below it, for every c < 16 and every
 // row slot r; tau[j] the reflectors' scales.
 // ---------------------------------------------------------------------------
-template <int RPL, typename Load, typename Store>
-__device__ inline void factor_panel(int nbw, int m, double (*Colj)[MAXN], double* tau, Load load, Store store) {
+template <int RPL, int CAP, typename Load, typename Store>
+__device__ inline void factor_panel(int nbw, int m, double (*Colj)[CAP], double* tau, Load load, Store store) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   double a[4][RPL];
@@ -164,7 +164,7 @@ __device__ inline void factor_panel(int nbw, int m, double (*Colj)[MAXN], double
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
           const int r = lane + 64 * t;
-          if (r < MAXN) Colj[j & 1][r] = a[jq][t];
+          if (r < CAP) Colj[j & 1][r] = a[jq][t];
         }
       }
       __syncthreads();
@@ -243,8 +243,8 @@ __device__ inline void factor_panel(int nbw, int m, double (*Colj)[MAXN], double
 // receives it eliminated, for every c < 16 and row slot r;
 // perm[p0 + j], pinv[row] and pivot[p0 + j] record the pivots.
 // ---------------------------------------------------------------------------
-template <int RPL, typename Load, typename Store>
-__device__ inline void eliminate_panel(int p0, int nbw, int n, double (*Colj)[MAXN], bool (&used)[RPL], int* perm,
+template <int RPL, int CAP, typename Load, typename Store>
+__device__ inline void eliminate_panel(int p0, int nbw, int n, double (*Colj)[CAP], bool (&used)[RPL], int* perm,
                                        int* pinv, double* pivot, Load load, Store store) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -264,7 +264,7 @@ __device__ inline void eliminate_panel(int p0, int nbw, int n, double (*Colj)[MA
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
           const int r = lane + 64 * t;
-          if (r < MAXN) Colj[j & 1][r] = a[jq][t];
+          if (r < CAP) Colj[j & 1][r] = a[jq][t];
         }
       }
       __syncthreads();
@@ -272,7 +272,7 @@ __device__ inline void eliminate_panel(int p0, int nbw, int n, double (*Colj)[MA
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const int r = lane + 64 * t;
-        aj[t] = (r < MAXN) ? Colj[j & 1][r] : 0.0;
+        aj[t] = (r < CAP) ? Colj[j & 1][r] : 0.0;
       }
       uint32_t key = 0;
 #pragma unroll
@@ -386,7 +386,8 @@ __device__ void apply_reflector(double* A, int n, int p0, int m, const double (*
 // V^T V, which comes from MFMA (both operands are the same V fragment, the
 // four waves taking every fourth 4-row chunk).  T is built by recursive
 // doubling, one element per thread (see below).
-__device__ void form_t(const double (*Vs)[VLD], int m, int nbw, const double* tau, double (*Gm)[NB + 1],
+template <int LD>
+__device__ void form_t(const double (*Vs)[LD], int m, int nbw, const double* tau, double (*Gm)[NB + 1],
                        double (*Ts)[NB + 1], double (*Sc)[NB][NB + 1]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -536,15 +537,22 @@ __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, d
                                                       double* __restrict__ Tg, int n) {
   constexpr int NTT = (MX + 15) / 16;      // tile rows
   constexpr int CPW = (NTT + 3) / 4;       // tile columns per wave
-  __shared__ double Vs[NB][VLD];
-  __shared__ double Pn[NB][VLD];           // the panel being factored, column-major
+  // panel rows and column j in LDS cover every row slot of factor_panel (64
+  // per lane register).  Compact rows where the registers leave room for
+  // three workgroups per CU (N <= 64: 35 KB of LDS instead of 90 KB); the
+  // larger sizes run one workgroup per CU and keep the full row length, with
+  // which the register allocation spills least
+  constexpr int CJ = 64 * Cap<MX>::rpl;
+  constexpr int LD = (MX <= 64) ? MX + 16 : VLD;   // panel row length (zero tail)
+  __shared__ double Vs[NB][LD];
+  __shared__ double Pn[NB][LD];            // the panel being factored, column-major
   __shared__ double Ts[NB][NB + 1];
   __shared__ double Gm[NB][NB + 1];
   __shared__ double Sc[4][NB][NB + 1];
-  __shared__ double norms[MAXN];
+  __shared__ double norms[MX];
   __shared__ double tau[NB];
-  __shared__ double Colj[2][MAXN];         // panel column j, alternating per column
-  __shared__ int perm[MAXN];
+  __shared__ double Colj[2][CJ];           // panel column j, alternating per column
+  __shared__ int perm[MX];
   const int z = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -649,13 +657,13 @@ __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, d
         nbw, m, Colj, tau, [&](int c, int r) { return Pn[c][r]; },
         [&](int c, int r, double v) {
           // V (unit diagonal, zero above, zero past the panel) to Vs; R and V to Pn and to W
-          if (r < VLD) {
+          if (r < LD) {
             Vs[c][r] = (c < nbw && r < m) ? ((r == c) ? 1.0 : ((r > c) ? v : 0.0)) : 0.0;
             Pn[c][r] = (c < nbw && r < m) ? v : 0.0;
           }
           if (c < nbw && r < m) W[(long)(p0 + r) * n + p0 + c] = v;
         });
-    Vs[tid >> 4][MAXN + (tid & 15)] = 0.0;
+    Vs[tid >> 4][MX + (tid & 15)] = 0.0;
     __syncthreads();
     form_t(Vs, m, nbw, tau, Gm, Ts, Sc);
     Tst[(long)p * NB * NB + tid] = Ts[tid >> 4][tid & 15];
@@ -724,14 +732,14 @@ __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, d
   for (int p = npan - 1; p >= 0; --p) {
     const int p0 = p * NB, nbw = min(NB, n - p0), m = n - p0;
     __syncthreads();
-    batched_copy<256, 17, double>(NB * VLD,
+    batched_copy<256, (NB * LD + 255) / 256, double>(NB * LD,
                                   [&](int e) {
-                                    const int j = e / VLD, r = e - j * VLD;
+                                    const int j = e / LD, r = e - j * LD;
                                     double v = 0.0;
                                     if (j < nbw && r < m) v = (r == j) ? 1.0 : ((r > j) ? W[(long)(p0 + r) * n + p0 + j] : 0.0);
                                     return v;
                                   },
-                                  [&](int e, double v) { Vs[e / VLD][e % VLD] = v; });
+                                  [&](int e, double v) { Vs[e / LD][e % LD] = v; });
     Ts[tid >> 4][tid & 15] = Tst[(long)p * NB * NB + tid];
     __syncthreads();
 #pragma unroll
@@ -875,13 +883,13 @@ __global__ __launch_bounds__(256) void gj_regs_kernel(double* __restrict__ Mg, d
   constexpr int CPW = (NTT + 3) / 4;       // tile columns per wave
   constexpr int RPL = Cap<MX>::rpl;
   static_assert(4 * NTT <= 64, "pivot-row flags hold 64 rows per lane");
-  __shared__ double Pn[NB][VLD];           // the panel, column-major; after elimination its F
+  __shared__ double Pn[NB][MX];            // the panel, column-major; after elimination its F
   __shared__ double Cs[4][NTT * 16][NB + 1];   // per-wave copy of one tile column
-  __shared__ int perm[MAXN];               // perm[j]: pivot row of column j
-  __shared__ int pinv[MAXN];
-  __shared__ double pivot[MAXN];           // pivot value of column j
-  __shared__ double Colj[2][MAXN];         // panel column j, alternating per column
-  __shared__ double rsl[MAXN], csl[MAXN];
+  __shared__ int perm[MX];                 // perm[j]: pivot row of column j
+  __shared__ int pinv[MX];
+  __shared__ double pivot[MX];             // pivot value of column j
+  __shared__ double Colj[2][64 * RPL];     // panel column j, alternating per column
+  __shared__ double rsl[MX], csl[MX];
   __shared__ double part[4];
   const int z = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63;

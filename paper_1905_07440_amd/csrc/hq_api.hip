@@ -601,7 +601,9 @@ hq_status tree_product(Sched& S, Group& g, const double* blocks, Udt& out) {
     x.cs.v = D; x.cs.so = (long)m * n; x.cs.si = 2L * n;
     x.inner_count = pairs;
     SCHED_TRY(launch_gemm(x, pairs > 2 ? g.tile_wide : g.tile, S.s));
-    SCHED_TRY(launch_qr(g.tX, g.tQW, g.tUp, g.tDp, g.tQT, n, C * pairs, S.s));
+    // with m even the next level's D has the layout of the QR's ([C][pairs])
+    double* Dq = (m % 2) ? g.tDp : g.tD[nxt];
+    SCHED_TRY(launch_qr(g.tX, g.tQW, g.tUp, Dq, g.tQT, n, C * pairs, S.s));
     // U_next = U_a U', T_next = T' T_b, D_next = D'; entries [C][m2]
     GemmArgs<double> u = sq(g, C * pairs);
     u.split = pairs;
@@ -615,14 +617,18 @@ hq_status tree_product(Sched& S, Group& g, const double* blocks, Udt& out) {
     t.B = T; t.sB = 2 * nn; t.sBo = (long)m * nn;
     t.C = g.tT[nxt]; t.sC = nn; t.sCo = (long)m2 * nn;
     SCHED_TRY(launch_gemm(t, pairs > 2 ? g.tile_wide : g.tile, S.s));
-    SCHED_TRY(launch_copy_blocks(g.tD[nxt], (long)m2 * n, n, g.tDp, (long)pairs * n, n, n, C, pairs, S.s));
-    if (m % 2) {                           // the unpaired last block
-      SCHED_TRY(launch_copy_blocks(g.tU[nxt] + (m2 - 1) * nn, (long)m2 * nn, 0, U + (m - 1) * nn, (long)m * nn, 0,
-                                   nn, C, 1, S.s));
-      SCHED_TRY(launch_copy_blocks(g.tT[nxt] + (m2 - 1) * nn, (long)m2 * nn, 0, T + (m - 1) * nn, (long)m * nn, 0,
-                                   nn, C, 1, S.s));
-      SCHED_TRY(launch_copy_blocks(g.tD[nxt] + (long)(m2 - 1) * n, (long)m2 * n, 0, D + (long)(m - 1) * n,
-                                   (long)m * n, 0, n, C, 1, S.s));
+    if (m % 2) {                           // D of the pairs, and the unpaired last block, in one launch
+      BlockCopies cp;
+      auto add = [&](double* dst, long dso, const double* src, long sso, long len) {
+        BlockCopy& q = cp.c[cp.k++];
+        q.dst = dst; q.dso = dso; q.src = src; q.sso = sso; q.len = len;
+        q.outer = C; q.inner = 1;
+      };
+      add(g.tD[nxt], (long)m2 * n, g.tDp, (long)pairs * n, (long)pairs * n);
+      add(g.tU[nxt] + (m2 - 1) * nn, (long)m2 * nn, U + (m - 1) * nn, (long)m * nn, nn);
+      add(g.tT[nxt] + (m2 - 1) * nn, (long)m2 * nn, T + (m - 1) * nn, (long)m * nn, nn);
+      add(g.tD[nxt] + (long)(m2 - 1) * n, (long)m2 * n, D + (long)(m - 1) * n, (long)m * n, n);
+      SCHED_TRY(launch_copy_blocks_multi(cp, S.s));
     }
     cur = nxt;
     m = m2;

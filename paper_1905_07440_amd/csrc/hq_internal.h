@@ -295,6 +295,18 @@ hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, long count, hipSt
 // dst[o dso + i dsi + e] = src[o sso + i ssi + e] for e < len, o < outer, i < inner
 hipError_t launch_copy_blocks(double* dst, long dso, long dsi, const double* src, long sso, long ssi, long len,
                               int outer, int inner, hipStream_t s);
+// up to four such copies in one launch (copies of nonpositive size are skipped)
+struct BlockCopy {
+  double* dst = nullptr;
+  const double* src = nullptr;
+  long dso = 0, dsi = 0, sso = 0, ssi = 0, len = 0;
+  int outer = 0, inner = 0;
+};
+struct BlockCopies {
+  BlockCopy c[4];
+  int k = 0;
+};
+hipError_t launch_copy_blocks_multi(const BlockCopies& c, hipStream_t s);
 
 // counters layout per chain
 enum { CNT_LOCAL_P = 0, CNT_LOCAL_A, CNT_GLOBAL_P, CNT_GLOBAL_A, CNT_NN_P, CNT_NN_A, CNT_CUM_P,

@@ -172,6 +172,33 @@ hipError_t launch_copy_blocks(double* dst, long dso, long dsi, const double* src
   return hipGetLastError();
 }
 
+// blockIdx.y runs over the (o, i) pairs of every copy in turn
+__global__ void copy_blocks_multi_kernel(BlockCopies c) {
+  int y = blockIdx.y, q = 0;
+  while (q < c.k - 1 && y >= c.c[q].outer * c.c[q].inner) {
+    y -= c.c[q].outer * c.c[q].inner;
+    ++q;
+  }
+  const BlockCopy& b = c.c[q];
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = y / b.inner, i = y - o * b.inner;
+  if (e < b.len) b.dst[o * b.dso + i * b.dsi + e] = b.src[o * b.sso + i * b.ssi + e];
+}
+hipError_t launch_copy_blocks_multi(const BlockCopies& c, hipStream_t s) {
+  BlockCopies d;
+  long len = 0, rows = 0;
+  for (int q = 0; q < c.k && q < 4; ++q)
+    if (c.c[q].len > 0 && c.c[q].outer > 0 && c.c[q].inner > 0) {
+      d.c[d.k++] = c.c[q];
+      len = std::max(len, c.c[q].len);
+      rows += (long)c.c[q].outer * c.c[q].inner;
+    }
+  if (d.k == 0) return hipSuccess;
+  if (rows > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(copy_blocks_multi_kernel, dim3(nblk(len), (unsigned)rows), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy_f64_to_f32(float* dst, const double* src, long count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(f64_to_f32_kernel, dim3(nblk(count)), dim3(256), 0, s, dst, src, count);
