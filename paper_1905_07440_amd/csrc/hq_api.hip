@@ -585,8 +585,8 @@ hq_status tree_product(Sched& S, Group& g, const double* blocks, Udt& out) {
   const long nn = (long)g.n * g.n;
   const int n = g.n, C = g.C;
   int cur = 0, m = g.nb;
-  // level 0: Z = C_b (copied: the QR writes its triangular factor over its input)
-  SCHED_TRY(launch_copy_f64(g.tT[0], blocks, (long)C * g.nb * nn, S.s));
+  // level 0: Z = C_b (in tT[0], where the QR writes its triangular factor over its input)
+  if (blocks != g.tT[0]) SCHED_TRY(launch_copy_f64(g.tT[0], blocks, (long)C * g.nb * nn, S.s));
   SCHED_TRY(launch_qr(g.tT[0], g.tQW, g.tU[0], g.tD[0], g.tQT, n, C * g.nb, S.s));
   while (m > 1) {
     const int pairs = m / 2, m2 = (m + 1) / 2, nxt = 1 - cur;
@@ -639,7 +639,8 @@ hq_status tree_product(Sched& S, Group& g, const double* blocks, Udt& out) {
 
 // G and log|det M| of the fields xs from scratch: all block products, the
 // left UDT chain over every block, and the merge with an identity right part.
-// Leaves the block products in `blocks`.
+// Leaves the block products in `blocks`, unless `blocks` is the tree's level-0
+// buffer, which the pairwise merges factor in place.
 hq_status from_scratch(Sched& S, Group& g, const double* xs, double* blocks) {
   const long nn = (long)g.n * g.n;
   ST_TRY(block_products(S, g, xs, blocks, 0, g.blks, 0, g.nb));
@@ -903,11 +904,13 @@ hq_status stab_down(Sched& S, Group& g, int b) {
   return HQ_OK;
 }
 
-// every left stack entry from the cached block products
+// every left stack entry from the block products of the current fields (the
+// cache is not kept current across sweeps: alternating sweeps combine straight
+// from the fields, and accepted block moves or cumulative updates change
+// whole columns of x without touching it)
 hq_status left_stack(Sched& S, Group& g) {
   const long nn = (long)g.n * g.n;
-  // the sweeps of alternating groups do not keep the block products current
-  if (g.alternate) ST_TRY(block_products(S, g, g.x, g.blk, (long)g.nb * nn, g.blks, 0, g.nb));
+  ST_TRY(block_products(S, g, g.x, g.blk, (long)g.nb * nn, g.blks, 0, g.nb));
   for (int b = 0; b < g.nb; ++b) {
     const Udt in = left_entry(g, b - 1), out = left_entry(g, b);
     ST_TRY(combine(S, g, g.blk + b * nn, (long)g.nb * nn, 0, in.U, in.sU, in.D, in.sD, in.T, in.sT, out.U, out.sU,
@@ -918,7 +921,7 @@ hq_status left_stack(Sched& S, Group& g) {
 
 hq_status right_stack(Sched& S, Group& g) {
   const long nn = (long)g.n * g.n;
-  if (g.alternate) ST_TRY(block_products(S, g, g.x, g.blk, (long)g.nb * nn, g.blks, 0, g.nb));
+  ST_TRY(block_products(S, g, g.x, g.blk, (long)g.nb * nn, g.blks, 0, g.nb));
   const long eU = (long)g.C * nn, eD = (long)g.C * g.n;   // one stack entry, all chains
   SCHED_TRY(launch_identity(g.RU + (g.nb - 1) * eU, g.RD + (g.nb - 1) * eD, g.RT + (g.nb - 1) * eU, g.n, g.C, S.s));
   for (int b = g.nb - 2; b >= 0; --b) {
@@ -938,11 +941,11 @@ hq_status global_moves(Sched& S, Group& g) {
     a.seed = S.ctx->seed; a.chain0 = g.chain0; a.sweep = S.ctx->sweep_counter;
     a.shift = g.shift; a.logdet = g.logdet; a.logdet_new = g.logdet_new;
     a.G = g.G; a.precision = S.ctx->opt.precision; a.Gnew = g.Gnew;
-    a.blk = g.blk; a.blkp = g.blkp; a.counters = g.counters;
+    a.counters = g.counters;
     a.log_margin = g.log_margin[HQ_KIND_GLOBAL]; a.log_accept = g.log_accept[HQ_KIND_GLOBAL];
     a.replay = g.replay[HQ_KIND_GLOBAL]; a.band = g.band[HQ_KIND_GLOBAL]; a.replay_counts = g.replay_counts;
     SCHED_TRY(launch_global_propose(a, g.C, S.s));
-    ST_TRY(from_scratch(S, g, g.xp, g.blkp));
+    ST_TRY(from_scratch(S, g, g.xp, g.tree ? g.tT[0] : g.blkp));
     SCHED_TRY(launch_global_accept(a, g.C, S.s));
   }
   return HQ_OK;
@@ -987,12 +990,12 @@ hq_status network_sweep(Sched& S, Group& g) {
         SCHED_TRY(launch_cnn_colour(a, g.C, S.s));
       }
   }
-  ST_TRY(from_scratch(S, g, g.xp, g.blkp));
+  ST_TRY(from_scratch(S, g, g.xp, g.tree ? g.tT[0] : g.blkp));
   CumulativeArgs c;
   c.n = g.n; c.L = g.L; c.nb = g.nb;
   c.x = g.x; c.xp = g.xp; c.logdet = g.logdet; c.logdet_new = g.logdet_new;
   c.G = g.G; c.precision = ctx->opt.precision; c.Gnew = g.Gnew;
-  c.blk = g.blk; c.blkp = g.blkp; c.sum_y = g.sum_y; c.accepted = g.nn_acc;
+  c.sum_y = g.sum_y; c.accepted = g.nn_acc;
   c.sum_yb = g.sum_yb; c.accepted_b = g.acc_b; c.inner = g.nu;
   c.seed = ctx->seed; c.chain0 = g.chain0; c.sweep = ctx->sweep_counter; c.counters = g.counters;
   c.log_margin = g.log_margin[HQ_KIND_CUMULATIVE]; c.log_accept = g.log_accept[HQ_KIND_CUMULATIVE];

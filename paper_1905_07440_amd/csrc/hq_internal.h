@@ -215,7 +215,6 @@ struct GlobalArgs {
   const double* logdet_new = nullptr;
   void* G = nullptr; int precision = 0;
   const double* Gnew = nullptr;
-  double* blk = nullptr; const double* blkp = nullptr;   // [C][nb][n][n]
   int64_t* counters = nullptr;
   float* log_margin = nullptr; uint8_t* log_accept = nullptr;
   const uint8_t* replay = nullptr; double band = 0; int64_t* replay_counts = nullptr;
@@ -279,7 +278,6 @@ struct CumulativeArgs {
   double* x = nullptr; const double* xp = nullptr;
   double* logdet = nullptr; const double* logdet_new = nullptr;
   void* G = nullptr; int precision = 0; const double* Gnew = nullptr;
-  double* blk = nullptr; const double* blkp = nullptr;
   const double* sum_y = nullptr; const uint8_t* accepted = nullptr;
   const double* sum_yb = nullptr; const uint8_t* accepted_b = nullptr;   // block moves, [C][n], or null
   int inner = 1;                // n_u: proposals per slot of each kind

@@ -322,10 +322,6 @@ __global__ void global_accept_kernel(GlobalArgs a) {
     copy_green<float>((float*)a.G + c * nn, a.Gnew + c * nn, nn);
   else
     copy_green<double>((double*)a.G + c * nn, a.Gnew + c * nn, nn);
-  const long nbk = (long)a.nb * nn;
-  const double* src = a.blkp + c * nbk;
-  double* dst = a.blk + c * nbk;
-  batched_copy<256, 16, double>((int)nbk, [&](int e) { return src[e]; }, [&](int e, double v) { dst[e] = v; });
 }
 
 hipError_t launch_global_accept(const GlobalArgs& a, int chains, hipStream_t s) {

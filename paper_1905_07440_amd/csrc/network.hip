@@ -342,10 +342,6 @@ __global__ void cumulative_kernel(CumulativeArgs a) {
     double* G = (double*)a.G + c * nn;
     batched_copy<256, 16, double>((int)nn, [&](int e) { return gn[e]; }, [&](int e, double v) { G[e] = v; });
   }
-  const long nblk = (long)a.nb * nn;
-  const double* bp = a.blkp + c * nblk;
-  double* bk = a.blk + c * nblk;
-  batched_copy<256, 16, double>((int)nblk, [&](int e) { return bp[e]; }, [&](int e, double v) { bk[e] = v; });
 }
 
 hipError_t launch_cumulative(const CumulativeArgs& a, int chains, hipStream_t s) {
