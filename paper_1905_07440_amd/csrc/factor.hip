@@ -382,6 +382,88 @@ __device__ void apply_reflector(double* A, int n, int p0, int m, const double (*
   }
 }
 
+// The same update with buffer loads and stores: one resource for rows p0..n
+// of A, so a tile element's address is a per-lane byte offset (four of them,
+// one per fragment row, plus the tile's start) instead of a 64-bit pointer
+// per element.  Rows past n fall outside the resource (loads give 0, stores
+// are dropped); columns past n take an offset past it on purpose.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr unsigned BUF_WORD3 = 0x00020000u;   // raw buffer, 32-bit data format (gfx9)
+constexpr unsigned BUF_OUTSIDE = 0x80000000u;  // an offset no resource here reaches
+// a double through the 64-bit buffer operations, word by word (a bit cast of an
+// accumulator element straight to the two-word type stored wrong values for
+// every element but the first)
+__device__ inline double buf_load_f64(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return __builtin_bit_cast(double, ((unsigned long long)w.y << 32) | w.x);
+}
+__device__ inline void buf_store_f64(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  u32x2 w;
+  w.x = (unsigned)u;
+  w.y = (unsigned)(u >> 32);
+  __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, 0);
+}
+
+template <int MX>
+__device__ __attribute__((always_inline)) void apply_reflector_buf(double* A, int n, int p0, int m, const double (*Vs)[VLD],
+                                    const double (*Ts)[NB + 1], int transT, int c_begin, double (*Sc)[NB + 1]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nstrip = (n - c_begin + 15) / 16;
+  const int ntile = (m + 15) / 16;
+  const __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc(A + (long)p0 * n, 0, (int)((long)m * n * 8), BUF_WORD3);
+  const unsigned tstep = 16u * (unsigned)n * 8u;   // bytes per 16 rows
+  for (int s = wave; s < nstrip; s += 4) {
+    const int col = c_begin + 16 * s + li;
+    unsigned off[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      off[v] = (col < n) ? ((unsigned)(frag_row<double>(lane, v) * n + col) * 8u) : BUF_OUTSIDE;
+    d4 tile[Cap<MX>::tiles];
+#pragma unroll
+    for (int t = 0; t < Cap<MX>::tiles; ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        tile[t][v] = (t < ntile && col < n) ? buf_load_f64(rsrc, off[v] + t * tstep) : 0.0;
+    }
+    d4 w1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < Cap<MX>::tiles; ++t)
+      if (t < ntile) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w1 = mfma16(Vs[li][16 * t + 4 * q + lk], tile[t][q], w1);
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Sc[frag_row<double>(lane, v)][li] = w1[v];
+    wave_sync_lds();
+    d4 w2 = {0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+      const double at = transT ? Ts[k0 + lk][li] : Ts[li][k0 + lk];
+      w2 = mfma16(at, Sc[k0 + lk][li], w2);
+    }
+    wave_sync_lds();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Sc[frag_row<double>(lane, v)][li] = w2[v];
+    wave_sync_lds();
+    double wb[NB / 4];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) wb[q] = Sc[4 * q + lk][li];
+#pragma unroll
+    for (int t = 0; t < Cap<MX>::tiles; ++t)
+      if (t < ntile) {
+#pragma unroll
+        for (int q = 0; q < NB / 4; ++q) tile[t] = mfma16(-Vs[4 * q + lk][16 * t + li], wb[q], tile[t]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          buf_store_f64(tile[t][v], rsrc, off[v] + t * tstep);
+      }
+    wave_sync_lds();
+  }
+}
+
 // T (upper triangular; H_0 ... H_{nb-1} = I - V T V^T) from the Gram matrix
 // V^T V, which comes from MFMA (both operands are the same V fragment, the
 // four waves taking every fourth 4-row chunk).  T is built by recursive
@@ -486,7 +568,7 @@ __global__ __launch_bounds__(256) void qr_blocked_kernel(double* __restrict__ Zg
     __syncthreads();
     form_t(Vs, m, nbw, tau, Gm, Ts, Sc);
     Tst[(long)pi * NB * NB + tid] = Ts[tid >> 4][tid & 15];
-    apply_reflector<MX>(W, n, p0, m, Vs, Ts, 1, p0 + nbw, Sc[wave]);
+    apply_reflector_buf<MX>(W, n, p0, m, Vs, Ts, 1, p0 + nbw, Sc[wave]);
     __syncthreads();
   }
 
@@ -517,7 +599,7 @@ __global__ __launch_bounds__(256) void qr_blocked_kernel(double* __restrict__ Zg
                                   [&](int e, double v) { Vs[e / VLD][e % VLD] = v; });
     Ts[tid >> 4][tid & 15] = Tst[(long)pi * NB * NB + tid];
     __syncthreads();
-    apply_reflector<MX>(Q, n, p0, m, Vs, Ts, 0, p0, Sc[wave]);
+    apply_reflector_buf<MX>(Q, n, p0, m, Vs, Ts, 0, p0, Sc[wave]);
     __syncthreads();
   }
 }
