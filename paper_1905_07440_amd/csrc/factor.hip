@@ -885,8 +885,11 @@ __global__ __launch_bounds__(256) void inv_blocked_kernel(double* __restrict__ M
     for (int j = tid; j < nbw; j += 256) panel_of[perm[p0 + j]] = pi;
     Fs[tid >> 4][MAXN + (tid & 15)] = 0.0;
     __syncthreads();
-    // rank-NB update of every column outside the panel, all rows
+    // rank-NB update of every column outside the panel, all rows (tiles through
+    // buffer loads and stores, as in the QR's reflector updates)
     const int nstrip = (n + 15) / 16;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(W, 0, (int)((long)n * n * 8), BUF_WORD3);
+    const unsigned tstep = 16u * (unsigned)n * 8u;
     for (int s = wave; s < nstrip; s += 4) {
       const int c0 = 16 * s;
       const int col = c0 + li;
@@ -900,13 +903,16 @@ __global__ __launch_bounds__(256) void inv_blocked_kernel(double* __restrict__ M
       }
       wave_sync_lds();
       const int ntile = (n + 15) / 16;
+      unsigned off[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) off[v] = incol ? ((unsigned)(frag_row<double>(lane, v) * n + col) * 8u) : BUF_OUTSIDE;
       d4 tile[Cap<MX>::tiles];
 #pragma unroll
       for (int t = 0; t < Cap<MX>::tiles; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = 16 * t + frag_row<double>(lane, v);
-          tile[t][v] = (t < ntile && row < n && incol && panel_of[row] != pi) ? W[(long)row * n + col] : 0.0;
+          const int row = 16 * t + frag_row<double>(lane, v);   // rows past n: outside the resource
+          tile[t][v] = (t < ntile && incol && panel_of[row] != pi) ? buf_load_f64(rsrc, off[v] + t * tstep) : 0.0;
         }
       double tb[NB / 4];
 #pragma unroll
@@ -917,10 +923,7 @@ __global__ __launch_bounds__(256) void inv_blocked_kernel(double* __restrict__ M
 #pragma unroll
           for (int q = 0; q < NB / 4; ++q) tile[t] = mfma16(Fs[4 * q + lk][16 * t + li], tb[q], tile[t]);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = 16 * t + frag_row<double>(lane, v);
-            if (row < n && incol) W[(long)row * n + col] = tile[t][v];
-          }
+          for (int v = 0; v < 4; ++v) buf_store_f64(tile[t][v], rsrc, off[v] + t * tstep);
         }
       wave_sync_lds();
     }
