@@ -18,7 +18,7 @@ namespace hq {
 // out of one buffer, every thread's loads of the next 16-wide K chunk are in
 // flight, and one barrier per chunk separates the two.
 template <typename T, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs<T>& a, int z, int tile) {
   constexpr int NT = WM * WN * 64;
   constexpr int BK = 16;
   constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
@@ -31,9 +31,7 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
   __shared__ double csv[BN];
   __shared__ double ksv[256];
 
-  const int tn = (a.N + BN - 1) / BN, tm = (a.M + BM - 1) / BM;
-  int z, tile;
-  if (!xcd_tile(tn * tm, a.batch, z, tile)) return;
+  const int tn = (a.N + BN - 1) / BN;
   const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -144,6 +142,25 @@ __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
           *dst = (T)val;
         }
       }
+}
+
+template <typename T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
+  int z, tile;
+  if (!xcd_tile(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch, z, tile)) return;
+  gemm_tile<T, BM, BN, WM, WN>(a, z, tile);
+}
+
+// two independent products of one shape in one launch: batch entries
+// [0, a.batch) are a's, the next b.batch are b's
+template <typename T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void gemm_pair_kernel(GemmArgs<T> a, GemmArgs<T> b) {
+  int z, tile;
+  if (!xcd_tile(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch + b.batch, z, tile)) return;
+  if (z < a.batch)
+    gemm_tile<T, BM, BN, WM, WN>(a, z, tile);
+  else
+    gemm_tile<T, BM, BN, WM, WN>(b, z - a.batch, tile);
 }
 
 // Full-K variant for K <= a few hundred (every DQMC product has K = N <= 256):
@@ -417,6 +434,34 @@ static hipError_t launch_tile(const GemmArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int BM, int BN, int WM, int WN>
+static hipError_t launch_pair_tile(const GemmArgs<T>& a, const GemmArgs<T>& b, hipStream_t s) {
+  const dim3 grid(xcd_grid(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch + b.batch));
+  hipLaunchKernelGGL((gemm_pair_kernel<T, BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s, a, b);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_any(const GemmArgs<T>& a, int tile, hipStream_t s);
+
+// a and b in one launch where both have the same M and N and the tile is a
+// staged one; otherwise one after the other
+template <typename T>
+static hipError_t launch_pair_any(const GemmArgs<T>& a, const GemmArgs<T>& b, int tile, hipStream_t s) {
+  const bool same = a.M == b.M && a.N == b.N && a.M > 0 && a.N > 0 && a.batch > 0 && b.batch > 0 &&
+                    !(a.ks.v && a.K > 256) && !(b.ks.v && b.K > 256);
+  if (same) switch (tile) {
+      case TILE_32x32: return launch_pair_tile<T, 32, 32, 2, 2>(a, b, s);
+      case TILE_48x48: return launch_pair_tile<T, 48, 48, 3, 1>(a, b, s);
+      case TILE_16x64: return launch_pair_tile<T, 16, 64, 1, 4>(a, b, s);
+      case TILE_64x64: return launch_pair_tile<T, 64, 64, 2, 2>(a, b, s);
+      default: break;
+    }
+  hipError_t e = launch_any(a, tile, s);
+  if (e != hipSuccess) return e;
+  return launch_any(b, tile, s);
+}
+
 template <typename T>
 static hipError_t launch_any(const GemmArgs<T>& a, int tile, hipStream_t s) {
   if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
@@ -438,6 +483,9 @@ static hipError_t launch_any(const GemmArgs<T>& a, int tile, hipStream_t s) {
 
 hipError_t launch_gemm(const GemmArgs<double>& a, int tile, hipStream_t s) { return launch_any(a, tile, s); }
 hipError_t launch_gemm(const GemmArgs<float>& a, int tile, hipStream_t s) { return launch_any(a, tile, s); }
+hipError_t launch_gemm_pair(const GemmArgs<double>& a, const GemmArgs<double>& b, int tile, hipStream_t s) {
+  return launch_pair_any(a, b, tile, s);
+}
 
 bool gemm_tile_fits(int tile, int K, int precision) {
   const bool f = precision != 0;

@@ -610,13 +610,12 @@ hq_status tree_product(Sched& S, Group& g, const double* blocks, Udt& out) {
     u.A = U + nn; u.sA = 2 * nn; u.sAo = (long)m * nn;
     u.B = g.tUp; u.sB = nn; u.sBo = (long)pairs * nn;
     u.C = g.tU[nxt]; u.sC = nn; u.sCo = (long)m2 * nn;
-    SCHED_TRY(launch_gemm(u, pairs > 2 ? g.tile_wide : g.tile, S.s));
     GemmArgs<double> t = sq(g, C * pairs);
     t.split = pairs;
     t.A = g.tX; t.sA = nn; t.sAo = (long)pairs * nn;
     t.B = T; t.sB = 2 * nn; t.sBo = (long)m * nn;
     t.C = g.tT[nxt]; t.sC = nn; t.sCo = (long)m2 * nn;
-    SCHED_TRY(launch_gemm(t, pairs > 2 ? g.tile_wide : g.tile, S.s));
+    SCHED_TRY(launch_gemm_pair(u, t, pairs > 2 ? g.tile_wide : g.tile, S.s));   // independent: one launch
     if (m % 2) {                           // D of the pairs, and the unpaired last block, in one launch
       BlockCopies cp;
       auto add = [&](double* dst, long dso, const double* src, long sso, long len) {

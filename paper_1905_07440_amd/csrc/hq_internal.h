@@ -134,6 +134,8 @@ hipError_t launch_kron(const KronArgs<float>& a, int side, hipStream_t s);
 
 hipError_t launch_gemm(const GemmArgs<double>& a, int tile, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs<float>& a, int tile, hipStream_t s);
+// two products of one M x N shape in one launch (one after the other where the tile cannot pair them)
+hipError_t launch_gemm_pair(const GemmArgs<double>& a, const GemmArgs<double>& b, int tile, hipStream_t s);
 bool gemm_tile_fits(int tile, int K, int precision);
 hipError_t prepare_gemm();
 
