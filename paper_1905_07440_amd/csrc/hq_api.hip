@@ -531,17 +531,22 @@ hq_status merge(Sched& S, Group& g, const double* UL, long sUL, const double* DL
   const long nn = (long)g.n * g.n;
   const int n = g.n;
   SCHED_TRY(launch_dsplit(DL, g.dLbinv, g.dLs, g.sumlog, 0, n, g.C, S.s));
-  const double *rb = g.ones, *rs_ = g.ones;
-  if (UR) {
-    // D_R may be strided (right stack); dsplit wants [C][n] contiguous
-    if (sDR != n) return fail(S.ctx, HQ_EINVAL, "internal: strided D_R");
-    SCHED_TRY(launch_dsplit(DR, g.dRbinv, g.dRs, g.sumlog, 1, n, g.C, S.s));
-    rb = g.dRbinv;
-    rs_ = g.dRs;
-  } else {
-    UR = g.ident; sUR = 0;
-    TR = g.ident; sTR = 0;
+  if (!UR) {
+    // right part the identity (a from-scratch recompute): M = Db_L^-1 U_L^T + Ds_L T_L
+    // elementwise, and G = Minv U_L^T straight into Gnew
+    SCHED_TRY(launch_merge_identity(UL, sUL, TL, sTL, g.dLbinv, g.dLs, g.M, n, g.C, S.s));
+    SCHED_TRY(launch_gj(g.M, g.Minv, g.ones, g.dLbinv, g.sumlog, g.logdet_new, n, g.C, S.s));
+    GemmArgs<double> c = sq(g, g.C);
+    c.A = g.M; c.sA = nn;
+    c.B = UL; c.sB = sUL; c.tB = 1;
+    c.C = g.Gnew; c.sC = nn;
+    SCHED_TRY(launch_gemm(c, g.tile, S.s));
+    return HQ_OK;
   }
+  // D_R may be strided (right stack); dsplit wants [C][n] contiguous
+  if (sDR != n) return fail(S.ctx, HQ_EINVAL, "internal: strided D_R");
+  SCHED_TRY(launch_dsplit(DR, g.dRbinv, g.dRs, g.sumlog, 1, n, g.C, S.s));
+  const double *rb = g.dRbinv, *rs_ = g.dRs;
   GemmArgs<double> a = sq(g, g.C);                 // M = Db_L^-1 (U_L^T U_R) Db_R^-1
   a.A = UL; a.sA = sUL; a.tA = 1;
   a.B = UR; a.sB = sUR;

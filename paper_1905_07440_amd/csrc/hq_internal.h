@@ -190,6 +190,9 @@ hipError_t launch_identity(double* U, double* D, double* T, int n, int batch, hi
 // dbinv = 1/max(D,1), ds = min(D,1), sumlog[z] (+)= sum log max(D,1)
 hipError_t launch_dsplit(const double* D, double* dbinv, double* ds, double* sumlog, int accumulate,
                          int n, int batch, hipStream_t s);
+// M = diag(dbinv) U^T + diag(ds) T per chain ([batch] n x n, U and T with chain strides sU, sT)
+hipError_t launch_merge_identity(const double* U, long sU, const double* T, long sT, const double* dbinv,
+                                 const double* ds, double* M, int n, int batch, hipStream_t s);
 // drift of the tracked state against the recomputed one, then replace it;
 // part: stab_part_doubles(batch) of scratch
 size_t stab_part_doubles(int batch);

@@ -46,6 +46,39 @@ hipError_t launch_dsplit(const double* D, double* dbinv, double* ds, double* sum
   return hipGetLastError();
 }
 
+// M = diag(dbinv) U^T + diag(ds) T for every chain (the merge matrix when the
+// right factor is the identity), U read through 32 x 32 LDS tiles so that
+// both reads and the write are row-contiguous
+__global__ void merge_identity_kernel(const double* __restrict__ U, long sU, const double* __restrict__ T, long sT,
+                                      const double* __restrict__ dbinv, const double* __restrict__ ds,
+                                      double* __restrict__ M, int n) {
+  __shared__ double tile[32][33];
+  const int z = blockIdx.z;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  const double* u = U + (long)z * sU;
+  for (int r = threadIdx.y; r < 32; r += 8) {        // tile[jj][ii] = U[j0 + jj][i0 + ii]
+    const int j = j0 + r, i = i0 + threadIdx.x;
+    tile[r][threadIdx.x] = (j < n && i < n) ? u[(long)j * n + i] : 0.0;
+  }
+  __syncthreads();
+  const double* t = T + (long)z * sT;
+  for (int r = threadIdx.y; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + threadIdx.x;
+    if (i < n && j < n) {
+      const double a = dbinv[(long)z * n + i] * tile[threadIdx.x][r];
+      const double b = ds[(long)z * n + i] * t[(long)i * n + j];
+      M[(long)z * n * n + (long)i * n + j] = a + b;
+    }
+  }
+}
+hipError_t launch_merge_identity(const double* U, long sU, const double* T, long sT, const double* dbinv,
+                                 const double* ds, double* M, int n, int batch, hipStream_t s) {
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  const unsigned t = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(merge_identity_kernel, dim3(t, t, batch), dim3(32, 8), 0, s, U, sU, T, sT, dbinv, ds, M, n);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // end of a stabilisation point: drift of the tracked G / log det against the
 // FP64 recomputation, then the tracked state is replaced by it.
