@@ -415,22 +415,25 @@ __device__ __attribute__((always_inline)) void apply_reflector_buf(double* A, in
   const __amdgpu_buffer_rsrc_t rsrc =
       __builtin_amdgcn_make_buffer_rsrc(A + (long)p0 * n, 0, (int)((long)m * n * 8), BUF_WORD3);
   const unsigned tstep = 16u * (unsigned)n * 8u;   // bytes per 16 rows
-  for (int s = wave; s < nstrip; s += 4) {
+  constexpr int NTL = Cap<MX>::tiles;
+  auto offsets = [&](int s, unsigned (&off)[4]) {
     const int col = c_begin + 16 * s + li;
-    unsigned off[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v)
       off[v] = (col < n) ? ((unsigned)(frag_row<double>(lane, v) * n + col) * 8u) : BUF_OUTSIDE;
-    d4 tile[Cap<MX>::tiles];
+  };
+  auto load = [&](int s, d4 (&tile)[NTL]) {
+    unsigned off[4];
+    offsets(s, off);
 #pragma unroll
-    for (int t = 0; t < Cap<MX>::tiles; ++t) {
+    for (int t = 0; t < NTL; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        tile[t][v] = (t < ntile && col < n) ? buf_load_f64(rsrc, off[v] + t * tstep) : 0.0;
-    }
+      for (int v = 0; v < 4; ++v) tile[t][v] = (t < ntile) ? buf_load_f64(rsrc, off[v] + t * tstep) : 0.0;
+  };
+  auto update = [&](int s, d4 (&tile)[NTL]) {
     d4 w1 = {0, 0, 0, 0};
 #pragma unroll
-    for (int t = 0; t < Cap<MX>::tiles; ++t)
+    for (int t = 0; t < NTL; ++t)
       if (t < ntile) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) w1 = mfma16(Vs[li][16 * t + 4 * q + lk], tile[t][q], w1);
@@ -451,16 +454,28 @@ __device__ __attribute__((always_inline)) void apply_reflector_buf(double* A, in
     double wb[NB / 4];
 #pragma unroll
     for (int q = 0; q < NB / 4; ++q) wb[q] = Sc[4 * q + lk][li];
+    unsigned off[4];
+    offsets(s, off);
 #pragma unroll
-    for (int t = 0; t < Cap<MX>::tiles; ++t)
+    for (int t = 0; t < NTL; ++t)
       if (t < ntile) {
 #pragma unroll
         for (int q = 0; q < NB / 4; ++q) tile[t] = mfma16(-Vs[4 * q + lk][16 * t + li], wb[q], tile[t]);
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          buf_store_f64(tile[t][v], rsrc, off[v] + t * tstep);
+        for (int v = 0; v < 4; ++v) buf_store_f64(tile[t][v], rsrc, off[v] + t * tstep);
       }
     wave_sync_lds();
+  };
+  // strips s = wave, wave + 4, ...; the next strip's tiles are loaded while
+  // the current one is multiplied (two register sets, taken in turn)
+  d4 ta[NTL], tb[NTL];
+  if (wave < nstrip) load(wave, ta);
+  for (int s = wave; s < nstrip; s += 8) {
+    if (s + 4 < nstrip) load(s + 4, tb);
+    update(s, ta);
+    if (s + 4 >= nstrip) break;
+    if (s + 8 < nstrip) load(s + 8, ta);
+    update(s + 4, tb);
   }
 }
 
