@@ -548,12 +548,13 @@ __global__ __launch_bounds__(256) void qr_blocked_kernel(double* __restrict__ Zg
   // pre-pivoting: columns of Z in order of decreasing norm (NaN last)
   if (tid < n) {
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int r0 = 0; r0 < n; r0 += 8) {
-      double v[8];
+    // 32 rows in flight per round trip; s[u] sums rows u, u + 8, u + 16, ... in order
+    for (int r0 = 0; r0 < n; r0 += 32) {
+      double v[32];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (r0 + u < n) ? Z[(long)(r0 + u) * n + tid] : 0.0;
+      for (int u = 0; u < 32; ++u) v[u] = (r0 + u < n) ? Z[(long)(r0 + u) * n + tid] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s[u] += v[u] * v[u];
+      for (int u = 0; u < 32; ++u) s[u & 7] += v[u] * v[u];
     }
     const double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     norms[tid] = (t == t) ? t : -1.0;
@@ -664,12 +665,14 @@ __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, d
   // pre-pivoting: columns of Z in order of decreasing norm (NaN last)
   if (tid < n) {
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int r0 = 0; r0 < n; r0 += 8) {
-      double v[8];
+    // 16 rows in flight per round trip (32 make the N = 144 kernel spill more);
+    // s[u] sums rows u, u + 8, u + 16, ... in order
+    for (int r0 = 0; r0 < n; r0 += 16) {
+      double v[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (r0 + u < n) ? Z[(long)(r0 + u) * n + tid] : 0.0;
+      for (int u = 0; u < 16; ++u) v[u] = (r0 + u < n) ? Z[(long)(r0 + u) * n + tid] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s[u] += v[u] * v[u];
+      for (int u = 0; u < 16; ++u) s[u & 7] += v[u] * v[u];
     }
     const double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     norms[tid] = (t == t) ? t : -1.0;
