@@ -908,35 +908,44 @@ __global__ __launch_bounds__(256) void inv_blocked_kernel(double* __restrict__ M
     const int nstrip = (n + 15) / 16;
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(W, 0, (int)((long)n * n * 8), BUF_WORD3);
     const unsigned tstep = 16u * (unsigned)n * 8u;
-    for (int s = wave; s < nstrip; s += 4) {
-      const int c0 = 16 * s;
-      const int col = c0 + li;
-      const bool incol = col < n && !(col >= p0 && col < p0 + nbw);
-      for (int e = lane; e < NB * 16; e += 64) {   // old pivot rows of this strip
-        const int k = e >> 4, cc = e & 15;
-        const int cg = c0 + cc;
-        double v = 0.0;
-        if (k < nbw && cg < n && !(cg >= p0 && cg < p0 + nbw)) v = W[(long)perm[p0 + k] * n + cg];
-        Sc[wave][k][cc] = v;
-      }
-      wave_sync_lds();
-      const int ntile = (n + 15) / 16;
+    const int ntile = (n + 15) / 16;
+    constexpr int NTL = Cap<MX>::tiles;
+    auto outside = [&](int c) { return c >= n || (c >= p0 && c < p0 + nbw); };   // columns this panel leaves alone
+    // strip s: its tiles (rows of this panel's pivots as 0) and its old pivot rows
+    auto load = [&](int s, d4 (&tile)[NTL], double (&pv)[4]) {
+      const int col = 16 * s + li;
       unsigned off[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) off[v] = incol ? ((unsigned)(frag_row<double>(lane, v) * n + col) * 8u) : BUF_OUTSIDE;
-      d4 tile[Cap<MX>::tiles];
+      for (int v = 0; v < 4; ++v) off[v] = outside(col) ? BUF_OUTSIDE : ((unsigned)(frag_row<double>(lane, v) * n + col) * 8u);
 #pragma unroll
-      for (int t = 0; t < Cap<MX>::tiles; ++t)
+      for (int t = 0; t < NTL; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = 16 * t + frag_row<double>(lane, v);   // rows past n: outside the resource
-          tile[t][v] = (t < ntile && incol && panel_of[row] != pi) ? buf_load_f64(rsrc, off[v] + t * tstep) : 0.0;
+          tile[t][v] = (t < ntile && panel_of[row] != pi) ? buf_load_f64(rsrc, off[v] + t * tstep) : 0.0;
         }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e = lane + 64 * i, k = e >> 4, cg = 16 * s + (e & 15);
+        pv[i] = (k < nbw && !outside(cg)) ? W[(long)perm[p0 + k] * n + cg] : 0.0;
+      }
+    };
+    auto update = [&](int s, d4 (&tile)[NTL], const double (&pv)[4]) {
+      const int col = 16 * s + li;
+      unsigned off[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) off[v] = outside(col) ? BUF_OUTSIDE : ((unsigned)(frag_row<double>(lane, v) * n + col) * 8u);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e = lane + 64 * i;
+        Sc[wave][e >> 4][e & 15] = pv[i];
+      }
+      wave_sync_lds();
       double tb[NB / 4];
 #pragma unroll
       for (int q = 0; q < NB / 4; ++q) tb[q] = Sc[wave][4 * q + lk][li];
 #pragma unroll
-      for (int t = 0; t < Cap<MX>::tiles; ++t)
+      for (int t = 0; t < NTL; ++t)
         if (t < ntile) {
 #pragma unroll
           for (int q = 0; q < NB / 4; ++q) tile[t] = mfma16(Fs[4 * q + lk][16 * t + li], tb[q], tile[t]);
@@ -944,6 +953,17 @@ __global__ __launch_bounds__(256) void inv_blocked_kernel(double* __restrict__ M
           for (int v = 0; v < 4; ++v) buf_store_f64(tile[t][v], rsrc, off[v] + t * tstep);
         }
       wave_sync_lds();
+    };
+    // strips s = wave, wave + 4, ...; the next strip loads while the current one is updated
+    d4 ta[NTL], tb2[NTL];
+    double pa[4], pb[4];
+    if (wave < nstrip) load(wave, ta, pa);
+    for (int s = wave; s < nstrip; s += 8) {
+      if (s + 4 < nstrip) load(s + 4, tb2, pb);
+      update(s, ta, pa);
+      if (s + 4 >= nstrip) break;
+      if (s + 8 < nstrip) load(s + 8, ta, pa);
+      update(s + 4, tb2, pb);
     }
     __syncthreads();
   }
