@@ -182,7 +182,7 @@ def run_workload(w, steps, warmup, profile=True):
 # counter runs on the mixed 12x12 workload, scaled by the same counters on a
 # plain copy (profiles/local_regs_kernel_12x12_mixed_traffic.txt); valid only
 # for the kernel source those runs measured
-LOCAL_TRAFFIC = {"sha1": "13b0e41a139c54486709023f4dea8796586c3b93", "bytes": 22785818,
+LOCAL_TRAFFIC = {"sha1": "13b0e41a139c54486709023f4dea8796586c3b93", "bytes": 22785803,
                  "workload": "holstein-12x12-L120-mixed-nstab6-128chains"}
 
 
