@@ -295,10 +295,8 @@ struct CumulativeArgs {
 hipError_t launch_cumulative(const CumulativeArgs& a, int chains, hipStream_t s);
 hipError_t launch_copy_f64(double* dst, const double* src, long count, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, long count, hipStream_t s);
-// dst[o dso + i dsi + e] = src[o sso + i ssi + e] for e < len, o < outer, i < inner
-hipError_t launch_copy_blocks(double* dst, long dso, long dsi, const double* src, long sso, long ssi, long len,
-                              int outer, int inner, hipStream_t s);
-// up to four such copies in one launch (copies of nonpositive size are skipped)
+// up to four copies dst[o dso + i dsi + e] = src[o sso + i ssi + e] (e < len,
+// o < outer, i < inner) in one launch; copies of nonpositive size are skipped
 struct BlockCopy {
   double* dst = nullptr;
   const double* src = nullptr;

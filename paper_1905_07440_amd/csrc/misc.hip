@@ -190,32 +190,22 @@ __global__ void add_i64_kernel(int64_t* p, int64_t v) {
 
 static inline unsigned nblk(long n) { return (unsigned)((n + 255) / 256); }
 
-// dst[o dso + i dsi + e] = src[o sso + i ssi + e] for e < len, o < outer, i < inner
-__global__ void copy_blocks_kernel(double* dst, long dso, long dsi, const double* src, long sso, long ssi, long len,
-                                   int inner) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int o = blockIdx.y / inner, i = blockIdx.y - (blockIdx.y / inner) * inner;
-  if (e < len) dst[o * dso + i * dsi + e] = src[o * sso + i * ssi + e];
-}
-hipError_t launch_copy_blocks(double* dst, long dso, long dsi, const double* src, long sso, long ssi, long len,
-                              int outer, int inner, hipStream_t s) {
-  if (len <= 0 || outer <= 0 || inner <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_blocks_kernel, dim3(nblk(len), outer * inner), dim3(256), 0, s, dst, dso, dsi, src, sso,
-                     ssi, len, inner);
-  return hipGetLastError();
-}
 
-// blockIdx.y runs over the (o, i) pairs of every copy in turn
-__global__ void copy_blocks_multi_kernel(BlockCopies c) {
-  int y = blockIdx.y, q = 0;
-  while (q < c.k - 1 && y >= c.c[q].outer * c.c[q].inner) {
-    y -= c.c[q].outer * c.c[q].inner;
-    ++q;
-  }
-  const BlockCopy& b = c.c[q];
+// rows (the (o, i) pairs of every copy in turn) are dealt to blockIdx.y with
+// stride gridDim.y
+__global__ void copy_blocks_multi_kernel(BlockCopies c, long rows) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int o = y / b.inner, i = y - o * b.inner;
-  if (e < b.len) b.dst[o * b.dso + i * b.dsi + e] = b.src[o * b.sso + i * b.ssi + e];
+  for (long row = blockIdx.y; row < rows; row += gridDim.y) {
+    long y = row;
+    int q = 0;
+    while (q < c.k - 1 && y >= (long)c.c[q].outer * c.c[q].inner) {
+      y -= (long)c.c[q].outer * c.c[q].inner;
+      ++q;
+    }
+    const BlockCopy& b = c.c[q];
+    const long o = y / b.inner, i = y - o * b.inner;
+    if (e < b.len) b.dst[o * b.dso + i * b.dsi + e] = b.src[o * b.sso + i * b.ssi + e];
+  }
 }
 hipError_t launch_copy_blocks_multi(const BlockCopies& c, hipStream_t s) {
   BlockCopies d;
@@ -227,8 +217,8 @@ hipError_t launch_copy_blocks_multi(const BlockCopies& c, hipStream_t s) {
       rows += (long)c.c[q].outer * c.c[q].inner;
     }
   if (d.k == 0) return hipSuccess;
-  if (rows > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(copy_blocks_multi_kernel, dim3(nblk(len), (unsigned)rows), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(copy_blocks_multi_kernel, dim3(nblk(len), (unsigned)std::min(rows, 65535L)), dim3(256), 0, s, d,
+                     rows);
   return hipGetLastError();
 }
 
