@@ -288,12 +288,23 @@ def autocorr_run(w, sweeps, warmup):
         t_ms += e0.elapsed_time(e1)
         for c in range(C):
             series[c, s] = ctx.stats(c)["s_cdw"]
+    # a chain that never accepts a move has no autocorrelation to speak of:
+    # report how often the moves that change the fields were accepted
+    acc = {"local": [0, 0], "block": [0, 0], "cumulative": [0, 0]}
+    for c in range(C):
+        st = ctx.stats(c)
+        for k, (p, q) in (("local", ("local_proposals", "local_accepts")),
+                          ("block", ("global_proposals", "global_accepts")),
+                          ("cumulative", ("cumulative_proposals", "cumulative_accepts"))):
+            acc[k][0] += st[p]
+            acc[k][1] += st[q]
     ctx.close()
     tau = autocorr.tau_int_chains(series)
     ms = t_ms / sweeps
     return {"metric": "independent S_CDW samples/s", "value": C * 1e3 / ms / (2.0 * tau),
             "unit": "samples/s", "tau_int_sweeps": tau, "ms_per_sweep": ms, "sweeps": sweeps,
             "warmup": warmup, "chains": C, "s_cdw_mean": float(series.mean()),
+            "acceptance": {k: (a_ / p_ if p_ else None) for k, (p_, a_) in acc.items()},
             "estimator": "binning, tau_B = B var(bin means) / (2 var(x)) at the largest B with >= 64 bins, "
                          "variances pooled over chains",
             "config": {"workload": w.name}, "data": "synthetic (seeded random initial fields; random "
