@@ -153,6 +153,14 @@ hq_status hq_recompute(hq_ctx* ctx);
  * green: N*N row-major FP64, G_ij = <c_i c_j^dagger> at the imaginary-time
  * boundary.  fields: L*N FP64, x[l*N + i]. */
 hq_status hq_read_green(hq_ctx* ctx, int32_t chain, double* out, int64_t n);
+/* The tracked G (N*N, row-major, widened to FP64) and tracked log|det M| of
+ * one chain as they stood just before the last stabilisation point of the
+ * last sweep replaced them with the FP64 recomputation (section "Determinant
+ * quantum Monte Carlo": G is carried from slice to slice by wraps and rank-1
+ * updates and periodically recomputed).  In mixed precision this is the
+ * FP32 state the sweep produced.  Needs options.record = 1 (HQ_EINVAL
+ * otherwise); a context that has not swept yet returns zeros. */
+hq_status hq_read_green_tracked(hq_ctx* ctx, int32_t chain, double* out, int64_t n, double* logdet);
 hq_status hq_read_fields(hq_ctx* ctx, int32_t chain, double* out, int64_t n);
 hq_status hq_read_stats(hq_ctx* ctx, int32_t chain, hq_stats* out);
 

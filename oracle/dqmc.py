@@ -115,8 +115,11 @@ class Chain:
         return accept
 
     def recompute(self, l):
-        """Replace G (after slice l) and log|det M| by the from-scratch values."""
+        """Replace G (after slice l) and log|det M| by the from-scratch values.
+        The tracked pair is kept as G_tracked, logdet_tracked (for comparisons
+        of the state a sweep carries before it is replaced)."""
         g_rec, ld_rec = green_and_logdet(self.p, self.expk, self.x, (l + 1) % self.p.L)
+        self.G_tracked, self.logdet_tracked = self.G.copy(), self.logdet
         self.max_drift_g = max(self.max_drift_g, float(np.max(np.abs(self.G - g_rec))))
         self.max_drift_logdet = max(self.max_drift_logdet, abs(self.logdet - ld_rec))
         self.G, self.logdet = g_rec, ld_rec
@@ -178,24 +181,46 @@ class Chain:
         return equal_time_observables(self.p, self.G, self.x)
 
 
+def density_correlations(G):
+    """<n_i n_j> for one field configuration, n_i = n_i,up + n_i,dn, two equal spins.
+
+    Wick's theorem with G_ij = <c_i c_j^dagger> (the same for both spins):
+      <n_is n_js'> = (1 - G_ii)(1 - G_jj)                      for s != s'
+      <n_is n_js>  = (1 - G_ii)(1 - G_jj) + (delta_ij - G_ji) G_ij
+    and summing the four spin pairs,
+      <n_i n_j> = 4 (1 - G_ii)(1 - G_jj) + 2 (delta_ij - G_ji) G_ij.
+    """
+    n = G.shape[0]
+    occ = 1.0 - np.diag(G)
+    nn = np.empty((n, n))
+    for i in range(n):
+        for j in range(n):
+            nn[i, j] = 4.0 * occ[i] * occ[j] + 2.0 * ((1.0 if i == j else 0.0) - G[j, i]) * G[i, j]
+    return nn
+
+
 def equal_time_observables(p, G, x):
     """Equal-time estimators for one field configuration (two equal spins).
 
     density     <n>        = (2/N) sum_i (1 - G_ii)
-    double occ. <n_u n_d>  = (1/N) sum_i (1 - G_ii)^2
-    S_CDW(pi,pi)           = (1/N) sum_ij (-1)^(i+j) <n_i n_j>, with Wick's theorem
-                             <n_i n_j> = 4(1-G_ii)(1-G_jj) + 2(delta_ij - G_ji) G_ij
+    double occ. <n_u n_d>  = (1/N) sum_i (1 - G_ii)^2     (the spins are independent
+                                                           for a fixed field)
+    S_CDW(pi,pi)           = (1/N) sum_ij (-1)^(i+j) <n_i n_j>, <n_i n_j> from
+                             density_correlations
     <x>, <x^2>             field moments over all (l, i)
+
+    Parity: pinned against traces over the full 2N-mode Fock space of a 2x2
+    lattice (tests/test_oracle_observables.py).
     """
     n = p.n
     nx = p.nx
     eps = np.array([(-1.0) ** ((i % nx) + (i // nx)) for i in range(n)])
     occ = 1.0 - np.diag(G)
+    nn = density_correlations(G)
     s_cdw = 0.0
     for i in range(n):
         for j in range(n):
-            nn = 4.0 * occ[i] * occ[j] + 2.0 * ((1.0 if i == j else 0.0) - G[j, i]) * G[i, j]
-            s_cdw += eps[i] * eps[j] * nn
+            s_cdw += eps[i] * eps[j] * nn[i, j]
     return {
         "density": 2.0 * float(np.sum(occ)) / n,
         "double_occupancy": float(np.sum(occ * occ)) / n,

@@ -81,6 +81,8 @@ struct Group {
   int* flags = nullptr;
   int64_t* replay_counts = nullptr;
   float* log_margin[N_KIND_SLOTS] = {};
+  double* Gtrk = nullptr;                  // record: tracked G and log det before the last replacement
+  double* ldtrk = nullptr;
   uint8_t* log_accept[N_KIND_SLOTS] = {};
   uint8_t* replay[N_KIND_SLOTS] = {};
   double band[N_KIND_SLOTS] = {};
@@ -283,6 +285,10 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
         g.log_margin[k] = cv.take<float>(slots);
         g.log_accept[k] = cv.take<uint8_t>(slots);
       }
+    }
+    if (o.record) {
+      g.Gtrk = cv.take<double>(C * nn);
+      g.ldtrk = cv.take<double>(C);
     }
     if (g.network) {
       g.sum_y = cv.take<double>(C * L * n);
@@ -883,7 +889,7 @@ hq_status stab_up(Sched& S, Group& g, int b) {
   }
   ST_TRY(merge(S, g, out.U, out.sU, out.D, out.T, out.sT, r.U, r.sU, r.D, r.sD, r.T, r.sT));
   SCHED_TRY(launch_stab_finish(g.G, S.ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.dpart, g.n,
-                               g.C, 1, S.s));
+                               g.C, 1, S.s, g.Gtrk, g.ldtrk));
   return HQ_OK;
 }
 
@@ -904,7 +910,7 @@ hq_status stab_down(Sched& S, Group& g, int b) {
   const Udt l = left_entry(g, b - 1);
   ST_TRY(merge(S, g, l.U, l.sU, l.D, l.T, l.sT, out.U, out.sU, out.D, out.sD, out.T, out.sT));
   SCHED_TRY(launch_stab_finish(g.G, S.ctx->opt.precision, g.Gnew, g.logdet, g.logdet_new, g.drift, g.dpart, g.n,
-                               g.C, 1, S.s));
+                               g.C, 1, S.s, g.Gtrk, g.ldtrk));
   return HQ_OK;
 }
 
@@ -1499,6 +1505,18 @@ hq_status hq_read_green(hq_ctx* ctx, int32_t chain, double* out, int64_t n) {
   } else {
     HQ_TRY(hipMemcpy(out, (double*)g->G + (long)lc * n, n * sizeof(double), hipMemcpyDeviceToHost));
   }
+  return HQ_OK;
+}
+
+hq_status hq_read_green_tracked(hq_ctx* ctx, int32_t chain, double* out, int64_t n, double* logdet) {
+  ST_TRY(check_ctx(ctx));
+  if (!ctx->opt.record) return fail(ctx, HQ_EINVAL, "the tracked state is only kept with options.record = 1");
+  int lc = 0;
+  Group* g = find_chain(ctx, chain, lc);
+  if (!g || !out || !logdet || n != (int64_t)g->n * g->n) return fail(ctx, HQ_EINVAL, "bad chain or size");
+  ST_TRY(sync(ctx));
+  HQ_TRY(hipMemcpy(out, g->Gtrk + (long)lc * n, n * sizeof(double), hipMemcpyDeviceToHost));
+  HQ_TRY(hipMemcpy(logdet, g->ldtrk + lc, sizeof(double), hipMemcpyDeviceToHost));
   return HQ_OK;
 }
 

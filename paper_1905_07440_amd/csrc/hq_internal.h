@@ -194,11 +194,13 @@ hipError_t launch_dsplit(const double* D, double* dbinv, double* ds, double* sum
 hipError_t launch_merge_identity(const double* U, long sU, const double* T, long sT, const double* dbinv,
                                  const double* ds, double* M, int n, int batch, hipStream_t s);
 // drift of the tracked state against the recomputed one, then replace it;
-// part: stab_part_doubles(batch) of scratch
+// part: stab_part_doubles(batch) of scratch.  saved / saved_logdet (may be
+// null): the tracked G (as FP64) and log det just before the replacement
 size_t stab_part_doubles(int batch);
 hipError_t launch_stab_finish(void* G, int precision, const double* Gnew, double* logdet,
                               const double* logdet_new, double* drift, double* part, int n, int batch,
-                              int record_drift, hipStream_t s);
+                              int record_drift, hipStream_t s, double* saved = nullptr,
+                              double* saved_logdet = nullptr);
 hipError_t launch_copy_f64_to_f32(float* dst, const double* src, long count, hipStream_t s);
 hipError_t launch_copy_f32_to_f64(double* dst, const float* src, long count, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, long count, hipStream_t s);

@@ -254,28 +254,33 @@ __device__ inline void recur_row(const BlockHdr* hdr, int p, bool isA, bool live
 // SIMD.  They hold G in their MFMA accumulators for the whole slice, as a
 // 2 x 2 grid over the nt x nt tiles: wave (wr, wc) = (w & 1, w >> 1) holds
 // tiles (wr + 2a, wc + 2b), so every tile address of a wave is one base plus
-// a compile-time offset.  Wave 0 is also the walker: during the walk it holds
-// the block's column strip G[:, S] and row strip G[S, :] in registers, lane l
-// keeping rows (and columns) l, l + 64, ...  Each accepted move is one rank-1 update of both
-// strips, and the column and row it used are column m of A and Bv, written to
-// LDS panels as they arise.  Per block: walk, then the tile waves apply the
-// rank-p flush G -= A Bv^T and extract the next block's strips; two barriers.
+// a compile-time offset.  Per block of K sites:
+//   walk     wave 0 takes the K decisions on the K x K block G_cur[S, S]
+//            (walk_diag below) and records A[S, m], Bv[S, m], i_m and c_m;
+//   rows     every thread runs the row recurrences for one row j of A and
+//            of Bv, reading G0[j, i_m] and G0[i_m, j] from the strips;
+//   flush    the tile waves apply G -= A Bv^T on the accumulators (MFMA)
+//            and extract the next block's strips G[:, S'] and G[S', :].
+// Three barriers per block.
 //
 // LDS (bytes): header | site constants | replay bits | flags | ratios R |
-// A, Bv panels [npw][KL] | Cs = G[:, S] [npw][K+1] | Rs = G[S, :] [K][npw+1],
-// npw = N rounded up to 64 (the walker's rows).
-template <typename T, int K>
+// A, Bv panels [P][KL] | Cs = G[:, S] [P][K+1] | Rs = G[S, :] [K][P+1] |
+// records A[S, m], Bv[S, m] [K][KR] each.  P = 32 H rows, H = (NT + 1) / 2:
+// every tile row of every wave's 2 x 2 grid, those past N included (zero).
+template <typename T, int K, int NT>
 struct RegLds {
-  enum { KL = K + 16 / (int)sizeof(T) };
+  enum { KL = K + 16 / (int)sizeof(T), KR = K + 16 / (int)sizeof(T), P = 32 * ((NT + 1) / 2) };
   static __host__ __device__ size_t sc() { return align16(sizeof(BlockHdr)); }
   static __host__ __device__ size_t rp(int n) { return sc() + sizeof(SiteConst) * (size_t)n; }
   static __host__ __device__ size_t flags(int n) { return rp(n) + n; }
   static __host__ __device__ size_t rv(int n) { return align16(flags(n) + n); }
   static __host__ __device__ size_t ap(int n) { return align16(rv(n) + 8 * (size_t)n); }
-  static __host__ __device__ size_t bp(int n) { return ap(n) + sizeof(T) * (size_t)pad64(n) * KL; }
-  static __host__ __device__ size_t cs(int n) { return bp(n) + sizeof(T) * (size_t)pad64(n) * KL; }
-  static __host__ __device__ size_t rs(int n) { return cs(n) + sizeof(T) * (size_t)pad64(n) * (K + 1); }
-  static __host__ __device__ size_t total(int n) { return align16(rs(n) + sizeof(T) * (size_t)K * (pad64(n) + 1)); }
+  static __host__ __device__ size_t bp(int n) { return ap(n) + sizeof(T) * (size_t)P * KL; }
+  static __host__ __device__ size_t cs(int n) { return bp(n) + sizeof(T) * (size_t)P * KL; }
+  static __host__ __device__ size_t rs(int n) { return cs(n) + sizeof(T) * (size_t)P * (K + 1); }
+  static __host__ __device__ size_t ar(int n) { return align16(rs(n) + sizeof(T) * (size_t)K * (P + 1)); }
+  static __host__ __device__ size_t br(int n) { return ar(n) + sizeof(T) * (size_t)K * KR; }
+  static __host__ __device__ size_t total(int n) { return align16(br(n) + sizeof(T) * (size_t)K * KR); }
 };
 
 template <typename T, int NT>
@@ -299,125 +304,197 @@ __device__ inline double recip(double r) {
 }
 __device__ inline float recip(float r) { return __builtin_amdgcn_rcpf(r); }
 
-// The walker: the block of cnt <= K sites at `base`.  base is a multiple of
-// K and K divides 64, so the block's own rows are lanes l0 .. l0 + K - 1 of
-// row group T0.
-template <typename T, int K, int RT>
-__device__ inline void walk_strips(int npw, int base, int cnt, int blk, const T* Cs, const T* Rs, int cl, int rl, T* Ap,
-                                   T* Bp,
-                                   const SiteConst* sc, const uint8_t* rp, BlockHdr* hdr, uint8_t* flags, double* Rv,
-                                   bool test_hooks, double band_lo, double band_hi, WalkState& st) {
-  constexpr int KL = RegLds<T, K>::KL;
+// The walker: the decisions of the block of cnt <= K sites at `base` on
+// G_cur[S, S] (g0(r, c) = G0[base + r][base + c]).
+//
+// Lane k (mod K) owns site base + k: it holds row k and column k of the
+// block and its diagonal entry d_k, and keeps its own ratio
+//     r_k = 1 + delta_k (1 - d_k),  R_k = r_k^2 exp(-dS_b,k),  accept_k = u_k < R_k
+// current, so the decision on site q is bit q of one ballot.  An accepted
+// move at q with c = delta_q / r_q changes the rest of the block by
+//     G'[a][b] = G[a][b] + c G[a][q] G[q][b]        (a, b != q)
+// so the diagonal of lane k moves by c G[k][q] G[q][k], two values lane k
+// holds: the ratios of the remaining sites are new after one multiply-add
+// per lane.  The rows and columns are then brought up to date with lane q's
+// row and column, broadcast one entry at a time (only entries after q are
+// read again).  The lane also records A[k, m] = c G[k][q] and
+// Bv[k, m] = [k = q] - G[q][k], the entries of the accepted moves' rank-1
+// factors on the block rows, which the row recurrences need.
+template <typename T, int K, bool HOOKS, typename GetG>
+__device__ __attribute__((always_inline)) inline void walk_diag(GetG g0, int base, int cnt, int blk,
+                                                                const SiteConst* sc, const uint8_t* rp, BlockHdr* hdr,
+                                                                T* Arec, T* Brec, uint8_t* flags, double* Rv,
+                                                                double band_lo, double band_hi, WalkState& st) {
+  constexpr int KR = K + 16 / (int)sizeof(T);
   const int lane = threadIdx.x & 63;
-  const int T0 = base >> 6, l0 = base & 63;
-  T cs[RT][K], rs[RT][K];                  // cs[t][k] = G[lane + 64t][base + k], rs[t][k] = G[base + k][lane + 64t]
+  const int k = lane & (K - 1);
+  const bool act = k < cnt;
+  T row[K], col[K];
 #pragma unroll
-  for (int t = 0; t < RT; ++t)
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      cs[t][k] = (64 * t < npw) ? Cs[(lane + 64 * t) * cl + k] : T(0);
-      rs[t][k] = (64 * t < npw) ? Rs[k * rl + lane + 64 * t] : T(0);
-    }
-  SiteConst my = {0.0, 0.0, 2.0, 0.0};
-  int my_rp = 255;
-  if (lane < cnt) {
-    my = sc[base + lane];
-    my_rp = rp[base + lane];
+  for (int j = 0; j < K; ++j) {
+    row[j] = (act && j < cnt) ? g0(k, j) : T(0);
+    col[j] = (act && j < cnt) ? g0(j, k) : T(0);
   }
-  double lp = 1.0;                         // product of |r| over the accepted moves
+  T dg = act ? g0(k, k) : T(0);
+  SiteConst my = {0.0, 0.0, 2.0, 0.0};     // u = 2: never accepted
+  int my_rp = 255;
+  if (act) {
+    my = sc[base + k];
+    my_rp = rp[base + k];
+  }
+  double r = 1.0, R = 0.0, racc = 1.0;
+  T coef = T(0);
+  int nover = 0, nmis = 0;
+  // this lane's ratio on the current diagonal; the replayed bit inside the band
+  auto judge = [&]() -> bool {
+    r = 1.0 + my.delta * (1.0 - (double)dg);
+    R = r * r * my.bos;
+    coef = (T)(my.delta * recip(r));
+    bool a = my.u < R;
+    if (HOOKS && my_rp != 255 && my.u >= R * band_lo && my.u <= R * band_hi) a = my_rp != 0;
+    return a;
+  };
+  uint64_t ball = __ballot(judge());
   int m = 0;
 #pragma unroll
   for (int q = 0; q < K; ++q) {
     if (q < cnt) {                         // a guard, not a break: the loop stays unrolled
-      // column q and row q of the strips in the block's row group
-      T cq = cs[0][q], rq = rs[0][q];
-#pragma unroll
-      for (int t = 1; t < RT; ++t) {
-        cq = (T0 == t) ? cs[t][q] : cq;
-        rq = (T0 == t) ? rs[t][q] : rq;
-      }
-      const double dg = (double)bcast(cq, l0 + q);
-      const double delta = bcast(my.delta, q);
-      const double r = 1.0 + delta * (1.0 - dg);
-      const double R = r * r * bcast(my.bos, q);
-      const double u = bcast(my.u, q);
-      int acc = (u < R) ? 1 : 0;
-      if (test_hooks) {
-        // replay inside the tie band |ln u - ln R| <= band, tested as
-        // R e^-band <= u <= R e^band; ln u - ln R is formed after the walk
-        const int rpi = __builtin_amdgcn_readlane(my_rp, q);
-        if (rpi != 255) {
-          if (u >= R * band_lo && u <= R * band_hi) {
-            st.counts[0] += (acc != rpi) ? 1 : 0;
-            acc = rpi;
-          } else {
-            st.counts[1] += (acc != rpi) ? 1 : 0;
-          }
+      if (HOOKS && lane == q) {
+        // the site's own ratio at its decision: logged, and the replay counted
+        Rv[base + q] = R;
+        if (my_rp != 255) {
+          const int raw = my.u < R ? 1 : 0;
+          if (my.u >= R * band_lo && my.u <= R * band_hi) nover += (raw != my_rp) ? 1 : 0;
+          else nmis += (raw != my_rp) ? 1 : 0;
         }
-        if (lane == 0) Rv[base + q] = R;
       }
-      acc = uniform(acc);                  // a scalar branch: every lane holds the same value
-      if (acc) {
-        const int i = base + q;
-        const T coef = (T)delta * recip((T)r);
-        // G[i, S] and G[S, i] as wave-uniform values.  Site k reads only
-        // column and row k of the strips, so the columns of the sites
-        // already walked are no longer updated: the update runs over k >= q.
-        T nb[K], ci[K];
-        const int k0 = q;                  // a compile-time bound once q is unrolled
-#pragma unroll
-        for (int k = k0; k < K; ++k) {
-          nb[k] = ((k == q) ? T(1) : T(0)) - bcast(rq, l0 + k);
-          ci[k] = bcast(cq, l0 + k);
+      if ((ball >> q) & 1) {               // a scalar branch on the ballot bit
+        const T c = bcast(coef, q);
+        const bool self = k == q;
+        const T gkq = self ? dg : row[q];  // G[k][q]
+        const T gqk = self ? dg : col[q];  // G[q][k]
+        const T ak = c * gkq;              // A[k, m]
+        racc = self ? r : racc;
+        dg = dg + ak * gqk;                // the diagonal first: the next decision waits on it
+        ball = __ballot(judge());
+        if (lane < K) {
+          Arec[k * KR + m] = ak;
+          Brec[k * KR + m] = (self ? T(1) : T(0)) - gqk;
         }
+        const T cg = c * gqk;
 #pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          const int j = lane + 64 * t;
-          const T na = coef * cs[t][q];    // A[j, m] = c G[j, i]
-          const T nr = ((j == i) ? T(1) : T(0)) - rs[t][q];   // Bv[j, m] = [j = i] - G[i, j]
-          if (64 * t < npw) {
-            Ap[j * KL + m] = na;
-            Bp[j * KL + m] = nr;
-          }
-#pragma unroll
-          for (int k = k0; k < K; ++k) {
-            cs[t][k] -= na * nb[k];
-            rs[t][k] -= (coef * ci[k]) * nr;
-          }
+        for (int j = q + 1; j < K; ++j) {
+          const T rqj = bcast(row[j], q);  // G[q][j]
+          const T cjq = bcast(col[j], q);  // G[j][q]
+          row[j] += ak * rqj;
+          col[j] += cg * cjq;
         }
         if (lane == 0) {
-          hdr->site[m] = i;
-          flags[i] = 1;
+          hdr->site[m] = base + q;
+          hdr->c[m] = (double)c;
+          flags[base + q] = 1;
         }
-        lp *= fabs(r);
         m = uniform(m + 1);
       }
     }
   }
-  // zero A, Bv columns m .. round4(m) - 1: the flush reads whole groups of four
-  for (int mz = m; mz < ((m + 3) & ~3); ++mz)
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-      if (64 * t < npw) {
-        Ap[(lane + 64 * t) * KL + mz] = T(0);
-        Bp[(lane + 64 * t) * KL + mz] = T(0);
-      }
-  st.logr += log(lp);
+  // log|r| of the accepted moves and the replay counts, over the owning lanes
+  double lr = (lane < K) ? log(fabs(racc)) : 0.0;
+  lr = wave_sum(lr);
+  st.logr += lr;
+  if (HOOKS) {
+    st.counts[0] += wave_sum(lane < K ? nover : 0);
+    st.counts[1] += wave_sum(lane < K ? nmis : 0);
+  }
   st.nacc += m;
   if (lane == 0) hdr->p[blk & 1] = m;
 }
 
-template <typename T, int K, int NT>
+// Rows of A and Bv for the flush, one row j per thread over `rows` rows
+// (rows >= n come out zero), KE >= p steps:
+//   A[j, m]  = c_m (G0[j, i_m] - sum_{m'<m} A[j, m'] Bv[i_m, m'])
+//   Bv[j, m] = [j = i_m] - G0[i_m, j] + sum_{m'<m} A[i_m, m'] Bv[j, m']
+// G0[j, i_m] = Cs[j][i_m - base], G0[i_m, j] = Rs[i_m - base][j]; A[i_m, .]
+// and Bv[i_m, .] are the walker's records of row i_m - base.  Entries m >= p
+// are zero.  The inputs of step m + 1 are loaded while step m computes, and a
+// scheduling barrier keeps later steps' loads from being hoisted (all of them
+// in flight at once would not fit the registers next to the tiles of G).
+template <typename T, int K, int KE>
+__device__ __attribute__((always_inline)) inline void recur_rows(const BlockHdr* hdr, int p, int base, int n, int rows,
+                                                                 const T* Cs, int cl, const T* Rs, int rl,
+                                                                 const T* Arec, const T* Brec, T* Ap, T* Bp) {
+  constexpr int KR = K + 16 / (int)sizeof(T), KL = K + 16 / (int)sizeof(T);
+  for (int j = threadIdx.x; j < rows; j += blockDim.x) {
+    const bool live = j < n;
+    T a[KE], b[KE];
+    T wa[2][KE], wb[2][KE], ga[2], gb[2], cm[2];
+    int im[2];
+    auto fetch = [&](int mq, int slot) {
+      const int mc = min(mq, p - 1);
+      im[slot] = hdr->site[mc] - base;
+      cm[slot] = (T)hdr->c[mc];
+      ga[slot] = live ? Cs[j * cl + im[slot]] : T(0);
+      gb[slot] = live ? Rs[im[slot] * rl + j] : T(0);
+#pragma unroll
+      for (int m2 = 0; m2 < KE; ++m2) {
+        if (m2 < mq) {
+          wb[slot][m2] = Brec[im[slot] * KR + m2];   // Bv[i_m, m']
+          wa[slot][m2] = Arec[im[slot] * KR + m2];   // A[i_m, m']
+        }
+      }
+    };
+    fetch(0, 0);
+#pragma unroll
+    for (int mq = 0; mq < KE; ++mq) {
+      const int cur = mq & 1;
+      if (mq + 1 < KE) fetch(mq + 1, cur ^ 1);
+      T sa = ga[cur];
+      T sb = ((j == base + im[cur]) ? T(1) : T(0)) - gb[cur];
+      T sa1 = T(0), sb1 = T(0);
+#pragma unroll
+      for (int m2 = 0; m2 < mq; ++m2) {
+        if (m2 & 1) {
+          sa1 -= a[m2] * wb[cur][m2];
+          sb1 += wa[cur][m2] * b[m2];
+        } else {
+          sa -= a[m2] * wb[cur][m2];
+          sb += wa[cur][m2] * b[m2];
+        }
+      }
+      a[mq] = (mq < p) ? cm[cur] * (sa + sa1) : T(0);
+      b[mq] = (mq < p) ? sb + sb1 : T(0);
+      Ap[j * KL + mq] = a[mq];
+      Bp[j * KL + mq] = b[mq];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+template <typename T, int K>
+__device__ __attribute__((always_inline)) inline void recur_rows_any(const BlockHdr* hdr, int p, int base, int n, int rows, const T* Cs, int cl,
+                                      const T* Rs, int rl, const T* Arec, const T* Brec, T* Ap, T* Bp) {
+  if (p <= 4) recur_rows<T, K, 4>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+  else if (p <= 8) recur_rows<T, K, 8>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+  else if (p <= 12) recur_rows<T, K, 12>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+  else if (p <= 16) recur_rows<T, K, 16>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+  else if constexpr (K > 16) {
+    if (p <= 24) recur_rows<T, K, 24>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+    else recur_rows<T, K, 32>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+  }
+}
+
+// HOOKS: the decision log and tie-band replay of the tests (a separate
+// instantiation, so that the plain sweep carries none of their work)
+template <typename T, int K, int NT, bool HOOKS>
 __global__ __launch_bounds__(256) void local_regs_kernel(LocalArgs a) {
   static_assert(K == 16 || K == 32, "blocks of whole tiles");
   extern __shared__ __align__(16) unsigned char smem[];
-  typedef RegLds<T, K> Lay;
-  constexpr int KL = Lay::KL;
+  typedef RegLds<T, K, NT> Lay;
+  constexpr int KL = Lay::KL, P = Lay::P;
   constexpr int H = RegTiles<T, NT>::H;
-  constexpr int RT = (16 * NT + 63) / 64;  // walker rows per lane
   const int n = a.n, L = a.L, s = a.slice;
   const int np = pad16(n), nt = np / 16;
-  const int cl = K + 1, rl = pad64(np) + 1;
+  const int cl = K + 1, rl = P + 1;
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = uniform(tid >> 6);      // scalar: tile tests below become scalar branches
@@ -429,10 +506,12 @@ __global__ __launch_bounds__(256) void local_regs_kernel(LocalArgs a) {
   uint8_t* rp = smem + Lay::rp(n);
   uint8_t* flags = smem + Lay::flags(n);
   double* Rv = (double*)(smem + Lay::rv(n));
-  T* Ap = (T*)(smem + Lay::ap(n));         // [npw][KL]: A
-  T* Bp = (T*)(smem + Lay::bp(n));         // [npw][KL]: Bv
-  T* Cs = (T*)(smem + Lay::cs(n));         // [npw][K+1]
-  T* Rs = (T*)(smem + Lay::rs(n));         // [K][npw+1]
+  T* Ap = (T*)(smem + Lay::ap(n));         // [P][KL]: A
+  T* Bp = (T*)(smem + Lay::bp(n));         // [P][KL]: Bv
+  T* Cs = (T*)(smem + Lay::cs(n));         // [P][K+1]
+  T* Rs = (T*)(smem + Lay::rs(n));         // [K][P+1]
+  T* Arec = (T*)(smem + Lay::ar(n));       // [K][KR]: A[base + k, m]
+  T* Brec = (T*)(smem + Lay::br(n));       // [K][KR]: Bv[base + k, m]
 
   // G into the accumulators
   RegTiles<T, NT> G;
@@ -454,7 +533,7 @@ __global__ __launch_bounds__(256) void local_regs_kernel(LocalArgs a) {
   }
   site_constants(a, c, sc, rp, flags, Rv);
   // strip rows and columns past N stay zero
-  for (int e = tid; e < pad64(np) * cl; e += blockDim.x) Cs[e] = T(0);
+  for (int e = tid; e < P * cl; e += blockDim.x) Cs[e] = T(0);
   for (int e = tid; e < K * rl; e += blockDim.x) Rs[e] = T(0);
   __syncthreads();
 
@@ -482,34 +561,36 @@ __global__ __launch_bounds__(256) void local_regs_kernel(LocalArgs a) {
   extract(0);
   __syncthreads();
 
-  const bool test_hooks = a.log_margin != nullptr || a.replay != nullptr;
   const double band_lo = exp(-a.band), band_hi = exp(a.band);
   WalkState st = {0.0, 0, {0, 0}};
   for (int base = 0, blk = 0; base < n; base += K, ++blk) {
     if (walker)
-      walk_strips<T, K, RT>(pad64(np), base, min(K, n - base), blk, Cs, Rs, cl, rl, Ap, Bp, sc, rp, hdr, flags, Rv,
-                            test_hooks, band_lo, band_hi, st);
+      walk_diag<T, K, HOOKS>([&](int r, int cc) { return Cs[(base + r) * cl + cc]; }, base, min(K, n - base), blk,
+                             sc, rp, hdr, Arec, Brec, flags, Rv, band_lo, band_hi, st);
     __syncthreads();
-    {
-      const int p = hdr->p[blk & 1];
-      // G -= A Bv^T on the accumulators
+    const int p = hdr->p[blk & 1];
+    if (p > 0) {                           // the same for every thread
+      recur_rows_any<T, K>(hdr, p, base, n, P, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+      __syncthreads();
+      // G -= A Bv^T on the accumulators.  Every tile of the wave's grid is
+      // multiplied, also those past nt: their rows of A and Bv lie in the
+      // zero rows of the panels (tile rows < 32 H = P), so they stay zero
+      // and are never stored; the MFMA chain then has no branches.
       const int mm = (p + 3) & ~3;
       for (int k0 = 0; k0 < mm; k0 += 4) {
         const int kk = k0 + (lane >> 4);
         T av[H], bv[H];
-        const int rmax = pad64(np) - 1;    // rows clamped into the panels; tiles past nt are skipped below
 #pragma unroll
-        for (int ta = 0; ta < H; ++ta) av[ta] = -Ap[min((wr + 2 * ta) * 16 + (lane & 15), rmax) * KL + kk];
+        for (int ta = 0; ta < H; ++ta) av[ta] = -Ap[((wr + 2 * ta) * 16 + (lane & 15)) * KL + kk];
 #pragma unroll
-        for (int tb = 0; tb < H; ++tb) bv[tb] = Bp[min((wc + 2 * tb) * 16 + (lane & 15), rmax) * KL + kk];
+        for (int tb = 0; tb < H; ++tb) bv[tb] = Bp[((wc + 2 * tb) * 16 + (lane & 15)) * KL + kk];
 #pragma unroll
         for (int ta = 0; ta < H; ++ta)
 #pragma unroll
-          for (int tb = 0; tb < H; ++tb)
-            if (wr + 2 * ta < nt && wc + 2 * tb < nt) G.t[ta][tb] = mfma16(av[ta], bv[tb], G.t[ta][tb]);
+          for (int tb = 0; tb < H; ++tb) G.t[ta][tb] = mfma16(av[ta], bv[tb], G.t[ta][tb]);
       }
-      if (base + K < n) extract(base + K);
     }
+    if (base + K < n) extract(base + K);
     __syncthreads();
   }
 
@@ -731,16 +812,26 @@ static int reg_class(int n, int precision) {
 }
 
 template <typename T, int K>
+static size_t lds_regs(int n, int rc) {
+  switch (rc) {
+    case 4: return RegLds<T, K, 4>::total(n);
+    case 7: return RegLds<T, K, 7>::total(n);
+    case 9: return RegLds<T, K, 9>::total(n);
+    case 16: return RegLds<T, K, 16>::total(n);
+    default: return ~(size_t)0;
+  }
+}
+template <typename T, int K>
 static size_t lds_t(int n, bool regs) {
-  return regs ? RegLds<T, K>::total(n) : StreamLds<T, K>::total(n);
+  return regs ? lds_regs<T, K>(n, reg_class(n, sizeof(T) == 4)) : StreamLds<T, K>::total(n);
 }
 
 static bool use_regs(int n, int precision, int kd) {
   if (kd != 16 && kd != 32) return false;
   const int rc = reg_class(n, precision);
   if (!rc || (rc == 16 && kd != 16)) return false;   // N > 144: blocks of 16 only
-  const size_t b = precision ? (kd == 16 ? lds_t<float, 16>(n, true) : lds_t<float, 32>(n, true))
-                             : (kd == 16 ? lds_t<double, 16>(n, true) : lds_t<double, 32>(n, true));
+  const size_t b = precision ? (kd == 16 ? lds_regs<float, 16>(n, rc) : lds_regs<float, 32>(n, rc))
+                             : (kd == 16 ? lds_regs<double, 16>(n, rc) : lds_regs<double, 32>(n, rc));
   return b <= kMaxLds;
 }
 
@@ -760,8 +851,11 @@ bool local_g_in_lds(int n, int precision, int kd) { return use_regs(n, precision
 
 template <typename T, int K, int NT>
 static hipError_t launch_regs(const LocalArgs& a, int chains, hipStream_t s) {
-  const size_t lds = RegLds<T, K>::total(a.n);
-  hipLaunchKernelGGL((local_regs_kernel<T, K, NT>), dim3(chains), dim3(256), lds, s, a);
+  const size_t lds = RegLds<T, K, NT>::total(a.n);
+  if (a.log_margin != nullptr || a.replay != nullptr)
+    hipLaunchKernelGGL((local_regs_kernel<T, K, NT, true>), dim3(chains), dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL((local_regs_kernel<T, K, NT, false>), dim3(chains), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
@@ -800,14 +894,21 @@ static hipError_t allow_all_t() {
   HQ_ALLOW(local_stream_kernel<T, 8>);
   HQ_ALLOW(local_stream_kernel<T, 16>);
   HQ_ALLOW(local_stream_kernel<T, 32>);
-  HQ_ALLOW(local_regs_kernel<T, 16, 4>);
-  HQ_ALLOW(local_regs_kernel<T, 16, 7>);
-  HQ_ALLOW(local_regs_kernel<T, 16, 9>);
-  HQ_ALLOW(local_regs_kernel<T, 32, 4>);
-  HQ_ALLOW(local_regs_kernel<T, 32, 7>);
-  HQ_ALLOW(local_regs_kernel<T, 32, 9>);
+  HQ_ALLOW(local_regs_kernel<T, 16, 4, false>);
+  HQ_ALLOW(local_regs_kernel<T, 16, 4, true>);
+  HQ_ALLOW(local_regs_kernel<T, 16, 7, false>);
+  HQ_ALLOW(local_regs_kernel<T, 16, 7, true>);
+  HQ_ALLOW(local_regs_kernel<T, 16, 9, false>);
+  HQ_ALLOW(local_regs_kernel<T, 16, 9, true>);
+  HQ_ALLOW(local_regs_kernel<T, 32, 4, false>);
+  HQ_ALLOW(local_regs_kernel<T, 32, 4, true>);
+  HQ_ALLOW(local_regs_kernel<T, 32, 7, false>);
+  HQ_ALLOW(local_regs_kernel<T, 32, 7, true>);
+  HQ_ALLOW(local_regs_kernel<T, 32, 9, false>);
+  HQ_ALLOW(local_regs_kernel<T, 32, 9, true>);
   if constexpr (sizeof(T) == 4) {
-    HQ_ALLOW(local_regs_kernel<T, 16, 16>);
+    HQ_ALLOW(local_regs_kernel<T, 16, 16, false>);
+    HQ_ALLOW(local_regs_kernel<T, 16, 16, true>);
   }
 #undef HQ_ALLOW
   return e;

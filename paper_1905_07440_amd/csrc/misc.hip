@@ -92,18 +92,22 @@ hipError_t launch_merge_identity(const double* U, long sU, const double* T, long
 constexpr int STAB_SPLIT = 8;
 
 template <typename T>
-__global__ __launch_bounds__(256) void stab_copy_kernel(T* G, const double* Gnew, double* part, int n, int record) {
+__global__ __launch_bounds__(256) void stab_copy_kernel(T* G, const double* Gnew, double* part, int n, int record,
+                                                        double* saved) {
   __shared__ double red[4];
   const int k = blockIdx.x, z = blockIdx.y;
   const long nn = (long)n * n;
   const long e0 = nn * k / STAB_SPLIT, e1 = nn * (k + 1) / STAB_SPLIT;
   T* g = G + z * nn;
   const double* gn = Gnew + z * nn;
+  double* sv = saved ? saved + z * nn : nullptr;
   double mx = 0.0, bad = 0.0;
   batched_copy<256, 8, double>((int)(e1 - e0), [&](int e) { return gn[e0 + e]; },
                                [&](int e, double v) {
                                  if (!isfinite(v)) bad = 1.0;
-                                 if (record) mx = fmax(mx, fabs((double)g[e0 + e] - v));
+                                 const double old = (double)g[e0 + e];
+                                 if (record) mx = fmax(mx, fabs(old - v));
+                                 if (sv) sv[e0 + e] = old;
                                  g[e0 + e] = (T)v;
                                });
   mx = block_max<256>(mx, red);
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(256) void stab_copy_kernel(T* G, const double* Gnew
 }
 
 __global__ void stab_fold_kernel(const double* part, double* logdet, const double* logdet_new, double* drift,
-                                 int chains, int record) {
+                                 int chains, int record, double* saved_logdet) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= chains) return;
   double mx = 0.0, bad = 0.0;
@@ -133,23 +137,26 @@ __global__ void stab_fold_kernel(const double* part, double* logdet, const doubl
     dr[3] = dl;
   }
   if (bad > 0.0 || !isfinite(ldn)) dr[4] = 1.0;
+  if (saved_logdet) saved_logdet[z] = logdet[z];
   logdet[z] = ldn;
 }
 
 size_t stab_part_doubles(int batch) { return (size_t)batch * STAB_SPLIT * 2; }
 
 hipError_t launch_stab_finish(void* G, int precision, const double* Gnew, double* logdet, const double* logdet_new,
-                              double* drift, double* part, int n, int batch, int record_drift, hipStream_t s) {
+                              double* drift, double* part, int n, int batch, int record_drift, hipStream_t s,
+                              double* saved, double* saved_logdet) {
   if (batch <= 0) return hipSuccess;
   const dim3 grid(STAB_SPLIT, batch);
   if (precision)
-    hipLaunchKernelGGL(stab_copy_kernel<float>, grid, dim3(256), 0, s, (float*)G, Gnew, part, n, record_drift);
+    hipLaunchKernelGGL(stab_copy_kernel<float>, grid, dim3(256), 0, s, (float*)G, Gnew, part, n, record_drift, saved);
   else
-    hipLaunchKernelGGL(stab_copy_kernel<double>, grid, dim3(256), 0, s, (double*)G, Gnew, part, n, record_drift);
+    hipLaunchKernelGGL(stab_copy_kernel<double>, grid, dim3(256), 0, s, (double*)G, Gnew, part, n, record_drift,
+                       saved);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(stab_fold_kernel, dim3((batch + 63) / 64), dim3(64), 0, s, part, logdet, logdet_new, drift,
-                     batch, record_drift);
+                     batch, record_drift, saved_logdet);
   return hipGetLastError();
 }
 

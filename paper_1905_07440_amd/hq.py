@@ -83,7 +83,7 @@ def tile_name(code):
 
 EXPORTS = [
     "hq_workspace_bytes", "hq_create", "hq_set_fields", "hq_set_network", "hq_set_block_network", "hq_sweep",
-    "hq_recompute", "hq_read_green", "hq_read_fields", "hq_read_stats", "hq_read_decisions",
+    "hq_recompute", "hq_read_green", "hq_read_green_tracked", "hq_read_fields", "hq_read_stats", "hq_read_decisions",
     "hq_set_replay", "hq_num_chains", "hq_chain_shape", "hq_set_profiling", "hq_phase_time",
     "hq_read_tuning", "hq_set_tuning", "hq_gemm_tile_name", "hq_synchronize", "hq_last_error", "hq_destroy",
 ]
@@ -111,6 +111,7 @@ def load(path=LIB_PATH):
     lib.hq_sweep.argtypes = [P, I32]
     lib.hq_recompute.argtypes = [P]
     lib.hq_read_green.argtypes = [P, I32, P, I64]
+    lib.hq_read_green_tracked.argtypes = [P, I32, P, I64, P]
     lib.hq_read_fields.argtypes = [P, I32, P, I64]
     lib.hq_read_stats.argtypes = [P, I32, ctypes.POINTER(Stats)]
     lib.hq_read_decisions.argtypes = [P, I32, I32, P, P, I64]
@@ -203,6 +204,16 @@ class Context:
         out = np.empty((n, n))
         self._check(self._lib.hq_read_green(self._ctx, chain, out.ctypes.data, out.size))
         return out
+
+    def green_tracked(self, chain):
+        """The tracked G and log|det M| just before the last stabilisation point
+        replaced them (needs record=True)."""
+        n, _ = self.shape(chain)
+        out = np.empty((n, n))
+        ld = ctypes.c_double(0.0)
+        self._check(self._lib.hq_read_green_tracked(self._ctx, chain, out.ctypes.data, out.size,
+                                                    ctypes.byref(ld)))
+        return out, ld.value
 
     def fields(self, chain):
         n, L = self.shape(chain)

@@ -165,8 +165,14 @@ def test_batched_8x8_full_size_sampled(hq):
     ctx.close()
 
 
-def _mixed_replay_case(hq, gr, chains_to_check, seed, sweeps=1, setup=None):
-    ctx = make_ctx(hq, [gr], precision=1, seed=seed, delay=32)
+def _mixed_replay_case(hq, gr, chains_to_check, seed, sweeps=1, setup=None, delay=32, drift_gate=False):
+    """Mixed-precision sweeps beside the oracle, the oracle's decisions replayed
+    inside the tie band.  After each sweep: fields bit-identical, G and log det
+    after the FP64 recompute, and the FP32-tracked G just before that recompute
+    against the oracle's tracked G (1e-5 relative when drift_gate is set: the
+    recompute interval then keeps the FP32 drift within the gate, which is
+    also asserted)."""
+    ctx = make_ctx(hq, [gr], precision=1, seed=seed, delay=delay)
     if setup is not None:
         setup(ctx)
     oracles = {c: dqmc.Chain(params_of(gr), seed, c) for c in chains_to_check}
@@ -175,15 +181,21 @@ def _mixed_replay_case(hq, gr, chains_to_check, seed, sweeps=1, setup=None):
             ch.sweep()
             ctx.set_replay(c, hq.KIND_LOCAL, oracle_local_bits(ch, s), BAND_MIXED)
         ctx.sweep(1)
-    for c, ch in oracles.items():
-        st = ctx.stats(c)
-        assert st["replay_mismatches"] == 0, "chain %d: decision outside the tie band differs" % c
-        assert np.array_equal(ctx.fields(c), ch.x)
-        assert rel_g(ctx.green(c), ch.G) <= TOL_MIXED
-        assert abs(st["logdet"] - ch.logdet) <= TOL64 * max(1.0, abs(ch.logdet))
-        assert st["local_accepts"] == ch.local_accepts
-        say("  chain %d: overrides in band %d, max drift %.2e" % (c, st["replay_overrides"],
-                                                                 st["max_drift_green"]))
+        for c, ch in oracles.items():
+            st = ctx.stats(c)
+            assert st["replay_mismatches"] == 0, "chain %d: decision outside the tie band differs" % c
+            assert np.array_equal(ctx.fields(c), ch.x), "sweep %d chain %d" % (s, c)
+            assert rel_g(ctx.green(c), ch.G) <= TOL_MIXED
+            assert abs(st["logdet"] - ch.logdet) <= TOL64 * max(1.0, abs(ch.logdet))
+            assert st["local_accepts"] == ch.local_accepts
+            gt, ldt = ctx.green_tracked(c)
+            rt = rel_g(gt, ch.G_tracked)
+            if drift_gate:
+                assert st["max_drift_green"] <= TOL_MIXED, "chain %d: drift %g" % (c, st["max_drift_green"])
+                assert rt <= TOL_MIXED, "sweep %d chain %d: tracked G rel %g" % (s, c, rt)
+                assert abs(ldt - ch.logdet_tracked) <= TOL_MIXED * max(1.0, abs(ch.logdet_tracked))
+            say("  sweep %d chain %d: overrides in band %d, max drift %.2e, tracked G rel %.2e"
+                % (s, c, st["replay_overrides"], st["max_drift_green"], rt))
     ctx.close()
 
 
@@ -221,11 +233,87 @@ def test_block_product_chunks_16x16(hq, ns):
     ctx.close()
 
 
-def test_mixed_16x16_register_form(hq):
-    """N = 256 in mixed precision: G in the accumulators of four waves (64
-    tiles each), an upward and a downward sweep."""
-    say("16x16 mixed, register form")
-    _mixed_replay_case(hq, dict(nx=16, chains=1, g=1.2, beta=0.4, n_stab=2), (0,), seed=8, sweeps=2)
+@pytest.mark.parametrize("delay", [16, 32])
+def test_mixed_16x16(hq, delay):
+    """N = 256 in mixed precision, an upward and a downward sweep: at delay 16
+    G lives in the accumulators of four waves (64 tiles each, the register
+    form the 16x16 chains of the uneven batch take); at delay 32 it is
+    streamed from global memory."""
+    say("16x16 mixed, delay %d" % delay)
+    _mixed_replay_case(hq, dict(nx=16, chains=1, g=1.2, beta=0.4, n_stab=2), (0,), seed=8, sweeps=2, delay=delay,
+                       drift_gate=True)
+
+
+@pytest.mark.parametrize("nx,delay", [(12, 16), (12, 32), (10, 16), (7, 16), (5, 32)])
+def test_mixed_register_forms(hq, nx, delay):
+    """The register-resident local-move kernel in FP32 for each tile-grid
+    class (N = 25, 49, 144) and block size, an upward and a downward sweep,
+    with the drift gate at a short recompute interval."""
+    say("mixed register form nx=%d delay=%d" % (nx, delay))
+    _mixed_replay_case(hq, dict(nx=nx, chains=2, g=1.5, beta=1.2, n_stab=6), (0, 1), seed=31, sweeps=2,
+                       delay=delay, drift_gate=True)
+
+
+@pytest.mark.parametrize("delay", [16, 32])
+def test_fp64_12x12_register_form(hq, delay):
+    """FP64 at N = 144 (the FP64 baseline's lattice): the register form at
+    delay 16, the streamed form at delay 32 (its LDS panels do not fit)."""
+    say("FP64 12x12 delay %d" % delay)
+    gr = dict(nx=12, chains=2, g=1.5, beta=1.0, n_stab=5)
+    ctx = make_ctx(hq, [gr], seed=33, delay=delay)
+    ctx.sweep(2)
+    for c in range(2):
+        ch = dqmc.Chain(params_of(gr), 33, c)
+        ch.sweep(); ch.sweep()
+        assert_state(ctx, c, ch, TOL64, "12x12 FP64 delay %d chain %d" % (delay, c))
+    ctx.close()
+
+
+def golden(name):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    with np.load(path) as z:
+        return {k: z[k] for k in z.files}
+
+
+def test_mixed_12x12_gate_full_size_golden(hq):
+    """Exactly the benchmarked configuration: 128 chains of 12x12, L = 120,
+    mixed precision, recompute every 6 slices, delay 16 (the register form
+    local_regs_kernel<float, 16, 9>).  Chains 0 and 127 over one upward and
+    one downward sweep against the oracle's stored results
+    (tests/golden/make_golden.py): decisions replayed inside the tie band,
+    fields bit-identical, G and log det after the recompute, and the
+    FP32-tracked G and log det just before it, all within 1e-5."""
+    w = workloads.ALL["c3-gate"]()
+    g = w.groups[0]
+    say("12x12 x128 mixed n_stab=6 delay 16, two sweeps against golden data")
+    gr = dict(nx=g.nx, chains=g.n_chains, g=g.g, beta=g.beta, n_stab=g.n_stab)
+    ref = {c: golden("c3gate_chain%d.npz" % c) for c in (0, 127)}
+    ctx = make_ctx(hq, [gr], precision=1, seed=w.seed, delay=16)
+    n_slots = g.nx ** 2 * round(g.beta / g.dtau)
+    for s in range(2):
+        for c, z in ref.items():
+            ctx.set_replay(c, hq.KIND_LOCAL, np.unpackbits(z["bits%d" % s])[:n_slots], BAND_MIXED)
+        ctx.sweep(1)
+        for c, z in ref.items():
+            st = ctx.stats(c)
+            tag = "sweep %d chain %d" % (s, c)
+            assert st["replay_mismatches"] == 0, tag
+            assert st["local_accepts"] == int(z["accepts%d" % s]), tag
+            assert np.array_equal(ctx.fields(c), z["x%d" % s]), tag
+            Gref = z["G%d" % s].astype(np.float64)
+            assert rel_g(ctx.green(c), Gref) <= TOL_MIXED, tag
+            ld = float(z["logdet%d" % s])
+            assert abs(st["logdet"] - ld) <= TOL64 * max(1.0, abs(ld)), tag
+            gt, ldt = ctx.green_tracked(c)
+            rt = rel_g(gt, z["Gtr%d" % s].astype(np.float64))
+            assert rt <= TOL_MIXED, "%s: tracked G rel %g" % (tag, rt)
+            ldr = float(z["logdet_tr%d" % s])
+            assert abs(ldt - ldr) <= TOL_MIXED * max(1.0, abs(ldr)), tag
+            assert st["max_drift_green"] <= TOL_MIXED, tag
+            say("  %s: overrides %d, tracked G rel %.2e, drift %.2e" % (tag, st["replay_overrides"], rt,
+                                                                       st["max_drift_green"]))
+    ctx.close()
 
 
 def test_mixed_12x12_full_size_sampled(hq):
@@ -392,6 +480,9 @@ def test_uneven_batch_full_size_sampled(hq):
     for c, ch in oracles.items():
         ch.sweep()
         ctx.set_replay(c, hq.KIND_LOCAL, oracle_local_bits(ch, 0), BAND_MIXED)
+    z = golden("c4n16_chain%d.npz" % c16)
+    assert float(z["g"]) == p16.g
+    ctx.set_replay(c16, hq.KIND_LOCAL, np.unpackbits(z["bits0"])[:p16.n * p16.L], BAND_MIXED)
     ctx.sweep(1)
     for c, ch in oracles.items():
         st = ctx.stats(c)
@@ -400,6 +491,17 @@ def test_uneven_batch_full_size_sampled(hq):
         assert rel_g(ctx.green(c), ch.G) <= TOL_MIXED, "chain %d" % c
         assert abs(st["logdet"] - ch.logdet) <= TOL64 * max(1.0, abs(ch.logdet)), "chain %d" % c
         assert st["local_accepts"] == ch.local_accepts, "chain %d" % c
+    # the first 16x16 chain against the oracle's stored sweep
+    st = ctx.stats(c16)
+    assert st["replay_mismatches"] == 0
+    assert st["local_accepts"] == int(z["accepts0"])
+    assert np.array_equal(ctx.fields(c16), z["x0"])
+    assert rel_g(ctx.green(c16), z["G0"].astype(np.float64)) <= TOL_MIXED
+    assert abs(st["logdet"] - float(z["logdet0"])) <= TOL64 * max(1.0, abs(float(z["logdet0"])))
+    gt, _ = ctx.green_tracked(c16)
+    say("  16x16 chain: tracked G rel %.2e, drift %.2e" % (rel_g(gt, z["Gtr0"].astype(np.float64)),
+                                                           st["max_drift_green"]))
+    assert rel_g(gt, z["Gtr0"].astype(np.float64)) <= TOL_MIXED
     st = ctx.stats(c16)
     x16 = ctx.fields(c16)
     _, ld = green_and_logdet(p16, ch16.expk, x16, 0)
@@ -442,6 +544,7 @@ def test_network_full_size_sampled(hq):
         assert st["replay_mismatches"] == 0, "chain %d" % c
         assert np.array_equal(ctx.fields(c), nn.c.x), "chain %d" % c
         assert abs(st["logdet"] - nn.c.logdet) <= TOL64 * max(1.0, abs(nn.c.logdet)), "chain %d" % c
+        assert rel_g(ctx.green(c), nn.c.G) <= TOL64, "chain %d" % c
         assert st["cumulative_accepts"] == nn.cumulative_accepts
         assert st["nn_accepts"] == nn.inner_accepts
     ctx.close()
@@ -588,6 +691,7 @@ def test_network_block_moves_and_inner_sweeps(hq, nu):
             assert st["replay_mismatches"] == 0
             assert np.array_equal(ctx.fields(c), nn.c.x), "sweep %d chain %d" % (s, c)
             assert abs(st["logdet"] - nn.c.logdet) <= TOL64 * max(1.0, abs(nn.c.logdet))
+            assert rel_g(ctx.green(c), nn.c.G) <= TOL64, "sweep %d chain %d" % (s, c)
             assert st["cumulative_accepts"] == nn.cumulative_accepts
             assert st["nn_proposals"] == nn.inner_proposals and st["nn_accepts"] == nn.inner_accepts
             assert st["global_proposals"] == nn.block_proposals and st["global_accepts"] == nn.block_accepts
@@ -625,6 +729,7 @@ def test_network_proposals_and_cumulative_update(hq):
             assert st["replay_mismatches"] == 0
             assert np.array_equal(ctx.fields(c), nn.c.x), "sweep %d chain %d" % (s, c)
             assert abs(st["logdet"] - nn.c.logdet) <= TOL64 * max(1.0, abs(nn.c.logdet))
+            assert rel_g(ctx.green(c), nn.c.G) <= TOL64, "sweep %d chain %d" % (s, c)
             assert st["cumulative_accepts"] == nn.cumulative_accepts
             assert st["nn_accepts"] == nn.inner_accepts
     ctx.close()
