@@ -122,6 +122,25 @@ hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* 
                     uint64_t seed, void* workspace, size_t workspace_bytes,
                     void* stream, hq_ctx** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hq_create
+ * with the library's own workspace, a static device array of
+ * HQ_STATIC_WORKSPACE_BYTES that every GPU the library runs on holds until
+ * the process ends.  The call allocates no device memory: no hipMalloc, no
+ * hipFree, no side streams and no timing events (the autotuner does not run:
+ * the products take the 64 x 64 tile and the wraps the Kronecker form, as
+ * hq_set_tuning(ctx, 0, 0, 0, HQ_WRAP_KRON) would pin).  Limits: one group
+ * (n_groups = 1), and hq_workspace_bytes + 256 <= HQ_STATIC_WORKSPACE_BYTES,
+ * else HQ_ENOMEM; one static context per GPU at a time: while one is alive on
+ * the current device, another call returns HQ_ESTATE (two contexts on the
+ * one array would race; hq_destroy frees it for the next).  Every buffer the
+ * sweep reads is initialised here, so nothing of an earlier context leaks
+ * into a new one.  Failures of hq_create and hq_create_static are described
+ * by hq_last_error(NULL). */
+#define HQ_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+hq_status hq_create_static(const hq_group* groups, int32_t n_groups, const hq_options* opt,
+                           uint64_t seed, void* stream, hq_ctx** out);
+
 /* Replace one chain's fields (host array x[l*N + i], L*N doubles) and recompute
  * G and log|det M| of its group from scratch.  Counters are kept. */
 hq_status hq_set_fields(hq_ctx* ctx, int32_t chain, const double* x_host, int64_t n);
@@ -228,6 +247,8 @@ const char* hq_gemm_tile_name(int32_t tile);
 /* Wait for all work on the context's stream. */
 hq_status hq_synchronize(hq_ctx* ctx);
 
+/* The message of the last failed call on ctx; with ctx = NULL, of the last
+ * failed hq_create or hq_create_static on this thread. */
 const char* hq_last_error(const hq_ctx* ctx);
 void hq_destroy(hq_ctx* ctx);
 

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -153,6 +154,7 @@ struct hq_ctx {
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
+  int static_device = -1;        // >= 0: the workspace is that device's static array
 };
 
 namespace {
@@ -1310,14 +1312,107 @@ size_t hq_workspace_bytes(const hq_group* groups, int32_t n_groups, const hq_opt
   return layout(nullptr, gs, nullptr, *opt);
 }
 
+namespace {
+// the reason of the last failed hq_create / hq_create_static of this thread
+thread_local std::string create_error;
+
+hq_status create_fail(hq_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  create_error = buf;
+  return st;
+}
+
+// fixed tiles and wrap form for a context created without timing runs
+void untuned_choices(hq_ctx* ctx) {
+  for (Group& g : ctx->groups) {
+    g.tile = g.tile32 = g.tile_wide = TILE_64x64;
+    g.tile_us = g.tile32_us = 0.0;
+    g.wrap_kind = WRAP_KRON;
+    g.wrap_us = 0.0;
+  }
+}
+
+hq_status create_ctx(const hq_group* groups, int32_t n_groups, const hq_options* opt, uint64_t seed, void* workspace,
+                     size_t workspace_bytes, void* stream, bool tune, int static_device, hq_ctx** out);
+}  // namespace
+
 hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* opt, uint64_t seed, void* workspace,
                     size_t workspace_bytes, void* stream, hq_ctx** out) {
-  if (!out) return HQ_EINVAL;
+  return create_ctx(groups, n_groups, opt, seed, workspace, workspace_bytes, stream, true, -1, out);
+}
+
+// ---------------------------------------------------------------------------
+// The workspace of hq_create_static: a file-scope device array.  Every GPU the
+// library runs on holds its own copy until the process ends.  Host code never
+// passes the array's name to a kernel or a copy: it is a host-side stand-in
+// there.  Its device address, from hipGetSymbolAddress with the device
+// current, is kept per device and used instead.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[HQ_STATIC_WORKSPACE_BYTES];
+
+namespace {
+std::mutex static_mu;
+std::vector<void*> static_ptr;           // device address of `scratch`, per device (null: not looked up)
+std::vector<char> static_busy;           // a static context is alive on the device
+}  // namespace
+
+hq_status hq_create_static(const hq_group* groups, int32_t n_groups, const hq_options* opt, uint64_t seed,
+                           void* stream, hq_ctx** out) {
+  if (!out) return create_fail(HQ_EINVAL, "out is null");
   *out = nullptr;
-  if (!groups || n_groups < 1 || !opt || !workspace || !stream) return HQ_EINVAL;
-  if (opt->precision != HQ_PREC_FP64 && opt->precision != HQ_PREC_MIXED) return HQ_EINVAL;
-  if (opt->delay != 0 && opt->delay != 8 && opt->delay != 16 && opt->delay != 32) return HQ_EINVAL;
-  if (opt->activation != 0 && opt->activation != 1) return HQ_EINVAL;
+  if (!groups || n_groups != 1 || !opt || !stream)
+    return create_fail(HQ_EINVAL, "hq_create_static takes one group, options and a stream");
+  const size_t need = hq_workspace_bytes(groups, n_groups, opt);
+  if (need == 0) return create_fail(HQ_EINVAL, "invalid group or options");
+  if (need + 256 > (size_t)HQ_STATIC_WORKSPACE_BYTES)
+    return create_fail(HQ_ENOMEM, "the group needs %zu bytes of workspace; the static workspace holds %zu",
+                       need + 256, (size_t)HQ_STATIC_WORKSPACE_BYTES);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0) return create_fail(HQ_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(static_mu);
+    if ((int)static_ptr.size() <= dev) {
+      static_ptr.resize(dev + 1, nullptr);
+      static_busy.resize(dev + 1, 0);
+    }
+    if (static_busy[dev]) return create_fail(HQ_ESTATE, "a static context is already alive on device %d", dev);
+    if (!static_ptr[dev]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return create_fail(HQ_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      static_ptr[dev] = ptr;
+    }
+    base = static_ptr[dev];
+    static_busy[dev] = 1;
+  }
+  const hq_status st = create_ctx(groups, n_groups, opt, seed, base, (size_t)HQ_STATIC_WORKSPACE_BYTES, stream,
+                                  false, dev, out);
+  if (!*out) {                           // nothing was created: the array is free again
+    std::lock_guard<std::mutex> lk(static_mu);
+    static_busy[dev] = 0;
+  }
+  return st;
+}
+
+namespace {
+hq_status create_ctx(const hq_group* groups, int32_t n_groups, const hq_options* opt, uint64_t seed, void* workspace,
+                     size_t workspace_bytes, void* stream, bool tune, int static_device, hq_ctx** out) {
+  if (!out) return create_fail(HQ_EINVAL, "out is null");
+  *out = nullptr;
+  if (!groups || n_groups < 1 || !opt || !workspace || !stream)
+    return create_fail(HQ_EINVAL, "null groups, options, workspace or stream");
+  if (opt->precision != HQ_PREC_FP64 && opt->precision != HQ_PREC_MIXED)
+    return create_fail(HQ_EINVAL, "unknown precision");
+  if (opt->delay != 0 && opt->delay != 8 && opt->delay != 16 && opt->delay != 32)
+    return create_fail(HQ_EINVAL, "delay must be 0, 8, 16 or 32");
+  if (opt->activation != 0 && opt->activation != 1) return create_fail(HQ_EINVAL, "unknown activation");
   hq_ctx* ctx = new hq_ctx();
   ctx->opt = *opt;
   ctx->seed = seed;
@@ -1325,13 +1420,14 @@ hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* 
   std::string why;
   if (!build_groups(groups, n_groups, *opt, ctx->groups, why)) {
     delete ctx;
-    return HQ_EINVAL;
+    return create_fail(HQ_EINVAL, "%s", why.c_str());
   }
   const size_t need = layout(nullptr, ctx->groups, nullptr, *opt);
   if (workspace_bytes < need) {
     delete ctx;
-    return HQ_ENOMEM;
+    return create_fail(HQ_ENOMEM, "the workspace holds %zu bytes; %zu are needed", workspace_bytes, need);
   }
+  ctx->static_device = static_device;
   ctx->ws = workspace;
   ctx->ws_bytes = workspace_bytes;
   // align the base to 256 bytes
@@ -1401,15 +1497,29 @@ hq_status hq_create(const hq_group* groups, int32_t n_groups, const hq_options* 
     HQ_TRY(launch_fill_f64(g.drift, 0.0, (long)C * 5, s));
     HQ_TRY(launch_fill_f64(g.lastpc, 0.0, (long)C * 2, s));
     HQ_TRY(launch_fill_i64((int64_t*)g.flags, 0, ((long)C * sizeof(int) + 7) / 8, s));
-    for (int k : KINDS)
+    for (int k : KINDS) {
       HQ_TRY(launch_fill_u8(g.replay[k], 255, (long)C * g.kind_slots(k), s));
+      if (opt->record) {                 // the workspace may hold an earlier context's data
+        HQ_TRY(launch_fill_u8(g.log_accept[k], 0, (long)C * g.kind_slots(k), s));
+        HQ_TRY(launch_fill_u8((uint8_t*)g.log_margin[k], 0, (long)C * g.kind_slots(k) * (long)sizeof(float), s));
+      }
+    }
+    if (opt->record) {
+      HQ_TRY(launch_fill_f64(g.Gtrk, 0.0, (long)C * n * n, s));
+      HQ_TRY(launch_fill_f64(g.ldtrk, 0.0, (long)C, s));
+    }
   }
   HQ_TRY(launch_fill_i64(ctx->sweep_counter, 0, 1, s));
-  ST_TRY(autotune(ctx));
+  if (tune) {
+    ST_TRY(autotune(ctx));
+  } else {
+    untuned_choices(ctx);
+  }
   hq_status st = recompute_all(ctx);
   if (st != HQ_OK) return st;
   return sync(ctx);
 }
+}  // namespace
 
 hq_status hq_set_fields(hq_ctx* ctx, int32_t chain, const double* x_host, int64_t n) {
   ST_TRY(check_ctx(ctx));
@@ -1713,11 +1823,15 @@ hq_status hq_synchronize(hq_ctx* ctx) {
   return sync(ctx);
 }
 
-const char* hq_last_error(const hq_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* hq_last_error(const hq_ctx* ctx) { return ctx ? ctx->err.c_str() : create_error.c_str(); }
 
 void hq_destroy(hq_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->static_device >= 0) {
+    std::lock_guard<std::mutex> lk(static_mu);
+    static_busy[ctx->static_device] = 0;
+  }
   for (int d = 0; d < 2; ++d)
     for (int r = 0; r < 2; ++r) {
       if (ctx->exec[d][r]) (void)hipGraphExecDestroy(ctx->exec[d][r]);

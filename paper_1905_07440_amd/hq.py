@@ -82,7 +82,7 @@ def tile_name(code):
 
 
 EXPORTS = [
-    "hq_workspace_bytes", "hq_create", "hq_set_fields", "hq_set_network", "hq_set_block_network", "hq_sweep",
+    "hq_workspace_bytes", "hq_create", "hq_create_static", "hq_set_fields", "hq_set_network", "hq_set_block_network", "hq_sweep",
     "hq_recompute", "hq_read_green", "hq_read_green_tracked", "hq_read_fields", "hq_read_stats", "hq_read_decisions",
     "hq_set_replay", "hq_num_chains", "hq_chain_shape", "hq_set_profiling", "hq_phase_time",
     "hq_read_tuning", "hq_set_tuning", "hq_gemm_tile_name", "hq_synchronize", "hq_last_error", "hq_destroy",
@@ -105,6 +105,7 @@ def load(path=LIB_PATH):
     lib.hq_workspace_bytes.argtypes = [GP, I32, OP]
     lib.hq_workspace_bytes.restype = ctypes.c_size_t
     lib.hq_create.argtypes = [GP, I32, OP, ctypes.c_uint64, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+    lib.hq_create_static.argtypes = [GP, I32, OP, ctypes.c_uint64, P, ctypes.POINTER(P)]
     lib.hq_set_fields.argtypes = [P, I32, P, I64]
     lib.hq_set_network.argtypes = [P, P, I64]
     lib.hq_set_block_network.argtypes = [P, P, I64, I32]
@@ -156,7 +157,9 @@ class Context:
     """A set of Markov chains on the current GPU (torch supplies memory and stream)."""
 
     def __init__(self, groups, precision=PREC_FP64, seed=1, delay=0, activation=0, record=False,
-                 device="cuda"):
+                 device="cuda", static=False):
+        """static=True: the library's own static workspace (hq_create_static:
+        one group, no device allocation in the call) instead of a torch buffer."""
         import torch
         lib = load()
         self._lib = lib
@@ -166,14 +169,19 @@ class Context:
         if nbytes == 0:
             raise HQError(HQ_EINVAL, "invalid groups/options (see include/hq.h limits)")
         self.workspace_bytes = int(nbytes)
-        self._ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
         self._stream = torch.cuda.Stream(device=device)
         self._ctx = ctypes.c_void_p()
-        st = lib.hq_create(self._groups, len(groups), ctypes.byref(self._opt), ctypes.c_uint64(seed),
-                           ctypes.c_void_p(self._ws.data_ptr()), ctypes.c_size_t(self._ws.numel()),
-                           ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(self._ctx))
+        if static:
+            self._ws = None
+            st = lib.hq_create_static(self._groups, len(groups), ctypes.byref(self._opt), ctypes.c_uint64(seed),
+                                      ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(self._ctx))
+        else:
+            self._ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+            st = lib.hq_create(self._groups, len(groups), ctypes.byref(self._opt), ctypes.c_uint64(seed),
+                               ctypes.c_void_p(self._ws.data_ptr()), ctypes.c_size_t(self._ws.numel()),
+                               ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(self._ctx))
         if st != HQ_OK:
-            msg = lib.hq_last_error(self._ctx).decode() if self._ctx else "create failed"
+            msg = lib.hq_last_error(self._ctx if self._ctx else None).decode()
             if self._ctx:
                 lib.hq_destroy(self._ctx)
                 self._ctx = ctypes.c_void_p()

@@ -76,4 +76,19 @@ def test_create_rejects_null_arguments(lib):
     assert lib.hq_create(None, 1, ctypes.byref(opt), 1, None, 0, None, ctypes.byref(out)) == hq.HQ_EINVAL
     assert not out.value
     assert lib.hq_num_chains(None) == 0
-    assert lib.hq_last_error(None) == b"null context"
+    assert b"null" in lib.hq_last_error(None)      # the reason of the last failed create
+
+
+def test_create_static_validates_before_any_device_call(lib):
+    """hq_create_static: argument and size checks run on the host first."""
+    opt = hq.Options(1, 0, 0, 0)
+    out = ctypes.c_void_p()
+    one = (hq.Group * 1)(hq.make_group(4, 1))
+    two = (hq.Group * 2)(hq.make_group(4, 1), hq.make_group(6, 1))
+    assert lib.hq_create_static(one, 1, ctypes.byref(opt), 1, None, ctypes.byref(out)) == hq.HQ_EINVAL
+    assert lib.hq_create_static(two, 2, ctypes.byref(opt), 1, ctypes.c_void_p(1), ctypes.byref(out)) == hq.HQ_EINVAL
+    assert b"one group" in lib.hq_last_error(None)
+    big = (hq.Group * 1)(hq.make_group(12, 16, beta=2.4, n_stab=6))   # about 100 MB of workspace
+    assert lib.hq_create_static(big, 1, ctypes.byref(opt), 1, ctypes.c_void_p(1), ctypes.byref(out)) == hq.HQ_ENOMEM
+    assert b"static workspace holds 67108864" in lib.hq_last_error(None)
+    assert not out.value
