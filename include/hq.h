@@ -19,10 +19,15 @@
  *   - coupling g*x_i*(n_i - 1): B_l = diag(exp(-dtau g x[l,:])) exp(-dtau K)
  *     and the bosonic action S_b = dtau*S_ph - dtau*g*sum(x);
  *   - both spins are equal, W = exp(-S_b) det(M)^2; only log|det M| is kept;
- *   - sweep: slices ascending; per slice the wrap G <- B_l G B_l^-1, then
- *     sites ascending, one local move each; G and log|det M| recomputed
- *     (FP64, QR-stabilised) after every n_stab slices; then, if enabled, one
- *     block move per site in ascending order;
+ *   - sweep order (the paper fixes none): one local move per (site, slice),
+ *     sites ascending within a slice.  Groups without block moves or network
+ *     proposals alternate direction: even sweeps (counting from 0) take the
+ *     slices ascending, each slice the wrap G <- B_l G B_l^-1 then its sites,
+ *     with G and log|det M| recomputed (FP64, QR-stabilised) after slices l
+ *     with (l+1) % n_stab == 0; odd sweeps take the slices descending, each
+ *     slice its sites then the unwrap G <- B_l^-1 G B_l, recomputed after
+ *     slices l with l % n_stab == 0.  Groups with block moves always ascend,
+ *     then make one block move per site, sites ascending;
  *   - every random number comes from Philox4x64-10 with key (seed, 0) and
  *     counter (chain, sweep, slot, kind), so results do not depend on the
  *     execution order on the GPU.
@@ -162,15 +167,29 @@ hq_status hq_set_network(hq_ctx* ctx, const float* weights, int64_t n);
  * this L. */
 hq_status hq_set_block_network(hq_ctx* ctx, const float* weights, int64_t n, int32_t L);
 
-/* Run n_sweeps full sweeps of every chain (asynchronous on the stream). */
+/* Run n_sweeps full sweeps of every chain (asynchronous on the stream): the
+ * local moves of section "Determinant quantum Monte Carlo" (ratio
+ * r = 1 + delta (1 - G_ii), W'/W = r^2 exp(-dS_b), rank-1 update of G, done
+ * in delayed blocks of options.delay sites) with periodic recomputation, the
+ * block moves of section "Global Updates" accepted with the exact weight
+ * ratio, and, for network groups, the network proposals of sections "Local
+ * Updates" and "Global Updates" followed by the cumulative accept p_c.  The
+ * sweep is captured into a HIP graph once and replayed; a capture that fails
+ * leaves nothing behind. */
 hq_status hq_sweep(hq_ctx* ctx, int32_t n_sweeps);
 
-/* Recompute G and log|det M| of every chain from its fields (FP64). */
+/* Recompute G = M^-1 and log|det M|, M = I + B_{L-1} ... B_0, of every chain
+ * from its fields (FP64, QR/UDT-stabilised products; section "Determinant
+ * quantum Monte Carlo").  The drift counters are not changed. */
 hq_status hq_recompute(hq_ctx* ctx);
 
 /* Copy one chain's state to host memory (synchronises the stream).
- * green: N*N row-major FP64, G_ij = <c_i c_j^dagger> at the imaginary-time
- * boundary.  fields: L*N FP64, x[l*N + i]. */
+ * green: N*N row-major FP64, G_ij = <c_i c_j^dagger> = (M^-1)_ij at the
+ * imaginary-time boundary (section "Determinant quantum Monte Carlo"; in
+ * mixed precision the FP32 copy, widened).  fields: L*N FP64, x[l*N + i],
+ * the phonon field X_{i,l} of section "Model".  stats: counters, drift and
+ * the equal-time observables of section "Benchmarks" (density, double
+ * occupancy, S_CDW(pi, pi)) from the current G by Wick's theorem. */
 hq_status hq_read_green(hq_ctx* ctx, int32_t chain, double* out, int64_t n);
 /* The tracked G (N*N, row-major, widened to FP64) and tracked log|det M| of
  * one chain as they stood just before the last stabilisation point of the
@@ -207,7 +226,7 @@ hq_status hq_set_profiling(hq_ctx* ctx, int32_t on);
 hq_status hq_phase_time(hq_ctx* ctx, const char* phase, double* ms_total, int64_t* launches);
 
 /* How a wrap G <- B_l G B_l^-1 (B_l = exp(-dtau V_l) exp(-dtau K), paper:
- * Methods, DQMC) multiplies by exp(-+dtau K):
+ * section "Determinant quantum Monte Carlo") multiplies by exp(-+dtau K):
  *   HQ_WRAP_TWO    two tiled dense products;
  *   HQ_WRAP_FUSED  both dense products in one launch (N <= 144);
  *   HQ_WRAP_KRON   exp(s dtau K) = E1 (x) E1 on the periodic square lattice

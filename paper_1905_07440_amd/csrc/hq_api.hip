@@ -1579,7 +1579,10 @@ hq_status hq_sweep(hq_ctx* ctx, int32_t n_sweeps) {
         hq_status st = enqueue_sweep(ctx, dir, rebuild);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
-        if (st != HQ_OK) return st;
+        if (st != HQ_OK) {
+          if (graph) (void)hipGraphDestroy(graph);   // the partial capture is not kept
+          return st;
+        }
         if (e != hipSuccess) return fail(ctx, HQ_EDEVICE, "graph capture: %s", hipGetErrorString(e));
         ctx->graph[dir][rebuild ? 1 : 0] = graph;
         HQ_TRY(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0));
