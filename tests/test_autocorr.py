@@ -44,3 +44,26 @@ def test_rejects_short_or_constant_series():
         autocorr.tau_int(np.arange(10.0))
     with pytest.raises(ValueError):
         autocorr.tau_int(np.ones(1000))
+
+
+def test_frozen_chains_are_refused():
+    """Copies of one value: numpy's variance is ~1e-31, not 0; still constant."""
+    x = np.full((64, 1024), 0.9660547121099028)
+    assert x.var(axis=1).max() >= 0.0
+    with pytest.raises(ValueError):
+        autocorr.tau_int_chains(x)
+    y = np.random.default_rng(2).standard_normal((4, 1024))
+    y[1] = 0.25                                     # one frozen chain among moving ones
+    with pytest.raises(ValueError):
+        autocorr.tau_int_chains(y)
+
+
+def test_short_runs_are_flagged_as_lower_bounds():
+    """AR(1) with tau = 9.5 over 1024 samples: the largest bin (16) is below
+    the plateau, so the estimate is not converged; over 65536 samples it is."""
+    rho = 0.9
+    exact = (1.0 + rho) / (2.0 * (1.0 - rho))
+    short = autocorr.estimate_chains(ar1(rho, 1024, 64, seed=5))
+    assert not short["converged"] and short["tau"] < exact
+    long = autocorr.estimate_chains(ar1(rho, 65536, 4, seed=6))
+    assert long["converged"] and abs(long["tau"] - exact) < 0.1 * exact
