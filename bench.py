@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-sample-chains", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (reference for HBM byte counters)")
+    ap.add_argument("--nu", type=int, default=0,
+                    help="network workloads: sweeps of each kind of network move per cumulative accept (n_u)")
     ap.add_argument("--autocorr", type=int, default=0, metavar="SWEEPS",
                     help="instead of the throughput line: SWEEPS measured sweeps (>= 128) of the workload, "
                          "S_CDW of every chain after each, and the integrated autocorrelation time")
@@ -131,12 +133,8 @@ def run_workload(w, steps, warmup, profile=True):
     from paper_1905_07440_amd import hq
 
     ctx = hq.Context(hq.groups_from_workload(w), precision=w.precision, seed=w.seed, delay=w.delay)
-    if any(g.proposal == 1 for g in w.groups):
-        import workloads
-        ctx.set_network(workloads.random_network(1001))   # seeded random weights, no trained set
-        blocks = {round(g.beta / g.dtau) for g in w.groups if g.proposal == 1 and g.global_width > 0}
-        for L in blocks:
-            ctx.set_block_network(workloads.random_block_network(1002, L), L)
+    load_networks(ctx, w)
+    eq = equilibrate(ctx, w)
     stream = ctx._stream
     ctx.sweep(warmup)
     ctx.synchronize()
@@ -159,6 +157,20 @@ def run_workload(w, steps, warmup, profile=True):
         "max_drift_logdet": max(s["max_drift_logdet"] for s in stats),
         "tuning": [ctx.tuning(k) for k in range(len(w.groups))],
     }
+    if any(g.proposal == 1 for g in w.groups):
+        import numpy as np
+        pcs = np.array([s["last_log_pc"] for s in stats])
+        out["network"] = {
+            "inner_acceptance_local": sum(s["nn_accepts"] for s in stats) / max(1, sum(s["nn_proposals"] for s in stats)),
+            "inner_acceptance_block": (sum(s["global_accepts"] for s in stats) / sum(s["global_proposals"] for s in stats)
+                                       if any(s["global_proposals"] for s in stats) else None),
+            "cumulative_acceptance": sum(s["cumulative_accepts"] for s in stats)
+                                     / max(1, sum(s["cumulative_proposals"] for s in stats)),
+            "cumulative_proposals": sum(s["cumulative_proposals"] for s in stats),
+            "log_pc_last_sweep": {"mean": float(pcs.mean()), "median": float(np.median(pcs)),
+                                  "min": float(pcs.min()), "max": float(pcs.max()),
+                                  "mean_min_1_pc": float(np.mean(np.minimum(1.0, np.exp(np.minimum(pcs, 0.0)))))},
+            "weights": "trained (paper_1905_07440_amd/weights)", "start": eq}
     c0, by_group = 0, []
     for g in w.groups:
         by_group.append(max(s["max_drift_green"] for s in stats[c0:c0 + g.n_chains]))
@@ -292,11 +304,8 @@ def autocorr_run(w, sweeps, warmup):
     from paper_1905_07440_amd import autocorr, hq
 
     ctx = hq.Context(hq.groups_from_workload(w), precision=w.precision, seed=w.seed, delay=w.delay)
-    if any(g.proposal == 1 for g in w.groups):
-        ctx.set_network(workloads_mod().random_network(1001))
-        blocks = {round(g.beta / g.dtau) for g in w.groups if g.proposal == 1 and g.global_width > 0}
-        for L in blocks:
-            ctx.set_block_network(workloads_mod().random_block_network(1002, L), L)
+    load_networks(ctx, w)
+    eq = equilibrate(ctx, w)
     ctx.sweep(warmup)
     ctx.synchronize()
     C = w.n_chains
@@ -327,7 +336,7 @@ def autocorr_run(w, sweeps, warmup):
     acceptance = {k: (a_ / p_ if p_ else None) for k, (p_, a_) in acc.items()}
     out = {"metric": "independent S_CDW samples/s", "value": None, "unit": "samples/s", "tau_int_sweeps": None,
            "tau_converged": False, "ms_per_sweep": ms, "sweeps": sweeps, "warmup": warmup, "chains": C,
-           "s_cdw_mean": float(series.mean()), "acceptance": acceptance}
+           "s_cdw_mean": float(series.mean()), "acceptance": acceptance, "start": eq}
     moves = [a for a in acceptance.values() if a is not None]
     try:
         if not moves or max(moves) == 0.0:
@@ -359,6 +368,54 @@ def dtype_of(w):
     return "f32+f64" if w.precision else "f64"
 
 
+EQUILIBRATION_SWEEPS = 30
+
+
+def equilibrate(ctx, w, sweeps=EQUILIBRATION_SWEEPS):
+    """Network chains start from fields of the exact sampler: the same lattice
+    and chains (same seed, so the same initial fields) swept `sweeps` times by
+    the conventional DQMC sweep in mixed precision (recompute every 5 slices),
+    then loaded with hq_set_fields.  A network trained on equilibrium fields
+    says little about the initial N(0, 1) fields, and a chain whose every
+    cumulative proposal is rejected stays where it started."""
+    from paper_1905_07440_amd import hq
+    if not any(g.proposal == 1 for g in w.groups):
+        return None
+    groups = []
+    for g in w.groups:
+        L = round(g.beta / g.dtau)
+        ns = 5 if L % 5 == 0 else g.n_stab
+        groups.append(hq.make_group(g.nx, g.n_chains, g.t, g.mu, g.mass, g.omega, g.g, g.g_range, g.beta, g.dtau,
+                                    ns, 0, g.local_width, 0.0, 1))
+    eq = hq.Context(groups, precision=hq.PREC_MIXED, seed=w.seed)
+    eq.sweep(sweeps)
+    fields = [eq.fields(c) for c in range(eq.n_chains)]
+    acc = sum(eq.stats(c)["local_accepts"] for c in range(eq.n_chains)) / \
+        max(1, sum(eq.stats(c)["local_proposals"] for c in range(eq.n_chains)))
+    eq.close()
+    for c, x in enumerate(fields):
+        ctx.set_fields(c, x)
+    return {"sweeps": sweeps, "sampler": "conventional DQMC, mixed precision, recompute every 5 slices",
+            "local_acceptance": acc}
+
+
+def load_networks(ctx, w):
+    """The trained proposal networks (paper_1905_07440_amd/weights, written by
+    paper_1905_07440_amd.train) for the network workloads."""
+    if not any(g.proposal == 1 for g in w.groups):
+        return
+    from paper_1905_07440_amd import train
+    net = train.load_weights("local")
+    if net is None:
+        raise RuntimeError("no trained local-move network: run paper_1905_07440_amd.train")
+    ctx.set_network(net)
+    for L in {round(g.beta / g.dtau) for g in w.groups if g.proposal == 1 and g.global_width > 0}:
+        cnn = train.load_weights("block", L)
+        if cnn is None:
+            raise RuntimeError("no trained block-move network for L = %d" % L)
+        ctx.set_block_network(cnn, L)
+
+
 def workloads_mod():
     import workloads
     return workloads
@@ -380,6 +437,11 @@ def main():
     if headline == "c3":
         headline = "c3-gate"                 # mixed precision at the stated accuracy
     w = workloads.ALL[headline]()
+    if a.nu:
+        for g in w.groups:
+            if g.proposal == 1:
+                g.nn_sweeps = a.nu
+        w.name += "-nu%d" % a.nu
     if a.autocorr:
         if a.autocorr < 128:
             print("--autocorr needs at least 128 sweeps", file=sys.stderr)
@@ -429,6 +491,7 @@ def main():
         "tuning": res["tuning"],
         "phases": res["phases"],
         "dominant_phase": dominant,
+        "network": res.get("network"),
         "roofline": local_roofline(w, res),
         "sweep_roofline": sweep_roofline(w, res),
         "cpu_baseline": cpu,

@@ -69,7 +69,8 @@ typedef enum {
 enum { HQ_PREC_FP64 = 0, HQ_PREC_MIXED = 1 };
 enum { HQ_PROPOSAL_DQMC = 0, HQ_PROPOSAL_NETWORK = 1 };
 /* decision kinds; equal to word 3 of the Philox counter of the draw */
-enum { HQ_KIND_LOCAL = 0, HQ_KIND_GLOBAL = 1, HQ_KIND_NN = 3, HQ_KIND_CUMULATIVE = 4, HQ_KIND_NN_GLOBAL = 6 };
+enum { HQ_KIND_LOCAL = 0, HQ_KIND_GLOBAL = 1, HQ_KIND_NN = 3, HQ_KIND_CUMULATIVE = 4, HQ_KIND_NN_GLOBAL = 6,
+       HQ_KIND_SCAN = 7 /* the direction draw of a network sweep; no decisions are logged */ };
 
 /* One group of chains sharing a lattice and model parameters.  Chains are
  * numbered consecutively over the groups in the order given. */
@@ -113,6 +114,8 @@ typedef struct {
   double density, double_occupancy, s_cdw, x_mean, x2_mean;  /* from the current G, x */
   int64_t replay_overrides;  /* decisions taken from the replay log inside the tie band */
   int64_t replay_mismatches; /* replay disagreements outside the tie band */
+  double last_log_pc;        /* network groups: log p_c of the last cumulative accept */
+  double last_sum_y;         /* and the sum of the accepted network estimates in it */
   int32_t n, L, flags;       /* flags: bit 0 non-finite G / log det seen */
 } hq_stats;
 
@@ -151,7 +154,16 @@ hq_status hq_create_static(const hq_group* groups, int32_t n_groups, const hq_op
 hq_status hq_set_fields(hq_ctx* ctx, int32_t chain, const double* x_host, int64_t n);
 
 /* Load the 45-64-64-1 network (7169 FP32 values: W1[64][45], b1[64],
- * W2[64][64], b2[64], W3[64], b3) used by HQ_PROPOSAL_NETWORK groups. */
+ * W2[64][64], b2[64], W3[64], b3) used by HQ_PROPOSAL_NETWORK groups
+ * (section "Local Updates").  Inputs of a move of x[l][i] by d:
+ * p = 9 (dl+2) + 3 (dy+1) + (dx+1) holds x at slice l+dl, site
+ * (ix+dx, iy+dy), periodic, except p = 22, which holds d.  The estimate of
+ * the move's fermionic change of log W is the odd part (f(d) - f(-d)) / 2 of
+ * the output f.  Each sweep of a network group draws its direction (Philox
+ * kind 7, chain 0, slot 0; word 0 >= 1/2: reversed) and visits its colour
+ * classes forward or in reverse, so that p_c is the exact Metropolis-Hastings
+ * ratio of the whole network sweep (section "Global Updates", the p_c
+ * equation). */
 hq_status hq_set_network(hq_ctx* ctx, const float* weights, int64_t n);
 
 /* Load the convolutional network of network block moves (paper: "Global

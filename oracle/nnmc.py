@@ -7,14 +7,28 @@ space (a 3 x 3 patch) and in imaginary time (slices l-2 .. l+2), 45 inputs
 in all.  Input p = 9 (dl + 2) + 3 (dy + 1) + (dx + 1) holds x at slice l+dl,
 site (ix+dx, iy+dy), periodic in both, except the centre p = 22, which holds
 the displacement d.  Two hidden layers of 64 units (ReLU, or the paper's
-softplus), one linear output y: the network's estimate of the fermionic
-change of log W, 2 log|r|.  The bosonic change is exact, so a proposal is
+softplus), one linear output f.  The estimate of the move's fermionic change
+of log W (2 log|r|) is the odd part in d,
+    y = (f(patch, d) - f(patch, -d)) / 2,
+so that the move back from x + d by -d (the same patch: only the centre
+changed) has estimate -y.  The bosonic change is exact, so a proposal is
 accepted inside the sweep iff u < exp(y - dS_b).
 
-After the sweep the whole proposal X' is accepted with p_c:
-    log p_c = [log W(X') - log W(X)] - [log W_NN(X') - log W_NN(X)]
-            = 2 (log|det M(X')| - log|det M(X)|) - sum of accepted y,
-the bosonic terms cancelling.  The determinant is from scratch in FP64.
+After the inner sweeps the whole proposal X' is accepted with
+    log p_c = 2 (log|det M(X')| - log|det M(X)|) - sum of accepted y,
+the determinant from scratch in FP64.  Why this is exact: the inner sweeps
+are a path of Metropolis steps X = X_0 -> ... -> X_T = X'.  The same steps in
+reverse order, each move undone by its opposite displacement, are a path of
+the reversed schedule from X' back to X; a rejected step has the same
+probability on both paths, and an accepted one contributes
+min(1, e^a) / min(1, e^-a) = e^a, a = y - dS_b, because every estimate is
+odd under the reversal (for block moves f(x + D) - f(x) with unchanged
+neighbour channels is odd too).  So P(reverse path) / P(path) =
+exp(-sum y + S_b(X') - S_b(X)), and the Metropolis-Hastings ratio of the
+composite move, W(X') P(reverse) / (W(X) P(path)), is p_c.  For the reversed
+schedule to be one the sampler itself may run, every sweep draws its
+direction (Philox kind 7, shared by the chains of the sweep): forward, or
+every step of the schedule in reverse order, with probability 1/2 each.
 
 Visiting order: the paper does not fix one.  Points are visited by colour
 classes (l mod 4, iy mod 2, ix mod 2), class after class; two points of one
@@ -36,13 +50,15 @@ channels unchanged.  Sites are visited by colour classes (iy mod 2, ix mod 2):
 a site's inputs come from its 3 x 3 neighbourhood, which holds no other site
 of its class.
 
-A full sweep: n_u sweeps of network local moves, then n_u sweeps of network
-block moves (if the block width is > 0), then one cumulative accept with the
-sum of every accepted y.
+A full forward sweep: n_u sweeps of network local moves, then n_u sweeps of
+network block moves (if the block width is > 0); the reversed sweep takes the
+same classes in the opposite order; then one cumulative accept with the sum
+of every accepted y.
 
 Parity: both forward passes are pinned against torch.nn.functional on the
-same weights, the p_c algebra against log W from scratch
-(tests/test_oracle_nn.py).
+same weights, the p_c algebra against log W from scratch, and the cumulative
+ratio against the probabilities of the path and of its reverse evaluated
+step by step (tests/test_oracle_nn.py).
 """
 import math
 
@@ -168,25 +184,58 @@ def patch(nx, x, l, i, d):
     return out
 
 
-def colour_order(nx, L):
-    """(l, i) in visiting order: classes (l mod 4, iy mod 2, ix mod 2), then l, iy, ix."""
+def local_classes(nx, L):
+    """The 16 colour classes (l mod 4, iy mod 2, ix mod 2) of local moves, in
+    forward order, each a list of (l, i)."""
     if nx % 2 or L % 4:
         raise ValueError("network sweep needs even Nx and L divisible by 4")
-    order = []
+    out = []
     for cl in range(4):
         for py in range(2):
             for px in range(2):
-                for l in range(cl, L, 4):
-                    for iy in range(py, nx, 2):
-                        for ix in range(px, nx, 2):
-                            order.append((l, ix + nx * iy))
-    return order
+                out.append([(l, ix + nx * iy) for l in range(cl, L, 4)
+                            for iy in range(py, nx, 2) for ix in range(px, nx, 2)])
+    return out
+
+
+def colour_order(nx, L):
+    """(l, i) in forward visiting order."""
+    return [pt for cls in local_classes(nx, L) for pt in cls]
+
+
+def block_classes(nx):
+    """The 4 colour classes (iy mod 2, ix mod 2) of block moves, in forward order."""
+    order = cnn_colour_order(nx)
+    k = len(order) // 4
+    return [order[j * k:(j + 1) * k] for j in range(4)]
+
+
+def local_estimate(weights, nx, x, l, i, d, kind=0):
+    """The network's estimate of the fermionic change of log W for x[l, i] += d:
+    the odd part (f(d) - f(-d)) / 2 of the network output."""
+    return 0.5 * (forward(weights, patch(nx, x, l, i, d), kind) - forward(weights, patch(nx, x, l, i, -d), kind))
+
+
+def block_estimate(cnn, nx, x, i, d):
+    """f(x_i + d) - f(x_i), the neighbour channels unchanged."""
+    inp = cnn_inputs(nx, x, i)
+    moved = inp.copy()
+    moved[0] += d
+    return cnn_forward(cnn, moved) - cnn_forward(cnn, inp)
+
+
+def scan_reversed(seed, sweep):
+    """Whether sweep `sweep` visits the schedule in reverse (Philox kind 7)."""
+    u0, _ = philox.uniforms(seed, 0, sweep, 0, philox.KIND_SCAN)
+    return u0 >= 0.5
 
 
 class NNChain:
     """A chain driven by network proposals and exact cumulative accepts.
     cnn: flat block-move network weights (used when the chain's block width
-    is > 0); nu: sweeps of each kind per cumulative accept."""
+    is > 0); nu: sweeps of each kind per cumulative accept.  After a sweep,
+    `path` holds its steps in the order taken: (kind, u, points, x before the
+    step) with points = [(l or None, i, d, accepted, y, dS_b)]."""
 
     def __init__(self, chain, weights_flat, kind=0, cnn=None, nu=1):
         self.c = chain                   # a dqmc.Chain: params, fields, G, log det, seed
@@ -201,56 +250,91 @@ class NNChain:
         self.cumulative_accepts = 0
         self.last_log_pc = 0.0
         self.last_sum_y = 0.0
+        self.last_reversed = False
         self.decisions = []
+        self.path = []
+
+    def schedule(self):
+        """The steps of one forward sweep: ("local", u, class) then ("block", u, class)."""
+        p = self.c.p
+        steps = [("local", u, cls) for u in range(self.nu) for cls in local_classes(p.nx, p.L)]
+        if self.cnn is not None and p.global_width > 0:
+            steps += [("block", u, cls) for u in range(self.nu) for cls in block_classes(p.nx)]
+        return steps
+
+    def _local_step(self, xp, u, cls):
+        c, p = self.c, self.c.p
+        L, n = p.L, p.n
+        pts, y_acc = [], 0.0
+        for l, i in cls:
+            slot = u * L * n + l * n + i
+            u0, u1 = philox.uniforms(c.seed, c.chain, c.sweep_index, slot, philox.KIND_NN)
+            d = p.local_width * (2.0 * u0 - 1.0)
+            y = local_estimate(self.weights, p.nx, xp, l, i, d, self.kind)
+            ds = local_action_change(p, xp[l, i], xp[(l - 1) % L, i], xp[(l + 1) % L, i], d)
+            R = math.exp(min(y - ds, 700.0))
+            accept = u1 < R
+            self.decisions.append((philox.KIND_NN, c.sweep_index, slot, accept,
+                                   math.log(u1) - (y - ds) if u1 > 0 else -math.inf))
+            self.inner_proposals += 1
+            pts.append((l, i, d, accept, y, ds))
+            if accept:
+                y_acc += y
+                self.inner_accepts += 1
+        for l, i, d, accept, _, _ in pts:          # the points of a class do not interact
+            if accept:
+                xp[l, i] += d
+        return pts, y_acc
+
+    def _block_step(self, xp, u, cls):
+        c, p = self.c, self.c.p
+        L, n = p.L, p.n
+        pts, y_acc = [], 0.0
+        for i in cls:
+            slot = u * n + i
+            u0, u1 = philox.uniforms(c.seed, c.chain, c.sweep_index, slot, philox.KIND_NN_GLOBAL)
+            d = p.global_width * (2.0 * u0 - 1.0)
+            y = block_estimate(self.cnn, p.nx, xp, i, d)
+            ds = global_action_change(p, float(np.sum(xp[:, i])), d, L)
+            R = math.exp(min(y - ds, 700.0))
+            accept = u1 < R
+            self.decisions.append((philox.KIND_NN_GLOBAL, c.sweep_index, slot, accept,
+                                   math.log(u1) - (y - ds) if u1 > 0 else -math.inf))
+            self.block_proposals += 1
+            pts.append((None, i, d, accept, y, ds))
+            if accept:
+                y_acc += y
+                self.block_accepts += 1
+        for _, i, d, accept, _, _ in pts:
+            if accept:
+                xp[:, i] += d
+        return pts, y_acc
 
     def sweep(self):
         c, p = self.c, self.c.p
-        L, n = p.L, p.n
         xp = c.x.copy()
         sum_y = 0.0
-        for u in range(self.nu):
-            for l, i in colour_order(p.nx, L):
-                slot = u * L * n + l * n + i
-                u0, u1 = philox.uniforms(c.seed, c.chain, c.sweep_index, slot, philox.KIND_NN)
-                d = p.local_width * (2.0 * u0 - 1.0)
-                y = forward(self.weights, patch(p.nx, xp, l, i, d), self.kind)
-                ds = local_action_change(p, xp[l, i], xp[(l - 1) % L, i], xp[(l + 1) % L, i], d)
-                R = math.exp(min(y - ds, 700.0))
-                accept = u1 < R
-                self.decisions.append((philox.KIND_NN, c.sweep_index, slot, accept,
-                                       math.log(u1) - (y - ds) if u1 > 0 else -math.inf))
-                self.inner_proposals += 1
-                if accept:
-                    xp[l, i] += d
-                    sum_y += y
-                    self.inner_accepts += 1
-        if self.cnn is not None and p.global_width > 0:
-            for u in range(self.nu):
-                for i in cnn_colour_order(p.nx):
-                    slot = u * n + i
-                    u0, u1 = philox.uniforms(c.seed, c.chain, c.sweep_index, slot, philox.KIND_NN_GLOBAL)
-                    d = p.global_width * (2.0 * u0 - 1.0)
-                    inp = cnn_inputs(p.nx, xp, i)
-                    moved = inp.copy()
-                    moved[0] += d
-                    y = cnn_forward(self.cnn, moved) - cnn_forward(self.cnn, inp)
-                    ds = global_action_change(p, float(np.sum(xp[:, i])), d, L)
-                    R = math.exp(min(y - ds, 700.0))
-                    accept = u1 < R
-                    self.decisions.append((philox.KIND_NN_GLOBAL, c.sweep_index, slot, accept,
-                                           math.log(u1) - (y - ds) if u1 > 0 else -math.inf))
-                    self.block_proposals += 1
-                    if accept:
-                        xp[:, i] += d
-                        sum_y += y
-                        self.block_accepts += 1
+        steps = self.schedule()
+        rev = scan_reversed(c.seed, c.sweep_index)
+        if rev:
+            steps = steps[::-1]
+        self.path = []
+        for kind, u, cls in steps:
+            before = xp.copy()
+            if kind == "local":
+                pts, y_acc = self._local_step(xp, u, cls)
+            else:
+                pts, y_acc = self._block_step(xp, u, cls)
+            sum_y += y_acc
+            self.path.append((kind, u, pts, before))
         g_new, ld_new = green_and_logdet(p, c.expk, xp, 0)
         log_pc = 2.0 * (ld_new - c.logdet) - sum_y
         uc, _ = philox.uniforms(c.seed, c.chain, c.sweep_index, 0, philox.KIND_CUMULATIVE)
         accept = uc < math.exp(min(log_pc, 700.0))
         self.decisions.append((philox.KIND_CUMULATIVE, c.sweep_index, 0, accept,
                                math.log(uc) - log_pc if uc > 0 else -math.inf))
-        self.last_log_pc, self.last_sum_y = log_pc, sum_y
+        self.last_log_pc, self.last_sum_y, self.last_reversed = log_pc, sum_y, rev
+        self.proposal = xp
         if accept:
             c.x, c.G, c.logdet = xp, g_new, ld_new
             self.cumulative_accepts += 1

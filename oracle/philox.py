@@ -27,6 +27,7 @@ KIND_NN = 3         # network-proposed local move: word 0 -> displacement, 1 -> 
 KIND_CUMULATIVE = 4  # cumulative update of one sweep: word 0 -> accept
 KIND_COUPLING = 5   # per-chain coupling g: word 0
 KIND_NN_GLOBAL = 6  # network-proposed block move of site i: word 0 -> shift, word 1 -> accept
+KIND_SCAN = 7       # visiting direction of a network sweep (chain 0, slot 0): word 0 < 1/2 -> forward
 
 
 def philox4x64_10(ctr, key):

@@ -138,8 +138,11 @@ struct hq_ctx {
   std::string err;
   // one captured graph per (direction, stack rebuild) and the host's view of
   // the sweep state: the next sweep's index and which UDT stack is current
-  hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-  hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  // [direction][stack rebuild][network scan reversed]
+  hipGraph_t graph[2][2][2] = {};
+  hipGraphExec_t exec[2][2][2] = {};
+  int scan = 0;                  // the sweep being enqueued visits the network schedule in reverse
+  bool any_network = false;
   int64_t sweep_index = 0;
   bool left_valid = false, right_valid = false;
   bool profiling = false;
@@ -969,8 +972,22 @@ hq_status network_sweep(Sched& S, Group& g) {
   SCHED_TRY(launch_copy_f64(g.xp, g.x, (long)g.C * ln, S.s));
   SCHED_TRY(launch_fill_f64(g.sum_y, 0.0, (long)g.C * ln, S.s));
   SCHED_TRY(launch_fill_u8(g.nn_acc, 0, (long)g.C * ln, S.s));
+  // the steps of the forward schedule: (kind, inner sweep, colour class);
+  // a reversed sweep takes them from the last to the first
+  struct Step { int block, u, colour; };
+  std::vector<Step> steps;
   for (int u = 0; u < g.nu; ++u)
-    for (int colour = 0; colour < 16; ++colour) {
+    for (int colour = 0; colour < 16; ++colour) steps.push_back({0, u, colour});
+  if (g.cnn) {
+    SCHED_TRY(launch_fill_f64(g.sum_yb, 0.0, (long)g.C * g.n, S.s));
+    SCHED_TRY(launch_fill_u8(g.acc_b, 0, (long)g.C * g.n, S.s));
+    for (int u = 0; u < g.nu; ++u)
+      for (int colour = 0; colour < 4; ++colour) steps.push_back({1, u, colour});
+  }
+  if (ctx->scan) std::reverse(steps.begin(), steps.end());
+  for (const Step& st : steps) {
+    const int u = st.u, colour = st.colour;
+    if (!st.block) {
       NetArgs a;
       a.nx = g.nx; a.n = g.n; a.L = g.L; a.colour = colour;
       a.inner = u; a.nu = g.nu;
@@ -982,25 +999,20 @@ hq_status network_sweep(Sched& S, Group& g) {
       a.log_margin = g.log_margin[HQ_KIND_NN]; a.log_accept = g.log_accept[HQ_KIND_NN];
       a.replay = g.replay[HQ_KIND_NN]; a.band = g.band[HQ_KIND_NN]; a.replay_counts = g.replay_counts;
       SCHED_TRY(launch_network_colour(a, g.C, S.s));
+    } else {
+      CnnArgs a;
+      a.nx = g.nx; a.n = g.n; a.L = g.L; a.colour = colour;
+      a.inner = u; a.nu = g.nu;
+      a.xp = g.xp; a.g = g.g;
+      a.dtau = g.p.dtau; a.mass = g.p.mass; a.omega = g.p.omega; a.width = g.p.global_width;
+      a.seed = ctx->seed; a.chain0 = g.chain0; a.sweep = ctx->sweep_counter;
+      a.w = ctx->cnn; a.chains = g.C;
+      a.sum_y = g.sum_yb; a.accepted = g.acc_b;
+      a.log_margin = g.log_margin[HQ_KIND_NN_GLOBAL]; a.log_accept = g.log_accept[HQ_KIND_NN_GLOBAL];
+      a.replay = g.replay[HQ_KIND_NN_GLOBAL]; a.band = g.band[HQ_KIND_NN_GLOBAL];
+      a.replay_counts = g.replay_counts;
+      SCHED_TRY(launch_cnn_colour(a, g.C, S.s));
     }
-  if (g.cnn) {
-    SCHED_TRY(launch_fill_f64(g.sum_yb, 0.0, (long)g.C * g.n, S.s));
-    SCHED_TRY(launch_fill_u8(g.acc_b, 0, (long)g.C * g.n, S.s));
-    for (int u = 0; u < g.nu; ++u)
-      for (int colour = 0; colour < 4; ++colour) {
-        CnnArgs a;
-        a.nx = g.nx; a.n = g.n; a.L = g.L; a.colour = colour;
-        a.inner = u; a.nu = g.nu;
-        a.xp = g.xp; a.g = g.g;
-        a.dtau = g.p.dtau; a.mass = g.p.mass; a.omega = g.p.omega; a.width = g.p.global_width;
-        a.seed = ctx->seed; a.chain0 = g.chain0; a.sweep = ctx->sweep_counter;
-        a.w = ctx->cnn; a.chains = g.C;
-        a.sum_y = g.sum_yb; a.accepted = g.acc_b;
-        a.log_margin = g.log_margin[HQ_KIND_NN_GLOBAL]; a.log_accept = g.log_accept[HQ_KIND_NN_GLOBAL];
-        a.replay = g.replay[HQ_KIND_NN_GLOBAL]; a.band = g.band[HQ_KIND_NN_GLOBAL];
-        a.replay_counts = g.replay_counts;
-        SCHED_TRY(launch_cnn_colour(a, g.C, S.s));
-      }
   }
   ST_TRY(from_scratch(S, g, g.xp, g.tree ? g.tT[0] : g.blkp));
   CumulativeArgs c;
@@ -1434,7 +1446,10 @@ hq_status create_ctx(const hq_group* groups, int32_t n_groups, const hq_options*
   char* base = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
   layout(ctx, ctx->groups, base, *opt);
   for (int k = 0; k < N_PHASES; ++k) ctx->phases.push_back({kPhaseNames[k], 0.0, 0});
-  for (const Group& g : ctx->groups) ctx->n_chains += g.C;
+  for (const Group& g : ctx->groups) {
+    ctx->n_chains += g.C;
+    if (g.network) ctx->any_network = true;
+  }
   *out = ctx;
 
   HQ_TRY(prepare_local());
@@ -1570,10 +1585,17 @@ hq_status hq_sweep(hq_ctx* ctx, int32_t n_sweeps) {
   for (int k = 0; k < n_sweeps; ++k) {
     const int dir = (ctx->sweep_index % 2 == 1) ? DIR_DOWN : DIR_UP;
     const bool rebuild = (dir == DIR_UP) ? !ctx->right_valid : !ctx->left_valid;
+    // network sweeps visit their schedule forward or in reverse, one draw per
+    // sweep shared by the chains (Philox kind 7 at chain 0, slot 0)
+    ctx->scan = 0;
+    if (ctx->any_network) {
+      const Philox4 r = philox4x64_10(0, (uint64_t)ctx->sweep_index, 0, KIND_SCAN, ctx->seed, 0);
+      ctx->scan = u53(r.w[0]) >= 0.5 ? 1 : 0;
+    }
     if (ctx->profiling) {
       ST_TRY(enqueue_sweep(ctx, dir, rebuild));
     } else {
-      hipGraphExec_t& ex = ctx->exec[dir][rebuild ? 1 : 0];
+      hipGraphExec_t& ex = ctx->exec[dir][rebuild ? 1 : 0][ctx->scan];
       if (!ex) {
         HQ_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
         hq_status st = enqueue_sweep(ctx, dir, rebuild);
@@ -1584,7 +1606,7 @@ hq_status hq_sweep(hq_ctx* ctx, int32_t n_sweeps) {
           return st;
         }
         if (e != hipSuccess) return fail(ctx, HQ_EDEVICE, "graph capture: %s", hipGetErrorString(e));
-        ctx->graph[dir][rebuild ? 1 : 0] = graph;
+        ctx->graph[dir][rebuild ? 1 : 0][ctx->scan] = graph;
         HQ_TRY(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0));
       }
       HQ_TRY(hipGraphLaunch(ex, ctx->stream));
@@ -1666,6 +1688,8 @@ hq_status hq_read_stats(hq_ctx* ctx, int32_t chain, hq_stats* out) {
   HQ_TRY(hipMemcpy(cnt, g->counters + (long)lc * N_COUNTERS, sizeof cnt, hipMemcpyDeviceToHost));
   HQ_TRY(hipMemcpy(rc, g->replay_counts + 2 * lc, sizeof rc, hipMemcpyDeviceToHost));
   HQ_TRY(hipMemcpy(&fl, g->flags + lc, sizeof fl, hipMemcpyDeviceToHost));
+  double pc[2];
+  HQ_TRY(hipMemcpy(pc, g->lastpc + 2 * lc, sizeof pc, hipMemcpyDeviceToHost));
   std::memset(out, 0, sizeof *out);
   out->logdet = ld;
   out->g = gg;
@@ -1676,6 +1700,7 @@ hq_status hq_read_stats(hq_ctx* ctx, int32_t chain, hq_stats* out) {
   out->max_drift_green = dr[0]; out->max_drift_logdet = dr[1]; out->last_drift_green = dr[2];
   out->density = ob[0]; out->double_occupancy = ob[1]; out->s_cdw = ob[2]; out->x_mean = ob[3]; out->x2_mean = ob[4];
   out->replay_overrides = rc[0]; out->replay_mismatches = rc[1];
+  out->last_log_pc = pc[0]; out->last_sum_y = pc[1];
   out->n = g->n; out->L = g->L;
   out->flags = fl | (dr[4] != 0.0 ? 1 : 0);
   if (out->flags & 1) return fail(ctx, HQ_ENUMERIC, "non-finite G or log det in chain %d", chain);
@@ -1702,12 +1727,13 @@ hq_status hq_read_decisions(hq_ctx* ctx, int32_t chain, int32_t kind, uint8_t* a
 // of either they are captured again on the next hq_sweep.
 static void drop_graphs(hq_ctx* ctx) {
   for (int d = 0; d < 2; ++d)
-    for (int r = 0; r < 2; ++r) {
-      if (ctx->exec[d][r]) (void)hipGraphExecDestroy(ctx->exec[d][r]);
-      if (ctx->graph[d][r]) (void)hipGraphDestroy(ctx->graph[d][r]);
-      ctx->exec[d][r] = nullptr;
-      ctx->graph[d][r] = nullptr;
-    }
+    for (int r = 0; r < 2; ++r)
+      for (int v = 0; v < 2; ++v) {
+        if (ctx->exec[d][r][v]) (void)hipGraphExecDestroy(ctx->exec[d][r][v]);
+        if (ctx->graph[d][r][v]) (void)hipGraphDestroy(ctx->graph[d][r][v]);
+        ctx->exec[d][r][v] = nullptr;
+        ctx->graph[d][r][v] = nullptr;
+      }
 }
 
 hq_status hq_set_replay(hq_ctx* ctx, int32_t chain, int32_t kind, const uint8_t* bits, int64_t n, double band) {
@@ -1835,11 +1861,7 @@ void hq_destroy(hq_ctx* ctx) {
     std::lock_guard<std::mutex> lk(static_mu);
     static_busy[ctx->static_device] = 0;
   }
-  for (int d = 0; d < 2; ++d)
-    for (int r = 0; r < 2; ++r) {
-      if (ctx->exec[d][r]) (void)hipGraphExecDestroy(ctx->exec[d][r]);
-      if (ctx->graph[d][r]) (void)hipGraphDestroy(ctx->graph[d][r]);
-    }
+  drop_graphs(ctx);
   for (auto& pe : ctx->pending) { (void)hipEventDestroy(pe.first); (void)hipEventDestroy(pe.second); }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   for (auto st : ctx->side) {

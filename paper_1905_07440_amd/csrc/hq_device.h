@@ -50,7 +50,7 @@ __host__ __device__ inline double u53(uint64_t w) {
 }
 
 enum { KIND_LOCAL = 0, KIND_GLOBAL = 1, KIND_INIT = 2, KIND_NN = 3, KIND_CUMULATIVE = 4,
-       KIND_COUPLING = 5, KIND_NN_GLOBAL = 6 };
+       KIND_COUPLING = 5, KIND_NN_GLOBAL = 6, KIND_SCAN = 7 };
 
 // ---------------------------------------------------------------------------
 // MFMA 16x16x4 wrappers.  Operand layout (measured on gfx950):

@@ -4,10 +4,15 @@
 // The fully connected network sees the displacement d and the fields of the
 // 3 x 3 spatial patch over slices l-2..l+2 (45 inputs: input
 // p = 9 (dl+2) + 3 (dy+1) + (dx+1), the centre p = 22 holding d), two hidden
-// layers of 64 units and one linear output y, the estimate of the fermionic
-// change of log W.  A proposal is accepted inside the sweep iff
-// u < exp(y - dS_b), the bosonic part being exact.  After the sweep the whole
-// proposal is accepted with log p_c = 2 (log|det M'| - log|det M|) - sum y.
+// layers of 64 units and one linear output f.  The estimate of the move's
+// fermionic change of log W is the odd part y = (f(d) - f(-d)) / 2: the move
+// back (from x + d by -d, the patch unchanged) then has estimate -y, which
+// makes the cumulative accept below exact.  A proposal is accepted inside the
+// sweep iff u < exp(y - dS_b), the bosonic part being exact.  After the sweep
+// the whole proposal is accepted with log p_c = 2 (log|det M'| - log|det M|)
+// - sum y: the Metropolis-Hastings ratio of the composite move, whose reverse
+// path (the same classes in the opposite order, each move undone) the sweep
+// takes with the same probability because every sweep draws its direction.
 //
 // Visiting order: colour classes (l mod 4, iy mod 2, ix mod 2).  No two points
 // of a class lie in each other's patch, so a class is one parallel launch of
@@ -75,23 +80,32 @@ __global__ __launch_bounds__(256) void network_colour_kernel(NetArgs a) {
         in[9 * (dl + 2) + 3 * (dy + 1) + (dx + 1)] = (float)xp[(long)ll * n + j];
       }
   }
-  in[22] = (float)d;
-  float h1[64];
+  // the first layer once for both signs of d: only the centre input differs
+  in[22] = 0.0f;
+  const float df = (float)d;
+  float hp[64], hm[64];
 #pragma unroll
   for (int o = 0; o < 64; ++o) {
     float s = b1[o];
 #pragma unroll
     for (int p = 0; p < 45; ++p) s = fmaf(W1[o * 45 + p], in[p], s);
-    h1[o] = act(s, a.activation);
+    const float wd = W1[o * 45 + 22] * df;
+    hp[o] = act(s + wd, a.activation);
+    hm[o] = act(s - wd, a.activation);
   }
-  float y = b3;
+  float fp = b3, fm = b3;
 #pragma unroll 4
   for (int o = 0; o < 64; ++o) {
-    float s = b2[o];
+    float sp = b2[o], sm = b2[o];
 #pragma unroll
-    for (int p = 0; p < 64; ++p) s = fmaf(W2[o * 64 + p], h1[p], s);
-    y = fmaf(W3[o], act(s, a.activation), y);
+    for (int p = 0; p < 64; ++p) {
+      sp = fmaf(W2[o * 64 + p], hp[p], sp);
+      sm = fmaf(W2[o * 64 + p], hm[p], sm);
+    }
+    fp = fmaf(W3[o], act(sp, a.activation), fp);
+    fm = fmaf(W3[o], act(sm, a.activation), fm);
   }
+  const float y = 0.5f * (fp - fm);
 
   const double xa = xp[(long)l * n + i];
   const double xprev = xp[(long)((l - 1 + L) % L) * n + i];

@@ -56,6 +56,7 @@ class Stats(ctypes.Structure):
         ("density", ctypes.c_double), ("double_occupancy", ctypes.c_double),
         ("s_cdw", ctypes.c_double), ("x_mean", ctypes.c_double), ("x2_mean", ctypes.c_double),
         ("replay_overrides", ctypes.c_int64), ("replay_mismatches", ctypes.c_int64),
+        ("last_log_pc", ctypes.c_double), ("last_sum_y", ctypes.c_double),
         ("n", ctypes.c_int32), ("L", ctypes.c_int32), ("flags", ctypes.c_int32),
     ]
 

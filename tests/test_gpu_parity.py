@@ -515,14 +515,16 @@ def test_uneven_batch_full_size_sampled(hq):
 
 
 def test_network_full_size_sampled(hq):
-    """The network workload at full size (64 chains of 16x16, L = 160): chains 0
-    and 63 swept beside the oracle's network sweep, inner decisions replayed
-    inside the tie band, cumulative accept and state compared."""
+    """The network workload at full size (64 chains of 16x16, L = 160) with the
+    trained network: chains 0 and 63 swept beside the oracle's network sweep,
+    inner decisions replayed inside the tie band, cumulative accept, fields,
+    log det and G compared."""
     w = workloads.holstein_16x16_network()
     g = w.groups[0]
     say("network 16x16 x64 full size, one sweep")
     gr = dict(nx=g.nx, chains=g.n_chains, g=g.g, beta=g.beta, n_stab=g.n_stab, proposal=1)
-    net = workloads.random_network(1001)
+    from paper_1905_07440_amd import train
+    net = train.load_weights("local")          # the trained network: cumulative updates are accepted
     ctx = make_ctx(hq, [gr], seed=w.seed)
     ctx.set_network(net)
     p = params_of(gr)

@@ -193,3 +193,104 @@ def test_cumulative_ratio_with_block_moves_and_two_inner_sweeps():
     dsb = model.bosonic_action(p, xp) - model.bosonic_action(p, x0)
     assert abs((nn.last_log_pc + nn.last_sum_y) - (lw1 - lw0 + dsb)) < 1e-9
     assert np.array_equal(ch.x, xp if nn.cumulative_accepts else x0)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_local_and_block_estimates_are_odd_under_the_reverse_move(seed):
+    """The estimate of a move and of the move that undoes it cancel: for a
+    local move y(x -> x + d e_li) = -y(x + d e_li -> x), and for a block
+    move f(x_i + D) - f(x_i) = -(f((x_i + D) - D) - f(x_i + D))."""
+    rng = np.random.default_rng(seed)
+    nx, L = 4, 8
+    x = rng.standard_normal((L, nx * nx))
+    w = nnmc.unpack(random_weights(seed))
+    cnn = nnmc.unpack_cnn(random_cnn(seed, L), L)
+    for _ in range(5):
+        l, i, d = int(rng.integers(L)), int(rng.integers(nx * nx)), float(rng.uniform(-0.5, 0.5))
+        xm = x.copy()
+        xm[l, i] += d
+        y = nnmc.local_estimate(w, nx, x, l, i, d)
+        assert abs(y + nnmc.local_estimate(w, nx, xm, l, i, -d)) < 1e-12 * max(1.0, abs(y))
+        # the raw output is not odd: the reverse move of f(d) alone would not cancel
+        f_fwd = nnmc.forward(w, nnmc.patch(nx, x, l, i, d))
+        f_rev = nnmc.forward(w, nnmc.patch(nx, xm, l, i, -d))
+        assert abs(f_fwd + f_rev) > 1e-6
+        xb = x.copy()
+        xb[:, i] += d
+        yb = nnmc.block_estimate(cnn, nx, x, i, d)
+        assert abs(yb + nnmc.block_estimate(cnn, nx, xb, i, -d)) < 1e-12 * max(1.0, abs(yb))
+
+
+def _path_log_prob(nn, p, steps, x_start):
+    """log of the probability (proposal densities left out: uniform and
+    symmetric) that the network sweep takes the given steps from x_start,
+    each step's points with their displacement and decision; every estimate
+    evaluated afresh with the network on the state the step starts from."""
+    w, cnn = nn.weights, nn.cnn
+    x = x_start.copy()
+    L = p.L
+    lp = 0.0
+    for kind, pts in steps:
+        for l, i, d, accepted in pts:
+            if kind == "local":
+                y = nnmc.local_estimate(w, p.nx, x, l, i, d)
+                ds = model.local_action_change(p, x[l, i], x[(l - 1) % L, i], x[(l + 1) % L, i], d)
+            else:
+                y = nnmc.block_estimate(cnn, p.nx, x, i, d)
+                ds = model.global_action_change(p, float(np.sum(x[:, i])), d, L)
+            a = y - ds
+            lp += min(0.0, a) if accepted else math.log1p(-math.exp(min(0.0, a)))
+        for l, i, d, accepted in pts:
+            if accepted:
+                if kind == "local":
+                    x[l, i] += d
+                else:
+                    x[:, i] += d
+    return lp, x
+
+
+@pytest.mark.parametrize("seed,nu,block", [(5, 1, False), (6, 2, False), (7, 1, True), (8, 2, True)])
+def test_cumulative_ratio_is_the_metropolis_hastings_ratio_of_the_composite_move(seed, nu, block):
+    """The cumulative accept is exact: with P(path) the probability of the
+    inner sweep's steps from X to X' and P(reverse) that of the same steps
+    in reverse order, each accepted move undone by its opposite displacement
+    and each rejected one rejected again, taken from X' by the opposite scan
+    direction,
+        log p_c = [log W(X') + log P(reverse)] - [log W(X) + log P(path)].
+    Both path probabilities are evaluated step by step with fresh network
+    evaluations, so an estimate that is not odd under the reverse move fails."""
+    p = Params(nx=4, beta=0.8, g=1.2, n_stab=4, local_width=0.5, global_width=0.4 if block else 0.0)
+    ch = dqmc.Chain(p, seed=seed, chain=0)
+    nn = nnmc.NNChain(ch, random_weights(seed), cnn=random_cnn(seed + 1, p.L) if block else None, nu=nu)
+    reversed_seen = set()
+    for _ in range(4):
+        x0 = ch.x.copy()
+        lw0 = ch.log_weight()
+        nn.sweep()
+        reversed_seen.add(nn.last_reversed)
+        fwd = [(kind, [(l, i, d, acc) for l, i, d, acc, _, _ in pts]) for kind, _, pts, _ in nn.path]
+        lp_f, xp = _path_log_prob(nn, p, fwd, x0)
+        assert np.array_equal(xp, nn.proposal)
+        back = [(kind, [(l, i, -d if acc else d, acc) for l, i, d, acc in pts]) for kind, pts in fwd[::-1]]
+        lp_r, xb = _path_log_prob(nn, p, back, xp)
+        assert np.allclose(xb, x0, rtol=0, atol=1e-12)
+        lw1 = ch.log_weight(xp)
+        assert abs((lw1 + lp_r) - (lw0 + lp_f) - nn.last_log_pc) < 1e-9
+    assert reversed_seen == {False, True}, "both scan directions occur"
+
+
+def test_reversed_sweep_visits_the_schedule_backwards():
+    p = Params(nx=4, beta=0.8, g=1.2, n_stab=4, global_width=0.4)
+    for s in range(8):
+        ch = dqmc.Chain(p, seed=9, chain=0)
+        ch.sweep_index = s
+        nn = nnmc.NNChain(ch, random_weights(9), cnn=random_cnn(10, p.L), nu=2)
+        nn.sweep()
+        kinds = [k for k, _, _, _ in nn.path]
+        us = [u for _, u, _, _ in nn.path]
+        fwd_kinds = ["local"] * 32 + ["block"] * 8
+        fwd_us = [0] * 16 + [1] * 16 + [0] * 4 + [1] * 4
+        if nnmc.scan_reversed(9, s):
+            assert kinds == fwd_kinds[::-1] and us == fwd_us[::-1]
+        else:
+            assert kinds == fwd_kinds and us == fwd_us

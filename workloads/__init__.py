@@ -88,6 +88,14 @@ def holstein_16x16_network_block():
                              global_width=1.0)])
 
 
+def holstein_16x16_dqmc():
+    # the network workload's lattice and chains under the conventional sweep
+    # (mixed precision, recompute every 5 slices): the reference the paper
+    # compares the network sampler with
+    return Workload("holstein-16x16-L160-dqmc-mixed-nstab5-64chains", 5,
+                    [Lattice(nx=16, n_chains=64, g=1.2, beta=16.0, n_stab=5)], precision=1)
+
+
 ALL = {
     "c1": holstein_4x4_single,
     "c2": holstein_8x8_batched_global,
@@ -99,6 +107,7 @@ ALL = {
     "c4": holstein_uneven_batch,
     "c5": holstein_16x16_network,
     "c5-block": holstein_16x16_network_block,
+    "c5-dqmc": holstein_16x16_dqmc,
 }
 
 
