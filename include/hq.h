@@ -223,7 +223,9 @@ hq_status hq_read_decisions(hq_ctx* ctx, int32_t chain, int32_t kind,
 
 /* Tie-band replay for the next sweep only: where |ln u - ln R| <= band the
  * chain takes bits[slot] instead of its own decision; elsewhere a
- * disagreement is counted in hq_stats.replay_mismatches.  n = 0 clears. */
+ * disagreement is counted in hq_stats.replay_mismatches.  n = 0 clears.
+ * A test facility: needs options.record = 1 (HQ_EINVAL otherwise; the
+ * kernels of other contexts carry no replay work). */
 hq_status hq_set_replay(hq_ctx* ctx, int32_t chain, int32_t kind,
                         const uint8_t* bits, int64_t n, double band);
 

@@ -419,6 +419,13 @@ struct Sched {
   int phase = -1;   // profiling phase of the launches being issued
 };
 
+// the replay log of one kind, or null: replay is a test facility of contexts
+// created with options.record = 1, and the kernels of other contexts carry
+// none of its work
+const uint8_t* replay_of(const hq_ctx* ctx, const Group& g, int kind) {
+  return ctx->opt.record ? g.replay[kind] : nullptr;
+}
+
 hq_status begin_phase(Sched& S, int ph) {
   hq_ctx* ctx = S.ctx;
   if (!ctx->profiling) return HQ_OK;
@@ -784,7 +791,7 @@ hq_status local(Sched& S, Group& g, int slice) {
   a.seed = S.ctx->seed; a.chain0 = g.chain0; a.sweep = S.ctx->sweep_counter;
   a.logdet = g.logdet; a.counters = g.counters;
   a.log_margin = g.log_margin[HQ_KIND_LOCAL]; a.log_accept = g.log_accept[HQ_KIND_LOCAL];
-  a.replay = g.replay[HQ_KIND_LOCAL]; a.band = g.band[HQ_KIND_LOCAL]; a.replay_counts = g.replay_counts;
+  a.replay = replay_of(S.ctx, g, HQ_KIND_LOCAL); a.band = g.band[HQ_KIND_LOCAL]; a.replay_counts = g.replay_counts;
   SCHED_TRY(launch_local(a, S.ctx->opt.precision, g.nt, g.kd, g.C, S.s));
   return HQ_OK;
 }
@@ -958,7 +965,7 @@ hq_status global_moves(Sched& S, Group& g) {
     a.G = g.G; a.precision = S.ctx->opt.precision; a.Gnew = g.Gnew;
     a.counters = g.counters;
     a.log_margin = g.log_margin[HQ_KIND_GLOBAL]; a.log_accept = g.log_accept[HQ_KIND_GLOBAL];
-    a.replay = g.replay[HQ_KIND_GLOBAL]; a.band = g.band[HQ_KIND_GLOBAL]; a.replay_counts = g.replay_counts;
+    a.replay = replay_of(S.ctx, g, HQ_KIND_GLOBAL); a.band = g.band[HQ_KIND_GLOBAL]; a.replay_counts = g.replay_counts;
     SCHED_TRY(launch_global_propose(a, g.C, S.s));
     ST_TRY(from_scratch(S, g, g.xp, g.tree ? g.tT[0] : g.blkp));
     SCHED_TRY(launch_global_accept(a, g.C, S.s));
@@ -997,7 +1004,7 @@ hq_status network_sweep(Sched& S, Group& g) {
       a.w = ctx->net; a.activation = ctx->opt.activation; a.chains = g.C;
       a.sum_y = g.sum_y; a.accepted = g.nn_acc; a.counters = g.counters;
       a.log_margin = g.log_margin[HQ_KIND_NN]; a.log_accept = g.log_accept[HQ_KIND_NN];
-      a.replay = g.replay[HQ_KIND_NN]; a.band = g.band[HQ_KIND_NN]; a.replay_counts = g.replay_counts;
+      a.replay = replay_of(ctx, g, HQ_KIND_NN); a.band = g.band[HQ_KIND_NN]; a.replay_counts = g.replay_counts;
       SCHED_TRY(launch_network_colour(a, g.C, S.s));
     } else {
       CnnArgs a;
@@ -1009,7 +1016,7 @@ hq_status network_sweep(Sched& S, Group& g) {
       a.w = ctx->cnn; a.chains = g.C;
       a.sum_y = g.sum_yb; a.accepted = g.acc_b;
       a.log_margin = g.log_margin[HQ_KIND_NN_GLOBAL]; a.log_accept = g.log_accept[HQ_KIND_NN_GLOBAL];
-      a.replay = g.replay[HQ_KIND_NN_GLOBAL]; a.band = g.band[HQ_KIND_NN_GLOBAL];
+      a.replay = replay_of(ctx, g, HQ_KIND_NN_GLOBAL); a.band = g.band[HQ_KIND_NN_GLOBAL];
       a.replay_counts = g.replay_counts;
       SCHED_TRY(launch_cnn_colour(a, g.C, S.s));
     }
@@ -1023,7 +1030,7 @@ hq_status network_sweep(Sched& S, Group& g) {
   c.sum_yb = g.sum_yb; c.accepted_b = g.acc_b; c.inner = g.nu;
   c.seed = ctx->seed; c.chain0 = g.chain0; c.sweep = ctx->sweep_counter; c.counters = g.counters;
   c.log_margin = g.log_margin[HQ_KIND_CUMULATIVE]; c.log_accept = g.log_accept[HQ_KIND_CUMULATIVE];
-  c.replay = g.replay[HQ_KIND_CUMULATIVE]; c.band = g.band[HQ_KIND_CUMULATIVE]; c.replay_counts = g.replay_counts;
+  c.replay = replay_of(ctx, g, HQ_KIND_CUMULATIVE); c.band = g.band[HQ_KIND_CUMULATIVE]; c.replay_counts = g.replay_counts;
   c.last_log_pc = g.lastpc;
   SCHED_TRY(launch_cumulative(c, g.C, S.s));
   return HQ_OK;
@@ -1743,6 +1750,7 @@ hq_status hq_set_replay(hq_ctx* ctx, int32_t chain, int32_t kind, const uint8_t*
   if (!g || (kind != HQ_KIND_LOCAL && kind != HQ_KIND_GLOBAL && kind != HQ_KIND_NN && kind != HQ_KIND_CUMULATIVE &&
              kind != HQ_KIND_NN_GLOBAL))
     return fail(ctx, HQ_EINVAL, "bad chain or kind");
+  if (!ctx->opt.record) return fail(ctx, HQ_EINVAL, "replay needs options.record = 1");
   const long slots = g->kind_slots(kind);
   if (!(band >= 0) || (n != 0 && (n != slots || !bits))) return fail(ctx, HQ_EINVAL, "expected %ld bits", slots);
   // the band is a kernel argument: the captured graphs are rebuilt on next use

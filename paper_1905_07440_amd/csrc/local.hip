@@ -34,6 +34,8 @@
 //                        block pass through LDS.  The flush is pure MFMA work.
 //   local_stream_kernel  G stays in global memory and the flush streams it in
 //                        batches of tiles: any N <= 256, any K.
+#include <type_traits>
+
 #include "hq_device.h"
 #include "hq_internal.h"
 
@@ -342,16 +344,41 @@ __device__ __attribute__((always_inline)) inline void walk_diag(GetG g0, int bas
     my = sc[base + k];
     my_rp = rp[base + k];
   }
-  double r = 1.0, R = 0.0, racc = 1.0;
+  // The Metropolis test u < R = r^2 exp(-dS_b), r = 1 + delta (1 - G_kk), as
+  // a test on G_kk alone: r >= 0 (G_kk lies in [0, 1]), so u < R is
+  // r > s = sqrt(u exp(dS_b)), i.e. G_kk < 1 - (s - 1) / delta for delta > 0
+  // and G_kk > 1 - (s - 1) / delta for delta < 0; with sg = sign(delta) the
+  // test is sg G_kk < kthr, kthr = sg (1 - (s - 1) / delta), set once per
+  // block.  (delta = 0: r = 1, the test is u < exp(-dS_b) whatever G_kk.)
+  T ksg = T(1), kthr;
+  {
+    const double sq = sqrt(my.u / my.bos);
+    if (my.delta > 0.0) {
+      kthr = (T)(1.0 - (sq - 1.0) / my.delta);
+    } else if (my.delta < 0.0) {
+      ksg = T(-1);
+      kthr = (T)(-(1.0 - (sq - 1.0) / my.delta));
+    } else {
+      kthr = (my.u < my.bos) ? (T)INFINITY : (T)-INFINITY;
+    }
+  }
+  T gacc = T(0);                           // this lane's G_kk when its own move was accepted
+  bool mine = false;
   T coef = T(0);
+  double R = 0.0;
   int nover = 0, nmis = 0;
-  // this lane's ratio on the current diagonal; the replayed bit inside the band
+  // this lane's decision on the current diagonal (the replayed bit inside the
+  // band in the test build) and its coefficient c = delta / r in case it is
+  // accepted
   auto judge = [&]() -> bool {
-    r = 1.0 + my.delta * (1.0 - (double)dg);
-    R = r * r * my.bos;
-    coef = (T)(my.delta * recip(r));
-    bool a = my.u < R;
-    if (HOOKS && my_rp != 255 && my.u >= R * band_lo && my.u <= R * band_hi) a = my_rp != 0;
+    bool a = ksg * dg < kthr;
+    const T rt = fma((T)my.delta, T(1) - dg, T(1));
+    coef = (T)my.delta * recip(rt);
+    if (HOOKS) {
+      const double r = 1.0 + my.delta * (1.0 - (double)dg);
+      R = r * r * my.bos;
+      if (my_rp != 255 && my.u >= R * band_lo && my.u <= R * band_hi) a = my_rp != 0;
+    }
     return a;
   };
   uint64_t ball = __ballot(judge());
@@ -363,7 +390,7 @@ __device__ __attribute__((always_inline)) inline void walk_diag(GetG g0, int bas
         // the site's own ratio at its decision: logged, and the replay counted
         Rv[base + q] = R;
         if (my_rp != 255) {
-          const int raw = my.u < R ? 1 : 0;
+          const int raw = (ksg * dg < kthr) ? 1 : 0;
           if (my.u >= R * band_lo && my.u <= R * band_hi) nover += (raw != my_rp) ? 1 : 0;
           else nmis += (raw != my_rp) ? 1 : 0;
         }
@@ -374,7 +401,8 @@ __device__ __attribute__((always_inline)) inline void walk_diag(GetG g0, int bas
         const T gkq = self ? dg : row[q];  // G[k][q]
         const T gqk = self ? dg : col[q];  // G[q][k]
         const T ak = c * gkq;              // A[k, m]
-        racc = self ? r : racc;
+        gacc = self ? dg : gacc;
+        mine = mine || self;
         dg = dg + ak * gqk;                // the diagonal first: the next decision waits on it
         ball = __ballot(judge());
         if (lane < K) {
@@ -398,8 +426,158 @@ __device__ __attribute__((always_inline)) inline void walk_diag(GetG g0, int bas
       }
     }
   }
-  // log|r| of the accepted moves and the replay counts, over the owning lanes
-  double lr = (lane < K) ? log(fabs(racc)) : 0.0;
+  // log|r| of the accepted moves (r in FP64 from the diagonal at acceptance)
+  // and the replay counts, over the owning lanes
+  double lr = (lane < K && mine) ? log(fabs(1.0 + my.delta * (1.0 - (double)gacc))) : 0.0;
+  lr = wave_sum(lr);
+  st.logr += lr;
+  if (HOOKS) {
+    st.counts[0] += wave_sum(lane < K ? nover : 0);
+    st.counts[1] += wave_sum(lane < K ? nmis : 0);
+  }
+  st.nacc += m;
+  if (lane == 0) hdr->p[blk & 1] = m;
+}
+
+// The same walk for blocks of 16 sites with all 64 lanes at work.  Lane
+// k + 16 g (k < 16, g < 4) holds, for s < 4, the entries G[k][4s + g] and
+// G[4s + g][k] of the block, and every row of 16 lanes keeps a copy of the
+// diagonal and of the sites' constants.  The update after an accepted move at
+// q touches G[k][j] with G[q][j] and G[j][k] with G[j][q]: both are held by
+// lane q of the same 16-lane row, so one row broadcast (DPP row_newbcast)
+// serves the four row groups at once, 4 entries per lane instead of 16.  The
+// two coefficients G[k][q] and G[q][k] live in row group q mod 4 and reach the
+// others through two lane-swap steps (v_permlane16_swap, v_permlane32_swap).
+template <int Q> __device__ inline float row_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + Q, 0xF, 0xF, true));
+}
+template <int Q> __device__ inline double row_bcast(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + Q, 0xF, 0xF, true);
+}
+// the value row group G holds, in every row group
+template <int G> __device__ inline unsigned from_group(unsigned v) {
+  const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);   // [r0 r0 r2 r2], [r1 r1 r3 r3]
+  const unsigned z = (G & 1) ? p[1] : p[0];
+  const auto w = __builtin_amdgcn_permlane32_swap(z, z, false, false);   // [z0 z1 z0 z1], [z2 z3 z2 z3]
+  return (G >> 1) ? w[1] : w[0];
+}
+template <int G> __device__ inline float from_group(float v) { return __uint_as_float(from_group<G>(__float_as_uint(v))); }
+template <int G> __device__ inline double from_group(double v) {
+  const unsigned lo = from_group<G>((unsigned)__double2loint(v)), hi = from_group<G>((unsigned)__double2hiint(v));
+  return __hiloint2double((int)hi, (int)lo);
+}
+
+template <typename T, bool HOOKS, typename GetG>
+__device__ __attribute__((always_inline)) inline void walk_dense(GetG g0, int base, int cnt, int blk,
+                                                                 const SiteConst* sc, const uint8_t* rp, BlockHdr* hdr,
+                                                                 T* Arec, T* Brec, uint8_t* flags, double* Rv,
+                                                                 double band_lo, double band_hi, WalkState& st) {
+  constexpr int K = 16, KR = K + 16 / (int)sizeof(T);
+  const int lane = threadIdx.x & 63;
+  const int k = lane & 15, grp = lane >> 4;
+  const bool act = k < cnt;
+  T R[4], C[4];                            // R[s] = G[k][4s + grp], C[s] = G[4s + grp][k]
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) {
+    const int j = 4 * s4 + grp;
+    R[s4] = (act && j < cnt) ? g0(k, j) : T(0);
+    C[s4] = (act && j < cnt) ? g0(j, k) : T(0);
+  }
+  T dg = act ? g0(k, k) : T(0);
+  SiteConst my = {0.0, 0.0, 2.0, 0.0};     // u = 2: never accepted
+  int my_rp = 255;
+  if (act) {
+    my = sc[base + k];
+    my_rp = rp[base + k];
+  }
+  // the Metropolis test as a test on G_kk (see walk_diag)
+  T ksg = T(1), kthr;
+  {
+    const double sq = sqrt(my.u / my.bos);
+    if (my.delta > 0.0) {
+      kthr = (T)(1.0 - (sq - 1.0) / my.delta);
+    } else if (my.delta < 0.0) {
+      ksg = T(-1);
+      kthr = (T)(-(1.0 - (sq - 1.0) / my.delta));
+    } else {
+      kthr = (my.u < my.bos) ? (T)INFINITY : (T)-INFINITY;
+    }
+  }
+  T gacc = T(0);
+  bool mine = false;
+  T coef = T(0);
+  double Rr = 0.0;
+  int nover = 0, nmis = 0;
+  auto judge = [&]() -> bool {
+    bool a = ksg * dg < kthr;
+    const T rt = fma((T)my.delta, T(1) - dg, T(1));
+    coef = (T)my.delta * recip(rt);
+    if (HOOKS) {
+      const double r = 1.0 + my.delta * (1.0 - (double)dg);
+      Rr = r * r * my.bos;
+      if (my_rp != 255 && my.u >= Rr * band_lo && my.u <= Rr * band_hi) a = my_rp != 0;
+    }
+    return a;
+  };
+  uint64_t ball = __ballot(judge());
+  int m = 0;
+  auto step = [&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int qs = q >> 2, qg = q & 3;
+    if (q >= cnt) return;
+    if (HOOKS && lane == q) {
+      Rv[base + q] = Rr;
+      if (my_rp != 255) {
+        const int raw = (ksg * dg < kthr) ? 1 : 0;
+        if (my.u >= Rr * band_lo && my.u <= Rr * band_hi) nover += (raw != my_rp) ? 1 : 0;
+        else nmis += (raw != my_rp) ? 1 : 0;
+      }
+    }
+    if ((ball >> q) & 1) {                 // a scalar branch on the ballot bit
+      const T c = bcast(coef, q);
+      const bool self = k == q;
+      const T gkq = self ? dg : from_group<qg>(R[qs]);   // G[k][q]
+      const T gqk = self ? dg : from_group<qg>(C[qs]);   // G[q][k]
+      const T ak = c * gkq;                // A[k, m]
+      gacc = self ? dg : gacc;
+      mine = mine || self;
+      dg = dg + ak * gqk;
+      ball = __ballot(judge());
+      if (lane < K) {
+        Arec[k * KR + m] = ak;
+        Brec[k * KR + m] = (self ? T(1) : T(0)) - gqk;
+      }
+      const T cg = c * gqk;
+#pragma unroll
+      for (int s4 = qs; s4 < 4; ++s4) {    // entries j = 4 s4 + grp; those with j <= q are not read again
+        R[s4] += ak * row_bcast<q>(R[s4]);   // G[k][j] += c G[k][q] G[q][j]
+        C[s4] += cg * row_bcast<q>(C[s4]);   // G[j][k] += c G[q][k] G[j][q]
+      }
+      if (lane == 0) {
+        hdr->site[m] = base + q;
+        hdr->c[m] = (double)c;
+        flags[base + q] = 1;
+      }
+      m = uniform(m + 1);
+    }
+  };
+  step(std::integral_constant<int, 0>());
+  step(std::integral_constant<int, 1>());
+  step(std::integral_constant<int, 2>());
+  step(std::integral_constant<int, 3>());
+  step(std::integral_constant<int, 4>());
+  step(std::integral_constant<int, 5>());
+  step(std::integral_constant<int, 6>());
+  step(std::integral_constant<int, 7>());
+  step(std::integral_constant<int, 8>());
+  step(std::integral_constant<int, 9>());
+  step(std::integral_constant<int, 10>());
+  step(std::integral_constant<int, 11>());
+  step(std::integral_constant<int, 12>());
+  step(std::integral_constant<int, 13>());
+  step(std::integral_constant<int, 14>());
+  step(std::integral_constant<int, 15>());
+  double lr = (lane < K && mine) ? log(fabs(1.0 + my.delta * (1.0 - (double)gacc))) : 0.0;
   lr = wave_sum(lr);
   st.logr += lr;
   if (HOOKS) {
@@ -435,11 +613,23 @@ __device__ __attribute__((always_inline)) inline void recur_rows(const BlockHdr*
       cm[slot] = (T)hdr->c[mc];
       ga[slot] = live ? Cs[j * cl + im[slot]] : T(0);
       gb[slot] = live ? Rs[im[slot] * rl + j] : T(0);
+      // Bv[i_m, m'] and A[i_m, m'] for m' < m, 16 bytes at a time (the record
+      // rows are 16-byte aligned and K + 16 / sizeof(T) long)
+      constexpr int V = 16 / (int)sizeof(T);
+      typedef T vec __attribute__((ext_vector_type(V)));
+      const vec* vb = (const vec*)(Brec + im[slot] * KR);
+      const vec* va = (const vec*)(Arec + im[slot] * KR);
 #pragma unroll
-      for (int m2 = 0; m2 < KE; ++m2) {
-        if (m2 < mq) {
-          wb[slot][m2] = Brec[im[slot] * KR + m2];   // Bv[i_m, m']
-          wa[slot][m2] = Arec[im[slot] * KR + m2];   // A[i_m, m']
+      for (int g = 0; g < (KE + V - 1) / V; ++g) {
+        if (g * V < mq) {
+          const vec b4 = vb[g], a4 = va[g];
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            if (g * V + e < KE) {
+              wb[slot][g * V + e] = b4[e];
+              wa[slot][g * V + e] = a4[e];
+            }
+          }
         }
       }
     };
@@ -538,25 +728,44 @@ __global__ __launch_bounds__(256) void local_regs_kernel(LocalArgs a) {
   __syncthreads();
 
   // columns and rows [base, base + K) of G into Cs and Rs.  K is a multiple
-  // of 16 and base of K, so a tile lies wholly inside the block or outside it.
+  // of 16 and base of K, so the block is K / 16 whole tile columns (rows).
+  // Tile column t is in this wave's grid iff t - wc is even, as its index
+  // tb = (t - wc) / 2: one uniform test per tile column and row of the grid.
   auto extract = [&](int base) {
 #pragma unroll
-    for (int ta = 0; ta < H; ++ta)
+    for (int u = 0; u < K / 16; ++u) {
+      const int t = (base >> 4) + u;
+      const int tbr = ((t - wc) & 1) == 0 && t < nt ? (t - wc) >> 1 : -1;
+      const int tar = ((t - wr) & 1) == 0 && t < nt ? (t - wr) >> 1 : -1;
+      const int cc = t * 16 + (lane & 15) - base;
 #pragma unroll
       for (int tb = 0; tb < H; ++tb) {
-        const int ti = wr + 2 * ta, tj = wc + 2 * tb;
-        if (ti < nt && tj < nt) {
-          const int cc = tj * 16 + (lane & 15);
-          if (tj * 16 >= base && tj * 16 < base + K) {
+        if (tb == tbr) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Cs[(ti * 16 + frag_row<T>(lane, v)) * cl + (cc - base)] = G.t[ta][tb][v];
-          }
-          if (ti * 16 >= base && ti * 16 < base + K) {
+          for (int ta = 0; ta < H; ++ta) {
+            const int ti = wr + 2 * ta;
+            if (ti < nt) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Rs[(ti * 16 + frag_row<T>(lane, v) - base) * rl + cc] = G.t[ta][tb][v];
+              for (int v = 0; v < 4; ++v) Cs[(ti * 16 + frag_row<T>(lane, v)) * cl + cc] = G.t[ta][tb][v];
+            }
           }
         }
       }
+#pragma unroll
+      for (int ta = 0; ta < H; ++ta) {
+        if (ta == tar) {
+#pragma unroll
+          for (int tb = 0; tb < H; ++tb) {
+            const int tj = wc + 2 * tb;
+            if (tj < nt) {
+              const int c2 = tj * 16 + (lane & 15);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) Rs[(t * 16 + frag_row<T>(lane, v) - base) * rl + c2] = G.t[ta][tb][v];
+            }
+          }
+        }
+      }
+    }
   };
   extract(0);
   __syncthreads();
@@ -564,9 +773,15 @@ __global__ __launch_bounds__(256) void local_regs_kernel(LocalArgs a) {
   const double band_lo = exp(-a.band), band_hi = exp(a.band);
   WalkState st = {0.0, 0, {0, 0}};
   for (int base = 0, blk = 0; base < n; base += K, ++blk) {
-    if (walker)
-      walk_diag<T, K, HOOKS>([&](int r, int cc) { return Cs[(base + r) * cl + cc]; }, base, min(K, n - base), blk,
-                             sc, rp, hdr, Arec, Brec, flags, Rv, band_lo, band_hi, st);
+    if (walker) {
+      auto g0 = [&](int r, int cc) { return Cs[(base + r) * cl + cc]; };
+      if constexpr (K == 16)
+        walk_dense<T, HOOKS>(g0, base, min(K, n - base), blk, sc, rp, hdr, Arec, Brec, flags, Rv, band_lo, band_hi,
+                             st);
+      else
+        walk_diag<T, K, HOOKS>(g0, base, min(K, n - base), blk, sc, rp, hdr, Arec, Brec, flags, Rv, band_lo,
+                               band_hi, st);
+    }
     __syncthreads();
     const int p = hdr->p[blk & 1];
     if (p > 0) {                           // the same for every thread
