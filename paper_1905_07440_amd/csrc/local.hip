@@ -657,15 +657,26 @@ __device__ __attribute__((always_inline)) inline void recur_rows(const BlockHdr*
       Bp[j * KL + mq] = b[mq];
       __builtin_amdgcn_sched_barrier(0);
     }
+#pragma unroll
+    for (int mq = KE; mq < ((KE + 3) & ~3); ++mq) {   // zero columns up to the flush's group of four
+      Ap[j * KL + mq] = T(0);
+      Bp[j * KL + mq] = T(0);
+    }
   }
 }
 
 template <typename T, int K>
 __device__ __attribute__((always_inline)) inline void recur_rows_any(const BlockHdr* hdr, int p, int base, int n, int rows, const T* Cs, int cl,
                                       const T* Rs, int rl, const T* Arec, const T* Brec, T* Ap, T* Bp) {
-  if (p <= 4) recur_rows<T, K, 4>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+  // KE = p rounded up to even (the flush reads whole groups of four columns:
+  // an odd-sized KE leaves column KE untouched, so the zero fill covers it)
+  if (p <= 2) recur_rows<T, K, 2>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+  else if (p <= 4) recur_rows<T, K, 4>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+  else if (p <= 6) recur_rows<T, K, 6>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
   else if (p <= 8) recur_rows<T, K, 8>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+  else if (p <= 10) recur_rows<T, K, 10>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
   else if (p <= 12) recur_rows<T, K, 12>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
+  else if (p <= 14) recur_rows<T, K, 14>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
   else if (p <= 16) recur_rows<T, K, 16>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
   else if constexpr (K > 16) {
     if (p <= 24) recur_rows<T, K, 24>(hdr, p, base, n, rows, Cs, cl, Rs, rl, Arec, Brec, Ap, Bp);
