@@ -1140,12 +1140,594 @@ __global__ __launch_bounds__(256) void gj_regs_kernel(double* __restrict__ Mg, d
   (void)W;
 }
 
+// ===========================================================================
+// Wide forms for a few large matrices (N > 144 with a batch small enough that
+// one workgroup per matrix would leave most CUs idle): S workgroups per
+// matrix and one launch per panel.  Every wave holds the whole 16-column
+// panel in its registers and factors (or eliminates) it alone, so a column
+// step needs no barrier and no LDS round trip; the S x 4 waves of a matrix
+// then share the panel's independent work items, strips of 16 columns.
+// All waves reach the same reflectors and pivots (same data, same
+// instruction order), so no workgroup waits for another inside a launch:
+// the launch boundary orders the panels.  Workgroup w of matrix z is block
+// w * batch + z, which keeps a matrix's workgroups on one XCD (one L2) when
+// the batch is a multiple of 8.
+// ===========================================================================
+
+// totals over the 64 lanes of NV values (NV = 16, 8, 4, 2, 1), returned
+// wave-uniform.  The halving butterfly leaves value k in lane (64 / NV) k.
+template <int NV>
+__device__ inline void wave_totals_n(const double (&v)[NV], double (&t)[NV]) {
+  const int lane = threadIdx.x & 63;
+  if constexpr (NV == 16) {
+    double a8[8], a4[4], a2[2];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a8[i] = swap_sum32(v[i], v[8 + i]);     // lane bit 5 picks the upper half
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a4[i] = swap_sum16(a8[i], a8[4 + i]);   // bit 4
+    const bool h3 = (lane & 8) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a2[i] = (h3 ? a4[2 + i] : a4[i]) + dpp_move<0x128>(h3 ? a4[i] : a4[2 + i]);
+    const bool h2 = (lane & 4) != 0;
+    double a1 = (h2 ? a2[1] : a2[0]) + dpp_move<0x141>(h2 ? a2[0] : a2[1]);   // lane ^ 7 flips bit 2
+    a1 += dpp_move<0xB1>(a1);
+    a1 += dpp_move<0x4E>(a1);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) t[c] = lane_value(a1, 4 * c);
+  } else if constexpr (NV == 8) {
+    wave_totals8(v, t);
+  } else if constexpr (NV == 4) {
+    double a2[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a2[i] = swap_sum32(v[i], v[2 + i]);
+    double a1 = swap_sum16(a2[0], a2[1]);
+    a1 += dpp_move<0xB1>(a1);
+    a1 += dpp_move<0x4E>(a1);
+    a1 += dpp_move<0x141>(a1);
+    a1 += dpp_move<0x140>(a1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) t[c] = lane_value(a1, 16 * c);
+  } else if constexpr (NV == 2) {
+    double a1 = swap_sum32(v[0], v[1]);
+    a1 = swap_sum16(a1, a1);                                             // rows 2i and 2i + 1
+    a1 += dpp_move<0xB1>(a1);
+    a1 += dpp_move<0x4E>(a1);
+    a1 += dpp_move<0x141>(a1);
+    a1 += dpp_move<0x140>(a1);
+    t[0] = lane_value(a1, 0);
+    t[1] = lane_value(a1, 32);
+  } else {
+    t[0] = wave_total(v[0]);
+  }
+}
+
+// Column j of a panel held whole by the calling wave (a[c][t]: column c, row
+// lane + 64 t, rows relative to the panel's diagonal block, m of them).  One
+// butterfly gives the squared norm of the column's tail below the diagonal
+// (slot 0) and the tail's dots with the columns right of j (slot k: column
+// j + k); the reflector H = I - tau v v^T with v = e_j + tail / (al - be)
+// maps the column to be e_j and is applied to those columns.  NV >= 16 - j.
+template <int NV, int RPL>
+__device__ inline void qr_column(int j, int m, double (&a)[NB][RPL], double* tau) {
+  const int lane = threadIdx.x & 63;
+  double tail[RPL];
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r = lane + 64 * t;
+    tail[t] = (r > j && r < m) ? a[j][t] : 0.0;
+  }
+  double part[NV];
+  part[0] = 0.0;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) part[0] += tail[t] * tail[t];
+#pragma unroll
+  for (int k = 1; k < NV; ++k) {
+    part[k] = 0.0;
+    if (j + k < NB) {
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) part[k] += tail[t] * a[j + k][t];
+    }
+  }
+  double tot[NV];
+  wave_totals_n<NV>(part, tot);
+  const double sg = tot[0];
+  const double al = lane_value(a[j][0], j);          // row j < 16 lives in slot 0 of lane j
+  double be = al, tj = 0.0, scl = 0.0;
+  if (sg > 0.0) {
+    const double nrm = sqrt(al * al + sg);
+    be = (al >= 0.0) ? -nrm : nrm;
+    tj = (be - al) * rcp_nr(be);
+    scl = rcp_nr(al - be);                           // |al - be| = |al| + nrm > 0
+  }
+  double vr[RPL];
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) vr[t] = (lane + 64 * t == j) ? 1.0 : tail[t] * scl;
+#pragma unroll
+  for (int k = 1; k < NV; ++k)
+    if (j + k < NB) {
+      const double w = tj * (lane_value(a[j + k][0], j) + scl * tot[k]);   // v^T a_c = a_c[j] + scl (tail . a_c)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) a[j + k][t] -= vr[t] * w;
+    }
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r = lane + 64 * t;
+    if (r >= j) a[j][t] = (r == j) ? be : vr[t];
+  }
+  if (threadIdx.x == 0) tau[j] = tj;
+}
+
+// the nbw columns of a panel, in order; on return a holds R on and above the
+// diagonal and the reflectors' tails below it, tau (LDS, written by thread 0)
+// their scales, zero past nbw
+template <int RPL>
+__device__ inline void qr_panel_wave(int nbw, int m, double (&a)[NB][RPL], double* tau) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < nbw) {
+      if (j < 8) qr_column<16>(j, m, a, tau);
+      else if (j < 12) qr_column<8>(j, m, a, tau);
+      else if (j < 14) qr_column<4>(j, m, a, tau);
+      else if (j < 15) qr_column<2>(j, m, a, tau);
+      else qr_column<1>(j, m, a, tau);
+    } else if (threadIdx.x == 0) {
+      tau[j] = 0.0;
+    }
+  }
+}
+
+// Gauss-Jordan elimination of a panel held whole by the calling wave (all n
+// rows; a[c][t]: column c, row lane + 64 t).  Column j: the pivot is the
+// unused row of largest |a| (the FP32 key of eliminate_panel: near-equal
+// magnitudes go to the lower row); its row across the panel is read from its
+// lane; rows other than the pivot row lose a multiple of it, the pivot row is
+// divided by the pivot, and column j becomes -a / pivot with 1 / pivot on the
+// pivot row.  prow[j] and pval[j] (LDS, written by thread 0) record the pivots.
+template <int RPL>
+__device__ inline void gj_panel_wave(int nbw, int n, double (&a)[NB][RPL], bool (&used)[RPL], int* prow,
+                                     double* pval) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < nbw) {
+      uint32_t key = 0;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = lane + 64 * t;
+        const uint32_t kt = (__float_as_uint((float)fabs(a[j][t])) & ~0x1FFu) | (uint32_t)(511 - r);
+        if (r < n && !used[t]) key = max(key, kt);
+      }
+      key = wave_max_u32(key);
+      const int pr = 511 - (int)(key & 0x1FFu), pl = pr & 63, pt = pr >> 6;
+      double pv[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) pv[c] = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t)
+        if (pt == t) {                                  // uniform: the pivot row's register slot
+#pragma unroll
+          for (int c = 0; c < NB; ++c) pv[c] = lane_value(a[c][t], pl);
+        }
+      const double pj = pv[j];
+      const double ip = rcp_nr(pj);
+      double aj[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) aj[t] = a[j][t];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c == j) continue;
+        const double wp = pv[c] * ip;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) a[c][t] = fma(-aj[t], wp, a[c][t]);
+      }
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) a[j][t] = -aj[t] * ip;
+      const bool me = lane == pl;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t)
+        if (pt == t) {
+#pragma unroll
+          for (int c = 0; c < NB; ++c) a[c][t] = me ? ((c == j) ? ip : pv[c] * ip) : a[c][t];
+          used[t] = used[t] || me;
+        }
+      if (threadIdx.x == 0) {
+        prow[j] = pr;
+        pval[j] = pj;
+      }
+    }
+  }
+}
+
+// One wave applies I - V op(T) V^T (op(T) = T^T: the transposed block
+// reflector, Q^T from the left) to one strip of 16 columns on the rows from
+// the panel's top (m of them): w1 = V^T X, w2 = op(T) w1, X -= V w2.
+// load(rr, c) / store(rr, c, v) address row rr relative to the panel's top
+// and column c of the strip (0..15); load returns 0 outside the matrix and
+// store drops those elements.
+template <int MX, typename Load, typename Store>
+__device__ inline void strip_reflect(int m, const double (*Vs)[VLD], const double (*Ts)[NB + 1], double (*S)[NB + 1],
+                                     Load load, Store store) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  constexpr int NTL = Cap<MX>::tiles;
+  const int ntile = (m + 15) / 16;
+  d4 tile[NTL];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tile[t][v] = (t < ntile) ? load(16 * t + frag_row<double>(lane, v), li) : 0.0;
+  d4 w1 = {0, 0, 0, 0};
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+    if (t < ntile) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w1 = mfma16(Vs[li][16 * t + 4 * q + lk], tile[t][q], w1);
+    }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) S[frag_row<double>(lane, v)][li] = w1[v];
+  wave_sync_lds();
+  d4 w2 = {0, 0, 0, 0};
+#pragma unroll
+  for (int k0 = 0; k0 < NB; k0 += 4) w2 = mfma16(Ts[k0 + lk][li], S[k0 + lk][li], w2);
+  wave_sync_lds();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) S[frag_row<double>(lane, v)][li] = w2[v];
+  wave_sync_lds();
+  double wb[NB / 4];
+#pragma unroll
+  for (int q = 0; q < NB / 4; ++q) wb[q] = S[4 * q + lk][li];
+  wave_sync_lds();                                    // S is rewritten by the next strip
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+    if (t < ntile) {
+#pragma unroll
+      for (int q = 0; q < NB / 4; ++q) tile[t] = mfma16(-Vs[4 * q + lk][16 * t + li], wb[q], tile[t]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) store(16 * t + frag_row<double>(lane, v), li, tile[t][v]);
+    }
+}
+
+// wide-form scratch per matrix: Q^T and the factored panels (n x n each) and
+// S partial column norms (QR); the second work matrix, pivot rows and pivot
+// values (Gauss-Jordan) share the same space
+constexpr int WIDE_MAX_SPLIT = 8;
+__host__ __device__ inline long wide_stride(int n) { return 2L * n * n + (long)WIDE_MAX_SPLIT * n; }
+size_t wide_scratch_doubles(int n) { return (size_t)wide_stride(n); }
+
+int wide_split(int n, int batch) {
+  if (n <= 144 || batch < 1) return 1;
+  const int s = std::min(WIDE_MAX_SPLIT, 256 / batch);
+  return s >= 2 ? s : 1;
+}
+
+// partial squared column norms of Z over row block w of S
+__global__ __launch_bounds__(256) void qr_wide_norms_kernel(const double* __restrict__ Zg, double* __restrict__ Xg,
+                                                            int n, int batch, int S) {
+  const int z = blockIdx.x % batch, w = blockIdx.x / batch;
+  const int c = threadIdx.x;
+  if (c >= n) return;
+  const double* Z = Zg + (long)z * n * n;
+  const int r0 = (int)((long)w * n / S), r1 = (int)((long)(w + 1) * n / S);
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int r = r0; r < r1; r += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (r + u < r1) ? Z[(long)(r + u) * n + c] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += v[u] * v[u];
+  }
+  Xg[(long)z * wide_stride(n) + 2L * n * n + (long)w * n + c] =
+      ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+// the pre-pivoting order from the partial norms (decreasing norm, NaN last,
+// ties to the lower column), into perm (LDS), by every workgroup alike
+__device__ inline void wide_perm(const double* part, int n, int S, double* norms, int* perm) {
+  const int tid = threadIdx.x;
+  if (tid < n) {
+    double t = 0.0;
+    for (int w = 0; w < S; ++w) t += part[(long)w * n + tid];
+    norms[tid] = (t == t) ? t : -1.0;
+  }
+  __syncthreads();
+  if (tid < n) {
+    const double s = norms[tid];
+    int rank = 0;
+    for (int k = 0; k < n; ++k) rank += (norms[k] > s || (norms[k] == s && k < tid)) ? 1 : 0;
+    perm[rank] = tid;
+  }
+  __syncthreads();
+}
+
+// Panel p of the wide QR.  Z (input, read through the column order at p = 0),
+// W (R rows and trailing columns), X: Q^T, the factored panels Pf, partial
+// norms.  Work items: the trailing strips right of the panel, then every
+// strip of Q^T (rows from the panel's top), Q^T accumulated forwards as
+// H_p^T ... H_0^T.
+template <int MX>
+__global__ __launch_bounds__(256) void qr_wide_step_kernel(const double* __restrict__ Zg, double* __restrict__ Wg,
+                                                           double* __restrict__ Xg, int n, int batch, int S, int p) {
+  constexpr int RPL = Cap<MX>::rpl;
+  __shared__ double Vs[NB][VLD];
+  __shared__ double Ts[NB][NB + 1];
+  __shared__ double Gm[NB][NB + 1];
+  __shared__ double Sc[4][NB][NB + 1];
+  __shared__ double tau_s[NB];
+  __shared__ double norms[MAXN];
+  __shared__ int perm[MAXN];
+  const int z = blockIdx.x % batch, w = blockIdx.x / batch;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const long nn = (long)n * n;
+  const double* Z = Zg + z * nn;
+  double* W = Wg + z * nn;
+  double* QT = Xg + (long)z * wide_stride(n);
+  double* Pf = QT + nn;
+  const int p0 = p * NB, nbw = min(NB, n - p0), m = n - p0;
+  const bool first = (p == 0);
+  if (first) wide_perm(QT + 2 * nn, n, S, norms, perm);
+
+  double a[NB][RPL];
+  if (first) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = lane + 64 * t;
+        a[c][t] = (c < nbw && r < m) ? Z[(long)r * n + perm[c]] : 0.0;
+      }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = lane + 64 * t;
+        a[c][t] = (c < nbw && r < m) ? W[(long)(p0 + r) * n + p0 + c] : 0.0;
+      }
+  }
+  qr_panel_wave<RPL>(nbw, m, a, tau_s);
+  // V to LDS (unit diagonal, zero above and below the panel's rows), wave w
+  // writing columns w, w + 4, ...; the factored panel to Pf from workgroup 0
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    if ((c & 3) == wave) {
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = lane + 64 * t;
+        if (r < VLD) Vs[c][r] = (c < nbw && r < m) ? ((r == c) ? 1.0 : ((r > c) ? a[c][t] : 0.0)) : 0.0;
+        if (w == 0 && c < nbw && r < m) Pf[(long)(p0 + r) * n + p0 + c] = a[c][t];
+      }
+    }
+  if (64 * RPL < VLD) Vs[tid >> 4][64 * RPL + (tid & 15)] = 0.0;
+  __syncthreads();
+  form_t(Vs, m, nbw, tau_s, Gm, Ts, Sc);
+
+  const int nst = (n + 15) / 16, ntr = nst - p - 1;
+  const int nitems = ntr + nst, units = 4 * S;
+  for (int it = w * 4 + wave; it < nitems; it += units) {
+    const bool trailing = it < ntr;
+    const int c0 = trailing ? 16 * (p + 1 + it) : 16 * (it - ntr);
+    double* dst = trailing ? W : QT;
+    // at p = 0 the trailing strips come from the input in pre-pivoted column
+    // order and Q^T starts as the identity
+    const bool ident = first && !trailing;
+    const double* base = (first && trailing) ? Z : dst;
+    const int li = lane & 15;
+    const int colsrc = (first && trailing) ? perm[min(c0 + li, n - 1)] : c0 + li;
+    strip_reflect<MX>(
+        m, Vs, Ts, Sc[wave],
+        [&](int rr, int c) -> double {
+          const int r = p0 + rr, col = c0 + c;
+          if (r >= n || col >= n) return 0.0;
+          return ident ? ((r == col) ? 1.0 : 0.0) : base[(long)r * n + colsrc];
+        },
+        [&](int rr, int c, double v) {
+          const int r = p0 + rr, col = c0 + c;
+          if (r < n && col < n) dst[(long)r * n + col] = v;
+        });
+  }
+}
+
+// D = |diag R|, Rt = D^-1 R P^T over Z and Q = (Q^T)^T, rows w n / S ...
+// (w + 1) n / S of each; R is Pf on the panels' diagonal blocks and W right of them
+__global__ __launch_bounds__(256) void qr_wide_final_kernel(double* __restrict__ Zg, const double* __restrict__ Wg,
+                                                            double* __restrict__ Qg, double* __restrict__ Dg,
+                                                            const double* __restrict__ Xg, int n, int batch, int S) {
+  __shared__ double norms[MAXN];
+  __shared__ int perm[MAXN];
+  const int z = blockIdx.x % batch, w = blockIdx.x / batch;
+  const long nn = (long)n * n;
+  double* Z = Zg + z * nn;
+  const double* W = Wg + z * nn;
+  double* Q = Qg + z * nn;
+  const double* QT = Xg + (long)z * wide_stride(n);
+  const double* Pf = QT + nn;
+  wide_perm(QT + 2 * nn, n, S, norms, perm);
+  const int r0 = (int)((long)w * n / S), r1 = (int)((long)(w + 1) * n / S);
+  for (int e = threadIdx.x; e < (r1 - r0) * n; e += 256) {
+    const int r = r0 + e / n, c = e - (e / n) * n;
+    const int pe = min(n, (r / NB + 1) * NB);          // end of the panel holding row r's diagonal
+    const double d = fabs(Pf[(long)r * n + r]);
+    const double rv = (c < r) ? 0.0 : ((c < pe) ? Pf[(long)r * n + c] : W[(long)r * n + c]);
+    Z[(long)r * n + perm[c]] = (c >= r) ? rv / d : 0.0;
+    Q[(long)r * n + c] = QT[(long)c * n + r];
+    if (c == 0) Dg[(long)z * n + r] = d;
+  }
+}
+
+// Panel p of the wide Gauss-Jordan inversion.  The matrix alternates between
+// two work copies (W at even p, the scratch copy at odd p; step 0 reads M);
+// the pivot rows and values of earlier panels are read from the scratch.
+// Work items: every strip outside the panel.
+template <int MX>
+__global__ __launch_bounds__(256) void gj_wide_step_kernel(const double* __restrict__ Mg, double* __restrict__ Wg,
+                                                           double* __restrict__ Xg, int n, int batch, int S, int p) {
+  constexpr int RPL = Cap<MX>::rpl;
+  __shared__ double Fs[NB][VLD];           // the eliminated panel, column-major, zero tail
+  __shared__ double Sc[4][NB][NB + 1];
+  __shared__ int usedf[MAXN];              // rows pivoted in earlier panels
+  __shared__ int here[MAXN];               // rows pivoted in this panel
+  __shared__ int prs[NB];                  // this panel's pivot rows and values
+  __shared__ double pvs[NB];
+  const int z = blockIdx.x % batch, w = blockIdx.x / batch;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const long nn = (long)n * n;
+  double* X = Xg + (long)z * wide_stride(n);
+  double* X2 = X;                          // second work copy
+  int* perm_g = (int*)(X + nn);            // pivot row of column j
+  double* pivot_g = X + nn + n;            // pivot value of column j (n doubles after n ints)
+  const double* src = (p == 0) ? Mg + z * nn : ((p & 1) ? Wg + z * nn : X2);
+  double* dst = (p & 1) ? X2 : Wg + z * nn;
+  const int p0 = p * NB, nbw = min(NB, n - p0);
+  if (tid < MAXN) {
+    usedf[tid] = 0;
+    here[tid] = 0;
+  }
+  __syncthreads();
+  for (int k = tid; k < p0; k += 256) usedf[perm_g[k]] = 1;
+  __syncthreads();
+  bool used[RPL];
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r = lane + 64 * t;
+    used[t] = (r < n) ? usedf[r] != 0 : true;
+  }
+  double a[NB][RPL];
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int r = lane + 64 * t;
+      a[c][t] = (c < nbw && r < n) ? src[(long)r * n + p0 + c] : 0.0;
+    }
+  gj_panel_wave<RPL>(nbw, n, a, used, prs, pvs);
+  __syncthreads();
+  if (tid < nbw) {
+    here[prs[tid]] = 1;
+    if (w == 0) {
+      perm_g[p0 + tid] = prs[tid];
+      pivot_g[p0 + tid] = pvs[tid];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    if ((c & 3) == wave) {
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int r = lane + 64 * t;
+        if (r < VLD) Fs[c][r] = (c < nbw && r < n) ? a[c][t] : 0.0;
+        if (w == 0 && c < nbw && r < n) dst[(long)r * n + p0 + c] = a[c][t];
+      }
+    }
+  if (64 * RPL < VLD) Fs[tid >> 4][64 * RPL + (tid & 15)] = 0.0;
+  __syncthreads();
+
+  constexpr int NTL = Cap<MX>::tiles;
+  const int nst = (n + 15) / 16, ntile = nst;
+  for (int it = w * 4 + wave; it < nst - 1; it += 4 * S) {
+    const int s = (it < p) ? it : it + 1;
+    const int col = 16 * s + li;
+    // the strip's old pivot rows of this panel (k, column) and its tiles with
+    // those rows as 0
+    double pv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = lane + 64 * i, k = e >> 4, cg = 16 * s + (e & 15);
+      pv[i] = (k < nbw && cg < n) ? src[(long)prs[k] * n + cg] : 0.0;
+    }
+    d4 tile[NTL];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + frag_row<double>(lane, v);
+        tile[t][v] = (t < ntile && row < n && col < n && !here[row]) ? src[(long)row * n + col] : 0.0;
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = lane + 64 * i;
+      Sc[wave][e >> 4][e & 15] = pv[i];
+    }
+    wave_sync_lds();
+    double tb[NB / 4];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) tb[q] = Sc[wave][4 * q + lk][li];
+    wave_sync_lds();
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+      if (t < ntile) {
+#pragma unroll
+        for (int q = 0; q < NB / 4; ++q) tile[t] = mfma16(Fs[4 * q + lk][16 * t + li], tb[q], tile[t]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * t + frag_row<double>(lane, v);
+          if (row < n && col < n) dst[(long)row * n + col] = tile[t][v];
+        }
+      }
+  }
+}
+
+// M^-1[j][perm[k]] = A[perm[j]][k] scaled, over M (rows w n / S ... of A);
+// workgroup 0 also forms logdet = base + sum log|pivot|
+__global__ __launch_bounds__(256) void gj_wide_final_kernel(double* __restrict__ Mg, const double* __restrict__ Wg,
+                                                            const double* __restrict__ Xg,
+                                                            const double* __restrict__ rsg,
+                                                            const double* __restrict__ csg,
+                                                            const double* __restrict__ base,
+                                                            double* __restrict__ logdet, int n, int batch, int S,
+                                                            int npan) {
+  __shared__ int perm[MAXN];
+  __shared__ int pinv[MAXN];
+  __shared__ double part[4];
+  const int z = blockIdx.x % batch, w = blockIdx.x / batch;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long nn = (long)n * n;
+  const double* X = Xg + (long)z * wide_stride(n);
+  const int* perm_g = (const int*)(X + nn);
+  const double* pivot_g = X + nn + n;
+  const double* A = ((npan - 1) & 1) ? X : Wg + z * nn;   // the last step's output
+  double* M = Mg + z * nn;
+  const double* rs = rsg + (long)z * n;
+  const double* cs = csg + (long)z * n;
+  for (int j = tid; j < n; j += 256) {
+    const int r = perm_g[j];
+    perm[j] = r;
+    pinv[r] = j;
+  }
+  __syncthreads();
+  const int r0 = (int)((long)w * n / S), r1 = (int)((long)(w + 1) * n / S);
+  for (int e = tid; e < (r1 - r0) * n; e += 256) {
+    const int r = r0 + e / n, k = e - (e / n) * n;
+    const int j = pinv[r], pk = perm[k];
+    M[(long)j * n + pk] = rs[j] * A[(long)r * n + k] * cs[pk];
+  }
+  if (w == 0) {
+    double lg = 0.0;
+    for (int i = tid; i < n; i += 256) lg += log(fabs(pivot_g[i]));
+    lg = wave_total(lg);
+    if (lane == 0) part[wave] = lg;
+    __syncthreads();
+    if (tid == 0) logdet[z] = base[z] + ((part[0] + part[1]) + (part[2] + part[3]));
+  }
+}
+
 bool qr_supported(int n) { return n >= 1 && n <= MAXN; }
 bool gj_supported(int n) { return n >= 1 && n <= MAXN; }
 size_t qr_t_doubles(int n) { return (size_t)NB * (n + NB); }
 
-hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int n, int batch, hipStream_t s) {
+hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int n, int batch, hipStream_t s,
+                     double* X) {
   if (!qr_supported(n)) return hipErrorInvalidValue;
+  const int S = X ? wide_split(n, batch) : 1;
+  if (S > 1) {
+    const dim3 grid(batch * S);
+    hipLaunchKernelGGL(qr_wide_norms_kernel, grid, dim3(256), 0, s, Z, X, n, batch, S);
+    for (int p = 0; p < (n + NB - 1) / NB; ++p)
+      hipLaunchKernelGGL(qr_wide_step_kernel<256>, grid, dim3(256), 0, s, Z, W, X, n, batch, S, p);
+    hipLaunchKernelGGL(qr_wide_final_kernel, grid, dim3(256), 0, s, Z, W, Q, D, X, n, batch, S);
+    return hipGetLastError();
+  }
   if (n <= 64)
     hipLaunchKernelGGL(qr_regs_kernel<64>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
   else if (n <= 112)
@@ -1158,8 +1740,17 @@ hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int 
 }
 
 hipError_t launch_gj(double* M, double* W, const double* rs, const double* cs, const double* base, double* logdet,
-                     int n, int batch, hipStream_t s) {
+                     int n, int batch, hipStream_t s, double* X) {
   if (!gj_supported(n)) return hipErrorInvalidValue;
+  const int S = X ? wide_split(n, batch) : 1;
+  if (S > 1) {
+    const dim3 grid(batch * S);
+    const int npan = (n + NB - 1) / NB;
+    for (int p = 0; p < npan; ++p)
+      hipLaunchKernelGGL(gj_wide_step_kernel<256>, grid, dim3(256), 0, s, M, W, X, n, batch, S, p);
+    hipLaunchKernelGGL(gj_wide_final_kernel, grid, dim3(256), 0, s, M, W, X, rs, cs, base, logdet, n, batch, S, npan);
+    return hipGetLastError();
+  }
   if (n <= 64)
     hipLaunchKernelGGL(gj_regs_kernel<64>, dim3(batch), dim3(256), 0, s, M, W, rs, cs, base, logdet, n);
   else if (n <= 112)

@@ -75,6 +75,7 @@ struct Group {
   double *tX = nullptr, *tUp = nullptr, *tDp = nullptr, *tQW = nullptr, *tQT = nullptr;
   bool alternate = false;        // sweeps alternate upward / downward (local moves only)
   double *Z = nullptr, *Rt = nullptr, *M = nullptr, *Minv = nullptr, *Xm = nullptr, *Tq = nullptr;
+  double* Xw = nullptr;                        // wide-factorization scratch (large N, few chains)
   double *dLbinv = nullptr, *dLs = nullptr, *dRbinv = nullptr, *dRs = nullptr, *sumlog = nullptr;
   double *logdet = nullptr, *logdet_new = nullptr, *shift = nullptr;
   int64_t* counters = nullptr;
@@ -268,6 +269,7 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
     g.Minv = cv.take<double>(C * nn);
     g.Xm = cv.take<double>(C * nn);
     g.Tq = cv.take<double>(C * (long)qr_t_doubles(g.n));
+    if (wide_split(g.n, C) > 1) g.Xw = cv.take<double>(C * (long)wide_scratch_doubles(g.n));
     g.dLbinv = cv.take<double>(C * n);
     g.dLs = cv.take<double>(C * n);
     g.dRbinv = cv.take<double>(C * n);
@@ -533,7 +535,7 @@ hq_status combine_tail(Sched& S, Group& g, const double* Tin, long sT, double* U
   // Q and D go straight into the UDT arrays, which are contiguous per chain;
   // Rt comes back over Z
   if (sUo != nn || sDo != g.n) return fail(S.ctx, HQ_EINVAL, "internal: strided QR output");
-  SCHED_TRY(launch_qr(g.Z, g.Rt, Uout, Dout, g.Tq, g.n, g.C, S.s));
+  SCHED_TRY(launch_qr(g.Z, g.Rt, Uout, Dout, g.Tq, g.n, g.C, S.s, g.Xw));
   GemmArgs<double> b = sq(g, g.C);
   b.A = g.Z; b.sA = nn;
   b.B = Tin; b.sB = sT;
@@ -553,7 +555,7 @@ hq_status merge(Sched& S, Group& g, const double* UL, long sUL, const double* DL
     // right part the identity (a from-scratch recompute): M = Db_L^-1 U_L^T + Ds_L T_L
     // elementwise, and G = Minv U_L^T straight into Gnew
     SCHED_TRY(launch_merge_identity(UL, sUL, TL, sTL, g.dLbinv, g.dLs, g.M, n, g.C, S.s));
-    SCHED_TRY(launch_gj(g.M, g.Minv, g.ones, g.dLbinv, g.sumlog, g.logdet_new, n, g.C, S.s));
+    SCHED_TRY(launch_gj(g.M, g.Minv, g.ones, g.dLbinv, g.sumlog, g.logdet_new, n, g.C, S.s, g.Xw));
     GemmArgs<double> c = sq(g, g.C);
     c.A = g.M; c.sA = nn;
     c.B = UL; c.sB = sUL; c.tB = 1;
@@ -581,7 +583,7 @@ hq_status merge(Sched& S, Group& g, const double* UL, long sUL, const double* DL
   b.cs.v = rs_; b.cs.so = n;
   SCHED_TRY(launch_gemm(b, g.tile, S.s));
   // Minv = Db_R^-1 M^-1 Db_L^-1, logdet_new = sumlog + log|det M|
-  SCHED_TRY(launch_gj(g.M, g.Minv, rb, g.dLbinv, g.sumlog, g.logdet_new, n, g.C, S.s));
+  SCHED_TRY(launch_gj(g.M, g.Minv, rb, g.dLbinv, g.sumlog, g.logdet_new, n, g.C, S.s, g.Xw));
   GemmArgs<double> c = sq(g, g.C);                 // X = Minv U_L^T (Minv over M)
   c.A = g.M; c.sA = nn;
   c.B = UL; c.sB = sUL; c.tB = 1;
@@ -1107,8 +1109,9 @@ hq_status enqueue_group(hq_ctx* ctx, Group& g, hipStream_t s, int dir, bool rebu
     if (g.G != g.G0) std::swap(g.G, g.Wt);   // the enqueue failed part-way: keep the buffers' roles
     return st;
   }
-  for (int k : KINDS)
-    SCHED_TRY(launch_fill_u8(g.replay[k], 255, (long)g.C * g.kind_slots(k), S.s));
+  if (ctx->opt.record)                      // replay logs hold for one sweep only
+    for (int k : KINDS)
+      SCHED_TRY(launch_fill_u8(g.replay[k], 255, (long)g.C * g.kind_slots(k), S.s));
   return HQ_OK;
 }
 

@@ -173,14 +173,21 @@ hipError_t prepare_local();
 // Householder QR of Z[z] (n x n, n <= 256) with columns pre-sorted by
 // decreasing norm, Z P = Q R.  Outputs Q (explicit), D = |diag R| and, over Z,
 // Rt = D^-1 R P^T.  W: n x n work per matrix; T: qr_t_doubles(n) per matrix.
-hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int n, int batch, hipStream_t s);
+// X (optional): wide_scratch_doubles(n) per matrix; given, and with
+// wide_split(n, batch) > 1, the factorization of each matrix is spread over
+// that many workgroups (one launch per panel).
+hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int n, int batch, hipStream_t s,
+                     double* X = nullptr);
 bool qr_supported(int n);
 size_t qr_t_doubles(int n);
+size_t wide_scratch_doubles(int n);
+int wide_split(int n, int batch);
 
 // Gauss-Jordan inversion with partial pivoting: over M, diag(rs) M^-1 diag(cs)
 // (rs, cs: [batch][n]); logdet[z] = base[z] + log|det M|.  W: n x n work.
+// X (optional): as for launch_qr.
 hipError_t launch_gj(double* M, double* W, const double* rs, const double* cs, const double* base,
-                     double* logdet, int n, int batch, hipStream_t s);
+                     double* logdet, int n, int batch, hipStream_t s, double* X = nullptr);
 bool gj_supported(int n);
 
 // ---------------------------------------------------------------------------
