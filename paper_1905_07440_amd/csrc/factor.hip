@@ -1154,6 +1154,16 @@ __global__ __launch_bounds__(256) void gj_regs_kernel(double* __restrict__ Mg, d
 // the batch is a multiple of 8.
 // ===========================================================================
 
+// a buffer resource over bytes from p, with p made wave-uniform first: a
+// resource that the compiler keeps in vector registers (a select between two
+// of them, say) puts every load through it in a waterfall loop
+__device__ inline __amdgpu_buffer_rsrc_t uniform_rsrc(const void* p, unsigned bytes) {
+  const unsigned long long a = (unsigned long long)p;
+  const unsigned long long u = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(a >> 32)) << 32) |
+                               (unsigned)__builtin_amdgcn_readfirstlane((unsigned)a);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)u, 0, (int)bytes, BUF_WORD3);
+}
+
 // totals over the 64 lanes of NV values (NV = 16, 8, 4, 2, 1), returned
 // wave-uniform.  The halving butterfly leaves value k in lane (64 / NV) k.
 template <int NV>
@@ -1338,23 +1348,32 @@ __device__ inline void gj_panel_wave(int nbw, int n, double (&a)[NB][RPL], bool 
   }
 }
 
+// One strip of 16 columns as 16-row MFMA tiles (rows from the panel's top,
+// m of them): lane l, element v of tile t holds row 16 t + frag_row(l, v),
+// column l % 16.  ld(rr, c) gives row rr and strip column c; it returns 0
+// outside the matrix by a buffer load whose offset, not whose value, is
+// masked, so that nothing sinks the loads into branches: they issue back to
+// back, and a caller can issue them before work that does not need them.
+template <int MX, typename Load>
+__device__ inline void strip_load(int m, d4 (&tile)[Cap<MX>::tiles], Load ld) {
+  const int lane = threadIdx.x & 63, li = lane & 15;
+  const int ntile = (m + 15) / 16;
+#pragma unroll
+  for (int t = 0; t < Cap<MX>::tiles; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tile[t][v] = (t < ntile) ? ld(16 * t + frag_row<double>(lane, v), li) : 0.0;
+}
+
 // One wave applies I - V op(T) V^T (op(T) = T^T: the transposed block
-// reflector, Q^T from the left) to one strip of 16 columns on the rows from
-// the panel's top (m of them): w1 = V^T X, w2 = op(T) w1, X -= V w2.
-// load(rr, c) / store(rr, c, v) address row rr relative to the panel's top
-// and column c of the strip (0..15); load returns 0 outside the matrix and
-// store drops those elements.
-template <int MX, typename Load, typename Store>
-__device__ inline void strip_reflect(int m, const double (*Vs)[VLD], const double (*Ts)[NB + 1], double (*S)[NB + 1],
-                                     Load load, Store store) {
+// reflector, Q^T from the left) to a strip loaded by strip_load: w1 = V^T X,
+// w2 = op(T) w1, X -= V w2; store(rr, c, v) receives the result (and drops
+// elements outside the matrix).
+template <int MX, typename Store>
+__device__ inline void strip_apply(int m, d4 (&tile)[Cap<MX>::tiles], const double (*Vs)[VLD],
+                                   const double (*Ts)[NB + 1], double (*S)[NB + 1], Store store) {
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   constexpr int NTL = Cap<MX>::tiles;
   const int ntile = (m + 15) / 16;
-  d4 tile[NTL];
-#pragma unroll
-  for (int t = 0; t < NTL; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) tile[t][v] = (t < ntile) ? load(16 * t + frag_row<double>(lane, v), li) : 0.0;
   d4 w1 = {0, 0, 0, 0};
 #pragma unroll
   for (int t = 0; t < NTL; ++t)
@@ -1438,6 +1457,28 @@ __device__ inline void wide_perm(const double* part, int n, int S, double* norms
   __syncthreads();
 }
 
+// The tiles of work item it of panel p of the wide QR: the trailing strips
+// right of the panel (it < ntr), then every strip of Q^T, rows from the
+// panel's top; at p = 0 the trailing strips come from the input in
+// pre-pivoted column order (perm) and Q^T starts as the identity.
+template <int MX>
+__device__ __attribute__((always_inline)) inline void qr_item_load(d4 (&tile)[Cap<MX>::tiles], int it, int ntr, int p,
+                                                                   int m, int n, const double* Z, const double* W,
+                                                                   const double* QT, const int* perm, unsigned bytes) {
+  const int li = threadIdx.x & 15;
+  const bool first = (p == 0), trailing = it < ntr;
+  const int p0 = p * NB, c0 = trailing ? 16 * (p + 1 + it) : 16 * (it - ntr);
+  const bool ident = first && !trailing;
+  const __amdgpu_buffer_rsrc_t rs = uniform_rsrc((first && trailing) ? Z : (trailing ? W : QT), bytes);
+  const int colsrc = (first && trailing) ? perm[min(c0 + li, n - 1)] : c0 + li;
+  const bool live = (c0 + li < n) && !ident;
+  strip_load<MX>(m, tile, [&](int rr, int c) -> double {
+    const int r = p0 + rr, col = c0 + c;
+    const unsigned off = (live && r < n) ? (unsigned)((r * n + colsrc) * 8) : BUF_OUTSIDE;
+    return buf_load_f64(rs, off) + ((ident && r == col && r < n) ? 1.0 : 0.0);
+  });
+}
+
 // Panel p of the wide QR.  Z (input, read through the column order at p = 0),
 // W (R rows and trailing columns), X: Q^T, the factored panels Pf, partial
 // norms.  Work items: the trailing strips right of the panel, then every
@@ -1466,24 +1507,31 @@ __global__ __launch_bounds__(256) void qr_wide_step_kernel(const double* __restr
   const bool first = (p == 0);
   if (first) wide_perm(QT + 2 * nn, n, S, norms, perm);
 
+  // the panel through buffer loads (masked elements read 0 from outside the
+  // resource), then this wave's first work item, whose loads do not depend on
+  // the panel and so run under its factorization
+  const unsigned bytes = (unsigned)(nn * 8);
   double a[NB][RPL];
-  if (first) {
+  {
+    const __amdgpu_buffer_rsrc_t rp = uniform_rsrc(first ? (const double*)Z : W, bytes);
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-#pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const int r = lane + 64 * t;
-        a[c][t] = (c < nbw && r < m) ? Z[(long)r * n + perm[c]] : 0.0;
-      }
-  } else {
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
+    for (int c = 0; c < NB; ++c) {
+      const int col = first ? perm[min(c, n - 1)] : p0 + c;
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const int r = lane + 64 * t;
-        a[c][t] = (c < nbw && r < m) ? W[(long)(p0 + r) * n + p0 + c] : 0.0;
+        const unsigned off = (c < nbw && r < m) ? (unsigned)(((p0 + r) * n + col) * 8) : BUF_OUTSIDE;
+        a[c][t] = buf_load_f64(rp, off);
       }
+    }
   }
+  // work items (qr_item_load)
+  const int nst = (n + 15) / 16, ntr = nst - p - 1;
+  const int nitems = ntr + nst, units = 4 * S;
+  const int it0 = w * 4 + wave;
+  d4 tile[Cap<MX>::tiles];
+  if (it0 < nitems) qr_item_load<MX>(tile, it0, ntr, p, m, n, Z, W, QT, perm, bytes);
+
   qr_panel_wave<RPL>(nbw, m, a, tau_s);
   // V to LDS (unit diagonal, zero above and below the panel's rows), wave w
   // writing columns w, w + 4, ...; the factored panel to Pf from workgroup 0
@@ -1501,40 +1549,29 @@ __global__ __launch_bounds__(256) void qr_wide_step_kernel(const double* __restr
   __syncthreads();
   form_t(Vs, m, nbw, tau_s, Gm, Ts, Sc);
 
-  const int nst = (n + 15) / 16, ntr = nst - p - 1;
-  const int nitems = ntr + nst, units = 4 * S;
-  for (int it = w * 4 + wave; it < nitems; it += units) {
+  for (int it = it0; it < nitems; it += units) {
+    if (it != it0) qr_item_load<MX>(tile, it, ntr, p, m, n, Z, W, QT, perm, bytes);
     const bool trailing = it < ntr;
     const int c0 = trailing ? 16 * (p + 1 + it) : 16 * (it - ntr);
     double* dst = trailing ? W : QT;
-    // at p = 0 the trailing strips come from the input in pre-pivoted column
-    // order and Q^T starts as the identity
-    const bool ident = first && !trailing;
-    const double* base = (first && trailing) ? Z : dst;
-    const int li = lane & 15;
-    const int colsrc = (first && trailing) ? perm[min(c0 + li, n - 1)] : c0 + li;
-    strip_reflect<MX>(
-        m, Vs, Ts, Sc[wave],
-        [&](int rr, int c) -> double {
-          const int r = p0 + rr, col = c0 + c;
-          if (r >= n || col >= n) return 0.0;
-          return ident ? ((r == col) ? 1.0 : 0.0) : base[(long)r * n + colsrc];
-        },
-        [&](int rr, int c, double v) {
-          const int r = p0 + rr, col = c0 + c;
-          if (r < n && col < n) dst[(long)r * n + col] = v;
-        });
+    strip_apply<MX>(m, tile, Vs, Ts, Sc[wave], [&](int rr, int c, double v) {
+      const int r = p0 + rr, col = c0 + c;
+      if (r < n && col < n) dst[(long)r * n + col] = v;
+    });
   }
 }
 
 // D = |diag R|, Rt = D^-1 R P^T over Z and Q = (Q^T)^T, rows w n / S ...
-// (w + 1) n / S of each; R is Pf on the panels' diagonal blocks and W right of them
+// (w + 1) n / S of each; R is Pf on the panels' diagonal blocks and W right
+// of them.  Thread c takes column c of those rows, eight rows' loads in
+// flight at a time (clamped addresses, so none waits behind a branch).
 __global__ __launch_bounds__(256) void qr_wide_final_kernel(double* __restrict__ Zg, const double* __restrict__ Wg,
                                                             double* __restrict__ Qg, double* __restrict__ Dg,
                                                             const double* __restrict__ Xg, int n, int batch, int S) {
   __shared__ double norms[MAXN];
   __shared__ int perm[MAXN];
   const int z = blockIdx.x % batch, w = blockIdx.x / batch;
+  const int c = threadIdx.x, cc = min(c, n - 1);
   const long nn = (long)n * n;
   double* Z = Zg + z * nn;
   const double* W = Wg + z * nn;
@@ -1543,29 +1580,49 @@ __global__ __launch_bounds__(256) void qr_wide_final_kernel(double* __restrict__
   const double* Pf = QT + nn;
   wide_perm(QT + 2 * nn, n, S, norms, perm);
   const int r0 = (int)((long)w * n / S), r1 = (int)((long)(w + 1) * n / S);
-  for (int e = threadIdx.x; e < (r1 - r0) * n; e += 256) {
-    const int r = r0 + e / n, c = e - (e / n) * n;
-    const int pe = min(n, (r / NB + 1) * NB);          // end of the panel holding row r's diagonal
-    const double d = fabs(Pf[(long)r * n + r]);
-    const double rv = (c < r) ? 0.0 : ((c < pe) ? Pf[(long)r * n + c] : W[(long)r * n + c]);
-    Z[(long)r * n + perm[c]] = (c >= r) ? rv / d : 0.0;
-    Q[(long)r * n + c] = QT[(long)c * n + r];
-    if (c == 0) Dg[(long)z * n + r] = d;
+  const int pc = perm[cc];
+  constexpr int U = 8;
+  for (int b = r0; b < r1; b += U) {
+    double pf[U], wv[U], dg[U], qt[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = min(b + u, r1 - 1);
+      pf[u] = Pf[(long)r * n + cc];
+      wv[u] = W[(long)r * n + cc];
+      dg[u] = Pf[(long)r * n + r];
+      qt[u] = QT[(long)cc * n + r];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = b + u;
+      if (r < r1 && c < n) {
+        const int pe = min(n, (r / NB + 1) * NB);        // end of the panel holding row r's diagonal
+        const double d = fabs(dg[u]);
+        Z[(long)r * n + pc] = (c < r) ? 0.0 : ((c < pe) ? pf[u] : wv[u]) / d;
+        Q[(long)r * n + c] = qt[u];
+        if (c == 0) Dg[(long)z * n + r] = d;
+      }
+    }
   }
 }
 
 // Panel p of the wide Gauss-Jordan inversion.  The matrix alternates between
 // two work copies (W at even p, the scratch copy at odd p; step 0 reads M);
 // the pivot rows and values of earlier panels are read from the scratch.
-// Work items: every strip outside the panel.
+// Work items: every strip outside the panel, updated as
+//   A[r][C] = [r not a pivot row of the panel] A[r][C] + F[r][:] A_old[P][C]
+// (F: the eliminated panel, P: its pivot rows).  A wave's first strip is
+// loaded before the elimination; its old pivot rows are taken from those
+// registers afterwards.
 template <int MX>
 __global__ __launch_bounds__(256) void gj_wide_step_kernel(const double* __restrict__ Mg, double* __restrict__ Wg,
                                                            double* __restrict__ Xg, int n, int batch, int S, int p) {
   constexpr int RPL = Cap<MX>::rpl;
+  constexpr int NTL = Cap<MX>::tiles;
   __shared__ double Fs[NB][VLD];           // the eliminated panel, column-major, zero tail
   __shared__ double Sc[4][NB][NB + 1];
   __shared__ int usedf[MAXN];              // rows pivoted in earlier panels
-  __shared__ int here[MAXN];               // rows pivoted in this panel
+  __shared__ int kmap[MAXN];               // row -> its pivot index in this panel, or -1
   __shared__ int prs[NB];                  // this panel's pivot rows and values
   __shared__ double pvs[NB];
   const int z = blockIdx.x % batch, w = blockIdx.x / batch;
@@ -1580,12 +1637,41 @@ __global__ __launch_bounds__(256) void gj_wide_step_kernel(const double* __restr
   const double* src = (p == 0) ? Mg + z * nn : ((p & 1) ? Wg + z * nn : X2);
   double* dst = (p & 1) ? X2 : Wg + z * nn;
   const int p0 = p * NB, nbw = min(NB, n - p0);
+  const int nst = (n + 15) / 16;
+  // the earlier pivots first (their loads retire first), then the panel, then
+  // this wave's first strip; loads through a buffer resource, masked elements
+  // reading 0 from outside it
+  const int prev = (tid < p0) ? perm_g[tid] : -1;
+  const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(src, (unsigned)(nn * 8));
+  double a[NB][RPL];
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int r = lane + 64 * t;
+      a[c][t] = buf_load_f64(rs, (c < nbw && r < n) ? (unsigned)((r * n + p0 + c) * 8) : BUF_OUTSIDE);
+    }
+  auto load_strip = [&](int it, d4 (&tile)[NTL]) __attribute__((always_inline)) {
+    const int s = (it < p) ? it : it + 1;
+    const int col = 16 * s + li;
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + frag_row<double>(lane, v);
+        tile[t][v] = buf_load_f64(rs, (row < n && col < n) ? (unsigned)((row * n + col) * 8) : BUF_OUTSIDE);
+      }
+  };
+  const int it0 = w * 4 + wave;
+  d4 tile[NTL];
+  if (it0 < nst - 1) load_strip(it0, tile);
+
   if (tid < MAXN) {
     usedf[tid] = 0;
-    here[tid] = 0;
+    kmap[tid] = -1;
   }
   __syncthreads();
-  for (int k = tid; k < p0; k += 256) usedf[perm_g[k]] = 1;
+  if (prev >= 0) usedf[prev] = 1;
   __syncthreads();
   bool used[RPL];
 #pragma unroll
@@ -1593,18 +1679,10 @@ __global__ __launch_bounds__(256) void gj_wide_step_kernel(const double* __restr
     const int r = lane + 64 * t;
     used[t] = (r < n) ? usedf[r] != 0 : true;
   }
-  double a[NB][RPL];
-#pragma unroll
-  for (int c = 0; c < NB; ++c)
-#pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int r = lane + 64 * t;
-      a[c][t] = (c < nbw && r < n) ? src[(long)r * n + p0 + c] : 0.0;
-    }
   gj_panel_wave<RPL>(nbw, n, a, used, prs, pvs);
   __syncthreads();
   if (tid < nbw) {
-    here[prs[tid]] = 1;
+    kmap[prs[tid]] = tid;
     if (w == 0) {
       perm_g[p0 + tid] = prs[tid];
       pivot_g[p0 + tid] = pvs[tid];
@@ -1623,32 +1701,29 @@ __global__ __launch_bounds__(256) void gj_wide_step_kernel(const double* __restr
   if (64 * RPL < VLD) Fs[tid >> 4][64 * RPL + (tid & 15)] = 0.0;
   __syncthreads();
 
-  constexpr int NTL = Cap<MX>::tiles;
-  const int nst = (n + 15) / 16, ntile = nst;
-  for (int it = w * 4 + wave; it < nst - 1; it += 4 * S) {
+  for (int it = it0; it < nst - 1; it += 4 * S) {
+    if (it != it0) load_strip(it, tile);
     const int s = (it < p) ? it : it + 1;
     const int col = 16 * s + li;
-    // the strip's old pivot rows of this panel (k, column) and its tiles with
-    // those rows as 0
-    double pv[4];
+    // the strip's old pivot rows (k, column) to LDS from the registers that
+    // hold them, and those rows as 0 in the tiles
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int e = lane + 64 * i, k = e >> 4, cg = 16 * s + (e & 15);
-      pv[i] = (k < nbw && cg < n) ? src[(long)prs[k] * n + cg] : 0.0;
+      const int e = lane + 64 * i;
+      Sc[wave][e >> 4][e & 15] = 0.0;
     }
-    d4 tile[NTL];
+    wave_sync_lds();
 #pragma unroll
     for (int t = 0; t < NTL; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * t + frag_row<double>(lane, v);
-        tile[t][v] = (t < ntile && row < n && col < n && !here[row]) ? src[(long)row * n + col] : 0.0;
+        const int k = (row < n) ? kmap[row] : -1;
+        if (k >= 0) {
+          Sc[wave][k][li] = tile[t][v];
+          tile[t][v] = 0.0;
+        }
       }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = lane + 64 * i;
-      Sc[wave][e >> 4][e & 15] = pv[i];
-    }
     wave_sync_lds();
     double tb[NB / 4];
 #pragma unroll
@@ -1656,7 +1731,7 @@ __global__ __launch_bounds__(256) void gj_wide_step_kernel(const double* __restr
     wave_sync_lds();
 #pragma unroll
     for (int t = 0; t < NTL; ++t)
-      if (t < ntile) {
+      if (16 * t < n) {
 #pragma unroll
         for (int q = 0; q < NB / 4; ++q) tile[t] = mfma16(Fs[4 * q + lk][16 * t + li], tb[q], tile[t]);
 #pragma unroll
@@ -1668,8 +1743,9 @@ __global__ __launch_bounds__(256) void gj_wide_step_kernel(const double* __restr
   }
 }
 
-// M^-1[j][perm[k]] = A[perm[j]][k] scaled, over M (rows w n / S ... of A);
-// workgroup 0 also forms logdet = base + sum log|pivot|
+// M^-1[j][perm[k]] = A[perm[j]][k] scaled, over M (rows w n / S ... of A;
+// thread k takes column k, eight rows' loads in flight at a time); workgroup
+// 0 also forms logdet = base + sum log|pivot|
 __global__ __launch_bounds__(256) void gj_wide_final_kernel(double* __restrict__ Mg, const double* __restrict__ Wg,
                                                             const double* __restrict__ Xg,
                                                             const double* __restrict__ rsg,
@@ -1697,10 +1773,23 @@ __global__ __launch_bounds__(256) void gj_wide_final_kernel(double* __restrict__
   }
   __syncthreads();
   const int r0 = (int)((long)w * n / S), r1 = (int)((long)(w + 1) * n / S);
-  for (int e = tid; e < (r1 - r0) * n; e += 256) {
-    const int r = r0 + e / n, k = e - (e / n) * n;
-    const int j = pinv[r], pk = perm[k];
-    M[(long)j * n + pk] = rs[j] * A[(long)r * n + k] * cs[pk];
+  const int k = tid, kc = min(k, n - 1);
+  const int pk = perm[kc];
+  const double ck = cs[pk];
+  constexpr int U = 8;
+  for (int b = r0; b < r1; b += U) {
+    double av[U], rj[U];
+    int jr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = min(b + u, r1 - 1);
+      jr[u] = pinv[r];
+      av[u] = A[(long)r * n + kc];
+      rj[u] = rs[jr[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (b + u < r1 && k < n) M[(long)jr[u] * n + pk] = rj[u] * av[u] * ck;
   }
   if (w == 0) {
     double lg = 0.0;
