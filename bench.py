@@ -194,7 +194,7 @@ def run_workload(w, steps, warmup, profile=True):
 # counter runs on the mixed 12x12 workload, scaled by the same counters on a
 # plain copy (profiles/local_regs_kernel_12x12_mixed_traffic.txt); valid only
 # for the kernel source those runs measured
-LOCAL_TRAFFIC = {"sha1": "13b0e41a139c54486709023f4dea8796586c3b93", "bytes": 22785803,
+LOCAL_TRAFFIC = {"sha1": "f4690479f45bf939ef209926689a727260de76e2", "bytes": 22686519,
                  "workload": "holstein-12x12-L120-mixed-nstab6-128chains"}
 
 
@@ -212,22 +212,29 @@ def measured_traffic(w):
 
 def local_roofline(w, res):
     """Roofline of the local-move kernel (one launch per slice covers every
-    chain of the group): algorithmic flops = 2 N^2 per accepted move (the
+    chain of a group): algorithmic flops = 2 N^2 per accepted move (the
     rank-1 update of G the method defines), acceptance as measured, against
-    the dense MFMA peak of the precision G is held in."""
-    g = w.groups[0]
-    n = g.nx * g.nx
+    the dense MFMA peak of the precision G is held in.  With several lattice
+    groups the profiled sweep times their launches one after another, so the
+    flops of all groups are set against the whole local phase."""
     if "local" not in res["phases"]:
         return None            # network groups: proposals come from the network kernel, no local-move launches
-    per_launch_s = res["phases"]["local"]["us_per_region"] * 1e-6
-    flops = g.n_chains * res["local_acceptance"] * n * 2.0 * n * n
+    ph = res["phases"]["local"]
+    sweep_s = ph["ms_per_sweep"] * 1e-3
+    flops = sum(g.n_chains * res["local_acceptance"] * (g.nx * g.nx) * 2.0 * (g.nx * g.nx) ** 2
+                * round(g.beta / g.dtau) for g in w.groups)
     peak = MI355X_PEAK["fp32" if w.precision else "fp64"]
-    hbm = g.n_chains * 2.0 * n * n * (4 if w.precision else 8)
-    return {"bound": "mfma", "achieved": flops / per_launch_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": flops / per_launch_s / peak, "traffic": measured_traffic(w), "kernel": "local_regs_kernel",
-            "note": ("one launch = the local moves of one slice for all %d chains; its G traffic is %.1f MB, "
-                     "%.1f us at 8 TB/s, so the kernel is bound by the sequential accept chain, not HBM"
-                     % (g.n_chains, hbm / 1e6, hbm / 8e12 * 1e6))}
+    s = 4 if w.precision else 8
+    hbm = sum(g.n_chains * 2.0 * (g.nx * g.nx) ** 2 * s for g in w.groups)
+    one = len(w.groups) == 1
+    note = ("one launch = the local moves of one slice for all %d chains; its G traffic is %.1f MB, "
+            "%.1f us at 8 TB/s, so the kernel is bound by the sequential accept chain, not HBM"
+            % (w.n_chains, hbm / 1e6, hbm / 8e12 * 1e6)) if one else (
+            "all lattice groups' local-move launches of one sweep (timed one after another) against their "
+            "flops; one slice of every group moves %.1f MB of G, %.1f us at 8 TB/s" % (hbm / 1e6, hbm / 8e12 * 1e6))
+    return {"bound": "mfma", "achieved": flops / sweep_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": flops / sweep_s / peak, "traffic": measured_traffic(w) if one else None,
+            "kernel": "local_regs_kernel", "us_per_launch": ph["us_per_region"], "note": note}
 
 
 def sweep_roofline(w, res):
@@ -465,6 +472,19 @@ def main():
         d32 = run_workload(w32, a.steps, a.warmup, profile=False)
         extra["mixed_delay32"] = {k: d32[k] for k in ("value", "ms_per_step", "max_drift_green")}
         extra["mixed_delay32"]["config"] = "the headline workload with delayed updates in blocks of 32 sites"
+    if len(w.groups) > 1:
+        # each lattice group alone (same chains, seed and options) against the
+        # batch: the groups run as parallel branches of one captured graph, so
+        # the batch should take about as long as its slowest group
+        import copy
+        alone = []
+        for g in w.groups:
+            wg = copy.deepcopy(w)
+            wg.groups = [copy.deepcopy(g)]
+            alone.append(run_workload(wg, a.steps, a.warmup, profile=False)["ms_per_step"])
+        extra["groups_alone"] = {"nx": [g.nx for g in w.groups], "ms_per_step": alone, "sum_ms": sum(alone),
+                                 "batch_ms": res["ms_per_step"],
+                                 "hidden_ms": sum(alone) - res["ms_per_step"]}
 
     cpu = None
     if not a.no_cpu_baseline:

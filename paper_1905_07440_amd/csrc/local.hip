@@ -306,6 +306,23 @@ __device__ inline double recip(double r) {
 }
 __device__ inline float recip(float r) { return __builtin_amdgcn_rcpf(r); }
 
+// The thresholds of a site's Metropolis test on G_kk (walk_diag explains them)
+template <typename T>
+__device__ inline void site_thresholds(const SiteConst& my, T& ksg, T& kthr, T& kthr2) {
+  const double sq = sqrt(my.u / my.bos);
+  if (my.delta > 0.0) {
+    kthr = (T)(1.0 - (sq - 1.0) / my.delta);
+    kthr2 = (T)(1.0 + (1.0 + sq) / my.delta);
+  } else if (my.delta < 0.0) {
+    ksg = T(-1);
+    kthr = (T)(-(1.0 - (sq - 1.0) / my.delta));
+    kthr2 = (T)(-(1.0 + (1.0 + sq) / my.delta));
+  } else {
+    kthr = (my.u < my.bos) ? (T)INFINITY : (T)-INFINITY;
+    kthr2 = (T)INFINITY;
+  }
+}
+
 // The walker: the decisions of the block of cnt <= K sites at `base` on
 // G_cur[S, S] (g0(r, c) = G0[base + r][base + c]).
 //
@@ -345,23 +362,15 @@ __device__ __attribute__((always_inline)) inline void walk_diag(GetG g0, int bas
     my_rp = rp[base + k];
   }
   // The Metropolis test u < R = r^2 exp(-dS_b), r = 1 + delta (1 - G_kk), as
-  // a test on G_kk alone: r >= 0 (G_kk lies in [0, 1]), so u < R is
-  // r > s = sqrt(u exp(dS_b)), i.e. G_kk < 1 - (s - 1) / delta for delta > 0
-  // and G_kk > 1 - (s - 1) / delta for delta < 0; with sg = sign(delta) the
-  // test is sg G_kk < kthr, kthr = sg (1 - (s - 1) / delta), set once per
-  // block.  (delta = 0: r = 1, the test is u < exp(-dS_b) whatever G_kk.)
-  T ksg = T(1), kthr;
-  {
-    const double sq = sqrt(my.u / my.bos);
-    if (my.delta > 0.0) {
-      kthr = (T)(1.0 - (sq - 1.0) / my.delta);
-    } else if (my.delta < 0.0) {
-      ksg = T(-1);
-      kthr = (T)(-(1.0 - (sq - 1.0) / my.delta));
-    } else {
-      kthr = (my.u < my.bos) ? (T)INFINITY : (T)-INFINITY;
-    }
-  }
+  // a test on G_kk alone: u < R is |r| > s = sqrt(u exp(dS_b)), i.e. r > s or
+  // r < -s.  With sg = sign(delta), r > s is sg G_kk < kthr,
+  // kthr = sg (1 - (s - 1) / delta), and r < -s is sg G_kk > kthr2,
+  // kthr2 = sg (1 + (1 + s) / delta) (a determinant ratio of either sign: far
+  // outside the range of G_kk at the local moves' widths, but kept so that
+  // the test is the stated one).  Both are set once per block.  (delta = 0:
+  // r = 1, the test is u < exp(-dS_b) whatever G_kk.)
+  T ksg = T(1), kthr, kthr2;
+  site_thresholds(my, ksg, kthr, kthr2);
   T gacc = T(0);                           // this lane's G_kk when its own move was accepted
   bool mine = false;
   T coef = T(0);
@@ -371,7 +380,7 @@ __device__ __attribute__((always_inline)) inline void walk_diag(GetG g0, int bas
   // band in the test build) and its coefficient c = delta / r in case it is
   // accepted
   auto judge = [&]() -> bool {
-    bool a = ksg * dg < kthr;
+    bool a = (ksg * dg < kthr) || (ksg * dg > kthr2);
     const T rt = fma((T)my.delta, T(1) - dg, T(1));
     coef = (T)my.delta * recip(rt);
     if (HOOKS) {
@@ -390,7 +399,7 @@ __device__ __attribute__((always_inline)) inline void walk_diag(GetG g0, int bas
         // the site's own ratio at its decision: logged, and the replay counted
         Rv[base + q] = R;
         if (my_rp != 255) {
-          const int raw = (ksg * dg < kthr) ? 1 : 0;
+          const int raw = ((ksg * dg < kthr) || (ksg * dg > kthr2)) ? 1 : 0;
           if (my.u >= R * band_lo && my.u <= R * band_hi) nover += (raw != my_rp) ? 1 : 0;
           else nmis += (raw != my_rp) ? 1 : 0;
         }
@@ -491,25 +500,15 @@ __device__ __attribute__((always_inline)) inline void walk_dense(GetG g0, int ba
     my_rp = rp[base + k];
   }
   // the Metropolis test as a test on G_kk (see walk_diag)
-  T ksg = T(1), kthr;
-  {
-    const double sq = sqrt(my.u / my.bos);
-    if (my.delta > 0.0) {
-      kthr = (T)(1.0 - (sq - 1.0) / my.delta);
-    } else if (my.delta < 0.0) {
-      ksg = T(-1);
-      kthr = (T)(-(1.0 - (sq - 1.0) / my.delta));
-    } else {
-      kthr = (my.u < my.bos) ? (T)INFINITY : (T)-INFINITY;
-    }
-  }
+  T ksg = T(1), kthr, kthr2;                 // the threshold test of walk_diag
+  site_thresholds(my, ksg, kthr, kthr2);
   T gacc = T(0);
   bool mine = false;
   T coef = T(0);
   double Rr = 0.0;
   int nover = 0, nmis = 0;
   auto judge = [&]() -> bool {
-    bool a = ksg * dg < kthr;
+    bool a = (ksg * dg < kthr) || (ksg * dg > kthr2);
     const T rt = fma((T)my.delta, T(1) - dg, T(1));
     coef = (T)my.delta * recip(rt);
     if (HOOKS) {
@@ -528,7 +527,7 @@ __device__ __attribute__((always_inline)) inline void walk_dense(GetG g0, int ba
     if (HOOKS && lane == q) {
       Rv[base + q] = Rr;
       if (my_rp != 255) {
-        const int raw = (ksg * dg < kthr) ? 1 : 0;
+        const int raw = ((ksg * dg < kthr) || (ksg * dg > kthr2)) ? 1 : 0;
         if (my.u >= Rr * band_lo && my.u <= Rr * band_hi) nover += (raw != my_rp) ? 1 : 0;
         else nmis += (raw != my_rp) ? 1 : 0;
       }
