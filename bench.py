@@ -194,7 +194,7 @@ def run_workload(w, steps, warmup, profile=True):
 # counter runs on the mixed 12x12 workload, scaled by the same counters on a
 # plain copy (profiles/local_regs_kernel_12x12_mixed_traffic.txt); valid only
 # for the kernel source those runs measured
-LOCAL_TRAFFIC = {"sha1": "f4690479f45bf939ef209926689a727260de76e2", "bytes": 22686519,
+LOCAL_TRAFFIC = {"sha1": "b4da4b2fdf63a7172ee97f95d64cc8a8d184b7f8", "bytes": 22698226,
                  "workload": "holstein-12x12-L120-mixed-nstab6-128chains"}
 
 
