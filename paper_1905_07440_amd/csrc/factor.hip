@@ -1412,11 +1412,18 @@ constexpr int WIDE_MAX_SPLIT = 8;
 __host__ __device__ inline long wide_stride(int n) { return 2L * n * n + (long)WIDE_MAX_SPLIT * n; }
 size_t wide_scratch_doubles(int n) { return (size_t)wide_stride(n); }
 
+// Workgroups per matrix of the wide forms: as many as leave every CU one (at
+// most 8), for N > 144 only.  Up to 144 the register-resident forms are
+// faster: at 12x12 with 128 chains the wide QR over two workgroups per
+// matrix took 358 us per batch against 278 us (nine launches, each paying a
+// memory round trip, against one).
 int wide_split(int n, int batch) {
   if (n <= 144 || batch < 1) return 1;
   const int s = std::min(WIDE_MAX_SPLIT, 256 / batch);
   return s >= 2 ? s : 1;
 }
+static int qr_wide_split(int n, int batch) { return wide_split(n, batch); }
+static int gj_wide_split(int n, int batch) { return wide_split(n, batch); }
 
 // partial squared column norms of Z over row block w of S
 __global__ __launch_bounds__(256) void qr_wide_norms_kernel(const double* __restrict__ Zg, double* __restrict__ Xg,
@@ -1808,7 +1815,7 @@ size_t qr_t_doubles(int n) { return (size_t)NB * (n + NB); }
 hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int n, int batch, hipStream_t s,
                      double* X) {
   if (!qr_supported(n)) return hipErrorInvalidValue;
-  const int S = X ? wide_split(n, batch) : 1;
+  const int S = X ? qr_wide_split(n, batch) : 1;
   if (S > 1) {
     const dim3 grid(batch * S);
     hipLaunchKernelGGL(qr_wide_norms_kernel, grid, dim3(256), 0, s, Z, X, n, batch, S);
@@ -1831,7 +1838,7 @@ hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int 
 hipError_t launch_gj(double* M, double* W, const double* rs, const double* cs, const double* base, double* logdet,
                      int n, int batch, hipStream_t s, double* X) {
   if (!gj_supported(n)) return hipErrorInvalidValue;
-  const int S = X ? wide_split(n, batch) : 1;
+  const int S = X ? gj_wide_split(n, batch) : 1;
   if (S > 1) {
     const dim3 grid(batch * S);
     const int npan = (n + NB - 1) / NB;
