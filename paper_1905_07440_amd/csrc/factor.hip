@@ -172,11 +172,14 @@ __device__ inline void factor_panel(int nbw, int m, double (*Colj)[CAP], double*
       // the dot of that tail with own column w + 4q (if right of j).  The
       // reflector's scale enters afterwards, since
       // v^T a_c = a_c[j] + scl * (tail . a_c[tail])
-      double tail[RPL];
+      // the column as loaded (row j too: its diagonal entry then comes from
+      // lane j's register instead of a second LDS round trip), and its tail
+      double raw[RPL], tail[RPL];
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const int r = lane + 64 * t;
-        tail[t] = (r > j && r < m) ? Colj[j & 1][r] : 0.0;
+        raw[t] = (r < CAP) ? Colj[j & 1][r] : 0.0;
+        tail[t] = (r > j && r < m) ? raw[t] : 0.0;
       }
       double part[8];
 #pragma unroll
@@ -192,7 +195,7 @@ __device__ inline void factor_panel(int nbw, int m, double (*Colj)[CAP], double*
       double tot[8];
       wave_totals8(part, tot);
       const double sg = tot[0];
-      const double al = Colj[j & 1][j];
+      const double al = lane_value(raw[0], j);   // row j < 16 lives in slot 0 of lane j
       double be = al, tj = 0.0, scl = 0.0;
       if (sg > 0.0) {
         const double nrm = sqrt(al * al + sg);
