@@ -1126,7 +1126,15 @@ hq_status enqueue_sweep(hq_ctx* ctx, int dir, bool rebuild) {
     for (Group& g : ctx->groups) ST_TRY(enqueue_group(ctx, g, ctx->stream, dir, rebuild));
   } else {
     HQ_TRY(hipEventRecord(ctx->fork, ctx->stream));
-    for (size_t k = 0; k < ctx->groups.size(); ++k) {
+    // the branch with the most work per chain (N^3 L) first, so that the
+    // longest path starts first; the small groups fill in beside it
+    std::vector<size_t> order(ctx->groups.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+      const Group &ga = ctx->groups[a], &gb = ctx->groups[b];
+      return (double)ga.n * ga.n * ga.n * ga.L > (double)gb.n * gb.n * gb.n * gb.L;
+    });
+    for (size_t k : order) {
       HQ_TRY(hipStreamWaitEvent(ctx->side[k], ctx->fork, 0));
       ST_TRY(enqueue_group(ctx, ctx->groups[k], ctx->side[k], dir, rebuild));
       HQ_TRY(hipEventRecord(ctx->join[k], ctx->side[k]));
