@@ -1630,7 +1630,7 @@ __global__ __launch_bounds__(256) void gj_wide_step_kernel(const double* __restr
   constexpr int RPL = Cap<MX>::rpl;
   constexpr int NTL = Cap<MX>::tiles;
   __shared__ double Fs[NB][VLD];           // the eliminated panel, column-major, zero tail
-  __shared__ double Sc[4][NB][NB + 1];
+  __shared__ double Sc[4][NB + 1][NB + 1];   // per wave: the strip's old pivot rows (+ a row for the rest)
   __shared__ int usedf[MAXN];              // rows pivoted in earlier panels
   __shared__ int kmap[MAXN];               // row -> its pivot index in this panel, or -1
   __shared__ int prs[NB];                  // this panel's pivot rows and values
@@ -1716,7 +1716,9 @@ __global__ __launch_bounds__(256) void gj_wide_step_kernel(const double* __restr
     const int s = (it < p) ? it : it + 1;
     const int col = 16 * s + li;
     // the strip's old pivot rows (k, column) to LDS from the registers that
-    // hold them, and those rows as 0 in the tiles
+    // hold them, and those rows as 0 in the tiles; every element is written,
+    // the rows that are no pivot of this panel to the spare row NB, so that
+    // no LDS access sits behind a branch
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int e = lane + 64 * i;
@@ -1729,10 +1731,8 @@ __global__ __launch_bounds__(256) void gj_wide_step_kernel(const double* __restr
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * t + frag_row<double>(lane, v);
         const int k = (row < n) ? kmap[row] : -1;
-        if (k >= 0) {
-          Sc[wave][k][li] = tile[t][v];
-          tile[t][v] = 0.0;
-        }
+        Sc[wave][(k >= 0) ? k : NB][li] = tile[t][v];
+        tile[t][v] = (k >= 0) ? 0.0 : tile[t][v];
       }
     wave_sync_lds();
     double tb[NB / 4];
