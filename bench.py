@@ -499,9 +499,11 @@ def main():
         "dtype": dtype_of(w), "data": "synthetic",
         "config": {"workload": w.name, "chains": w.n_chains, "nx": [g.nx for g in w.groups],
                    "L": [round(g.beta / g.dtau) for g in w.groups], "n_stab": g0.n_stab,
-                   "precision": "mixed" if w.precision else "fp64", "delay": w.delay or 16,
-                   "delay_note": "block of sites per delayed update (the workload states rank 32; "
-                                 "mixed_delay32 times that)" if a.workload == "c3" else None,
+                   "precision": "mixed" if w.precision else "fp64",
+                   "delay": w.delay or [t["local_block"] for t in res["tuning"]],
+                   "delay_note": "block of sites per delayed update, per lattice group as the library's tuning "
+                                 "chose it (the workload states rank 32; mixed_delay32 times that)"
+                                 if a.workload == "c3" else "block of sites per delayed update, per lattice group",
                    "parallelism": "independent chains, one GPU"},
         "accuracy": {"max_abs_G_minus_fp64": res["max_drift_green"],
                      "max_abs_G_minus_fp64_by_group": res["max_drift_green_by_group"],

@@ -96,7 +96,10 @@ typedef struct {
   int32_t precision;     /* HQ_PREC_FP64 or HQ_PREC_MIXED (FP32 wraps and updates) */
   int32_t delay;         /* local-move block size k (8, 16 or 32): the sites are taken k
                             at a time and G gets one delayed rank-(accepts) update per
-                            block; 0 = library default (16) */
+                            block; 0 = chosen by the library (hq_create times one slice
+                            of local moves with each block size the lattice supports,
+                            on copies of the chains' state, and keeps the faster;
+                            hq_create_static takes 16) */
   int32_t activation;    /* network hidden activation: 0 ReLU, 1 softplus */
   int32_t record;        /* 1: keep every decision of the last sweep (hq_read_decisions) */
 } hq_options;
@@ -254,7 +257,9 @@ enum { HQ_WRAP_TWO = 0, HQ_WRAP_FUSED = 1, HQ_WRAP_KRON = 2, HQ_WRAP_KRON_LDS = 
  * the FP64 products (UDT combines and merges) and of the wraps' dense
  * products in the context's precision, found by timing every tile that fits
  * on the group's own shape; the wrap form (HQ_WRAP_*) that timed fastest;
- * and the local-move block size.  Block products always take the Kronecker
+ * and the local-move block size (timed when options.delay is 0; local_us
+ * is then the chosen size's time of one slice of local moves, else 0).
+ * Block products always take the Kronecker
  * form.  Tile names from hq_gemm_tile_name (a static string; "?" for an
  * unknown code). */
 typedef struct {
@@ -262,6 +267,7 @@ typedef struct {
   double gemm_us_fp64, gemm_us_wrap;   /* measured time of one batched product */
   int32_t wrap_kind;                   /* HQ_WRAP_* */
   double wrap_us;                      /* measured time of one wrap of all the group's chains */
+  double local_us;                     /* measured time of one slice of local moves (see above) */
 } hq_tuning;
 hq_status hq_read_tuning(const hq_ctx* ctx, int32_t group, hq_tuning* out);
 

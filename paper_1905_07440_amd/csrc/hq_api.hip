@@ -44,6 +44,8 @@ struct Group {
   int nt = 256, kd = 16, tile = TILE_64x64, tile32 = TILE_64x64;
   int tile_wide = TILE_64x64;              // FP64 products over all blocks of all chains
   double tile_us = 0.0, tile32_us = 0.0;   // autotuner timings
+  double local_us = 0.0;                   // timed local slice at the chosen block size (0: not timed)
+  int64_t* tune_cnt = nullptr;             // counters of the timed local slices (thrown away)
   int wrap_kind = WRAP_TWO;                // how a wrap is computed (autotuner's choice)
   double wrap_us = 0.0;                    // measured time of one wrap as chosen
   bool global = false, network = false;
@@ -279,6 +281,7 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
     g.logdet_new = cv.take<double>(C);
     g.shift = cv.take<double>(C);
     g.counters = cv.take<int64_t>(C * N_COUNTERS);
+    g.tune_cnt = cv.take<int64_t>(C * N_COUNTERS);
     g.drift = cv.take<double>(C * 5);
     g.dpart = cv.take<double>((long)stab_part_doubles(C));
     g.obs = cv.take<double>(C * 5);
@@ -1280,6 +1283,69 @@ hq_status autotune(hq_ctx* ctx) {
   return st;
 }
 
+// The local-move block size, when the caller left it to the library: one
+// slice of local moves (slice 0 of the first sweep, the draws the sweep will
+// make) timed with each block size the group's lattice supports, on copies
+// of G, the fields and the log determinants, so that the chains' state is
+// untouched; the faster is kept (32 only when more than 5% faster).
+hq_status tune_delay(hq_ctx* ctx) {
+  if (ctx->opt.delay) return HQ_OK;
+  hipStream_t s = ctx->stream;
+  hipEvent_t e0, e1;
+  HQ_TRY(hipEventCreate(&e0));
+  HQ_TRY(hipEventCreate(&e1));
+  hq_status st = HQ_OK;
+  for (Group& g : ctx->groups) {
+    if (g.network || st != HQ_OK) continue;       // network groups make no local-move launches
+    const long nn = (long)g.n * g.n;
+    const size_t gbytes = (size_t)g.C * nn * (ctx->opt.precision == HQ_PREC_MIXED ? 4 : 8);
+    double best = 1e30;
+    int bestk = g.kd;
+    for (int kd : {16, 32}) {
+      if (!local_supported(g.n, ctx->opt.precision, g.nt, kd)) continue;
+      LocalArgs a;
+      a.n = g.n; a.L = g.L; a.slice = 0;
+      a.G = g.Wt; a.x = g.xp; a.g = g.g;
+      a.dtau = g.p.dtau; a.mass = g.p.mass; a.omega = g.p.omega; a.width = g.p.local_width;
+      a.seed = ctx->seed; a.chain0 = g.chain0; a.sweep = ctx->sweep_counter;
+      a.logdet = g.logdet_new; a.counters = g.tune_cnt;
+      float ms = 0.f;
+      hipError_t e = hipSuccess;
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {   // the first is a warm-up
+        e = hipMemcpyAsync(g.Wt, g.G, gbytes, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(g.xp, g.x, (size_t)g.C * g.L * g.n * sizeof(double), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(g.logdet_new, g.logdet, g.C * sizeof(double), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && rep > 0) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = launch_local(a, ctx->opt.precision, g.nt, kd, g.C, s);
+        if (e == hipSuccess && rep > 0) e = hipEventRecord(e1, s);
+        if (e == hipSuccess && rep > 0) e = hipEventSynchronize(e1);
+        float m = 0.f;
+        if (e == hipSuccess && rep > 0) e = hipEventElapsedTime(&m, e0, e1);
+        ms += m;
+      }
+      if (e != hipSuccess) {
+        st = fail(ctx, HQ_EDEVICE, "local block tuning: %s", hipGetErrorString(e));
+        break;
+      }
+      const double us = 1e3 * ms / 2.0;
+      // 16 (timed first) stays unless 32 is clearly faster: close timings
+      // would otherwise pick either from one context to the next
+      if (best == 1e30 || us < 0.95 * best) {
+        best = us;
+        bestk = kd;
+      }
+    }
+    if (st == HQ_OK && best < 1e30) {
+      g.kd = bestk;
+      g.local_us = best;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 hq_status recompute_all(hq_ctx* ctx) {
   Sched S{ctx, ctx->stream};
   for (Group& g : ctx->groups) {
@@ -1550,6 +1616,7 @@ hq_status create_ctx(const hq_group* groups, int32_t n_groups, const hq_options*
   }
   hq_status st = recompute_all(ctx);
   if (st != HQ_OK) return st;
+  if (tune) ST_TRY(tune_delay(ctx));
   return sync(ctx);
 }
 }  // namespace
@@ -1816,6 +1883,7 @@ hq_status hq_read_tuning(const hq_ctx* ctx, int32_t group, hq_tuning* out) {
   out->gemm_tile_fp64 = g.tile;
   out->gemm_tile_wrap = g.tile32;
   out->local_block = g.kd;
+  out->local_us = g.local_us;
   out->gemm_us_fp64 = g.tile_us;
   out->gemm_us_wrap = g.tile32_us;
   out->wrap_kind = g.wrap_kind;

@@ -68,7 +68,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("gemm_tile_fp64", ctypes.c_int32), ("gemm_tile_wrap", ctypes.c_int32),
                 ("local_block", ctypes.c_int32), ("gemm_us_fp64", ctypes.c_double),
                 ("gemm_us_wrap", ctypes.c_double), ("wrap_kind", ctypes.c_int32),
-                ("wrap_us", ctypes.c_double)]
+                ("wrap_us", ctypes.c_double), ("local_us", ctypes.c_double)]
 
 
 N_GEMM_TILES = 11
@@ -303,7 +303,7 @@ class Context:
         return {"gemm_tile_fp64": name(t.gemm_tile_fp64).decode(), "gemm_us_fp64": t.gemm_us_fp64,
                 "gemm_tile_wrap": name(t.gemm_tile_wrap).decode(), "gemm_us_wrap": t.gemm_us_wrap,
                 "wrap": WRAP_KINDS[t.wrap_kind] if 0 <= t.wrap_kind < len(WRAP_KINDS) else "?",
-                "wrap_us": t.wrap_us, "local_block": t.local_block}
+                "wrap_us": t.wrap_us, "local_block": t.local_block, "local_us": t.local_us}
 
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx:
