@@ -273,7 +273,7 @@ hq_status hq_read_tuning(const hq_ctx* ctx, int32_t group, hq_tuning* out);
 
 /* Pin one group's GEMM tiles and wrap form in place of the autotuner's
  * choice (for reproducible timings and for testing every path).  Tile codes
- * are those of hq_read_tuning, 0 .. 10; wrap_kind one of HQ_WRAP_*.
+ * are those of hq_read_tuning, 0 .. 13; wrap_kind one of HQ_WRAP_*.
  * HQ_EINVAL, with nothing changed, for an unknown code, a tile that does not
  * fit the group's N in that precision, in FP64 precision tile_wrap !=
  * tile_fp64, HQ_WRAP_FUSED with N > 144, or HQ_WRAP_KRON_LDS beyond its

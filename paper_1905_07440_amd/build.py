@@ -28,6 +28,11 @@ FLAGS = [
     "-I" + os.path.join(ROOT, "include"),
 ]
 
+# per-file additions: the products in gemm.hip keep their MFMA accumulators in
+# ordinary vector registers (the VGPR form of the instructions), so a chunk loop
+# does not copy them to and from the accumulation registers on every trip
+FILE_FLAGS = {"gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
 
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
@@ -35,7 +40,7 @@ def sources():
 
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -390,23 +390,6 @@ __device__ void apply_reflector(double* A, int n, int p0, int m, const double (*
 // one per fragment row, plus the tile's start) instead of a 64-bit pointer
 // per element.  Rows past n fall outside the resource (loads give 0, stores
 // are dropped); columns past n take an offset past it on purpose.
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-constexpr unsigned BUF_WORD3 = 0x00020000u;   // raw buffer, 32-bit data format (gfx9)
-constexpr unsigned BUF_OUTSIDE = 0x80000000u;  // an offset no resource here reaches
-// a double through the 64-bit buffer operations, word by word (a bit cast of an
-// accumulator element straight to the two-word type stored wrong values for
-// every element but the first)
-__device__ inline double buf_load_f64(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
-  return __builtin_bit_cast(double, ((unsigned long long)w.y << 32) | w.x);
-}
-__device__ inline void buf_store_f64(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  u32x2 w;
-  w.x = (unsigned)u;
-  w.y = (unsigned)(u >> 32);
-  __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, 0);
-}
 
 template <int MX>
 __device__ __attribute__((always_inline)) void apply_reflector_buf(double* A, int n, int p0, int m, const double (*Vs)[VLD],
@@ -1156,16 +1139,6 @@ __global__ __launch_bounds__(256) void gj_regs_kernel(double* __restrict__ Mg, d
 // w * batch + z, which keeps a matrix's workgroups on one XCD (one L2) when
 // the batch is a multiple of 8.
 // ===========================================================================
-
-// a buffer resource over bytes from p, with p made wave-uniform first: a
-// resource that the compiler keeps in vector registers (a select between two
-// of them, say) puts every load through it in a waterfall loop
-__device__ inline __amdgpu_buffer_rsrc_t uniform_rsrc(const void* p, unsigned bytes) {
-  const unsigned long long a = (unsigned long long)p;
-  const unsigned long long u = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(a >> 32)) << 32) |
-                               (unsigned)__builtin_amdgcn_readfirstlane((unsigned)a);
-  return __builtin_amdgcn_make_buffer_rsrc((void*)u, 0, (int)bytes, BUF_WORD3);
-}
 
 // totals over the 64 lanes of NV values (NV = 16, 8, 4, 2, 1), returned
 // wave-uniform.  The halving butterfly leaves value k in lane (64 / NV) k.

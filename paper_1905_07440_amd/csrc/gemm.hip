@@ -16,83 +16,97 @@ namespace hq {
 
 // K staged 16 at a time through two LDS buffers: while the waves multiply
 // out of one buffer, every thread's loads of the next 16-wide K chunk are in
-// flight, and one barrier per chunk separates the two.
-template <typename T, int BM, int BN, int WM, int WN>
+// flight, and one barrier per chunk separates the two.  Loads and stores go
+// through buffer resources with masked byte offsets: a thread's offsets into
+// op(A) and op(B) are set once (rows past M or N already outside) and step by
+// one chunk's stride, an index past K takes the outside offset, so the loop
+// has no per-element bounds branches and no 64-bit address arithmetic.
+template <typename T, int BM, int BN, int WM, int WN, bool TA, bool TB>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& a, int z, int tile) {
   constexpr int NT = WM * WN * 64;
   constexpr int BK = 16;
   constexpr int FM = BM / (WM * 16), FN = BN / (WN * 16);
   constexpr int PA = (BM * BK + NT - 1) / NT, PB = (BN * BK + NT - 1) / NT;   // loads per thread per chunk
   constexpr int PAD = 1;
+  constexpr unsigned ES = sizeof(T);
   static_assert(FM >= 1 && FN >= 1, "tile too small");
   __shared__ T As[2][BK][BM + PAD];
   __shared__ T Bs[2][BK][BN + PAD];
   __shared__ double rsv[BM];
   __shared__ double csv[BN];
-  __shared__ double ksv[256];
+  __shared__ double ksv[256 + 16];   // K <= 256, plus the zero chunk after the last
 
   const int tn = (a.N + BN - 1) / BN;
   const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
-  const T* A = a.A + batch_offset(z, a.split, a.sA, a.sAo);
-  const T* B = a.B + batch_offset(z, a.split, a.sB, a.sBo);
-  T* C = a.C + batch_offset(z, a.split, a.sC, a.sCo);
+  // resources over this batch entry's storage of A (M x K, or K x M when
+  // transposed), B and C; every in-range element lies inside them
+  const __amdgpu_buffer_rsrc_t ra_ = uniform_rsrc(a.A + batch_offset(z, a.split, a.sA, a.sAo),
+                                                  (unsigned)((TA ? a.K : a.M) * a.lda) * ES);
+  const __amdgpu_buffer_rsrc_t rb_ = uniform_rsrc(a.B + batch_offset(z, a.split, a.sB, a.sBo),
+                                                  (unsigned)((TB ? a.N : a.K) * a.ldb) * ES);
+  const __amdgpu_buffer_rsrc_t rc_ = uniform_rsrc(a.C + batch_offset(z, a.split, a.sC, a.sCo),
+                                                  (unsigned)(a.M * a.ldc) * ES);
   const int nchunk = (a.K + BK - 1) / BK;
 
   for (int i = tid; i < BM; i += NT)
     rsv[i] = (m0 + i < a.M) ? scale_value(a.rs, z, a.inner_count, m0 + i) : 0.0;
   for (int i = tid; i < BN; i += NT)
     csv[i] = (n0 + i < a.N) ? scale_value(a.cs, z, a.inner_count, n0 + i) : 0.0;
-  const bool kscale = a.ks.v != nullptr;
-  if (kscale)
-    for (int i = tid; i < a.K; i += NT) ksv[i] = scale_value(a.ks, z, a.inner_count, i);
+  // the inner scale (1 without one; 0 from K to the end of the chunk after
+  // the last, where rb is 0 as well): every B element is scaled on its way
+  // into LDS, with no test
+  for (int i = tid; i < BK * (nchunk + 1); i += NT) ksv[i] = (i < a.K) ? scale_value(a.ks, z, a.inner_count, i) : 0.0;
 
-  // chunk element e -> (row, k), consecutive threads on the source's contiguous index
-  auto a_pos = [&](int e, int& m, int& k) {
-    if (a.tA) { m = e % BM; k = e / BM; } else { m = e / BK; k = e % BK; }
+  // chunk element e -> (row, k), consecutive threads on the source's
+  // contiguous index; per load: byte offset at chunk 0, k within the chunk,
+  // LDS slot (-1: past the chunk, when NT does not divide it)
+  unsigned oa[PA], ob[PB];
+  int ka[PA], kb[PB], sa[PA], sb[PB];
+#pragma unroll
+  for (int q = 0; q < PA; ++q) {
+    const int e = tid + NT * q;
+    const int m = TA ? e % BM : e / BK, k = TA ? e / BM : e % BK;
+    const bool live = e < BM * BK && m0 + m < a.M;
+    oa[q] = live ? (unsigned)(TA ? k * a.lda + m0 + m : (m0 + m) * a.lda + k) * ES : BUF_OUTSIDE;
+    ka[q] = k;
+    sa[q] = (e < BM * BK) ? k * (BM + PAD) + m : -1;
+  }
+#pragma unroll
+  for (int q = 0; q < PB; ++q) {
+    const int e = tid + NT * q;
+    const int n = TB ? e / BK : e % BN, k = TB ? e % BK : e / BN;
+    const bool live = e < BN * BK && n0 + n < a.N;
+    ob[q] = live ? (unsigned)(TB ? (n0 + n) * a.ldb + k : k * a.ldb + n0 + n) * ES : BUF_OUTSIDE;
+    kb[q] = k;
+    sb[q] = (e < BN * BK) ? k * (BN + PAD) + n : -1;
+  }
+  const unsigned stepA = (unsigned)(TA ? BK * a.lda : BK) * ES;   // one chunk further along K
+  const unsigned stepB = (unsigned)(TB ? BK : BK * a.ldb) * ES;
+
+  // two register sets: the loads of chunk c + 2 go out while chunk c is
+  // multiplied, so each load has two chunks' work to arrive in.  Loads and
+  // stores take no branches (a chunk past K reads zeros through the outside
+  // offset), so the wait before a store covers only the set it stores.
+  T ra[2][PA], rb[2][PB];
+  auto load = [&](int c, int set) {
+    const int kc = BK * c;
+#pragma unroll
+    for (int q = 0; q < PA; ++q)
+      ra[set][q] = buf_load(ra_, (kc + ka[q] < a.K) ? oa[q] + c * stepA : BUF_OUTSIDE, (T*)nullptr);
+#pragma unroll
+    for (int q = 0; q < PB; ++q)
+      rb[set][q] = buf_load(rb_, (kc + kb[q] < a.K) ? ob[q] + c * stepB : BUF_OUTSIDE, (T*)nullptr);
   };
-  auto b_pos = [&](int e, int& k, int& n) {
-    if (a.tB) { n = e / BK; k = e % BK; } else { k = e / BN; n = e % BN; }
-  };
-  T ra[PA], rb[PB];
-  auto load = [&](int c) {
+  auto store = [&](int c, int set, int buf) {
 #pragma unroll
-    for (int q = 0; q < PA; ++q) {
-      const int e = tid + NT * q;
-      int m, k;
-      a_pos(e, m, k);
-      const int gm = m0 + m, gk = BK * c + k;
-      ra[q] = (e < BM * BK && gm < a.M && gk < a.K) ? (a.tA ? A[(long)gk * a.lda + gm] : A[(long)gm * a.lda + gk])
-                                                    : T(0);
-    }
+    for (int q = 0; q < PA; ++q)
+      if (PA * NT == BM * BK || sa[q] >= 0) (&As[buf][0][0])[sa[q]] = ra[set][q];
 #pragma unroll
-    for (int q = 0; q < PB; ++q) {
-      const int e = tid + NT * q;
-      int k, n;
-      b_pos(e, k, n);
-      const int gn = n0 + n, gk = BK * c + k;
-      rb[q] = (e < BN * BK && gn < a.N && gk < a.K) ? (a.tB ? B[(long)gn * a.ldb + gk] : B[(long)gk * a.ldb + gn])
-                                                    : T(0);
-    }
-  };
-  auto store = [&](int c, int buf) {
-#pragma unroll
-    for (int q = 0; q < PA; ++q) {
-      const int e = tid + NT * q;
-      int m, k;
-      a_pos(e, m, k);
-      if (e < BM * BK) As[buf][k][m] = ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < PB; ++q) {
-      const int e = tid + NT * q;
-      int k, n;
-      b_pos(e, k, n);
-      const int gk = BK * c + k;           // rb is 0 past K; ksv is only written below K
-      if (e < BN * BK) Bs[buf][k][n] = (kscale && gk < a.K) ? (T)((double)rb[q] * ksv[gk]) : rb[q];
-    }
+    for (int q = 0; q < PB; ++q)
+      if (PB * NT == BN * BK || sb[q] >= 0) (&Bs[buf][0][0])[sb[q]] = (T)((double)rb[set][q] * ksv[BK * c + kb[q]]);
   };
 
   typedef typename Frag<T>::type F;
@@ -101,14 +115,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& a, int z, int tile)
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = F{0, 0, 0, 0};
-
-  load(0);
-  __syncthreads();                         // rsv, csv, ksv
-  store(0, 0);
-  __syncthreads();
-  for (int c = 0; c < nchunk; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nchunk) load(c + 1);
+  auto multiply = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T af[FM], bf[FN];
@@ -121,11 +128,30 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& a, int z, int tile)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
     }
-    // buffer buf ^ 1 was last read before the previous barrier
-    if (c + 1 < nchunk) store(c + 1, buf ^ 1);
+  };
+
+  load(0, 0);
+  load(1, 1);
+  __syncthreads();                         // rsv, csv, ksv
+  store(0, 0, 0);
+  __syncthreads();
+  // chunk c sits in LDS buffer c & 1 and came through register set c & 1;
+  // a pair of chunks per trip keeps the set and buffer indices static
+  int c = 0;
+  for (; c + 1 < nchunk; c += 2) {
+    load(c + 2, 0);
+    multiply(0);
+    store(c + 1, 1, 1);                    // buffer 1 was last read before the previous barrier
+    __syncthreads();
+    load(c + 3, 1);
+    multiply(1);
+    store(c + 2, 0, 0);                    // zeros when c + 2 = nchunk
     __syncthreads();
   }
+  if (c < nchunk) multiply(0);             // an odd last chunk, in buffer 0
 
+  // C through the resource: elements past M or N take the outside offset
+  // (the beta read gives 0 there and the store is dropped)
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -135,32 +161,154 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& a, int z, int tile)
         const int lr = wm * FM * 16 + i * 16 + frag_row<T>(lane, v);
         const int lc = wn * FN * 16 + j * 16 + (lane & 15);
         const int r = m0 + lr, c = n0 + lc;
-        if (r < a.M && c < a.N) {
-          double val = a.alpha * rsv[lr] * (double)acc[i][j][v] * csv[lc];
-          T* dst = C + (long)r * a.ldc + c;
-          if (a.beta != 0.0) val += a.beta * (double)(*dst);
-          *dst = (T)val;
-        }
+        const unsigned off = (r < a.M && c < a.N) ? (unsigned)(r * a.ldc + c) * ES : BUF_OUTSIDE;
+        double val = a.alpha * rsv[lr] * (double)acc[i][j][v] * csv[lc];
+        if (a.beta != 0.0) val += a.beta * (double)buf_load(rc_, off, (T*)nullptr);
+        buf_store((T)val, rc_, off);
       }
 }
 
-template <typename T, int BM, int BN, int WM, int WN>
+// TA, TB: the transposition flags of a, fixed per instantiation
+template <typename T, int BM, int BN, int WM, int WN, bool TA, bool TB>
 __global__ __launch_bounds__(WM * WN * 64) void gemm_kernel(GemmArgs<T> a) {
   int z, tile;
   if (!xcd_tile(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch, z, tile)) return;
-  gemm_tile<T, BM, BN, WM, WN>(a, z, tile);
+  gemm_tile<T, BM, BN, WM, WN, TA, TB>(a, z, tile);
 }
 
-// two independent products of one shape in one launch: batch entries
-// [0, a.batch) are a's, the next b.batch are b's
-template <typename T, int BM, int BN, int WM, int WN>
+// two independent products of one shape and the same transpositions in one
+// launch: batch entries [0, a.batch) are a's, the next b.batch are b's
+template <typename T, int BM, int BN, int WM, int WN, bool TA, bool TB>
 __global__ __launch_bounds__(WM * WN * 64) void gemm_pair_kernel(GemmArgs<T> a, GemmArgs<T> b) {
   int z, tile;
   if (!xcd_tile(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch + b.batch, z, tile)) return;
   if (z < a.batch)
-    gemm_tile<T, BM, BN, WM, WN>(a, z, tile);
+    gemm_tile<T, BM, BN, WM, WN, TA, TB>(a, z, tile);
   else
-    gemm_tile<T, BM, BN, WM, WN>(b, z - a.batch, tile);
+    gemm_tile<T, BM, BN, WM, WN, TA, TB>(b, z - a.batch, tile);
+}
+
+// Direct-load variant: the operands do not pass through LDS.  Each wave owns
+// a (16 FM) x (16 FN) block of C and fetches its own MFMA operands straight
+// into registers, one 16-wide K chunk ahead of the MFMAs that use them.  The
+// chunk's k are spread over the four lane groups so that lane (r, g), r =
+// lane & 15, g = lane >> 4, holds k = 16 c + 4 g + s (s = 0 .. 3) of row r of
+// each of its A blocks and of column r of each of its B blocks, and MFMA
+// step s sums over those four k (a relabelling of k within the chunk, the
+// same on both operands).  No barrier sits inside the K loop: the W waves of
+// a workgroup (stacked over rows, sharing the B columns, whose loads then
+// meet in the L1 cache) run independently.  Masked buffer offsets zero
+// everything past M, N or K.
+template <typename T, int FM, int FN, int W, bool TA, bool TB>
+__global__ __launch_bounds__(W * 64) void gemm_direct_kernel(GemmArgs<T> a) {
+  constexpr int BM = 16 * FM * W, BN = 16 * FN, NT = W * 64;
+  constexpr unsigned ES = sizeof(T);
+  __shared__ double rsv[BM];
+  __shared__ double csv[BN];
+  __shared__ double ksv[256 + 16];         // K <= 256, plus the zero chunk after the last
+
+  const int tn = (a.N + BN - 1) / BN, tm = (a.M + BM - 1) / BM;
+  int z, tile;
+  if (!xcd_tile(tn * tm, a.batch, z, tile)) return;
+  const int m0 = (tile / tn) * BM, n0 = (tile % tn) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nchunk = (a.K + 15) / 16;
+  const __amdgpu_buffer_rsrc_t ra_ = uniform_rsrc(a.A + batch_offset(z, a.split, a.sA, a.sAo),
+                                                  (unsigned)((TA ? a.K : a.M) * a.lda) * ES);
+  const __amdgpu_buffer_rsrc_t rb_ = uniform_rsrc(a.B + batch_offset(z, a.split, a.sB, a.sBo),
+                                                  (unsigned)((TB ? a.N : a.K) * a.ldb) * ES);
+  const __amdgpu_buffer_rsrc_t rc_ = uniform_rsrc(a.C + batch_offset(z, a.split, a.sC, a.sCo),
+                                                  (unsigned)(a.M * a.ldc) * ES);
+
+  for (int i = tid; i < BM; i += NT)
+    rsv[i] = (m0 + i < a.M) ? scale_value(a.rs, z, a.inner_count, m0 + i) : 0.0;
+  for (int i = tid; i < BN; i += NT)
+    csv[i] = (n0 + i < a.N) ? scale_value(a.cs, z, a.inner_count, n0 + i) : 0.0;
+  const bool kscale = a.ks.v != nullptr;
+  if (kscale)
+    for (int i = tid; i < 16 * nchunk; i += NT) ksv[i] = (i < a.K) ? scale_value(a.ks, z, a.inner_count, i) : 0.0;
+  __syncthreads();
+
+  // byte offsets of this lane's elements at chunk 0, s = 0 (outside past M or N)
+  const int wr0 = m0 + wave * 16 * FM;
+  unsigned oa[FM], ob[FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int row = wr0 + 16 * i + r;
+    oa[i] = (row < a.M) ? (unsigned)(TA ? 4 * g * a.lda + row : row * a.lda + 4 * g) * ES : BUF_OUTSIDE;
+  }
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int col = n0 + 16 * j + r;
+    ob[j] = (col < a.N) ? (unsigned)(TB ? col * a.ldb + 4 * g : 4 * g * a.ldb + col) * ES : BUF_OUTSIDE;
+  }
+  const unsigned sA = (unsigned)(TA ? a.lda : 1) * ES, sB = (unsigned)(TB ? 1 : a.ldb) * ES;   // k + 1
+  const unsigned cA = 16 * sA, cB = 16 * sB;                                                    // chunk + 1
+
+  T va[2][FM][4], vb[2][FN][4];
+  auto load = [&](int c, int set) {
+    const int kg = 16 * c + 4 * g;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      // bit 31 (past every resource) when k = kg + t >= K: arithmetic, not a
+      // select, which the compiler would turn into a branch around the load
+      const unsigned out = (unsigned)(a.K - 1 - kg - t) & BUF_OUTSIDE;
+#pragma unroll
+      for (int i = 0; i < FM; ++i) va[set][i][t] = buf_load(ra_, (oa[i] + c * cA + t * sA) | out, (T*)nullptr);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) vb[set][j][t] = buf_load(rb_, (ob[j] + c * cB + t * sB) | out, (T*)nullptr);
+    }
+  };
+  typedef typename Frag<T>::type F;
+  F acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = F{0, 0, 0, 0};
+  auto multiply = [&](int c, int set) {
+    if (kscale) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double kv = ksv[16 * c + 4 * g + t];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) vb[set][j][t] = (T)((double)vb[set][j][t] * kv);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = mfma16(va[set][i][t], vb[set][j][t], acc[i][j]);
+  };
+
+  // chunk c comes through register set c & 1; loads of chunk c + 1 are in
+  // flight while chunk c is multiplied (a chunk past K loads zeros)
+  load(0, 0);
+  int c = 0;
+  for (; c + 1 < nchunk; c += 2) {
+    load(c + 1, 1);
+    multiply(c, 0);
+    load(c + 2, 0);
+    multiply(c + 1, 1);
+  }
+  if (c < nchunk) multiply(c, 0);
+
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = wave * 16 * FM + i * 16 + frag_row<T>(lane, v);
+        const int lc = j * 16 + r;
+        const int row = m0 + lr, col = n0 + lc;
+        const unsigned off = (row < a.M && col < a.N) ? (unsigned)(row * a.ldc + col) * ES : BUF_OUTSIDE;
+        double val = a.alpha * rsv[lr] * (double)acc[i][j][v] * csv[lc];
+        if (a.beta != 0.0) val += a.beta * (double)buf_load(rc_, off, (T*)nullptr);
+        buf_store((T)val, rc_, off);
+      }
 }
 
 // Full-K variant for K <= a few hundred (every DQMC product has K = N <= 256):
@@ -415,6 +563,19 @@ static hipError_t launch_regpf(const GemmArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int FM, int FN, int W>
+static hipError_t launch_direct(const GemmArgs<T>& a, hipStream_t s) {
+  if (a.K > 256) return hipErrorInvalidValue;   // the inner scales sit in LDS
+  constexpr int BM = 16 * FM * W, BN = 16 * FN;
+  const dim3 grid(xcd_grid(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch)), block(W * 64);
+  if (a.tA)
+    if (a.tB) hipLaunchKernelGGL((gemm_direct_kernel<T, FM, FN, W, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((gemm_direct_kernel<T, FM, FN, W, true, false>), grid, block, 0, s, a);
+  else if (a.tB) hipLaunchKernelGGL((gemm_direct_kernel<T, FM, FN, W, false, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gemm_direct_kernel<T, FM, FN, W, false, false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int BM, int BN>
 static size_t fullk_lds(int K) { return sizeof(T) * (size_t)((K + 3) & ~3) * (BM + BN + 4); }
 
@@ -429,15 +590,27 @@ static hipError_t launch_fullk(const GemmArgs<T>& a, hipStream_t s) {
 
 template <typename T, int BM, int BN, int WM, int WN>
 static hipError_t launch_tile(const GemmArgs<T>& a, hipStream_t s) {
-  const dim3 grid(xcd_grid(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch));
-  hipLaunchKernelGGL((gemm_kernel<T, BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s, a);
+  if (a.K > 256) return hipErrorInvalidValue;   // the inner scales sit in LDS
+  const dim3 grid(xcd_grid(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch)), block(WM * WN * 64);
+  if (a.tA)
+    if (a.tB) hipLaunchKernelGGL((gemm_kernel<T, BM, BN, WM, WN, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((gemm_kernel<T, BM, BN, WM, WN, true, false>), grid, block, 0, s, a);
+  else if (a.tB) hipLaunchKernelGGL((gemm_kernel<T, BM, BN, WM, WN, false, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((gemm_kernel<T, BM, BN, WM, WN, false, false>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
+// one launch when a and b have the same transpositions and neither is
+// transposed; otherwise one after the other
 template <typename T, int BM, int BN, int WM, int WN>
 static hipError_t launch_pair_tile(const GemmArgs<T>& a, const GemmArgs<T>& b, hipStream_t s) {
+  if (a.tA || a.tB || b.tA || b.tB || a.K > 256 || b.K > 256) {
+    hipError_t e = launch_tile<T, BM, BN, WM, WN>(a, s);
+    if (e != hipSuccess) return e;
+    return launch_tile<T, BM, BN, WM, WN>(b, s);
+  }
   const dim3 grid(xcd_grid(((a.N + BN - 1) / BN) * ((a.M + BM - 1) / BM), a.batch + b.batch));
-  hipLaunchKernelGGL((gemm_pair_kernel<T, BM, BN, WM, WN>), grid, dim3(WM * WN * 64), 0, s, a, b);
+  hipLaunchKernelGGL((gemm_pair_kernel<T, BM, BN, WM, WN, false, false>), grid, dim3(WM * WN * 64), 0, s, a, b);
   return hipGetLastError();
 }
 
@@ -477,6 +650,9 @@ static hipError_t launch_any(const GemmArgs<T>& a, int tile, hipStream_t s) {
     case TILE_PF_48x48: return launch_regpf<T, 48, 48, 3, 1>(a, s);
     case TILE_PF_64x64: return launch_regpf<T, 64, 64, 2, 2>(a, s);
     case TILE_PF_32x32: return launch_regpf<T, 32, 32, 1, 1>(a, s);
+    case TILE_DX_48x48: return launch_direct<T, 1, 3, 3>(a, s);
+    case TILE_DX_32x32: return launch_direct<T, 1, 2, 2>(a, s);
+    case TILE_DX_64x64: return launch_direct<T, 1, 4, 4>(a, s);
     default: return launch_tile<T, 64, 64, 2, 2>(a, s);
   }
 }
@@ -497,7 +673,7 @@ bool gemm_tile_fits(int tile, int K, int precision) {
     case TILE_PF_48x48:
     case TILE_PF_64x64: return K <= 256;
     case TILE_PF_32x32: return K <= 160;
-    default: return true;
+    default: return K <= 256;               // the staged and direct tiles hold the inner scales in LDS
   }
 }
 

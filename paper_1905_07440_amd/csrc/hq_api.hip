@@ -1158,7 +1158,8 @@ hq_status autotune(hq_ctx* ctx) {
   HQ_TRY(hipEventCreate(&e0));
   HQ_TRY(hipEventCreate(&e1));
   const int cands[] = {TILE_64x64, TILE_32x32, TILE_48x48, TILE_FK_32x32, TILE_FK_48x48, TILE_FK_64x64,
-                       TILE_FK_32x64, TILE_PF_48x48, TILE_PF_64x64, TILE_PF_32x32};
+                       TILE_FK_32x64, TILE_PF_48x48, TILE_PF_64x64, TILE_PF_32x32,
+                       TILE_DX_48x48, TILE_DX_32x32, TILE_DX_64x64};
   hq_status st = HQ_OK;
   for (Group& g : ctx->groups) {
     const long nn = (long)g.n * g.n;
@@ -1930,6 +1931,9 @@ const char* hq_gemm_tile_name(int32_t tile) {
     case TILE_PF_48x48: return "48x48/prefetch";
     case TILE_PF_64x64: return "64x64/prefetch";
     case TILE_PF_32x32: return "32x32/prefetch";
+    case TILE_DX_48x48: return "48x48/direct";
+    case TILE_DX_32x32: return "32x32/direct";
+    case TILE_DX_64x64: return "64x64/direct";
     default: return "?";
   }
 }

@@ -143,4 +143,45 @@ __device__ inline void batched_copy(int count, Src src, Dst dst) {
   }
 }
 
+// Raw buffer loads and stores: an element's address is a 32-bit byte offset
+// into a resource (base, size); an offset at or past the size reads 0 and
+// drops the store, so a masked offset replaces a bounds branch.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr unsigned BUF_WORD3 = 0x00020000u;   // raw buffer, 32-bit data format (gfx9)
+constexpr unsigned BUF_OUTSIDE = 0x80000000u;  // an offset no resource here reaches
+// a double through the 64-bit buffer operations, word by word (a bit cast of an
+// accumulator element straight to the two-word type stored wrong values for
+// every element but the first)
+__device__ inline double buf_load_f64(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return __builtin_bit_cast(double, ((unsigned long long)w.y << 32) | w.x);
+}
+__device__ inline void buf_store_f64(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  u32x2 w;
+  w.x = (unsigned)u;
+  w.y = (unsigned)(u >> 32);
+  __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, 0);
+}
+__device__ inline float buf_load_f32(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline void buf_store_f32(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ inline double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, double*) { return buf_load_f64(r, off); }
+__device__ inline float buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, float*) { return buf_load_f32(r, off); }
+__device__ inline void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned off) { buf_store_f64(v, r, off); }
+__device__ inline void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off) { buf_store_f32(v, r, off); }
+
+// a buffer resource over bytes from p, with p made wave-uniform first: a
+// resource that the compiler keeps in vector registers (a select between two
+// of them, say) puts every load through it in a waterfall loop
+__device__ inline __amdgpu_buffer_rsrc_t uniform_rsrc(const void* p, unsigned bytes) {
+  const unsigned long long a = (unsigned long long)p;
+  const unsigned long long u = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(a >> 32)) << 32) |
+                               (unsigned)__builtin_amdgcn_readfirstlane((unsigned)a);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)u, 0, (int)bytes, BUF_WORD3);
+}
+
 }  // namespace hq

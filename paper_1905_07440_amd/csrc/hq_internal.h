@@ -72,9 +72,10 @@ __device__ inline double scale_value(const Scale& s, int z, int inner_count, int
 // GEMM tile configurations (see gemm.hip); the autotuner picks one per shape.
 // TILE_FK_*: the whole K extent staged at once (needs K small enough for LDS).
 // TILE_PF_*: each thread prefetches its whole share of K into registers.
+// TILE_DX_*: every wave loads its own operands into registers, no LDS staging.
 enum GemmTile { TILE_64x64 = 0, TILE_32x32 = 1, TILE_48x48 = 2, TILE_16x64 = 3, TILE_FK_32x32 = 4, TILE_FK_48x48 = 5,
                 TILE_FK_64x64 = 6, TILE_FK_32x64 = 7, TILE_PF_48x48 = 8, TILE_PF_64x64 = 9, TILE_PF_32x32 = 10,
-                N_GEMM_TILES = 11 };
+                TILE_DX_48x48 = 11, TILE_DX_32x32 = 12, TILE_DX_64x64 = 13, N_GEMM_TILES = 14 };
 
 // Both products of a wrap for every chain in one launch (gemm.hip):
 //   Gout[z] = diag(rs2) (A1 diag(ks1) Gin[z] diag(cs1)) A2 diag(cs2)

@@ -71,7 +71,7 @@ class Tuning(ctypes.Structure):
                 ("wrap_us", ctypes.c_double), ("local_us", ctypes.c_double)]
 
 
-N_GEMM_TILES = 11
+N_GEMM_TILES = 14
 # forms of a wrap (HQ_WRAP_*): two tiled dense products, both in one launch,
 # the Kronecker passes of exp(-+dtau K) = E1 (x) E1 in two launches, or in
 # one launch with G held in LDS

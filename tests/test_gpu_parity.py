@@ -329,7 +329,7 @@ _TILE_CASE = dict(nx=10, chains=2, g=1.3, beta=2.0, n_stab=5)
 _tile_oracle = {}
 
 
-@pytest.mark.parametrize("tile", range(11))
+@pytest.mark.parametrize("tile", range(14))
 def test_every_gemm_tile_fp64(hq, tile):
     """Each GEMM tile pinned in turn (N = 100: whole tiles plus a ragged edge
     for the 32, 48 and 64 tiles), an upward and a downward sweep in FP64."""
@@ -349,7 +349,7 @@ def test_every_gemm_tile_fp64(hq, tile):
     ctx.close()
 
 
-@pytest.mark.parametrize("tile", range(11))
+@pytest.mark.parametrize("tile", range(14))
 def test_every_gemm_tile_mixed_wraps(hq, tile):
     """Each tile pinned for the FP32 wraps of a mixed-precision sweep."""
     say("mixed sweep with FP32 GEMM tile %s" % hq.tile_name(tile))
