@@ -1389,14 +1389,17 @@ __host__ __device__ inline long wide_stride(int n) { return 2L * n * n + (long)W
 size_t wide_scratch_doubles(int n) { return (size_t)wide_stride(n); }
 
 // Workgroups per matrix of the wide forms: as many as leave every CU one (at
-// most 8), for N > 144 only.  Up to 144 the register-resident forms are
-// faster: at 12x12 with 128 chains the wide QR over two workgroups per
-// matrix took 358 us per batch against 278 us (nine launches, each paying a
-// memory round trip, against one).
+// most 8), for N > 144 only, and only from four on.  Up to 144 the
+// register-resident forms are faster: at 12x12 with 128 chains the wide QR
+// over two workgroups per matrix took 358 us per batch against 278 us (nine
+// launches, each paying a memory round trip, against one).  At N = 256 two
+// workgroups do not pay either: 128 QRs took 1.36 ms spread over two each,
+// while 256 QRs took 1.13 ms at one workgroup each; four per matrix (64
+// QRs) took 0.90 ms.
 int wide_split(int n, int batch) {
   if (n <= 144 || batch < 1) return 1;
   const int s = std::min(WIDE_MAX_SPLIT, 256 / batch);
-  return s >= 2 ? s : 1;
+  return s >= 4 ? s : 1;
 }
 static int qr_wide_split(int n, int batch) { return wide_split(n, batch); }
 static int gj_wide_split(int n, int batch) { return wide_split(n, batch); }

@@ -77,7 +77,7 @@ struct Group {
   double *tX = nullptr, *tUp = nullptr, *tDp = nullptr, *tQW = nullptr, *tQT = nullptr;
   bool alternate = false;        // sweeps alternate upward / downward (local moves only)
   double *Z = nullptr, *Rt = nullptr, *M = nullptr, *Minv = nullptr, *Xm = nullptr, *Tq = nullptr;
-  double* Xw = nullptr;                        // wide-factorization scratch (large N, few chains)
+  double* Xw = nullptr;                        // wide-factorization scratch (large N, few matrices)
   double *dLbinv = nullptr, *dLs = nullptr, *dRbinv = nullptr, *dRs = nullptr, *sumlog = nullptr;
   double *logdet = nullptr, *logdet_new = nullptr, *shift = nullptr;
   int64_t* counters = nullptr;
@@ -271,7 +271,16 @@ size_t layout(hq_ctx* ctx, std::vector<Group>& gs, void* base, const hq_options&
     g.Minv = cv.take<double>(C * nn);
     g.Xm = cv.take<double>(C * nn);
     g.Tq = cv.take<double>(C * (long)qr_t_doubles(g.n));
-    if (wide_split(g.n, C) > 1) g.Xw = cv.take<double>(C * (long)wide_scratch_doubles(g.n));
+    // the wide factorizations' scratch, for the largest batch of this group
+    // that they take: the group's C matrices, and the levels of the pairwise
+    // UDT tree (C * nb, C * pairs, ...) small enough to spread
+    long wide_batch = wide_split(g.n, C) > 1 ? C : 0;
+    if ((g.global || g.network) && nb > 1) {
+      if (wide_split(g.n, (int)(C * nb)) > 1) wide_batch = std::max(wide_batch, C * nb);
+      for (long m = nb; m > 1; m = (m + 1) / 2)
+        if (wide_split(g.n, (int)(C * (m / 2))) > 1) wide_batch = std::max(wide_batch, C * (m / 2));
+    }
+    if (wide_batch) g.Xw = cv.take<double>(wide_batch * (long)wide_scratch_doubles(g.n));
     g.dLbinv = cv.take<double>(C * n);
     g.dLs = cv.take<double>(C * n);
     g.dRbinv = cv.take<double>(C * n);
@@ -608,14 +617,15 @@ struct Udt { double *U, *D, *T; long sU, sD, sT; };
 // is factored at once, then level by level
 //   (U_a D_a T_a)(U_b D_b T_b) = (U_a U') D' (T' T_b),  U' D' T' = QR-UDT of D_a (T_a U_b) D_b
 // with a the later block of each pair; an unpaired last block passes to the
-// next level.  Returns pointers to the [C][1] result.
+// next level.  Levels of few enough large matrices (N > 144) spread each QR
+// over several workgroups.  Returns pointers to the [C][1] result.
 hq_status tree_product(Sched& S, Group& g, const double* blocks, Udt& out) {
   const long nn = (long)g.n * g.n;
   const int n = g.n, C = g.C;
   int cur = 0, m = g.nb;
   // level 0: Z = C_b (in tT[0], where the QR writes its triangular factor over its input)
   if (blocks != g.tT[0]) SCHED_TRY(launch_copy_f64(g.tT[0], blocks, (long)C * g.nb * nn, S.s));
-  SCHED_TRY(launch_qr(g.tT[0], g.tQW, g.tU[0], g.tD[0], g.tQT, n, C * g.nb, S.s));
+  SCHED_TRY(launch_qr(g.tT[0], g.tQW, g.tU[0], g.tD[0], g.tQT, n, C * g.nb, S.s, g.Xw));
   while (m > 1) {
     const int pairs = m / 2, m2 = (m + 1) / 2, nxt = 1 - cur;
     const double *U = g.tU[cur], *T = g.tT[cur], *D = g.tD[cur];
@@ -631,7 +641,7 @@ hq_status tree_product(Sched& S, Group& g, const double* blocks, Udt& out) {
     SCHED_TRY(launch_gemm(x, pairs > 2 ? g.tile_wide : g.tile, S.s));
     // with m even the next level's D has the layout of the QR's ([C][pairs])
     double* Dq = (m % 2) ? g.tDp : g.tD[nxt];
-    SCHED_TRY(launch_qr(g.tX, g.tQW, g.tUp, Dq, g.tQT, n, C * pairs, S.s));
+    SCHED_TRY(launch_qr(g.tX, g.tQW, g.tUp, Dq, g.tQT, n, C * pairs, S.s, g.Xw));
     // U_next = U_a U', T_next = T' T_b, D_next = D'; entries [C][m2]
     GemmArgs<double> u = sq(g, C * pairs);
     u.split = pairs;
