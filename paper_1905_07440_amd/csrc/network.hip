@@ -16,7 +16,7 @@
 //
 // Visiting order: colour classes (l mod 4, iy mod 2, ix mod 2).  No two points
 // of a class lie in each other's patch, so a class is one parallel launch of
-// independent proposals: one thread per point, the weights in LDS.
+// independent proposals, 16 points per wave on the matrix cores.
 //
 // Block moves shift a whole column x[:, i] by d.  The convolutional network
 // sees three channels over l (the column, the means of the four nearest and
@@ -36,6 +36,25 @@ __device__ inline float act(float h, int kind) {
   return kind == 0 ? fmaxf(h, 0.0f) : (h > 20.0f ? h : log1pf(expf(h)));
 }
 
+// The network on the matrix cores: each wave evaluates 16 points at a time
+// with FP32 MFMA (16 x 16 x 4), the layers transposed (hidden units as the
+// MFMA rows, the 16 points as its columns) so that one layer's output
+// fragment is the next layer's operand in place.  Lane (r, q), r = lane & 15,
+// q = lane >> 4, works on point r.
+//   layer 1: H1[o][pt] = W1[o][p] In[p][pt] over the 45 inputs (padded to 48,
+//            the centre input zero), MFMA step s taking p = 4 s + q, so each
+//            lane gathers 12 of its point's inputs; the d-dependent term
+//            W1[o][22] (+-d) and b1 are added after, once per sign.
+//   layer 2: the fragment a lane holds after layer 1, hidden rows
+//            16 t + 4 q + v of its point, is the B operand of step s = 4 t + v
+//            when that step's k for lane group q is taken to be 16 t + 4 q + v
+//            (a relabelling of the sum over the 64 hidden units); W2 is read
+//            in the same labelling.
+//   output:  f = W3 . act(H2 + b2) + b3, each lane summing its 16 hidden rows,
+//            then across the four lane groups of the point.
+// The weight fragments stay in registers for all the wave's points.
+// ACT: the activation (0 ReLU, 1 softplus), fixed per instantiation.
+template <int ACT>
 __global__ __launch_bounds__(256) void network_colour_kernel(NetArgs a) {
   __shared__ float w[7169 + 3];
   for (int e = threadIdx.x; e < 7169; e += blockDim.x) w[e] = a.w[e];
@@ -46,101 +65,175 @@ __global__ __launch_bounds__(256) void network_colour_kernel(NetArgs a) {
   const float* b2 = W2 + 64 * 64;
   const float* W3 = b2 + 64;
   const float b3 = W3[64];
+  const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+
+  float w1f[4][12], w2f[4][16];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int st = 0; st < 12; ++st) {
+      const int p = 4 * st + q;
+      w1f[t][st] = (p < 45 && p != 22) ? W1[(16 * t + r) * 45 + p] : 0.0f;
+    }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) w2f[t][4 * u + v] = W2[(16 * t + r) * 64 + 16 * u + 4 * q + v];
 
   const int nx = a.nx, n = a.n, L = a.L;
   const int cl = a.colour >> 2, py = (a.colour >> 1) & 1, px = a.colour & 1;
   const int hx = nx / 2, per_slice = hx * hx, nl = L / 4;
   const int per_chain = nl * per_slice;
-  const long item = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = (int)(item / per_chain);
-  if (c >= a.chains) return;
-  const int k = (int)(item - (long)c * per_chain);
-  const int l = cl + 4 * (k / per_slice);
-  const int rem = k % per_slice;
-  const int iy = py + 2 * (rem / hx), ix = px + 2 * (rem % hx);
-  const int i = ix + nx * iy;
-
-  double* xp = a.xp + (long)c * L * n;
+  const long total = (long)a.chains * per_chain;
+  const long groups = (total + 15) / 16;
+  const long nwave = (long)gridDim.x * (blockDim.x >> 6);
   const long ln = (long)L * n;
-  const long draw = (long)a.inner * ln + (long)l * n + i;
-  const Philox4 rn = philox4x64_10((uint64_t)(a.chain0 + c), (uint64_t)(*a.sweep), (uint64_t)draw,
-                                   KIND_NN, a.seed, 0);
-  const double u1 = u53(rn.w[1]);
-  const double d = a.width * (2.0 * u53(rn.w[0]) - 1.0);
 
-  float in[45];
+  // point r of a group: chain, slice, site; a spare lane past the class
+  // repeats its last point and writes nothing
+  struct Pt { int c, l, ix, iy; bool valid; };
+  auto locate = [&](long grp) {
+    const long item0 = grp * 16 + r;
+    Pt P;
+    P.valid = item0 < total;
+    const long item = P.valid ? item0 : total - 1;
+    P.c = (int)(item / per_chain);
+    const int k = (int)(item - (long)P.c * per_chain);
+    P.l = cl + 4 * (k / per_slice);
+    const int rem = k % per_slice;
+    P.iy = py + 2 * (rem / hx);
+    P.ix = px + 2 * (rem % hx);
+    return P;
+  };
+  // this lane's 12 inputs of its point: p = 4 st + q (the centre and p >= 45 zero)
+  auto gather = [&](const Pt& P, float (&in)[12]) {
+    const double* xp = a.xp + (long)P.c * ln;
 #pragma unroll
-  for (int dl = -2; dl <= 2; ++dl) {
-    const int ll = (l + dl + L) % L;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int j = (ix + dx + nx) % nx + nx * ((iy + dy + nx) % nx);
-        in[9 * (dl + 2) + 3 * (dy + 1) + (dx + 1)] = (float)xp[(long)ll * n + j];
-      }
-  }
-  // the first layer once for both signs of d: only the centre input differs
-  in[22] = 0.0f;
-  const float df = (float)d;
-  float hp[64], hm[64];
-#pragma unroll
-  for (int o = 0; o < 64; ++o) {
-    float s = b1[o];
-#pragma unroll
-    for (int p = 0; p < 45; ++p) s = fmaf(W1[o * 45 + p], in[p], s);
-    const float wd = W1[o * 45 + 22] * df;
-    hp[o] = act(s + wd, a.activation);
-    hm[o] = act(s - wd, a.activation);
-  }
-  float fp = b3, fm = b3;
-#pragma unroll 4
-  for (int o = 0; o < 64; ++o) {
-    float sp = b2[o], sm = b2[o];
-#pragma unroll
-    for (int p = 0; p < 64; ++p) {
-      sp = fmaf(W2[o * 64 + p], hp[p], sp);
-      sm = fmaf(W2[o * 64 + p], hm[p], sm);
+    for (int st = 0; st < 12; ++st) {
+      const int p = 4 * st + q;
+      const int dl = p / 9 - 2, dy = (p % 9) / 3 - 1, dx = p % 3 - 1;
+      const int ll = (P.l + dl + L) % L;
+      const int j = (P.ix + dx + nx) % nx + nx * ((P.iy + dy + nx) % nx);
+      in[st] = (p < 45 && p != 22) ? (float)xp[(long)ll * n + j] : 0.0f;
     }
-    fp = fmaf(W3[o], act(sp, a.activation), fp);
-    fm = fmaf(W3[o], act(sm, a.activation), fm);
-  }
-  const float y = 0.5f * (fp - fm);
+  };
 
-  const double xa = xp[(long)l * n + i];
-  const double xprev = xp[(long)((l - 1 + L) % L) * n + i];
-  const double xnext = xp[(long)((l + 1) % L) * n + i];
-  const double g = a.g[c];
-  const double kin = (a.mass / a.dtau) * (d * (2.0 * xa - xprev - xnext) + d * d);
-  const double pot = a.dtau * 0.5 * a.mass * a.omega * a.omega * (2.0 * xa * d + d * d);
-  const double ds = kin + pot - a.dtau * g * d;
-  const double lr = (double)y - ds;
-  int acc = (u1 < exp(lr)) ? 1 : 0;
-  const double margin = log(u1) - lr;
-  const long slot = (long)c * a.nu * ln + draw;       // decision log and replay
-  if (a.replay) {
-    const uint8_t rp = a.replay[slot];
-    if (rp != 255) {
-      if (fabs(margin) <= a.band) {
-        if (acc != (int)rp) atomicAdd((unsigned long long*)&a.replay_counts[2 * c], 1ull);
-        acc = rp;
-      } else if (acc != (int)rp) {
-        atomicAdd((unsigned long long*)&a.replay_counts[2 * c + 1], 1ull);
+  long grp = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (grp >= groups) return;
+  Pt P = locate(grp);
+  float in[12];
+  gather(P, in);
+  for (; grp < groups; grp += nwave) {
+    // the next group's inputs are in flight while this one is evaluated
+    const long gn = grp + nwave < groups ? grp + nwave : grp;
+    const Pt Pn = locate(gn);
+    float inn[12];
+    gather(Pn, inn);
+
+    const int c = P.c, l = P.l, i = P.ix + nx * P.iy;
+    double* xp = a.xp + (long)c * ln;
+    const long draw = (long)a.inner * ln + (long)l * n + i;
+    const Philox4 rn = philox4x64_10((uint64_t)(a.chain0 + c), (uint64_t)(*a.sweep), (uint64_t)draw,
+                                     KIND_NN, a.seed, 0);
+    const double d = a.width * (2.0 * u53(rn.w[0]) - 1.0);
+    const float df = (float)d;
+
+    f4 h1[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      h1[t] = f4{0, 0, 0, 0};
+#pragma unroll
+      for (int st = 0; st < 12; ++st) h1[t] = mfma16(w1f[t][st], in[st], h1[t]);
+    }
+    float hp[4][4], hm[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = 16 * t + 4 * q + v;
+        const float s0 = h1[t][v] + b1[o], wd = W1[o * 45 + 22] * df;
+        hp[t][v] = act(s0 + wd, ACT);
+        hm[t][v] = act(s0 - wd, ACT);
+      }
+    f4 op[4], om[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      op[t] = f4{0, 0, 0, 0};
+      om[t] = f4{0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          op[t] = mfma16(w2f[t][4 * u + v], hp[u][v], op[t]);
+          om[t] = mfma16(w2f[t][4 * u + v], hm[u][v], om[t]);
+        }
+    }
+    float fp = 0.0f, fm = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = 16 * t + 4 * q + v;
+        fp = fmaf(W3[o], act(op[t][v] + b2[o], ACT), fp);
+        fm = fmaf(W3[o], act(om[t][v] + b2[o], ACT), fm);
+      }
+    fp += __shfl_xor(fp, 16);
+    fm += __shfl_xor(fm, 16);
+    fp += __shfl_xor(fp, 32);
+    fm += __shfl_xor(fm, 32);
+    const float y = 0.5f * ((fp + b3) - (fm + b3));
+
+    if (q == 0 && P.valid) {
+      const double u1 = u53(rn.w[1]);
+      const double xa = xp[(long)l * n + i];
+      const double xprev = xp[(long)((l - 1 + L) % L) * n + i];
+      const double xnext = xp[(long)((l + 1) % L) * n + i];
+      const double g = a.g[c];
+      const double kin = (a.mass / a.dtau) * (d * (2.0 * xa - xprev - xnext) + d * d);
+      const double pot = a.dtau * 0.5 * a.mass * a.omega * a.omega * (2.0 * xa * d + d * d);
+      const double ds = kin + pot - a.dtau * g * d;
+      const double lr = (double)y - ds;
+      int acc = (u1 < exp(lr)) ? 1 : 0;
+      const double margin = log(u1) - lr;
+      const long slot = (long)c * a.nu * ln + draw;     // decision log and replay
+      if (a.replay) {
+        const uint8_t rp = a.replay[slot];
+        if (rp != 255) {
+          if (fabs(margin) <= a.band) {
+            if (acc != (int)rp) atomicAdd((unsigned long long*)&a.replay_counts[2 * c], 1ull);
+            acc = rp;
+          } else if (acc != (int)rp) {
+            atomicAdd((unsigned long long*)&a.replay_counts[2 * c + 1], 1ull);
+          }
+        }
+      }
+      if (a.log_margin) { a.log_margin[slot] = (float)margin; a.log_accept[slot] = (uint8_t)acc; }
+      const long s2 = (long)c * ln + (long)l * n + i;
+      if (acc) {
+        a.sum_y[s2] += (double)y;
+        a.accepted[s2] += 1;
+        xp[(long)l * n + i] = xa + d;
       }
     }
-  }
-  if (a.log_margin) { a.log_margin[slot] = (float)margin; a.log_accept[slot] = (uint8_t)acc; }
-  const long s2 = (long)c * ln + (long)l * n + i;
-  if (acc) {
-    a.sum_y[s2] += (double)y;
-    a.accepted[s2] += 1;
-    xp[(long)l * n + i] = xa + d;
+    P = Pn;
+#pragma unroll
+    for (int st = 0; st < 12; ++st) in[st] = inn[st];
   }
 }
 
+// one workgroup of four waves per CU; each wave takes groups of 16 points in
+// turn
 hipError_t launch_network_colour(const NetArgs& a, int chains, hipStream_t s) {
   const long items = (long)chains * (a.L / 4) * (a.nx / 2) * (a.nx / 2);
-  hipLaunchKernelGGL(network_colour_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, a);
+  const long groups = (items + 15) / 16;
+  const long blocks = (groups + 3) / 4 < 256 ? (groups + 3) / 4 : 256;
+  if (blocks <= 0) return hipSuccess;
+  if (a.activation == 0)
+    hipLaunchKernelGGL(network_colour_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(network_colour_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

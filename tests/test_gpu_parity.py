@@ -49,7 +49,7 @@ def params_of(gr, g=None):
                   local_width=gr.get("local_width", 0.5), global_width=gr.get("global_width", 0.0))
 
 
-def make_ctx(hq, groups, precision=0, seed=1, delay=0, record=True):
+def make_ctx(hq, groups, precision=0, seed=1, delay=0, record=True, activation=0):
     hg = [hq.make_group(gr["nx"], gr["chains"], t=gr.get("t", 1.0), mu=gr.get("mu", 0.0),
                         mass=gr.get("mass", 1.0), omega=gr.get("omega", 1.0), g=gr.get("g", 1.0),
                         g_range=gr.get("g_range"), beta=gr["beta"], dtau=gr.get("dtau", 0.1),
@@ -57,7 +57,7 @@ def make_ctx(hq, groups, precision=0, seed=1, delay=0, record=True):
                         local_width=gr.get("local_width", 0.5), global_width=gr.get("global_width", 0.0),
                         nn_sweeps=gr.get("nn_sweeps", 1))
           for gr in groups]
-    return hq.Context(hg, precision=precision, seed=seed, delay=delay, record=record)
+    return hq.Context(hg, precision=precision, seed=seed, delay=delay, record=record, activation=activation)
 
 
 def rel_g(a, b):
@@ -703,15 +703,17 @@ def test_network_block_moves_and_inner_sweeps(hq, nu):
     ctx.close()
 
 
-def test_network_proposals_and_cumulative_update(hq):
-    """Network-proposed sweeps on 4x4 (L = 8): inner decisions replayed inside the
-    tie band (FP32 network vs the oracle's FP64 forward), cumulative accepts compared."""
-    say("network proposals 4x4")
+@pytest.mark.parametrize("kind", [0, 1])
+def test_network_proposals_and_cumulative_update(hq, kind):
+    """Network-proposed sweeps on 4x4 (L = 8), ReLU and softplus networks:
+    inner decisions replayed inside the tie band (FP32 network vs the oracle's
+    FP64 forward), cumulative accepts compared."""
+    say("network proposals 4x4, activation %d" % kind)
     gr = dict(nx=4, chains=2, g=1.2, beta=0.8, n_stab=4, proposal=1)
     w = workloads.random_network(17, scale=0.1)
-    ctx = make_ctx(hq, [gr], seed=6)
+    ctx = make_ctx(hq, [gr], seed=6, activation=kind)
     ctx.set_network(w)
-    nets = [nnmc.NNChain(dqmc.Chain(params_of(gr), 6, c), w) for c in range(2)]
+    nets = [nnmc.NNChain(dqmc.Chain(params_of(gr), 6, c), w, kind=kind) for c in range(2)]
     p = params_of(gr)
     for s in range(3):
         for c, nn in enumerate(nets):
