@@ -54,6 +54,14 @@ __device__ inline float act(float h, int kind) {
 //            then across the four lane groups of the point.
 // The weight fragments stay in registers for all the wave's points.
 // ACT: the activation (0 ReLU, 1 softplus), fixed per instantiation.
+//
+// A wave takes its groups four at a time.  Lane (r, q) owns point r of the
+// batch's group q: it draws that proposal's random numbers and, after the
+// four evaluations, takes its accept decision, so the 64-bit generator and
+// the FP64 exp/log run once per point, not once per lane of the point.
+// Evaluating group k, every lane of point r reads the point's place and d
+// from lane (r, k).  Decisions wait for the end of the batch, which changes
+// nothing: no point of a class reads another one's field.
 template <int ACT>
 __global__ __launch_bounds__(256) void network_colour_kernel(NetArgs a) {
   __shared__ float w[7169 + 3];
@@ -81,6 +89,16 @@ __global__ __launch_bounds__(256) void network_colour_kernel(NetArgs a) {
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) w2f[t][4 * u + v] = W2[(16 * t + r) * 64 + 16 * u + 4 * q + v];
+  // this lane's inputs p = 4 st + q of a patch: offsets (dl + 2, dy + 1, dx + 1)
+  // packed 4 bits each, and which of them exist (the centre and p >= 45 do not)
+  int pof[12];
+  unsigned live = 0;
+#pragma unroll
+  for (int st = 0; st < 12; ++st) {
+    const int p = 4 * st + q;
+    pof[st] = (p / 9) | (((p % 9) / 3) << 4) | ((p % 3) << 8);
+    if (p < 45 && p != 22) live |= 1u << st;
+  }
 
   const int nx = a.nx, n = a.n, L = a.L;
   const int cl = a.colour >> 2, py = (a.colour >> 1) & 1, px = a.colour & 1;
@@ -91,135 +109,132 @@ __global__ __launch_bounds__(256) void network_colour_kernel(NetArgs a) {
   const long nwave = (long)gridDim.x * (blockDim.x >> 6);
   const long ln = (long)L * n;
 
-  // point r of a group: chain, slice, site; a spare lane past the class
-  // repeats its last point and writes nothing
-  struct Pt { int c, l, ix, iy; bool valid; };
-  auto locate = [&](long grp) {
-    const long item0 = grp * 16 + r;
-    Pt P;
-    P.valid = item0 < total;
-    const long item = P.valid ? item0 : total - 1;
-    P.c = (int)(item / per_chain);
-    const int k = (int)(item - (long)P.c * per_chain);
-    P.l = cl + 4 * (k / per_slice);
-    const int rem = k % per_slice;
-    P.iy = py + 2 * (rem / hx);
-    P.ix = px + 2 * (rem % hx);
-    return P;
-  };
-  // this lane's 12 inputs of its point: p = 4 st + q (the centre and p >= 45 zero)
-  auto gather = [&](const Pt& P, float (&in)[12]) {
-    const double* xp = a.xp + (long)P.c * ln;
+  // the 12 inputs of the point at chain pc, slice pl, site (pix, piy)
+  auto gather = [&](int pc, int pl, int pix, int piy, float (&in)[12]) {
+    const double* xp = a.xp + (long)pc * ln;
 #pragma unroll
     for (int st = 0; st < 12; ++st) {
-      const int p = 4 * st + q;
-      const int dl = p / 9 - 2, dy = (p % 9) / 3 - 1, dx = p % 3 - 1;
-      const int ll = (P.l + dl + L) % L;
-      const int j = (P.ix + dx + nx) % nx + nx * ((P.iy + dy + nx) % nx);
-      in[st] = (p < 45 && p != 22) ? (float)xp[(long)ll * n + j] : 0.0f;
+      int ll = pl + (pof[st] & 15) - 2, yy = piy + ((pof[st] >> 4) & 15) - 1, xx = pix + (pof[st] >> 8) - 1;
+      ll += (ll < 0) ? L : 0;
+      ll -= (ll >= L) ? L : 0;
+      yy += (yy < 0) ? nx : 0;
+      yy -= (yy >= nx) ? nx : 0;
+      xx += (xx < 0) ? nx : 0;
+      xx -= (xx >= nx) ? nx : 0;
+      in[st] = ((live >> st) & 1) ? (float)xp[ll * n + xx + nx * yy] : 0.0f;
     }
   };
 
-  long grp = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (grp >= groups) return;
-  Pt P = locate(grp);
-  float in[12];
-  gather(P, in);
-  for (; grp < groups; grp += nwave) {
-    // the next group's inputs are in flight while this one is evaluated
-    const long gn = grp + nwave < groups ? grp + nwave : grp;
-    const Pt Pn = locate(gn);
-    float inn[12];
-    gather(Pn, inn);
-
-    const int c = P.c, l = P.l, i = P.ix + nx * P.iy;
-    double* xp = a.xp + (long)c * ln;
+  for (long g0 = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); g0 < groups; g0 += 4 * nwave) {
+    // this lane's own point: point r of group g0 + q nwave (a spare lane past
+    // the class repeats the last point and decides nothing)
+    const long item0 = (g0 + q * nwave) * 16 + r;
+    const bool valid = item0 < total;
+    const long item = valid ? item0 : total - 1;
+    const int c = (int)(item / per_chain);
+    const int k = (int)(item - (long)c * per_chain);
+    const int l = cl + 4 * (k / per_slice);
+    const int rem = k % per_slice;
+    const int iy = py + 2 * (rem / hx), ix = px + 2 * (rem % hx);
+    const int i = ix + nx * iy;
     const long draw = (long)a.inner * ln + (long)l * n + i;
     const Philox4 rn = philox4x64_10((uint64_t)(a.chain0 + c), (uint64_t)(*a.sweep), (uint64_t)draw,
                                      KIND_NN, a.seed, 0);
     const double d = a.width * (2.0 * u53(rn.w[0]) - 1.0);
-    const float df = (float)d;
+    const double u1 = u53(rn.w[1]);
+    const int nk = (int)((groups - g0 + nwave - 1) / nwave) < 4 ? (int)((groups - g0 + nwave - 1) / nwave) : 4;
 
-    f4 h1[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      h1[t] = f4{0, 0, 0, 0};
-#pragma unroll
-      for (int st = 0; st < 12; ++st) h1[t] = mfma16(w1f[t][st], in[st], h1[t]);
-    }
-    float hp[4][4], hm[4][4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int o = 16 * t + 4 * q + v;
-        const float s0 = h1[t][v] + b1[o], wd = W1[o * 45 + 22] * df;
-        hp[t][v] = act(s0 + wd, ACT);
-        hm[t][v] = act(s0 - wd, ACT);
+    float in[12], inn[12];
+    gather(__shfl(c, r), __shfl(l, r), __shfl(ix, r), __shfl(iy, r), in);
+    float y_own = 0.0f;
+    for (int kk = 0; kk < nk; ++kk) {
+      // the next group's inputs are in flight while this one is evaluated
+      if (kk + 1 < nk) {
+        const int src = r + 16 * (kk + 1);
+        gather(__shfl(c, src), __shfl(l, src), __shfl(ix, src), __shfl(iy, src), inn);
       }
-    f4 op[4], om[4];
+      const float df = (float)__shfl(d, r + 16 * kk);
+
+      f4 h1[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      op[t] = f4{0, 0, 0, 0};
-      om[t] = f4{0, 0, 0, 0};
+      for (int t = 0; t < 4; ++t) {
+        h1[t] = f4{0, 0, 0, 0};
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+        for (int st = 0; st < 12; ++st) h1[t] = mfma16(w1f[t][st], in[st], h1[t]);
+      }
+      float hp[4][4], hm[4][4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          op[t] = mfma16(w2f[t][4 * u + v], hp[u][v], op[t]);
-          om[t] = mfma16(w2f[t][4 * u + v], hm[u][v], om[t]);
+          const int o = 16 * t + 4 * q + v;
+          const float s0 = h1[t][v] + b1[o], wd = W1[o * 45 + 22] * df;
+          hp[t][v] = act(s0 + wd, ACT);
+          hm[t][v] = act(s0 - wd, ACT);
         }
-    }
-    float fp = 0.0f, fm = 0.0f;
+      f4 op[4], om[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < 4; ++t) {
+        op[t] = f4{0, 0, 0, 0};
+        om[t] = f4{0, 0, 0, 0};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int o = 16 * t + 4 * q + v;
-        fp = fmaf(W3[o], act(op[t][v] + b2[o], ACT), fp);
-        fm = fmaf(W3[o], act(om[t][v] + b2[o], ACT), fm);
-      }
-    fp += __shfl_xor(fp, 16);
-    fm += __shfl_xor(fm, 16);
-    fp += __shfl_xor(fp, 32);
-    fm += __shfl_xor(fm, 32);
-    const float y = 0.5f * ((fp + b3) - (fm + b3));
-
-    if (q == 0 && P.valid) {
-      const double u1 = u53(rn.w[1]);
-      const double xa = xp[(long)l * n + i];
-      const double xprev = xp[(long)((l - 1 + L) % L) * n + i];
-      const double xnext = xp[(long)((l + 1) % L) * n + i];
-      const double g = a.g[c];
-      const double kin = (a.mass / a.dtau) * (d * (2.0 * xa - xprev - xnext) + d * d);
-      const double pot = a.dtau * 0.5 * a.mass * a.omega * a.omega * (2.0 * xa * d + d * d);
-      const double ds = kin + pot - a.dtau * g * d;
-      const double lr = (double)y - ds;
-      int acc = (u1 < exp(lr)) ? 1 : 0;
-      const double margin = log(u1) - lr;
-      const long slot = (long)c * a.nu * ln + draw;     // decision log and replay
-      if (a.replay) {
-        const uint8_t rp = a.replay[slot];
-        if (rp != 255) {
-          if (fabs(margin) <= a.band) {
-            if (acc != (int)rp) atomicAdd((unsigned long long*)&a.replay_counts[2 * c], 1ull);
-            acc = rp;
-          } else if (acc != (int)rp) {
-            atomicAdd((unsigned long long*)&a.replay_counts[2 * c + 1], 1ull);
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            op[t] = mfma16(w2f[t][4 * u + v], hp[u][v], op[t]);
+            om[t] = mfma16(w2f[t][4 * u + v], hm[u][v], om[t]);
           }
+      }
+      float fp = 0.0f, fm = 0.0f;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int o = 16 * t + 4 * q + v;
+          fp = fmaf(W3[o], act(op[t][v] + b2[o], ACT), fp);
+          fm = fmaf(W3[o], act(om[t][v] + b2[o], ACT), fm);
+        }
+      fp += __shfl_xor(fp, 16);
+      fm += __shfl_xor(fm, 16);
+      fp += __shfl_xor(fp, 32);
+      fm += __shfl_xor(fm, 32);
+      const float y = 0.5f * ((fp + b3) - (fm + b3));
+      y_own = (q == kk) ? y : y_own;
+#pragma unroll
+      for (int st = 0; st < 12; ++st) in[st] = inn[st];
+    }
+    if (!valid) continue;
+
+    double* xp = a.xp + (long)c * ln;
+    const double xa = xp[(long)l * n + i];
+    const double xprev = xp[(long)((l - 1 + L) % L) * n + i];
+    const double xnext = xp[(long)((l + 1) % L) * n + i];
+    const double g = a.g[c];
+    const double kin = (a.mass / a.dtau) * (d * (2.0 * xa - xprev - xnext) + d * d);
+    const double pot = a.dtau * 0.5 * a.mass * a.omega * a.omega * (2.0 * xa * d + d * d);
+    const double ds = kin + pot - a.dtau * g * d;
+    const double lr = (double)y_own - ds;
+    int acc = (u1 < exp(lr)) ? 1 : 0;
+    const double margin = log(u1) - lr;
+    const long slot = (long)c * a.nu * ln + draw;       // decision log and replay
+    if (a.replay) {
+      const uint8_t rp = a.replay[slot];
+      if (rp != 255) {
+        if (fabs(margin) <= a.band) {
+          if (acc != (int)rp) atomicAdd((unsigned long long*)&a.replay_counts[2 * c], 1ull);
+          acc = rp;
+        } else if (acc != (int)rp) {
+          atomicAdd((unsigned long long*)&a.replay_counts[2 * c + 1], 1ull);
         }
       }
-      if (a.log_margin) { a.log_margin[slot] = (float)margin; a.log_accept[slot] = (uint8_t)acc; }
-      const long s2 = (long)c * ln + (long)l * n + i;
-      if (acc) {
-        a.sum_y[s2] += (double)y;
-        a.accepted[s2] += 1;
-        xp[(long)l * n + i] = xa + d;
-      }
     }
-    P = Pn;
-#pragma unroll
-    for (int st = 0; st < 12; ++st) in[st] = inn[st];
+    if (a.log_margin) { a.log_margin[slot] = (float)margin; a.log_accept[slot] = (uint8_t)acc; }
+    const long s2 = (long)c * ln + (long)l * n + i;
+    if (acc) {
+      a.sum_y[s2] += (double)y_own;
+      a.accepted[s2] += 1;
+      xp[(long)l * n + i] = xa + d;
+    }
   }
 }
 
