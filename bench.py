@@ -368,7 +368,7 @@ def autocorr_run(w, sweeps, warmup):
 
 def dtype_of(w):
     """The arithmetic the path computes in: network groups infer in FP32 and
-    judge with the FP64 determinant; mixed precision wraps and updates in FP32
+    accept with the FP64 determinant; mixed precision wraps and updates in FP32
     and stabilises in FP64."""
     if any(g.proposal == 1 for g in w.groups):
         return "f32 network + f64 determinant"
