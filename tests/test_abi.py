@@ -92,3 +92,12 @@ def test_create_static_validates_before_any_device_call(lib):
     assert lib.hq_create_static(big, 1, ctypes.byref(opt), 1, ctypes.c_void_p(1), ctypes.byref(out)) == hq.HQ_ENOMEM
     assert b"static workspace holds 67108864" in lib.hq_last_error(None)
     assert not out.value
+
+
+def test_tile_codes_match_the_library(lib):
+    """The binding's tile count is the library's: every code below it has a
+    name, the first code past it none (hq_gemm_tile_name is host-only)."""
+    names = [hq.tile_name(k) for k in range(hq.N_GEMM_TILES)]
+    assert "?" not in names and len(set(names)) == hq.N_GEMM_TILES
+    assert hq.tile_name(hq.N_GEMM_TILES) == "?"
+    assert hq.tile_name(-1) == "?"
