@@ -680,7 +680,9 @@ hq_status tree_product(Sched& S, Group& g, const double* blocks, Udt& out) {
 // buffer, which the pairwise merges factor in place.
 hq_status from_scratch(Sched& S, Group& g, const double* xs, double* blocks) {
   const long nn = (long)g.n * g.n;
-  ST_TRY(block_products(S, g, xs, blocks, 0, g.blks, 0, g.nb));
+  // chain stride nb n^2: the layout [C][nb][n][n] also when nb = 1 (with one
+  // block per chain the products are written per chain at this stride)
+  ST_TRY(block_products(S, g, xs, blocks, (long)g.nb * nn, g.blks, 0, g.nb));
   if (g.tree) {
     Udt l;
     ST_TRY(tree_product(S, g, blocks, l));

@@ -89,8 +89,11 @@ def oracle_local_bits(ch, sweep):
 
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("nx,beta,ns,prec", [(2, 1.0, 5, 0), (4, 4.0, 10, 0), (8, 8.0, 8, 0),
-                                             (10, 2.0, 10, 0), (12, 2.0, 10, 1), (6, 0.2, 1, 0)])
+                                             (10, 2.0, 10, 0), (12, 2.0, 10, 1), (6, 0.2, 1, 0),
+                                             (4, 1.0, 10, 0)])
 def test_initial_state(hq, nx, beta, ns, prec):
+    """Fields, G and log det at creation against the oracle; the last case has
+    one block per chain (L = n_stab) with two chains."""
     say("initial state nx=%d beta=%g ns=%d prec=%d" % (nx, beta, ns, prec))
     gr = dict(nx=nx, chains=2, g=1.1, beta=beta, n_stab=ns)
     ctx = make_ctx(hq, [gr], precision=prec, seed=7)
@@ -703,13 +706,14 @@ def test_network_block_moves_and_inner_sweeps(hq, nu):
     ctx.close()
 
 
-@pytest.mark.parametrize("kind", [0, 1])
-def test_network_proposals_and_cumulative_update(hq, kind):
-    """Network-proposed sweeps on 4x4 (L = 8), ReLU and softplus networks:
-    inner decisions replayed inside the tie band (FP32 network vs the oracle's
-    FP64 forward), cumulative accepts compared."""
-    say("network proposals 4x4, activation %d" % kind)
-    gr = dict(nx=4, chains=2, g=1.2, beta=0.8, n_stab=4, proposal=1)
+@pytest.mark.parametrize("kind,nx,beta", [(0, 4, 0.8), (1, 4, 0.8), (0, 2, 0.4)])
+def test_network_proposals_and_cumulative_update(hq, kind, nx, beta):
+    """Network-proposed sweeps on 4x4 (L = 8), ReLU and softplus networks, and
+    on 2x2 with L = 4 (every patch wraps around in space and time): inner
+    decisions replayed inside the tie band (FP32 network vs the oracle's FP64
+    forward), cumulative accepts compared."""
+    say("network proposals %dx%d, activation %d" % (nx, nx, kind))
+    gr = dict(nx=nx, chains=2, g=1.2, beta=beta, n_stab=4, proposal=1)
     w = workloads.random_network(17, scale=0.1)
     ctx = make_ctx(hq, [gr], seed=6, activation=kind)
     ctx.set_network(w)
