@@ -575,18 +575,25 @@ def test_uneven_groups_per_chain_coupling(hq):
     ctx.close()
 
 
-@pytest.mark.parametrize("case", ["atomic", "free", "nx2", "two_slices"])
+@pytest.mark.parametrize("case", ["atomic", "free", "nx2", "two_slices", "one_block", "one_block_global"])
 def test_edge_cases(hq, case):
+    """Degenerate lattices and slicings, every chain against the oracle after
+    an upward and a downward sweep (one_block: L = n_stab, a single block per
+    chain, with three chains; one_block_global: the same with block moves,
+    whose determinants come from scratch)."""
     say("edge case %s" % case)
     gr = {"atomic": dict(nx=3, chains=1, t=0.0, beta=1.0, n_stab=5, g=1.3),
           "free": dict(nx=4, chains=1, g=0.0, beta=2.0, n_stab=5),
-          "nx2": dict(nx=2, chains=1, beta=2.0, n_stab=4, g=1.0, mu=0.3),
-          "two_slices": dict(nx=4, chains=1, beta=0.2, n_stab=1, g=1.0)}[case]
+          "nx2": dict(nx=2, chains=2, beta=2.0, n_stab=4, g=1.0, mu=0.3),
+          "two_slices": dict(nx=4, chains=2, beta=0.2, n_stab=1, g=1.0),
+          "one_block": dict(nx=3, chains=3, beta=1.0, n_stab=10, g=1.2),
+          "one_block_global": dict(nx=3, chains=2, beta=1.0, n_stab=10, g=1.2, global_width=1.0)}[case]
     ctx = make_ctx(hq, [gr], seed=5)
     ctx.sweep(2)
-    ch = dqmc.Chain(params_of(gr), 5, 0)
-    ch.sweep(); ch.sweep()
-    assert_state(ctx, 0, ch, TOL64, case)
+    for c in range(gr["chains"]):
+        ch = dqmc.Chain(params_of(gr), 5, c)
+        ch.sweep(); ch.sweep()
+        assert_state(ctx, c, ch, TOL64, "%s chain %d" % (case, c))
     ctx.close()
 
 
