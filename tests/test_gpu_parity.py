@@ -202,22 +202,31 @@ def _mixed_replay_case(hq, gr, chains_to_check, seed, sweeps=1, setup=None, dela
     ctx.close()
 
 
+def test_mixed_one_block(hq):
+    """Mixed precision with one block per chain (L = n_stab) and two chains:
+    the recompute at the end of the only block, upward and downward."""
+    say("mixed 6x6, L = n_stab")
+    _mixed_replay_case(hq, dict(nx=6, chains=2, g=1.2, beta=1.0, n_stab=10), (0, 1), seed=21, sweeps=2, delay=16)
+
+
 def test_mixed_12x12_small(hq):
     say("12x12 mixed, beta=2")
     _mixed_replay_case(hq, dict(nx=12, chains=2, g=1.5, beta=2.0, n_stab=10), (0, 1), seed=3, sweeps=2)
 
 
-@pytest.mark.parametrize("nx", [13, 16])
+@pytest.mark.parametrize("nx", [13, 15, 16])
 def test_large_lattice_fp64(hq, nx):
-    """N = 169 (panels with a ragged last one) and 256 in FP64: the streamed
-    local form and the L2-resident QR and Gauss-Jordan kernels."""
+    """N = 169 and 225 (panels with a ragged last one) and 256 in FP64, two
+    chains: the streamed local form and the factorizations spread over
+    several workgroups per matrix."""
     say("FP64 %dx%d" % (nx, nx))
-    gr = dict(nx=nx, chains=1, g=1.1, beta=0.4, n_stab=2)
+    gr = dict(nx=nx, chains=2, g=1.1, beta=0.4, n_stab=2)
     ctx = make_ctx(hq, [gr], seed=12)
     ctx.sweep(2)
-    ch = dqmc.Chain(params_of(gr), 12, 0)
-    ch.sweep(); ch.sweep()
-    assert_state(ctx, 0, ch, TOL64, "%dx%d" % (nx, nx))
+    for c in range(2):
+        ch = dqmc.Chain(params_of(gr), 12, c)
+        ch.sweep(); ch.sweep()
+        assert_state(ctx, c, ch, TOL64, "%dx%d chain %d" % (nx, nx, c))
     ctx.close()
 
 
