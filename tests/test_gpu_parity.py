@@ -236,12 +236,13 @@ def test_block_product_chunks_16x16(hq, ns):
     one Kronecker chain launch holds: block products in two chunks (8 + 1,
     8 + 2) through the scratch buffer."""
     say("FP64 16x16 n_stab=%d" % ns)
-    gr = dict(nx=16, chains=1, g=1.1, beta=0.1 * 2 * ns, n_stab=ns)
+    gr = dict(nx=16, chains=2, g=1.1, beta=0.1 * 2 * ns, n_stab=ns)
     ctx = make_ctx(hq, [gr], seed=19)
     ctx.sweep(2)
-    ch = dqmc.Chain(params_of(gr), 19, 0)
-    ch.sweep(); ch.sweep()
-    assert_state(ctx, 0, ch, TOL64, "16x16 n_stab=%d" % ns)
+    for c in range(2):
+        ch = dqmc.Chain(params_of(gr), 19, c)
+        ch.sweep(); ch.sweep()
+        assert_state(ctx, c, ch, TOL64, "16x16 n_stab=%d chain %d" % (ns, c))
     ctx.close()
 
 
@@ -252,7 +253,7 @@ def test_mixed_16x16(hq, delay):
     form the 16x16 chains of the uneven batch take); at delay 32 it is
     streamed from global memory."""
     say("16x16 mixed, delay %d" % delay)
-    _mixed_replay_case(hq, dict(nx=16, chains=1, g=1.2, beta=0.4, n_stab=2), (0,), seed=8, sweeps=2, delay=delay,
+    _mixed_replay_case(hq, dict(nx=16, chains=2, g=1.2, beta=0.4, n_stab=2), (0, 1), seed=8, sweeps=2, delay=delay,
                        drift_gate=True)
 
 
@@ -391,7 +392,7 @@ def test_fused_wrap_fp64(hq, nx):
 @pytest.mark.parametrize("nx", [5, 12])
 def test_fused_wrap_mixed(hq, nx):
     say("mixed fused wrap nx=%d" % nx)
-    _mixed_replay_case(hq, dict(nx=nx, chains=1, g=1.3, beta=0.9, n_stab=3), (0,), seed=16, sweeps=2,
+    _mixed_replay_case(hq, dict(nx=nx, chains=2, g=1.3, beta=0.9, n_stab=3), (0, 1), seed=16, sweeps=2,
                        setup=lambda ctx: ctx.set_tuning(0, 0, 0, wrap="fused"))
 
 
@@ -416,7 +417,7 @@ def test_kron_wrap_fp64(hq, nx):
 @pytest.mark.parametrize("nx", [5, 12, 16])
 def test_kron_wrap_mixed(hq, nx):
     say("mixed Kronecker wrap nx=%d" % nx)
-    _mixed_replay_case(hq, dict(nx=nx, chains=1, g=1.3, beta=0.9, n_stab=3), (0,), seed=18, sweeps=2,
+    _mixed_replay_case(hq, dict(nx=nx, chains=2, g=1.3, beta=0.9, n_stab=3), (0, 1), seed=18, sweeps=2,
                        setup=lambda ctx: ctx.set_tuning(0, 0, 0, wrap="kron"))
 
 
@@ -441,7 +442,7 @@ def test_kron_lds_wrap_fp64(hq, nx):
 @pytest.mark.parametrize("nx", [5, 11, 12])
 def test_kron_lds_wrap_mixed(hq, nx):
     say("mixed LDS Kronecker wrap nx=%d" % nx)
-    _mixed_replay_case(hq, dict(nx=nx, chains=1, g=1.3, beta=0.9, n_stab=3), (0,), seed=21, sweeps=2,
+    _mixed_replay_case(hq, dict(nx=nx, chains=2, g=1.3, beta=0.9, n_stab=3), (0, 1), seed=21, sweeps=2,
                        setup=lambda ctx: ctx.set_tuning(0, 0, 0, wrap="kron_lds"))
 
 
