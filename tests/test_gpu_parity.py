@@ -585,19 +585,22 @@ def test_uneven_groups_per_chain_coupling(hq):
     ctx.close()
 
 
-@pytest.mark.parametrize("case", ["atomic", "free", "nx2", "two_slices", "one_block", "one_block_global"])
+@pytest.mark.parametrize("case", ["atomic", "free", "nx2", "two_slices", "one_block", "one_block_global",
+                                  "three_blocks_global"])
 def test_edge_cases(hq, case):
     """Degenerate lattices and slicings, every chain against the oracle after
     an upward and a downward sweep (one_block: L = n_stab, a single block per
     chain, with three chains; one_block_global: the same with block moves,
-    whose determinants come from scratch)."""
+    whose determinants come from scratch; three_blocks_global: a pairwise
+    tree with an unpaired block)."""
     say("edge case %s" % case)
     gr = {"atomic": dict(nx=3, chains=1, t=0.0, beta=1.0, n_stab=5, g=1.3),
           "free": dict(nx=4, chains=1, g=0.0, beta=2.0, n_stab=5),
           "nx2": dict(nx=2, chains=2, beta=2.0, n_stab=4, g=1.0, mu=0.3),
           "two_slices": dict(nx=4, chains=2, beta=0.2, n_stab=1, g=1.0),
           "one_block": dict(nx=3, chains=3, beta=1.0, n_stab=10, g=1.2),
-          "one_block_global": dict(nx=3, chains=2, beta=1.0, n_stab=10, g=1.2, global_width=1.0)}[case]
+          "one_block_global": dict(nx=3, chains=2, beta=1.0, n_stab=10, g=1.2, global_width=1.0),
+          "three_blocks_global": dict(nx=4, chains=2, beta=0.6, n_stab=2, g=1.2, global_width=1.0)}[case]
     ctx = make_ctx(hq, [gr], seed=5)
     ctx.sweep(2)
     for c in range(gr["chains"]):
@@ -723,10 +726,11 @@ def test_network_block_moves_and_inner_sweeps(hq, nu):
     ctx.close()
 
 
-@pytest.mark.parametrize("kind,nx,beta", [(0, 4, 0.8), (1, 4, 0.8), (0, 2, 0.4)])
+@pytest.mark.parametrize("kind,nx,beta", [(0, 4, 0.8), (1, 4, 0.8), (0, 2, 0.4), (0, 4, 1.2)])
 def test_network_proposals_and_cumulative_update(hq, kind, nx, beta):
-    """Network-proposed sweeps on 4x4 (L = 8), ReLU and softplus networks, and
-    on 2x2 with L = 4 (every patch wraps around in space and time): inner
+    """Network-proposed sweeps on 4x4 (L = 8), ReLU and softplus networks, on
+    2x2 with L = 4 (every patch wraps around in space and time, one block per
+    chain) and on 4x4 with L = 12 (three blocks: a tree with an unpaired one): inner
     decisions replayed inside the tie band (FP32 network vs the oracle's FP64
     forward), cumulative accepts compared."""
     say("network proposals %dx%d, activation %d" % (nx, nx, kind))
