@@ -585,6 +585,26 @@ def test_uneven_groups_per_chain_coupling(hq):
     ctx.close()
 
 
+def test_uneven_groups_shapes_and_directions(hq):
+    """Three lattice groups of different N, L and n_stab (one block per chain,
+    three blocks, four blocks) as parallel branches of one captured sweep, an
+    upward and a downward sweep, every chain against the oracle."""
+    say("uneven groups 4x4 / 6x6 / 3x3, mixed shapes")
+    groups = [dict(nx=4, chains=2, beta=1.0, n_stab=10, g=1.2),
+              dict(nx=6, chains=3, beta=1.2, n_stab=4, g=1.1),
+              dict(nx=3, chains=2, beta=0.8, n_stab=2, g=1.3)]
+    ctx = make_ctx(hq, groups, seed=9)
+    ctx.sweep(2)
+    chain = 0
+    for gr in groups:
+        for _ in range(gr["chains"]):
+            ch = dqmc.Chain(params_of(gr), 9, chain)
+            ch.sweep(); ch.sweep()
+            assert_state(ctx, chain, ch, TOL64, "group nx=%d chain %d" % (gr["nx"], chain))
+            chain += 1
+    ctx.close()
+
+
 @pytest.mark.parametrize("case", ["atomic", "free", "nx2", "two_slices", "one_block", "one_block_global",
                                   "three_blocks_global"])
 def test_edge_cases(hq, case):
