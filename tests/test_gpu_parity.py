@@ -209,6 +209,15 @@ def test_mixed_one_block(hq):
     _mixed_replay_case(hq, dict(nx=6, chains=2, g=1.2, beta=1.0, n_stab=10), (0, 1), seed=21, sweeps=2, delay=16)
 
 
+def test_mixed_delay8_streamed(hq):
+    """Mixed precision with blocks of 8 sites (the streamed local form: the
+    register form takes blocks of 16 and 32 only), two chains, both sweep
+    directions."""
+    say("mixed 8x8, delay 8")
+    _mixed_replay_case(hq, dict(nx=8, chains=2, g=1.3, beta=1.2, n_stab=6), (0, 1), seed=23, sweeps=2, delay=8,
+                       drift_gate=True)
+
+
 def test_mixed_12x12_small(hq):
     say("12x12 mixed, beta=2")
     _mixed_replay_case(hq, dict(nx=12, chains=2, g=1.5, beta=2.0, n_stab=10), (0, 1), seed=3, sweeps=2)
