@@ -615,13 +615,14 @@ def test_uneven_groups_shapes_and_directions(hq):
 
 
 @pytest.mark.parametrize("case", ["atomic", "free", "nx2", "two_slices", "one_block", "one_block_global",
-                                  "three_blocks_global"])
+                                  "three_blocks_global", "phonon_params"])
 def test_edge_cases(hq, case):
     """Degenerate lattices and slicings, every chain against the oracle after
     an upward and a downward sweep (one_block: L = n_stab, a single block per
     chain, with three chains; one_block_global: the same with block moves,
     whose determinants come from scratch; three_blocks_global: a pairwise
-    tree with an unpaired block)."""
+    tree with an unpaired block; phonon_params: mass, frequency, chemical
+    potential, time step and move widths away from their defaults)."""
     say("edge case %s" % case)
     gr = {"atomic": dict(nx=3, chains=1, t=0.0, beta=1.0, n_stab=5, g=1.3),
           "free": dict(nx=4, chains=1, g=0.0, beta=2.0, n_stab=5),
@@ -629,7 +630,9 @@ def test_edge_cases(hq, case):
           "two_slices": dict(nx=4, chains=2, beta=0.2, n_stab=1, g=1.0),
           "one_block": dict(nx=3, chains=3, beta=1.0, n_stab=10, g=1.2),
           "one_block_global": dict(nx=3, chains=2, beta=1.0, n_stab=10, g=1.2, global_width=1.0),
-          "three_blocks_global": dict(nx=4, chains=2, beta=0.6, n_stab=2, g=1.2, global_width=1.0)}[case]
+          "three_blocks_global": dict(nx=4, chains=2, beta=0.6, n_stab=2, g=1.2, global_width=1.0),
+          "phonon_params": dict(nx=4, chains=2, beta=1.0, n_stab=4, g=0.9, mass=2.0, omega=0.5, mu=-0.4,
+                                dtau=0.125, local_width=0.8, global_width=0.7)}[case]
     ctx = make_ctx(hq, [gr], seed=5)
     ctx.sweep(2)
     for c in range(gr["chains"]):
