@@ -758,15 +758,17 @@ def test_network_block_moves_and_inner_sweeps(hq, nu):
     ctx.close()
 
 
-@pytest.mark.parametrize("kind,nx,beta", [(0, 4, 0.8), (1, 4, 0.8), (0, 2, 0.4), (0, 4, 1.2)])
-def test_network_proposals_and_cumulative_update(hq, kind, nx, beta):
+@pytest.mark.parametrize("kind,nx,beta,extra", [(0, 4, 0.8, {}), (1, 4, 0.8, {}), (0, 2, 0.4, {}), (0, 4, 1.2, {}),
+                                                 (0, 4, 0.8, dict(mass=1.5, omega=0.7, mu=0.2, local_width=0.9))])
+def test_network_proposals_and_cumulative_update(hq, kind, nx, beta, extra):
     """Network-proposed sweeps on 4x4 (L = 8), ReLU and softplus networks, on
     2x2 with L = 4 (every patch wraps around in space and time, one block per
-    chain) and on 4x4 with L = 12 (three blocks: a tree with an unpaired one): inner
+    chain), on 4x4 with L = 12 (three blocks: a tree with an unpaired one), and
+    with non-default phonon mass, frequency, chemical potential and width: inner
     decisions replayed inside the tie band (FP32 network vs the oracle's FP64
     forward), cumulative accepts compared."""
     say("network proposals %dx%d, activation %d" % (nx, nx, kind))
-    gr = dict(nx=nx, chains=2, g=1.2, beta=beta, n_stab=4, proposal=1)
+    gr = dict(nx=nx, chains=2, g=1.2, beta=beta, n_stab=4, proposal=1, **extra)
     w = workloads.random_network(17, scale=0.1)
     ctx = make_ctx(hq, [gr], seed=6, activation=kind)
     ctx.set_network(w)
