@@ -326,8 +326,9 @@ def autocorr_run(w, sweeps, warmup):
         e1.record(stream)
         e1.synchronize()
         t_ms += e0.elapsed_time(e1)
-        for c in range(C):
-            series[c, s] = ctx.stats(c)["s_cdw"]
+        series[:, s] = ctx.observables()[:, 2]
+        if (s + 1) % 1024 == 0:
+            print("autocorr: %d of %d sweeps" % (s + 1, sweeps), file=sys.stderr, flush=True)
     # a chain that never accepts a move has no autocorrelation to speak of:
     # report how often the moves that change the fields were accepted
     acc = {"local": [0, 0], "block": [0, 0], "cumulative": [0, 0]}

@@ -216,6 +216,14 @@ hq_status hq_read_green(hq_ctx* ctx, int32_t chain, double* out, int64_t n);
 hq_status hq_read_green_tracked(hq_ctx* ctx, int32_t chain, double* out, int64_t n, double* logdet);
 hq_status hq_read_fields(hq_ctx* ctx, int32_t chain, double* out, int64_t n);
 hq_status hq_read_stats(hq_ctx* ctx, int32_t chain, hq_stats* out);
+/* The equal-time observables of section "Benchmarks" for every chain at once
+ * (one launch per lattice group, one copy per group; synchronises the
+ * stream): out[5c + k] for chain c = 0 .. chains-1 and k = density, double
+ * occupancy, S_CDW(pi, pi), mean of x, mean of x^2, the same values as the
+ * fields of hq_read_stats.  out: host array of n = 5 * chains doubles,
+ * caller-owned.  HQ_EINVAL for a null out or another n; HQ_ENUMERIC if a
+ * chain's G holds a non-finite value (out is filled all the same). */
+hq_status hq_read_observables(hq_ctx* ctx, double* out, int64_t n);
 
 /* Decisions of the last sweep for one chain and kind, in slot order (local:
  * l*N + i; network local moves: u*L*N + l*N + i and network block moves:

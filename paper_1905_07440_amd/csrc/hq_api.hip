@@ -1805,6 +1805,32 @@ hq_status hq_read_stats(hq_ctx* ctx, int32_t chain, hq_stats* out) {
   return HQ_OK;
 }
 
+hq_status hq_read_observables(hq_ctx* ctx, double* out, int64_t n) {
+  ST_TRY(check_ctx(ctx));
+  if (!out || n != 5L * ctx->n_chains)
+    return fail(ctx, HQ_EINVAL, "observables: out must hold 5 values for each of the %d chains", ctx->n_chains);
+  for (Group& g : ctx->groups) {
+    ObsArgs a;                              // every chain of the group
+    a.n = g.n; a.L = g.L; a.nx = g.nx;
+    a.G = g.G; a.precision = ctx->opt.precision; a.x = g.x;
+    a.out = g.obs; a.flags = g.flags; a.logdet = g.logdet;
+    HQ_TRY(launch_observables(a, g.C, ctx->stream));
+  }
+  ST_TRY(sync(ctx));
+  long off = 0;
+  int bad = -1;
+  for (Group& g : ctx->groups) {
+    HQ_TRY(hipMemcpy(out + 5 * off, g.obs, sizeof(double) * 5 * g.C, hipMemcpyDeviceToHost));
+    std::vector<int> fl(g.C);
+    HQ_TRY(hipMemcpy(fl.data(), g.flags, sizeof(int) * g.C, hipMemcpyDeviceToHost));
+    for (int c = 0; c < g.C && bad < 0; ++c)
+      if (fl[c] & 1) bad = (int)off + c;
+    off += g.C;
+  }
+  if (bad >= 0) return fail(ctx, HQ_ENUMERIC, "non-finite G or log det in chain %d", bad);
+  return HQ_OK;
+}
+
 hq_status hq_read_decisions(hq_ctx* ctx, int32_t chain, int32_t kind, uint8_t* accept, float* margin, int64_t n) {
   ST_TRY(check_ctx(ctx));
   int lc = 0;

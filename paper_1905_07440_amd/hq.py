@@ -84,7 +84,7 @@ def tile_name(code):
 
 EXPORTS = [
     "hq_workspace_bytes", "hq_create", "hq_create_static", "hq_set_fields", "hq_set_network", "hq_set_block_network", "hq_sweep",
-    "hq_recompute", "hq_read_green", "hq_read_green_tracked", "hq_read_fields", "hq_read_stats", "hq_read_decisions",
+    "hq_recompute", "hq_read_green", "hq_read_green_tracked", "hq_read_fields", "hq_read_stats", "hq_read_observables", "hq_read_decisions",
     "hq_set_replay", "hq_num_chains", "hq_chain_shape", "hq_set_profiling", "hq_phase_time",
     "hq_read_tuning", "hq_set_tuning", "hq_gemm_tile_name", "hq_synchronize", "hq_last_error", "hq_destroy",
 ]
@@ -116,6 +116,7 @@ def load(path=LIB_PATH):
     lib.hq_read_green_tracked.argtypes = [P, I32, P, I64, P]
     lib.hq_read_fields.argtypes = [P, I32, P, I64]
     lib.hq_read_stats.argtypes = [P, I32, ctypes.POINTER(Stats)]
+    lib.hq_read_observables.argtypes = [P, P, I64]
     lib.hq_read_decisions.argtypes = [P, I32, I32, P, P, I64]
     lib.hq_set_replay.argtypes = [P, I32, I32, P, I64, D]
     lib.hq_num_chains.argtypes = [P]
@@ -250,6 +251,15 @@ class Context:
         if st not in (HQ_OK, HQ_ENUMERIC):
             self._check(st)
         return s.as_dict()
+
+    def observables(self):
+        """[chains][5] FP64: density, double occupancy, S_CDW(pi, pi), mean x,
+        mean x^2 of every chain from the current G and fields, in one pass."""
+        out = np.zeros((self.n_chains, 5))
+        st = self._lib.hq_read_observables(self._ctx, out.ctypes.data, out.size)
+        if st not in (HQ_OK, HQ_ENUMERIC):
+            self._check(st)
+        return out
 
     def _inner_sweeps(self, chain):
         k = 0

@@ -642,6 +642,25 @@ def test_edge_cases(hq, case):
     ctx.close()
 
 
+def test_batched_observables_match_per_chain(hq):
+    """hq_read_observables over two lattice groups (FP64 and a mixed context)
+    gives each chain's five values exactly as hq_read_stats does."""
+    say("batched observables")
+    for prec in (0, 1):
+        groups = [dict(nx=4, chains=3, beta=1.0, n_stab=5, g=1.2), dict(nx=6, chains=2, beta=1.0, n_stab=5, g=1.1)]
+        ctx = make_ctx(hq, groups, precision=prec, seed=3)
+        ctx.sweep(1)
+        ob = ctx.observables()
+        assert ob.shape == (5, 5)
+        for c in range(5):
+            st = ctx.stats(c)
+            ref = [st["density"], st["double_occupancy"], st["s_cdw"], st["x_mean"], st["x2_mean"]]
+            assert np.array_equal(ob[c], np.array(ref)), "precision %d chain %d" % (prec, c)
+        with pytest.raises(hq.HQError):
+            ctx._check(ctx._lib.hq_read_observables(ctx._ctx, ob.ctypes.data, 24))
+        ctx.close()
+
+
 def test_observables_match_oracle(hq):
     say("observables")
     gr = dict(nx=4, chains=1, g=1.0, beta=2.0, n_stab=5)
