@@ -562,8 +562,8 @@ hq_status merge(Sched& S, Group& g, const double* UL, long sUL, const double* DL
                 const double* UR, long sUR, const double* DR, long sDR, const double* TR, long sTR) {
   const long nn = (long)g.n * g.n;
   const int n = g.n;
-  SCHED_TRY(launch_dsplit(DL, g.dLbinv, g.dLs, g.sumlog, 0, n, g.C, S.s));
   if (!UR) {
+    SCHED_TRY(launch_dsplit(DL, g.dLbinv, g.dLs, g.sumlog, 0, n, g.C, S.s));
     // right part the identity (a from-scratch recompute): M = Db_L^-1 U_L^T + Ds_L T_L
     // elementwise, and G = Minv U_L^T straight into Gnew
     SCHED_TRY(launch_merge_identity(UL, sUL, TL, sTL, g.dLbinv, g.dLs, g.M, n, g.C, S.s));
@@ -577,7 +577,7 @@ hq_status merge(Sched& S, Group& g, const double* UL, long sUL, const double* DL
   }
   // D_R may be strided (right stack); dsplit wants [C][n] contiguous
   if (sDR != n) return fail(S.ctx, HQ_EINVAL, "internal: strided D_R");
-  SCHED_TRY(launch_dsplit(DR, g.dRbinv, g.dRs, g.sumlog, 1, n, g.C, S.s));
+  SCHED_TRY(launch_dsplit2(DL, g.dLbinv, g.dLs, DR, g.dRbinv, g.dRs, g.sumlog, n, g.C, S.s));
   const double *rb = g.dRbinv, *rs_ = g.dRs;
   GemmArgs<double> a = sq(g, g.C);                 // M = Db_L^-1 (U_L^T U_R) Db_R^-1
   a.A = UL; a.sA = sUL; a.tA = 1;

@@ -196,6 +196,8 @@ bool gj_supported(int n);
 // ---------------------------------------------------------------------------
 hipError_t launch_identity(double* U, double* D, double* T, int n, int batch, hipStream_t s);
 // dbinv = 1/max(D,1), ds = min(D,1), sumlog[z] (+)= sum log max(D,1)
+hipError_t launch_dsplit2(const double* DL, double* lbinv, double* ls, const double* DR, double* rbinv, double* rs,
+                          double* sumlog, int n, int batch, hipStream_t s);
 hipError_t launch_dsplit(const double* D, double* dbinv, double* ds, double* sumlog, int accumulate,
                          int n, int batch, hipStream_t s);
 // M = diag(dbinv) U^T + diag(ds) T per chain ([batch] n x n, U and T with chain strides sU, sT)

@@ -46,6 +46,35 @@ hipError_t launch_dsplit(const double* D, double* dbinv, double* ds, double* sum
   return hipGetLastError();
 }
 
+// both splits of a merge in one launch: sumlog = sum log Db_L + sum log Db_R,
+// the two sums formed as the two launches of dsplit_kernel form them
+__global__ void dsplit2_kernel(const double* DL, double* lbinv, double* ls, const double* DR, double* rbinv,
+                               double* rs, double* sumlog, int n) {
+  __shared__ double red[4];
+  const int z = blockIdx.x;
+  double sl = 0.0, sr = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const long e = (long)z * n + i;
+    const double dl = DL[e], dr = DR[e];
+    const double bl = fmax(dl, 1.0), br = fmax(dr, 1.0);
+    lbinv[e] = 1.0 / bl;
+    ls[e] = fmin(dl, 1.0);
+    rbinv[e] = 1.0 / br;
+    rs[e] = fmin(dr, 1.0);
+    sl += log(bl);
+    sr += log(br);
+  }
+  sl = block_sum<256>(sl, red);
+  sr = block_sum<256>(sr, red);
+  if (threadIdx.x == 0) sumlog[z] = (0.0 + sl) + sr;
+}
+
+hipError_t launch_dsplit2(const double* DL, double* lbinv, double* ls, const double* DR, double* rbinv, double* rs,
+                          double* sumlog, int n, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(dsplit2_kernel, dim3(batch), dim3(256), 0, s, DL, lbinv, ls, DR, rbinv, rs, sumlog, n);
+  return hipGetLastError();
+}
+
 // M = diag(dbinv) U^T + diag(ds) T for every chain (the merge matrix when the
 // right factor is the identity), U read through 32 x 32 LDS tiles so that
 // both reads and the write are row-contiguous
