@@ -695,12 +695,19 @@ def test_set_fields_and_recompute(hq):
     ctx.close()
 
 
-def test_bitwise_deterministic(hq):
-    say("determinism")
-    gr = dict(nx=8, chains=2, g=1.2, beta=2.0, n_stab=4, global_width=0.5)
+@pytest.mark.parametrize("nx,precision,extra", [(8, 0, dict(global_width=0.5)), (12, 1, {})])
+def test_bitwise_deterministic(hq, nx, precision, extra):
+    """The same seed and the same kernel choices give the same bits.  The
+    autotuner picks GEMM tiles and the delayed-update block from timings, and
+    different tiles or blocks sum in different orders, so both contexts are
+    pinned to one choice, with G recomputed under it, before the sweeps."""
+    say("determinism nx=%d precision=%d" % (nx, precision))
+    gr = dict(nx=nx, chains=2, g=1.2, beta=2.0, n_stab=4, **extra)
     out = []
     for _ in range(2):
-        ctx = make_ctx(hq, [gr], seed=21)
+        ctx = make_ctx(hq, [gr], seed=21, precision=precision, delay=16)
+        ctx.set_tuning(0, 0, 0)        # 64x64 tiles for every product, two-pass wrap
+        ctx.recompute()
         ctx.sweep(2)
         out.append((ctx.fields(1), ctx.green(1), ctx.stats(1)["logdet"]))
         ctx.close()
