@@ -611,9 +611,10 @@ __global__ __launch_bounds__(256) void qr_blocked_kernel(double* __restrict__ Zg
 // waves hold it as 16 x 16 MFMA tiles, wave w owning tile columns w, w + 4,
 // w + 8.  A panel passes through LDS once to be factored by the four waves;
 // the block reflector is applied to the tiles in place, so the trailing
-// update touches no memory but the 16-column reflector.  Q is accumulated in the same
-// registers afterwards.  V and T of every panel go to W and T in global
-// memory for that second pass.
+// update touches no memory but the 16-column reflector.  V and T of every
+// panel go to W and T in global memory, from which qr_formq_kernel forms Q
+// (Q is not an input of the factorization's later panels, so its
+// accumulation need not wait on the four waves of this workgroup).
 // ---------------------------------------------------------------------------
 template <int MX>
 __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, double* __restrict__ Wg,
@@ -805,46 +806,107 @@ __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, d
     }
   }
 
-  // Q = H_0 H_1 ... accumulated backwards from the identity
+}
+
+// ---------------------------------------------------------------------------
+// Q = H_0 H_1 ... H_{np-1} of a QR left by qr_regs_kernel<MX>, one wave per
+// 16-column tile of Q and matrix.  Tile cj starts as the identity's and
+// takes the block reflectors I - V_p T_p V_p^T of panels p = cj, cj - 1, ...,
+// 0 (those right of its columns leave it unchanged), V_p from W (unit
+// diagonal, below it the stored reflector, zero above) and T_p from T,
+// backwards from the identity as in qr_blocked_kernel.  The tiles are
+// independent, so they run on as many SIMDs as there are tiles instead of
+// queueing on the four waves of the factorization's workgroup.  The next
+// panel's V and T are loaded to registers while the current one is applied.
+// ---------------------------------------------------------------------------
+template <int MX>
+__global__ __launch_bounds__(64) void qr_formq_kernel(const double* __restrict__ Wg, const double* __restrict__ Tg,
+                                                      double* __restrict__ Qg, int n) {
+  constexpr int NTT = (MX + 15) / 16;
+  constexpr int LD = 16 * NTT + 1;         // V row length (odd: column reads spread over the banks)
+  constexpr int RL = 4 * NTT;              // V values per lane and panel: 16 x 16 NTT / 64
+  __shared__ double Vs[NB][LD];
+  __shared__ double Ts[NB][NB + 1];
+  __shared__ double S[NB][NB + 1];
+  const int cj = blockIdx.x, z = blockIdx.y;
+  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+  const int nt = (n + 15) / 16;
+  if (cj >= nt) return;
+  const double* W = Wg + (long)z * n * n;
+  const double* Tst = Tg + (long)z * NB * (n + NB);
+  double* Q = Qg + (long)z * n * n;
+
+  // lane's share of panel p: column li, rows lk + 4i of the panel (below the
+  // diagonal only; the unit diagonal is set when it is staged)
+  double vn[RL], tn[4];
+  auto fetch = [&](int p) {
+    const int p0 = 16 * p, nbw = min(NB, n - p0), m = n - p0;
 #pragma unroll
-  for (int u = 0; u < CPW; ++u)
-#pragma unroll
-    for (int t = 0; t < NTT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 16 * t + frag_row<double>(lane, v), col = 16 * (wave + 4 * u) + li;
-        A[u][t][v] = (row == col && row < n) ? 1.0 : 0.0;
-      }
-  for (int p = npan - 1; p >= 0; --p) {
-    const int p0 = p * NB, nbw = min(NB, n - p0), m = n - p0;
-    __syncthreads();
-    batched_copy<256, (NB * LD + 255) / 256, double>(NB * LD,
-                                  [&](int e) {
-                                    const int j = e / LD, r = e - j * LD;
-                                    double v = 0.0;
-                                    if (j < nbw && r < m) v = (r == j) ? 1.0 : ((r > j) ? W[(long)(p0 + r) * n + p0 + j] : 0.0);
-                                    return v;
-                                  },
-                                  [&](int e, double v) { Vs[e / LD][e % LD] = v; });
-    Ts[tid >> 4][tid & 15] = Tst[(long)p * NB * NB + tid];
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < CPW; ++u) {
-      const int cj = wave + 4 * u;
-      if (cj >= p && cj < nt) apply(u, p, 0);
+    for (int i = 0; i < RL; ++i) {
+      const int r = lk + 4 * i;
+      vn[i] = (li < nbw && r < m && r > li) ? W[(long)(p0 + r) * n + p0 + li] : 0.0;
     }
-  }
 #pragma unroll
-  for (int u = 0; u < CPW; ++u) {
-    const int col = 16 * (wave + 4 * u) + li;
+    for (int k = 0; k < 4; ++k) tn[k] = Tst[(long)p * NB * NB + lane + 64 * k];
+  };
+
+  d4 A[NTT];
+#pragma unroll
+  for (int t = 0; t < NTT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * t + frag_row<double>(lane, v), col = 16 * cj + li;
+      A[t][v] = (row == col && row < n) ? 1.0 : 0.0;
+    }
+  fetch(cj);
+  for (int p = cj; p >= 0; --p) {
+    const int p0 = 16 * p, nbw = min(NB, n - p0), m = n - p0;
+    wave_sync_lds();
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+      const int r = lk + 4 * i;
+      Vs[li][r] = (r == li && li < nbw && r < m) ? 1.0 : vn[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Ts[(lane + 64 * k) >> 4][(lane + 64 * k) & 15] = tn[k];
+    wave_sync_lds();
+    if (p > 0) fetch(p - 1);
+    // A <- (I - V T V^T) A on the tiles t >= p
+    d4 w1 = {0, 0, 0, 0};
 #pragma unroll
     for (int t = 0; t < NTT; ++t)
+      if (t >= p && t < nt) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 16 * t + frag_row<double>(lane, v);
-        if (row < n && col < n) Q[(long)row * n + col] = A[u][t][v];
+        for (int q = 0; q < 4; ++q) w1 = mfma16(Vs[li][16 * (t - p) + 4 * q + lk], A[t][q], w1);
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[frag_row<double>(lane, v)][li] = w1[v];
+    wave_sync_lds();
+    d4 w2 = {0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < NB; k0 += 4) w2 = mfma16(Ts[li][k0 + lk], S[k0 + lk][li], w2);
+    wave_sync_lds();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[frag_row<double>(lane, v)][li] = w2[v];
+    wave_sync_lds();
+    double wb[NB / 4];
+#pragma unroll
+    for (int q = 0; q < NB / 4; ++q) wb[q] = S[4 * q + lk][li];
+#pragma unroll
+    for (int t = 0; t < NTT; ++t)
+      if (t >= p && t < nt) {
+#pragma unroll
+        for (int q = 0; q < NB / 4; ++q) A[t] = mfma16(-Vs[4 * q + lk][16 * (t - p) + li], wb[q], A[t]);
       }
   }
+  const int col = 16 * cj + li;
+#pragma unroll
+  for (int t = 0; t < NTT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * t + frag_row<double>(lane, v);
+      if (row < n && col < n) Q[(long)row * n + col] = A[t][v];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1803,12 +1865,21 @@ hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int 
     hipLaunchKernelGGL(qr_wide_final_kernel, grid, dim3(256), 0, s, Z, W, Q, D, X, n, batch, S);
     return hipGetLastError();
   }
-  if (n <= 64)
+  // up to N = 144: the factorization in registers, then Q over one wave per
+  // tile and matrix (at 12x12 and 128 matrices 256 us against 285 us with
+  // the accumulation left in the factorization's workgroup; 10x10 and 32
+  // matrices 148 against 163 us; 8x8 about the same)
+  const dim3 qgrid((n + 15) / 16, batch);
+  if (n <= 64) {
     hipLaunchKernelGGL(qr_regs_kernel<64>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
-  else if (n <= 112)
+    hipLaunchKernelGGL(qr_formq_kernel<64>, qgrid, dim3(64), 0, s, W, T, Q, n);
+  } else if (n <= 112) {
     hipLaunchKernelGGL(qr_regs_kernel<112>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
-  else if (n <= 144)
+    hipLaunchKernelGGL(qr_formq_kernel<112>, qgrid, dim3(64), 0, s, W, T, Q, n);
+  } else if (n <= 144) {
     hipLaunchKernelGGL(qr_regs_kernel<144>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
+    hipLaunchKernelGGL(qr_formq_kernel<144>, qgrid, dim3(64), 0, s, W, T, Q, n);
+  }
   else
     hipLaunchKernelGGL(qr_blocked_kernel<256>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
   return hipGetLastError();
