@@ -15,8 +15,10 @@
 //               block reflector I - V T V^T (compact WY, T by recursive
 //               doubling from the Gram matrix V^T V) is applied to the
 //               trailing columns with MFMA.  Q is accumulated backwards the
-//               same way.  Outputs Q, D = |diag R| and Rt = D^-1 R P^T (over
-//               Z), so Z = Q diag(D) Rt.
+//               same way, in a launch of its own that gives every 16-column
+//               tile of Q its own wave (qr_formq_kernel, qr_formq4_kernel).
+//               Outputs Q, D = |diag R| and Rt = D^-1 R P^T (over Z), so
+//               Z = Q diag(D) Rt.
 //  Gauss-Jordan in-place inversion with partial (row) pivoting, blocked the
 //               same way: the four waves eliminate a panel (eliminate_panel:
 //               pivot over all unused rows), then every other column gets the
@@ -583,27 +585,6 @@ __global__ __launch_bounds__(256) void qr_blocked_kernel(double* __restrict__ Zg
                                   const int r = e / n, c = e - r * n;
                                   Z[(long)r * n + perm[c]] = (r <= c) ? v / norms[r] : 0.0;
                                 });
-  // Q = H_0 H_1 ... accumulated backwards from the identity
-  for (int e = tid; e < n * n; e += 256) {
-    const int r = e / n, c = e - r * n;
-    Q[e] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int pi = npan - 1; pi >= 0; --pi) {
-    const int p0 = pi * NB, nbw = min(NB, n - p0), m = n - p0;
-    batched_copy<256, 17, double>(NB * VLD,
-                                  [&](int e) {
-                                    const int j = e / VLD, r = e - j * VLD;
-                                    double v = 0.0;
-                                    if (j < nbw && r < m) v = (r == j) ? 1.0 : ((r > j) ? W[(long)(p0 + r) * n + p0 + j] : 0.0);
-                                    return v;
-                                  },
-                                  [&](int e, double v) { Vs[e / VLD][e % VLD] = v; });
-    Ts[tid >> 4][tid & 15] = Tst[(long)pi * NB * NB + tid];
-    __syncthreads();
-    apply_reflector_buf<MX>(Q, n, p0, m, Vs, Ts, 0, p0, Sc[wave]);
-    __syncthreads();
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -907,6 +888,114 @@ __global__ __launch_bounds__(64) void qr_formq_kernel(const double* __restrict__
       const int row = 16 * t + frag_row<double>(lane, v);
       if (row < n && col < n) Q[(long)row * n + col] = A[t][v];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Q of a QR left by qr_blocked_kernel (N up to 256): as qr_formq_kernel, one
+// wave per 16-column tile of Q, but four waves per workgroup (tile columns
+// 4g .. 4g + 3 of one matrix) share each panel's V in LDS, so that V of a
+// panel, up to 32 KB at N = 256, is read once per four tiles and the
+// register prefetch of the next panel is 16 values per thread.  A wave
+// whose tile lies left of the panel only takes part in the staging.  The
+// operations on a tile and their order are those of apply_reflector_buf
+// in qr_blocked_kernel's former in-place accumulation, so Q is the same to
+// the bit.
+// ---------------------------------------------------------------------------
+template <int MX>
+__global__ __launch_bounds__(256) void qr_formq4_kernel(const double* __restrict__ Wg, const double* __restrict__ Tg,
+                                                        double* __restrict__ Qg, int n) {
+  constexpr int NTT = (MX + 15) / 16;
+  constexpr int LD = 16 * NTT + 1;         // V row length (odd: column reads spread over the banks)
+  constexpr int RL = NTT;                  // V values per thread and panel: 16 x 16 NTT / 256
+  __shared__ double Vs[NB][LD];
+  __shared__ double Ts[NB][NB + 1];
+  __shared__ double Sc[4][NB][NB + 1];
+  const int z = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int nt = (n + 15) / 16;
+  const int cj = 4 * blockIdx.x + wave;    // this wave's tile column (none when >= nt)
+  const int pmax = min(4 * (int)blockIdx.x + 3, nt - 1);
+  const double* W = Wg + (long)z * n * n;
+  const double* Tst = Tg + (long)z * NB * (n + NB);
+  double* Q = Qg + (long)z * n * n;
+  double (*S)[NB + 1] = Sc[wave];
+
+  // thread's share of panel p: column tid % 16, rows tid / 16 + 16 i of the
+  // panel (below the diagonal only; the unit diagonal is set when staged)
+  const int sc = tid & 15, sr = tid >> 4;
+  double vn[RL], tn;
+  auto fetch = [&](int p) {
+    const int p0 = 16 * p, nbw = min(NB, n - p0), m = n - p0;
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+      const int r = sr + 16 * i;
+      vn[i] = (sc < nbw && r < m && r > sc) ? W[(long)(p0 + r) * n + p0 + sc] : 0.0;
+    }
+    tn = Tst[(long)p * NB * NB + tid];
+  };
+
+  d4 A[NTT];
+#pragma unroll
+  for (int t = 0; t < NTT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * t + frag_row<double>(lane, v), col = 16 * cj + li;
+      A[t][v] = (row == col && row < n) ? 1.0 : 0.0;
+    }
+  fetch(pmax);
+  for (int p = pmax; p >= 0; --p) {
+    const int p0 = 16 * p, nbw = min(NB, n - p0), m = n - p0;
+    __syncthreads();                       // the previous panel's V and T are no longer read
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+      const int r = sr + 16 * i;
+      Vs[sc][r] = (r == sc && sc < nbw && r < m) ? 1.0 : vn[i];
+    }
+    Ts[tid >> 4][tid & 15] = tn;
+    __syncthreads();
+    if (p > 0) fetch(p - 1);
+    if (cj >= p && cj < nt) {
+      // A <- (I - V T V^T) A on the tiles t >= p
+      d4 w1 = {0, 0, 0, 0};
+#pragma unroll
+      for (int t = 0; t < NTT; ++t)
+        if (t >= p && t < nt) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w1 = mfma16(Vs[li][16 * (t - p) + 4 * q + lk], A[t][q], w1);
+        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S[frag_row<double>(lane, v)][li] = w1[v];
+      wave_sync_lds();
+      d4 w2 = {0, 0, 0, 0};
+#pragma unroll
+      for (int k0 = 0; k0 < NB; k0 += 4) w2 = mfma16(Ts[li][k0 + lk], S[k0 + lk][li], w2);
+      wave_sync_lds();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S[frag_row<double>(lane, v)][li] = w2[v];
+      wave_sync_lds();
+      double wb[NB / 4];
+#pragma unroll
+      for (int q = 0; q < NB / 4; ++q) wb[q] = S[4 * q + lk][li];
+#pragma unroll
+      for (int t = 0; t < NTT; ++t)
+        if (t >= p && t < nt) {
+#pragma unroll
+          for (int q = 0; q < NB / 4; ++q) A[t] = mfma16(-Vs[4 * q + lk][16 * (t - p) + li], wb[q], A[t]);
+        }
+    }
+  }
+  if (cj < nt) {
+    const int col = 16 * cj + li;
+#pragma unroll
+    for (int t = 0; t < NTT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + frag_row<double>(lane, v);
+        if (row < n && col < n) Q[(long)row * n + col] = A[t][v];
+      }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1880,8 +1969,12 @@ hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int 
     hipLaunchKernelGGL(qr_regs_kernel<144>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
     hipLaunchKernelGGL(qr_formq_kernel<144>, qgrid, dim3(64), 0, s, W, T, Q, n);
   }
-  else
+  else {
+    // Q in a launch of its own here too: 1010 against 1133 us for 256
+    // matrices of 256 x 256, 481 against 641 us for 64 of 200 x 200
     hipLaunchKernelGGL(qr_blocked_kernel<256>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
+    hipLaunchKernelGGL(qr_formq4_kernel<256>, dim3((n + 63) / 64, batch), dim3(256), 0, s, W, T, Q, n);
+  }
   return hipGetLastError();
 }
 
