@@ -894,15 +894,17 @@ __global__ __launch_bounds__(64) void qr_formq_kernel(const double* __restrict__
 // Q of a QR left by qr_blocked_kernel (N up to 256): as qr_formq_kernel, one
 // wave per 16-column tile of Q, but four waves per workgroup (tile columns
 // 4g .. 4g + 3 of one matrix) share each panel's V in LDS, so that V of a
-// panel, up to 32 KB at N = 256, is read once per four tiles and the
-// register prefetch of the next panel is 16 values per thread.  A wave
-// whose tile lies left of the panel only takes part in the staging.  The
+// panel, up to 32 KB at N = 256, is read once per four tiles.  Two
+// workgroups per CU (register cap) hide each other's panel loads: 939 us
+// for 256 matrices against 1008 us at one workgroup per CU with the next
+// panel prefetched to registers.  A wave whose tile lies left of the panel
+// only takes part in the staging.  The
 // operations on a tile and their order are those of apply_reflector_buf
 // in qr_blocked_kernel's former in-place accumulation, so Q is the same to
 // the bit.
 // ---------------------------------------------------------------------------
 template <int MX>
-__global__ __launch_bounds__(256) void qr_formq4_kernel(const double* __restrict__ Wg, const double* __restrict__ Tg,
+__global__ __launch_bounds__(256, 2) void qr_formq4_kernel(const double* __restrict__ Wg, const double* __restrict__ Tg,
                                                         double* __restrict__ Qg, int n) {
   constexpr int NTT = (MX + 15) / 16;
   constexpr int LD = 16 * NTT + 1;         // V row length (odd: column reads spread over the banks)
@@ -944,9 +946,9 @@ __global__ __launch_bounds__(256) void qr_formq4_kernel(const double* __restrict
       const int row = 16 * t + frag_row<double>(lane, v), col = 16 * cj + li;
       A[t][v] = (row == col && row < n) ? 1.0 : 0.0;
     }
-  fetch(pmax);
   for (int p = pmax; p >= 0; --p) {
     const int p0 = 16 * p, nbw = min(NB, n - p0), m = n - p0;
+    fetch(p);
     __syncthreads();                       // the previous panel's V and T are no longer read
 #pragma unroll
     for (int i = 0; i < RL; ++i) {
@@ -955,7 +957,6 @@ __global__ __launch_bounds__(256) void qr_formq4_kernel(const double* __restrict
     }
     Ts[tid >> 4][tid & 15] = tn;
     __syncthreads();
-    if (p > 0) fetch(p - 1);
     if (cj >= p && cj < nt) {
       // A <- (I - V T V^T) A on the tiles t >= p
       d4 w1 = {0, 0, 0, 0};
@@ -1970,8 +1971,8 @@ hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int 
     hipLaunchKernelGGL(qr_formq_kernel<144>, qgrid, dim3(64), 0, s, W, T, Q, n);
   }
   else {
-    // Q in a launch of its own here too: 1010 against 1133 us for 256
-    // matrices of 256 x 256, 481 against 641 us for 64 of 200 x 200
+    // Q in a launch of its own here too: 939 against 1133 us for 256
+    // matrices of 256 x 256 (3656 against 4446 us for 1024)
     hipLaunchKernelGGL(qr_blocked_kernel<256>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
     hipLaunchKernelGGL(qr_formq4_kernel<256>, dim3((n + 63) / 64, batch), dim3(256), 0, s, W, T, Q, n);
   }
