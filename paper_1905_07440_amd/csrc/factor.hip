@@ -16,7 +16,7 @@
 //               doubling from the Gram matrix V^T V) is applied to the
 //               trailing columns with MFMA.  Q is accumulated backwards the
 //               same way, in a launch of its own that gives every 16-column
-//               tile of Q its own wave (qr_formq_kernel, qr_formq4_kernel).
+//               tile of Q its own wave (qr_formq_kernel).
 //               Outputs Q, D = |diag R| and Rt = D^-1 R P^T (over Z), so
 //               Z = Q diag(D) Rt.
 //  Gauss-Jordan in-place inversion with partial (row) pivoting, blocked the
@@ -788,121 +788,26 @@ __global__ __launch_bounds__(256) void qr_regs_kernel(double* __restrict__ Zg, d
 }
 
 // ---------------------------------------------------------------------------
-// Q = H_0 H_1 ... H_{np-1} of a QR left by qr_regs_kernel<MX>, one wave per
-// 16-column tile of Q and matrix.  Tile cj starts as the identity's and
-// takes the block reflectors I - V_p T_p V_p^T of panels p = cj, cj - 1, ...,
-// 0 (those right of its columns leave it unchanged), V_p from W (unit
-// diagonal, below it the stored reflector, zero above) and T_p from T,
-// backwards from the identity as in qr_blocked_kernel.  The tiles are
-// independent, so they run on as many SIMDs as there are tiles instead of
-// queueing on the four waves of the factorization's workgroup.  The next
-// panel's V and T are loaded to registers while the current one is applied.
+// Q = H_0 H_1 ... H_{np-1} of a QR left by qr_regs_kernel or
+// qr_blocked_kernel (V of every panel below the diagonal of W, its T in T):
+// one wave per 16-column tile of Q and matrix, four tiles (4g .. 4g + 3) per
+// workgroup.  Tile cj starts as the identity's and takes the block
+// reflectors I - V_p T_p V_p^T of panels p = cj, cj - 1, ..., 0 (those right
+// of its columns leave it unchanged), backwards from the identity.  The
+// tiles are independent, so they spread over the SIMDs instead of queueing
+// on the four waves of the factorization's workgroup, and the four waves of
+// a workgroup share each panel's V in LDS (up to 32 KB at N = 256).  Two
+// workgroups per CU (register cap) hide each other's panel loads: 939 us for
+// 256 QRs of 256 x 256 against 1008 us at one per CU with the next panel
+// prefetched to registers; at 12 x 12, 128 matrices, the QR takes 246 us
+// against 285 us with Q accumulated in the factorization's workgroup and 257
+// us with one single-wave workgroup per tile.  A wave whose tile lies left
+// of the panel only takes part in the staging.  The operations on a tile,
+// and their order, are those of that former in-place accumulation, so Q is
+// the same to the bit.
 // ---------------------------------------------------------------------------
 template <int MX>
-__global__ __launch_bounds__(64) void qr_formq_kernel(const double* __restrict__ Wg, const double* __restrict__ Tg,
-                                                      double* __restrict__ Qg, int n) {
-  constexpr int NTT = (MX + 15) / 16;
-  constexpr int LD = 16 * NTT + 1;         // V row length (odd: column reads spread over the banks)
-  constexpr int RL = 4 * NTT;              // V values per lane and panel: 16 x 16 NTT / 64
-  __shared__ double Vs[NB][LD];
-  __shared__ double Ts[NB][NB + 1];
-  __shared__ double S[NB][NB + 1];
-  const int cj = blockIdx.x, z = blockIdx.y;
-  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
-  const int nt = (n + 15) / 16;
-  if (cj >= nt) return;
-  const double* W = Wg + (long)z * n * n;
-  const double* Tst = Tg + (long)z * NB * (n + NB);
-  double* Q = Qg + (long)z * n * n;
-
-  // lane's share of panel p: column li, rows lk + 4i of the panel (below the
-  // diagonal only; the unit diagonal is set when it is staged)
-  double vn[RL], tn[4];
-  auto fetch = [&](int p) {
-    const int p0 = 16 * p, nbw = min(NB, n - p0), m = n - p0;
-#pragma unroll
-    for (int i = 0; i < RL; ++i) {
-      const int r = lk + 4 * i;
-      vn[i] = (li < nbw && r < m && r > li) ? W[(long)(p0 + r) * n + p0 + li] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) tn[k] = Tst[(long)p * NB * NB + lane + 64 * k];
-  };
-
-  d4 A[NTT];
-#pragma unroll
-  for (int t = 0; t < NTT; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 16 * t + frag_row<double>(lane, v), col = 16 * cj + li;
-      A[t][v] = (row == col && row < n) ? 1.0 : 0.0;
-    }
-  fetch(cj);
-  for (int p = cj; p >= 0; --p) {
-    const int p0 = 16 * p, nbw = min(NB, n - p0), m = n - p0;
-    wave_sync_lds();
-#pragma unroll
-    for (int i = 0; i < RL; ++i) {
-      const int r = lk + 4 * i;
-      Vs[li][r] = (r == li && li < nbw && r < m) ? 1.0 : vn[i];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) Ts[(lane + 64 * k) >> 4][(lane + 64 * k) & 15] = tn[k];
-    wave_sync_lds();
-    if (p > 0) fetch(p - 1);
-    // A <- (I - V T V^T) A on the tiles t >= p
-    d4 w1 = {0, 0, 0, 0};
-#pragma unroll
-    for (int t = 0; t < NTT; ++t)
-      if (t >= p && t < nt) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) w1 = mfma16(Vs[li][16 * (t - p) + 4 * q + lk], A[t][q], w1);
-      }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) S[frag_row<double>(lane, v)][li] = w1[v];
-    wave_sync_lds();
-    d4 w2 = {0, 0, 0, 0};
-#pragma unroll
-    for (int k0 = 0; k0 < NB; k0 += 4) w2 = mfma16(Ts[li][k0 + lk], S[k0 + lk][li], w2);
-    wave_sync_lds();
-#pragma unroll
-    for (int v = 0; v < 4; ++v) S[frag_row<double>(lane, v)][li] = w2[v];
-    wave_sync_lds();
-    double wb[NB / 4];
-#pragma unroll
-    for (int q = 0; q < NB / 4; ++q) wb[q] = S[4 * q + lk][li];
-#pragma unroll
-    for (int t = 0; t < NTT; ++t)
-      if (t >= p && t < nt) {
-#pragma unroll
-        for (int q = 0; q < NB / 4; ++q) A[t] = mfma16(-Vs[4 * q + lk][16 * (t - p) + li], wb[q], A[t]);
-      }
-  }
-  const int col = 16 * cj + li;
-#pragma unroll
-  for (int t = 0; t < NTT; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = 16 * t + frag_row<double>(lane, v);
-      if (row < n && col < n) Q[(long)row * n + col] = A[t][v];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Q of a QR left by qr_blocked_kernel (N up to 256): as qr_formq_kernel, one
-// wave per 16-column tile of Q, but four waves per workgroup (tile columns
-// 4g .. 4g + 3 of one matrix) share each panel's V in LDS, so that V of a
-// panel, up to 32 KB at N = 256, is read once per four tiles.  Two
-// workgroups per CU (register cap) hide each other's panel loads: 939 us
-// for 256 matrices against 1008 us at one workgroup per CU with the next
-// panel prefetched to registers.  A wave whose tile lies left of the panel
-// only takes part in the staging.  The
-// operations on a tile and their order are those of apply_reflector_buf
-// in qr_blocked_kernel's former in-place accumulation, so Q is the same to
-// the bit.
-// ---------------------------------------------------------------------------
-template <int MX>
-__global__ __launch_bounds__(256, 2) void qr_formq4_kernel(const double* __restrict__ Wg, const double* __restrict__ Tg,
+__global__ __launch_bounds__(256, 2) void qr_formq_kernel(const double* __restrict__ Wg, const double* __restrict__ Tg,
                                                         double* __restrict__ Qg, int n) {
   constexpr int NTT = (MX + 15) / 16;
   constexpr int LD = 16 * NTT + 1;         // V row length (odd: column reads spread over the banks)
@@ -1953,26 +1858,21 @@ hipError_t launch_qr(double* Z, double* W, double* Q, double* D, double* T, int 
     hipLaunchKernelGGL(qr_wide_final_kernel, grid, dim3(256), 0, s, Z, W, Q, D, X, n, batch, S);
     return hipGetLastError();
   }
-  // up to N = 144: the factorization in registers, then Q over one wave per
-  // tile and matrix (at 12x12 and 128 matrices 256 us against 285 us with
-  // the accumulation left in the factorization's workgroup; 10x10 and 32
-  // matrices 148 against 163 us; 8x8 about the same)
-  const dim3 qgrid((n + 15) / 16, batch);
+  // R, D and Rt (in registers up to N = 144, else through L2), then Q in a
+  // launch of its own
+  const dim3 qgrid((n + 63) / 64, batch);
   if (n <= 64) {
     hipLaunchKernelGGL(qr_regs_kernel<64>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
-    hipLaunchKernelGGL(qr_formq_kernel<64>, qgrid, dim3(64), 0, s, W, T, Q, n);
+    hipLaunchKernelGGL(qr_formq_kernel<64>, qgrid, dim3(256), 0, s, W, T, Q, n);
   } else if (n <= 112) {
     hipLaunchKernelGGL(qr_regs_kernel<112>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
-    hipLaunchKernelGGL(qr_formq_kernel<112>, qgrid, dim3(64), 0, s, W, T, Q, n);
+    hipLaunchKernelGGL(qr_formq_kernel<112>, qgrid, dim3(256), 0, s, W, T, Q, n);
   } else if (n <= 144) {
     hipLaunchKernelGGL(qr_regs_kernel<144>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
-    hipLaunchKernelGGL(qr_formq_kernel<144>, qgrid, dim3(64), 0, s, W, T, Q, n);
-  }
-  else {
-    // Q in a launch of its own here too: 939 against 1133 us for 256
-    // matrices of 256 x 256 (3656 against 4446 us for 1024)
+    hipLaunchKernelGGL(qr_formq_kernel<144>, qgrid, dim3(256), 0, s, W, T, Q, n);
+  } else {
     hipLaunchKernelGGL(qr_blocked_kernel<256>, dim3(batch), dim3(256), 0, s, Z, W, Q, D, T, n);
-    hipLaunchKernelGGL(qr_formq4_kernel<256>, dim3((n + 63) / 64, batch), dim3(256), 0, s, W, T, Q, n);
+    hipLaunchKernelGGL(qr_formq_kernel<256>, qgrid, dim3(256), 0, s, W, T, Q, n);
   }
   return hipGetLastError();
 }
