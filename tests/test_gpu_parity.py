@@ -239,6 +239,27 @@ def test_large_lattice_fp64(hq, nx):
     ctx.close()
 
 
+@pytest.mark.parametrize("nx", [13, 15])
+def test_from_scratch_blocked_ragged(hq, nx):
+    """From-scratch G and log det with 80 matrices at the first level of the
+    pairwise UDT tree (8 chains x 10 blocks; the tree is what block-move
+    proposals are scored with), so that level takes the QR with one
+    workgroup per matrix through L2 and Q in a launch of its own, at N = 169
+    and 225 (ragged last panel; the later levels spread over several
+    workgroups per matrix).  At creation and after a recompute (an oracle
+    sweep with block moves at this size takes minutes)."""
+    say("from scratch, blocked QR, %dx%d" % (nx, nx))
+    gr = dict(nx=nx, chains=8, g=1.1, beta=2.0, n_stab=2, global_width=0.5)
+    ctx = make_ctx(hq, [gr], seed=31)
+    chains = {c: dqmc.Chain(params_of(gr), 31, c) for c in (0, 7)}
+    for c, ch in chains.items():
+        assert_state(ctx, c, ch, TOL64, "%dx%d chain %d at creation" % (nx, nx, c))
+    ctx.recompute()
+    for c, ch in chains.items():
+        assert_state(ctx, c, ch, TOL64, "%dx%d chain %d recomputed" % (nx, nx, c))
+    ctx.close()
+
+
 @pytest.mark.parametrize("ns", [9, 10])
 def test_block_product_chunks_16x16(hq, ns):
     """N = 256 with n_stab slices per block above the 8 row-scale sets that
